@@ -1,0 +1,24 @@
+"""Plain FP64 CPU oracle for AMG block-preconditioned GMRES on the multi-group
+radiation-diffusion block system (Yue, Zhang, Xu, Shu, Shi, "Algebraic
+multigrid block preconditioning for multi-group radiation diffusion
+equations", arXiv 2002.04958).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this package; it exists so that tests, the smoke check and the CPU
+baseline leg of the benchmark can compare the GPU library against an
+independent, slow, obviously correct implementation.  It shares no code with
+the GPU path; both consume the arrays drawn by ``synth_inputs``.
+
+Modules
+  assemble  block system of eq. 2.2 from per-cell coefficients
+  amg       classical AMG: strength, PMIS, modified classical interpolation,
+            Galerkin coarse operators, CF-l1-Jacobi V(1,1) cycle
+  precond   monolithic AMG, block-diagonal, PCTL (Sec. 3.3), Schur1/Schur2
+            (Sec. 3.4) with the diagonal approximations of Sec. 3.5
+  krylov    restarted right-preconditioned (flexible) GMRES(m)
+  adjoint   transposed-system solve and coefficient gradients
+
+Parity status: every function is pinned by a test in tests/test_oracle_*.py
+except where its docstring says "parity unpinned".
+"""
+from . import assemble, amg, precond, krylov, adjoint  # noqa: F401

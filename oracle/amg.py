@@ -1,0 +1,460 @@
+"""Classical AMG (oracle): the scalar and monolithic AMG the paper uses as its
+inner solver (Section 3.1; setup/solve phases, strength threshold 0.25,
+C-then-F relaxation going down and F-then-C going up, classical modified
+interpolation, Galerkin coarse operators with restriction P^T, at most 100
+unknowns on the coarsest level solved by Gaussian elimination).
+
+Components the paper names but does not define, and the readings taken here:
+  * coarsening: the paper uses hypre's Falgout coarsening; this oracle uses
+    PMIS (De Sterck, Yang, Heys 2006) with integer keys
+    (|S^T_i| << 32 | hash32) and ties broken by the larger row index.
+    hash32 is the top 32 bits of the first SplitMix64 output (Steele, Lea,
+    Flood 2014) for the state seed ^ (level << 56) ^ i.
+  * strength: classical, sign-aware: j is a strong dependency of i when
+    -a_ij >= theta * max_{k != i}(-a_ik); a row whose maximum is <= 0, or
+    whose row sum is >= dominance_theta * a_ii, has no strong dependencies
+    (the complement of the counted set of Definition 2, theta_wd = 0.9).
+    dominance_theta <= 0 disables that cut.
+  * interpolation: classical direct + distribution with the "modified"
+    treatment of strong F-F connections that share no C point (lumped into
+    the diagonal) and sign-filtered distribution coefficients; no truncation.
+  * smoother: CF-ordered l1-Jacobi, d_i = a_ii + sum_{j != i} |a_ij|
+    (in place of hybrid Gauss-Seidel, which is sequential).
+  * coarsest level: dense LU with partial pivoting when it has at most
+    dense_max rows; a stalled coarsening with more rows is relaxed by
+    n_pre + n_post l1-Jacobi sweeps instead.
+
+Every floating-point reduction that feeds a discrete decision or a stored
+entry is written as an explicit left-to-right sum in a stated order (see
+``seq_segment_sum``), so that another implementation following the same
+order obtains identical bits.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+C_PT = 1
+F_PT = -1
+UNDECIDED = 0
+
+_MASK64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+# ----------------------------------------------------------------------------
+# helpers
+# ----------------------------------------------------------------------------
+def csr_rows(A: sp.csr_matrix) -> np.ndarray:
+    """Row index of every stored entry."""
+    return np.repeat(np.arange(A.shape[0], dtype=np.int64), np.diff(A.indptr))
+
+
+def seq_segment_sum(starts: np.ndarray, lens: np.ndarray, vals: np.ndarray,
+                    init: Optional[np.ndarray] = None) -> np.ndarray:
+    """out[s] = init[s] + vals[starts[s]] + vals[starts[s]+1] + ... added
+    strictly left to right (one IEEE addition per term)."""
+    nseg = len(starts)
+    acc = np.zeros(nseg) if init is None else np.array(init, dtype=np.float64)
+    if nseg == 0:
+        return acc
+    maxlen = int(lens.max()) if len(lens) else 0
+    for p in range(maxlen):
+        m = lens > p
+        acc[m] = acc[m] + vals[starts[m] + p]
+    return acc
+
+
+def diagonal_of(A: sp.csr_matrix) -> np.ndarray:
+    rows = csr_rows(A)
+    is_d = A.indices == rows
+    if np.count_nonzero(is_d) != A.shape[0]:
+        raise ValueError("every row must store its diagonal entry")
+    d = np.empty(A.shape[0])
+    d[rows[is_d]] = A.data[is_d]
+    return d
+
+
+def splitmix64_first(state: np.ndarray) -> np.ndarray:
+    """First output of SplitMix64 seeded with ``state`` (uint64 array)."""
+    with np.errstate(over="ignore"):
+        z = (state + np.uint64(0x9E3779B97F4A7C15)) & _MASK64
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def hash32(seed: int, level: int, idx: np.ndarray) -> np.ndarray:
+    st = (np.uint64(seed) ^ (np.uint64(level) << np.uint64(56))
+          ^ idx.astype(np.uint64))
+    return splitmix64_first(st) >> np.uint64(32)
+
+
+# ----------------------------------------------------------------------------
+# strength of connection
+# ----------------------------------------------------------------------------
+def strength(A: sp.csr_matrix, theta: float = 0.25,
+             dominance_theta: float = 0.9) -> np.ndarray:
+    """Boolean flag per stored entry of A: True when the column is a strong
+    dependency of the row.  Row sums are taken left to right in ascending
+    column order starting from 0."""
+    n = A.shape[0]
+    rows = csr_rows(A)
+    cols = A.indices.astype(np.int64)
+    v = A.data
+    offd = cols != rows
+    m = np.full(n, -np.inf)
+    np.maximum.at(m, rows[offd], -v[offd])
+    lens = np.diff(A.indptr)
+    rs = seq_segment_sum(A.indptr[:-1].astype(np.int64), lens, v)
+    diag = diagonal_of(A)
+    empty = m <= 0.0
+    if dominance_theta > 0.0:
+        empty |= rs >= dominance_theta * diag
+    S = offd & (-v >= theta * m[rows]) & ~empty[rows]
+    return S
+
+
+def strength_transpose_counts(A: sp.csr_matrix, S: np.ndarray) -> np.ndarray:
+    """|S^T_i| = number of rows that depend strongly on i."""
+    return np.bincount(A.indices[S], minlength=A.shape[0]).astype(np.int64)
+
+
+# ----------------------------------------------------------------------------
+# PMIS coarsening
+# ----------------------------------------------------------------------------
+def pmis_keys(A: sp.csr_matrix, S: np.ndarray, seed: int, level: int) -> np.ndarray:
+    """PMIS measure as an integer: (|S^T_i| << 32) | hash32(seed, level, i)."""
+    stc = strength_transpose_counts(A, S)
+    return (stc.astype(np.uint64) << np.uint64(32)) | hash32(seed, level,
+                                                            np.arange(A.shape[0]))
+
+
+def pmis_with_keys(A: sp.csr_matrix, S: np.ndarray, key: np.ndarray,
+                   return_rounds: bool = False):
+    """PMIS rounds (De Sterck, Yang, Heys 2006) for given integer keys.
+
+    Rows nobody depends on (|S^T_i| = 0) start as F, all others undecided.
+    Each round, simultaneously over all rows:
+      1. an undecided row whose (key, index) is larger than that of every
+         undecided row in S_i u S^T_i becomes C;
+      2. every other undecided row with a strong dependency on a row made C
+         in step 1 becomes F.
+    """
+    n = A.shape[0]
+    rows = csr_rows(A)[S]
+    cols = A.indices[S].astype(np.int64)
+    stc = strength_transpose_counts(A, S)
+    state = np.zeros(n, dtype=np.int8)
+    state[stc == 0] = F_PT
+    ei = np.concatenate([rows, cols])
+    ej = np.concatenate([cols, rows])
+    rounds = 0
+    while np.any(state == UNDECIDED):
+        rounds += 1
+        und = state == UNDECIDED
+        live = und[ei] & und[ej]
+        beaten = (key[ej] > key[ei]) | ((key[ej] == key[ei]) & (ej > ei))
+        lose = np.zeros(n, dtype=bool)
+        lose[ei[live & beaten]] = True
+        new_c = und & ~lose
+        state[new_c] = C_PT
+        dep = np.zeros(n, dtype=bool)
+        hit = new_c[cols] & und[rows] & ~new_c[rows]
+        dep[rows[hit]] = True
+        state[dep] = F_PT
+    if return_rounds:
+        return state, rounds
+    return state
+
+
+def pmis(A: sp.csr_matrix, S: np.ndarray, seed: int, level: int,
+         return_rounds: bool = False):
+    """C/F splitting by PMIS.  Returns int8 array (1 = C, -1 = F)."""
+    return pmis_with_keys(A, S, pmis_keys(A, S, seed, level), return_rounds)
+
+
+# ----------------------------------------------------------------------------
+# classical modified interpolation
+# ----------------------------------------------------------------------------
+def interpolation(A: sp.csr_matrix, S: np.ndarray, cf: np.ndarray) -> sp.csr_matrix:
+    """Prolongation P (n x n_c).  Coarse numbering: C points in ascending fine
+    index.  C rows: identity.  F row i, with C_i = C & S_i, F_i = F & S_i and
+    W_i the remaining off-diagonal neighbours:
+        ahat_kj = a_kj if sign(a_kj) != sign(a_kk) else 0
+        sigma_ik = sum_{j in C_i} ahat_kj                  (ascending j)
+        L_i = {k in F_i : sigma_ik == 0}
+        at_ii = a_ii + sum_{n in W_i u L_i} a_in            (ascending column)
+        w_ij = -(a_ij + sum_{k in F_i \\ L_i} a_ik ahat_kj / sigma_ik) / at_ii
+                                                            (ascending k)
+    """
+    n = A.shape[0]
+    isC = cf == C_PT
+    cidx = np.cumsum(isC) - 1
+    nc = int(isC.sum())
+    rows = csr_rows(A)
+    cols = A.indices.astype(np.int64)
+    v = A.data
+    diag = diagonal_of(A)
+    offd = cols != rows
+    Frow = ~isC[rows]
+    sC = S & isC[cols] & Frow            # strong C entries of F rows
+    sF = S & ~isC[cols] & Frow           # strong F entries of F rows
+    weak = offd & ~S & Frow
+    ahat = np.where(np.sign(v) != np.sign(diag[rows]), v, 0.0)
+
+    # strong-C entry lists per row
+    eC = np.nonzero(sC)[0]
+    cntC = np.bincount(rows[eC], minlength=n)
+    startC = np.zeros(n + 1, dtype=np.int64)
+    startC[1:] = np.cumsum(cntC)
+    # strong-F pairs (i, k)
+    eF = np.nonzero(sF)[0]
+    pi = rows[eF]
+    pk = cols[eF]
+    tlen = cntC[pi]
+    # triplets (pair p, j in C_i), pairs in CSR order, j ascending
+    tp = np.repeat(np.arange(len(eF)), tlen)
+    toff = np.arange(len(tp)) - np.repeat(np.cumsum(tlen) - tlen, tlen)
+    tj_entry = eC[startC[pi][tp] + toff]             # entry (i, j) in A
+    tj = cols[tj_entry]
+    tk = pk[tp]
+    # look up A(k, j)
+    akey = rows * n + cols                            # sorted (CSR order)
+    q = tk * n + tj
+    pos = np.searchsorted(akey, q)
+    pos_c = np.minimum(pos, len(akey) - 1)
+    found = akey[pos_c] == q
+    ahat_kj = np.where(found, ahat[pos_c], 0.0)
+    # sigma per pair, ascending j
+    pstart = np.cumsum(tlen) - tlen
+    sigma = seq_segment_sum(pstart, tlen, ahat_kj)
+    lumped = sigma == 0.0
+    # modified diagonal, ascending column order, starting from a_ii
+    add = np.zeros(len(v))
+    add[weak] = v[weak]
+    add[eF[lumped]] = v[eF[lumped]]
+    lens = np.diff(A.indptr)
+    at_ii = seq_segment_sum(A.indptr[:-1].astype(np.int64), lens, add, init=diag)
+    # numerators per strong-C entry (i, j), contributions in ascending k
+    a_ik = v[eF][tp]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        term = np.where(lumped[tp], 0.0, (a_ik * ahat_kj) / sigma[tp])
+    order = np.lexsort((tk, tj_entry))               # group by (i,j), then k
+    grp = tj_entry[order]
+    term_o = term[order]
+    # segments: for every strong-C entry, its run in the sorted order
+    cnt_e = np.bincount(grp, minlength=len(v))[eC]
+    st_e = np.cumsum(cnt_e) - cnt_e
+    num = seq_segment_sum(st_e, cnt_e, term_o, init=v[eC])
+    w = -num / at_ii[rows[eC]]
+
+    # assemble P
+    p_rows = np.concatenate([rows[eC], np.nonzero(isC)[0]])
+    p_cols = np.concatenate([cidx[cols[eC]], cidx[isC]])
+    p_vals = np.concatenate([w, np.ones(nc)])
+    P = sp.csr_matrix((p_vals, (p_rows, p_cols)), shape=(n, nc))
+    P.sort_indices()
+    return P
+
+
+# ----------------------------------------------------------------------------
+# Galerkin coarse operator
+# ----------------------------------------------------------------------------
+def spgemm_ordered(A: sp.csr_matrix, B: sp.csr_matrix) -> sp.csr_matrix:
+    """C = A B with the structural pattern (every (i, j) reached by some
+    a_ik b_kj is stored, even if the sum is zero) and each entry summed left
+    to right over ascending k, starting from 0."""
+    n = A.shape[0]
+    m = B.shape[1]
+    ai = csr_rows(A)
+    ak = A.indices.astype(np.int64)
+    cnt = np.diff(B.indptr)[ak]
+    tot = int(cnt.sum())
+    e_rep = np.repeat(np.arange(len(ak)), cnt)
+    boff = np.arange(tot) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+    bidx = B.indptr[ak][e_rep] + boff
+    i_x = ai[e_rep]
+    j_x = B.indices[bidx].astype(np.int64)
+    prod = A.data[e_rep] * B.data[bidx]
+    key = i_x * m + j_x
+    order = np.argsort(key, kind="stable")           # keeps ascending k
+    ks = key[order]
+    uniq, first, counts = np.unique(ks, return_index=True, return_counts=True)
+    vals = seq_segment_sum(first, counts, prod[order])
+    C = sp.csr_matrix((vals, (uniq // m, uniq % m)), shape=(n, m))
+    C.sort_indices()
+    return C
+
+
+def transpose_csr(P: sp.csr_matrix) -> sp.csr_matrix:
+    """Explicit transpose with columns sorted (entries copied, no arithmetic)."""
+    R = sp.csr_matrix(P.T)
+    R.sort_indices()
+    return R
+
+
+def galerkin(A: sp.csr_matrix, P: sp.csr_matrix):
+    """R = P^T and A_c = R (A P), both products in canonical order."""
+    R = transpose_csr(P)
+    AP = spgemm_ordered(A, P)
+    Ac = spgemm_ordered(R, AP)
+    return R, Ac
+
+
+def l1_diagonal(A: sp.csr_matrix) -> np.ndarray:
+    """d_i = a_ii + sum_{j != i} |a_ij| added in ascending column order."""
+    rows = csr_rows(A)
+    offd = A.indices != rows
+    add = np.where(offd, np.abs(A.data), 0.0)
+    return seq_segment_sum(A.indptr[:-1].astype(np.int64), np.diff(A.indptr),
+                           add, init=diagonal_of(A))
+
+
+# ----------------------------------------------------------------------------
+# hierarchy
+# ----------------------------------------------------------------------------
+@dataclass
+class AMGParams:
+    strength_theta: float = 0.25       # Section 3.1
+    dominance_theta: float = 0.9       # Definition 2 threshold
+    seed: int = 1
+    max_levels: int = 25
+    coarse_max: int = 100              # Section 3.1: at most 100 DoFs
+    dense_max: int = 2000
+    n_pre: int = 1
+    n_post: int = 1
+
+
+@dataclass
+class Level:
+    A: sp.csr_matrix
+    d: np.ndarray                      # l1 diagonal
+    cf: Optional[np.ndarray] = None    # None on the coarsest level
+    P: Optional[sp.csr_matrix] = None
+    R: Optional[sp.csr_matrix] = None
+    pmis_rounds: int = 0
+
+
+@dataclass
+class Hierarchy:
+    levels: List[Level]
+    params: AMGParams
+    coarse_kind: str = "lu"            # "lu" or "jacobi"
+    lu: Optional[tuple] = None
+    stats: dict = field(default_factory=dict)
+
+    @property
+    def A(self) -> sp.csr_matrix:
+        return self.levels[0].A
+
+    def grid_complexity(self) -> float:
+        return sum(L.A.shape[0] for L in self.levels) / self.levels[0].A.shape[0]
+
+    def operator_complexity(self) -> float:
+        return sum(L.A.nnz for L in self.levels) / self.levels[0].A.nnz
+
+
+def setup(A: sp.csr_matrix, params: Optional[AMGParams] = None) -> Hierarchy:
+    """AMG setup: levels stop when n <= coarse_max, when coarsening stalls
+    (no C point, or more than 90% C points) or at max_levels."""
+    p = params or AMGParams()
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    levels: List[Level] = []
+    lvl = 0
+    while True:
+        n = A.shape[0]
+        d = l1_diagonal(A)
+        if n <= p.coarse_max or lvl == p.max_levels - 1:
+            levels.append(Level(A, d))
+            break
+        S = strength(A, p.strength_theta, p.dominance_theta)
+        cf, rounds = pmis(A, S, p.seed, lvl, return_rounds=True)
+        nc = int(np.count_nonzero(cf == C_PT))
+        if nc == 0 or 10 * nc > 9 * n:
+            levels.append(Level(A, d))
+            break
+        P = interpolation(A, S, cf)
+        R, Ac = galerkin(A, P)
+        levels.append(Level(A, d, cf, P, R, rounds))
+        A = Ac
+        lvl += 1
+    H = Hierarchy(levels, p)
+    Ac = levels[-1].A
+    if Ac.shape[0] <= p.dense_max:
+        H.coarse_kind = "lu"
+        H.lu = sla.lu_factor(Ac.toarray())
+    else:
+        H.coarse_kind = "jacobi"
+    return H
+
+
+# ----------------------------------------------------------------------------
+# solve phase
+# ----------------------------------------------------------------------------
+def half_sweep(A, d, b, x, mask):
+    """l1-Jacobi on the rows in ``mask``: x_S += (b_S - (A x)_S) / d_S, with
+    A x evaluated at the values x had when the half-sweep started."""
+    r = b - A @ x
+    y = x.copy()
+    y[mask] = x[mask] + r[mask] / d[mask]
+    return y
+
+
+def vcycle(H: Hierarchy, b: np.ndarray, lvl: int = 0) -> np.ndarray:
+    """One V(n_pre, n_post) cycle with zero initial guess (Section 3.1)."""
+    L = H.levels[lvl]
+    p = H.params
+    if lvl == len(H.levels) - 1:
+        if H.coarse_kind == "lu":
+            return sla.lu_solve(H.lu, b)
+        x = np.zeros_like(b)
+        allrows = np.ones(len(b), dtype=bool)
+        for _ in range(p.n_pre + p.n_post):
+            x = half_sweep(L.A, L.d, b, x, allrows)
+        return x
+    isC = L.cf == C_PT
+    isF = ~isC
+    x = np.zeros_like(b)
+    for _ in range(p.n_pre):                 # going down: C then F
+        x = half_sweep(L.A, L.d, b, x, isC)
+        x = half_sweep(L.A, L.d, b, x, isF)
+    r = b - L.A @ x
+    e = vcycle(H, L.R @ r, lvl + 1)
+    x = x + L.P @ e
+    for _ in range(p.n_post):                # going up: F then C
+        x = half_sweep(L.A, L.d, b, x, isF)
+        x = half_sweep(L.A, L.d, b, x, isC)
+    return x
+
+
+def apply_cycles(H: Hierarchy, b: np.ndarray, k: int = 1) -> np.ndarray:
+    """k V-cycles as a stationary iteration from zero: z <- z + V(b - A z)."""
+    z = vcycle(H, b)
+    for _ in range(k - 1):
+        z = z + vcycle(H, b - H.A @ z)
+    return z
+
+
+def solve_to_tolerance(H: Hierarchy, b: np.ndarray, rtol: float,
+                       max_cycles: int = 100):
+    """V-cycles until ||b - A z|| < rtol ||b|| (option #3 of Section 3.5).
+    Returns (z, cycles)."""
+    nb = np.linalg.norm(b)
+    z = np.zeros_like(b)
+    if nb == 0.0:
+        return z, 0
+    k = 0
+    r = b.copy()
+    while k < max_cycles:
+        z = z + vcycle(H, r)
+        k += 1
+        r = b - H.A @ z
+        if np.linalg.norm(r) < rtol * nb:
+            break
+    return z, k

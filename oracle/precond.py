@@ -1,0 +1,272 @@
+"""Block preconditioners of Section 3 (oracle).
+
+Each preconditioner acts as w = M^{-1} b on a Krylov vector b of length
+(G+2) N ordered [groups..., E, I].  The scalar inverses inside are
+"Inverse" objects; the paper's practical form uses a fixed number of AMG
+V-cycles (option #2 of Section 3.5) on:
+
+  monolithic   one hierarchy on the whole matrix (Section 3.1)
+  bdiag        A_1..A_G, A_E, A_I (block-diagonal special case, Section 3.6)
+  pctl         A_1..A_G, A_E, A_I for the block relaxation and A_c of eq. 3.3
+               for the coarse correction (Section 3.3); the diagonal
+               interpolation weights p_g = -A_g^{-1} D_gE 1, p_I = -A_I^{-1} D_IE 1
+               are computed by V-cycles to a relative residual below
+               pctl_p_tol (option #3)
+  schur1       A_I, C^_E, C^_g (Section 3.4, five steps; Section 3.5 hats)
+  schur2       A_E, S^_g, S^_I (Section 3.4, three steps; Section 3.5 hats)
+  schur2_lower Schur2 steps 1-2 only (the elimination factor of eq. 3.2)
+
+Diagonal ("hat") approximations of Section 3.5, each one entry update per
+row, evaluated as t = (d1 * d2) / diag, new = a_ii - t:
+  S^_g = A_g - D_gE diag(A_E)^-1 D_Eg       S^_I = A_I - D_IE diag(A_E)^-1 D_EI
+  C^_E = A_E - D_EI diag(A_I)^-1 D_IE       C^_g = A_g - D_gE diag(C^_E)^-1 D_Eg
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import amg
+from .assemble import BlockSystem
+
+KINDS = ("amg", "bdiag", "pctl", "schur1", "schur2", "schur2_lower")
+
+
+@dataclass
+class BlockParams:
+    kind: str = "schur2"
+    amg: amg.AMGParams = field(default_factory=amg.AMGParams)
+    cycles_rad: int = 1
+    cycles_E: int = 1
+    cycles_I: int = 1
+    pctl_p_tol: float = 1e-2           # inner tolerance, Section 4
+    pctl_p_maxcycles: int = 100
+
+
+class Counters:
+    def __init__(self):
+        self.inverses = 0
+        self.matvecs = 0
+
+
+class Inverse:
+    """Approximate action of a scalar matrix inverse."""
+
+    def __init__(self, M: sp.csr_matrix, fn: Callable[[np.ndarray], np.ndarray],
+                 counters: Counters):
+        self.M = M
+        self._fn = fn
+        self._c = counters
+
+    def __call__(self, b: np.ndarray) -> np.ndarray:
+        self._c.inverses += 1
+        return self._fn(b)
+
+
+def amg_inverse(M, params: amg.AMGParams, cycles: int, counters: Counters,
+                hier: Optional[amg.Hierarchy] = None) -> Inverse:
+    H = hier if hier is not None else amg.setup(M, params)
+    inv = Inverse(M, lambda b: amg.apply_cycles(H, b, cycles), counters)
+    inv.hierarchy = H
+    return inv
+
+
+def exact_inverse(M, counters: Counters) -> Inverse:
+    """Direct sparse LU: for the exactness tests of Section 3.4."""
+    lu = spla.splu(sp.csc_matrix(M))
+    return Inverse(M, lambda b: lu.solve(b), counters)
+
+
+def diag_update(A: sp.csr_matrix, d1: np.ndarray, d2: np.ndarray,
+                diag: np.ndarray) -> sp.csr_matrix:
+    """A - diag(d1 * d2 / diag) on A's own pattern."""
+    B = A.copy()
+    rows = amg.csr_rows(B)
+    isd = B.indices == rows
+    t = (d1 * d2) / diag
+    B.data[isd] = B.data[isd] - t[rows[isd]]
+    return B
+
+
+def hatted(sys: BlockSystem, kind: str):
+    """The explicit scalar matrices whose inverses a kind needs, keyed by
+    role: ('g', g) radiation groups, 'E', 'I', 'c' (PCTL coarse)."""
+    G = sys.G
+    A = sys.blocks
+    dE = amg.diagonal_of(A[G])
+    dI = amg.diagonal_of(A[G + 1])
+    out = {}
+    if kind in ("bdiag", "pctl"):
+        for g in range(G):
+            out[("g", g)] = A[g]
+        out["E"] = A[G]
+        out["I"] = A[G + 1]
+    elif kind == "schur1":
+        CE = diag_update(A[G], sys.d_EI, sys.d_IE, dI)
+        dCE = amg.diagonal_of(CE)
+        for g in range(G):
+            out[("g", g)] = diag_update(A[g], sys.d_gE[g], sys.d_Eg[g], dCE)
+        out["E"] = CE
+        out["I"] = A[G + 1]
+    elif kind in ("schur2", "schur2_lower"):
+        for g in range(G):
+            out[("g", g)] = diag_update(A[g], sys.d_gE[g], sys.d_Eg[g], dE)
+        out["E"] = A[G]
+        out["I"] = diag_update(A[G + 1], sys.d_IE, sys.d_EI, dE)
+    else:
+        raise ValueError(kind)
+    return out
+
+
+def pctl_coarse(sys: BlockSystem, p: np.ndarray, pI: np.ndarray) -> sp.csr_matrix:
+    """A_c of eq. 3.3 on the shared stencil pattern.  Entry order:
+    a^E_ij, then (p_g,i a^g_ij) p_g,j for g ascending, then the ion term,
+    then on the diagonal d_Eg p_g and p_g d_gE for g ascending, d_EI p_I,
+    p_I d_IE."""
+    G = sys.G
+    AE = sys.blocks[G]
+    for B in sys.blocks:
+        if not (np.array_equal(B.indptr, AE.indptr)
+                and np.array_equal(B.indices, AE.indices)):
+            raise ValueError("PCTL needs all diagonal blocks on one pattern")
+    rows = amg.csr_rows(AE)
+    cols = AE.indices
+    acc = AE.data.copy()
+    for g in range(G):
+        acc = acc + (p[g][rows] * sys.blocks[g].data) * p[g][cols]
+    acc = acc + (pI[rows] * sys.blocks[G + 1].data) * pI[cols]
+    isd = rows == cols
+    r = rows[isd]
+    dg = acc[isd]
+    for g in range(G):
+        dg = dg + sys.d_Eg[g][r] * p[g][r]
+        dg = dg + p[g][r] * sys.d_gE[g][r]
+    dg = dg + sys.d_EI[r] * pI[r]
+    dg = dg + pI[r] * sys.d_IE[r]
+    acc[isd] = dg
+    Ac = sp.csr_matrix((acc, AE.indices.copy(), AE.indptr.copy()), shape=AE.shape)
+    return Ac
+
+
+class BlockPreconditioner:
+    """M^{-1} for one of KINDS built on a BlockSystem."""
+
+    def __init__(self, sys: BlockSystem, params: BlockParams,
+                 inverse_factory: Optional[Callable] = None):
+        self.sys = sys
+        self.params = params
+        self.kind = params.kind
+        self.counters = Counters()
+        G = sys.G
+        self.G, self.N = G, sys.N
+        fac = inverse_factory or self._amg_factory
+        self.inv = {}
+        self.setup_info = {}
+        if self.kind == "amg":
+            self.Amono = sys.monolithic()
+            self.inv["mono"] = fac(self.Amono, "mono")
+            return
+        mats = hatted(sys, self.kind)
+        self.mats = mats
+        for key, M in mats.items():
+            self.inv[key] = fac(M, key)
+        if self.kind == "pctl":
+            self._pctl_setup(fac)
+
+    # -- scalar inverse construction -----------------------------------------
+    def _amg_factory(self, M, key):
+        """key: ('g', g), 'E', 'I', 'c' (PCTL coarse) or 'mono'."""
+        role = "g" if isinstance(key, tuple) else key
+        cyc = {"g": self.params.cycles_rad, "E": self.params.cycles_E,
+               "I": self.params.cycles_I, "c": self.params.cycles_E,
+               "mono": 1}[role]
+        return amg_inverse(M, self.params.amg, cyc, self.counters)
+
+    def _pctl_setup(self, fac):
+        G, N = self.G, self.N
+        sys = self.sys
+        p = np.empty((G, N))
+        cycles = []
+        for g in range(G):
+            p[g], k = self._p_solve(self.inv[("g", g)], -sys.d_gE[g])
+            cycles.append(k)
+        pI, k = self._p_solve(self.inv["I"], -sys.d_IE)
+        cycles.append(k)
+        self.p, self.pI = p, pI
+        self.setup_info["p_cycles"] = cycles
+        self.Ac = pctl_coarse(sys, p, pI)
+        self.inv["c"] = fac(self.Ac, "c")
+
+    def _p_solve(self, inv, rhs):
+        """Option #3 with AMG (V-cycles to pctl_p_tol); exact inverses solve once."""
+        H = getattr(inv, "hierarchy", None)
+        if H is None:
+            return inv._fn(rhs), 1
+        return amg.solve_to_tolerance(H, rhs, self.params.pctl_p_tol,
+                                      self.params.pctl_p_maxcycles)
+
+    # -- application -----------------------------------------------------------
+    def __call__(self, b: np.ndarray) -> np.ndarray:
+        G, N = self.G, self.N
+        sys = self.sys
+        if self.kind == "amg":
+            return self.inv["mono"](b)
+        B = b.reshape(G + 2, N)
+        W = np.empty_like(B)
+        inv = self.inv
+        if self.kind == "bdiag":
+            for g in range(G):
+                W[g] = inv[("g", g)](B[g])
+            W[G] = inv["E"](B[G])
+            W[G + 1] = inv["I"](B[G + 1])
+        elif self.kind == "pctl":
+            W[G] = inv["E"](B[G])
+            for g in range(G):
+                W[g] = inv[("g", g)](B[g] - sys.d_gE[g] * W[G])
+            W[G + 1] = inv["I"](B[G + 1] - sys.d_IE * W[G])
+            self.counters.matvecs += G + 2
+            Rr = (b - sys.matvec(W.reshape(-1))).reshape(G + 2, N)
+            rc = Rr[G].copy()
+            for g in range(G):
+                rc = rc + self.p[g] * Rr[g]
+            rc = rc + self.pI * Rr[G + 1]
+            wc = inv["c"](rc)
+            W[G] = W[G] + wc
+            for g in range(G):
+                W[g] = W[g] + self.p[g] * wc
+            W[G + 1] = W[G + 1] + self.pI * wc
+        elif self.kind == "schur1":
+            wI = inv["I"](B[G + 1])
+            wE = inv["E"](B[G] - sys.d_EI * wI)
+            for g in range(G):
+                W[g] = inv[("g", g)](B[g] - sys.d_gE[g] * wE)
+            s = np.zeros(N)
+            for g in range(G):
+                s = s + sys.d_Eg[g] * W[g]
+            W[G] = wE - inv["E"](s)
+            W[G + 1] = wI - inv["I"](sys.d_IE * W[G])
+        elif self.kind in ("schur2", "schur2_lower"):
+            wE = inv["E"](B[G])
+            for g in range(G):
+                W[g] = inv[("g", g)](B[g] - sys.d_gE[g] * wE)
+            W[G + 1] = inv["I"](B[G + 1] - sys.d_IE * wE)
+            if self.kind == "schur2":
+                s = np.zeros(N)
+                for g in range(G):
+                    s = s + sys.d_Eg[g] * W[g]
+                s = s + sys.d_EI * W[G + 1]
+                W[G] = wE - inv["E"](s)
+            else:
+                W[G] = wE
+        else:
+            raise ValueError(self.kind)
+        return W.reshape(-1)
+
+    def dense_operator(self) -> np.ndarray:
+        """M^{-1} as a dense matrix (tiny systems only)."""
+        n = (self.G + 2) * self.N
+        return np.column_stack([self(e) for e in np.eye(n)])
