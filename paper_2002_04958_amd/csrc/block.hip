@@ -1,0 +1,777 @@
+// Block preconditioners of Section 3: monolithic AMG, block-diagonal, PCTL
+// (Section 3.3, coarse operator eq. 3.3), Schur1 and Schur2 (Section 3.4)
+// with the diagonal Schur-complement approximations of Section 3.5, and the
+// elimination-only factor of Schur2.  The independent scalar V-cycles of a
+// step run either as one batched set of launches over a union of
+// hierarchies or one hierarchy after another.
+#pragma clang fp contract(off)
+
+#include <chrono>
+
+#include "handles.hpp"
+#include "kernels.hpp"
+#include "rowdot.hpp"
+
+using namespace mgd;
+
+// ===========================================================================
+// amg_hierarchy helpers
+// ===========================================================================
+Union<double>* amg_hierarchy::union64() {
+  if (!u64) {
+    std::vector<const SetupHierarchy*> m{&H};
+    u64 = build_union<double>(ctx, m, prm.n_pre, prm.n_post, prm.autotune);
+  }
+  return u64.get();
+}
+Union<float>* amg_hierarchy::union32() {
+  if (!u32) {
+    std::vector<const SetupHierarchy*> m{&H};
+    u32 = build_union<float>(ctx, m, prm.n_pre, prm.n_post, prm.autotune);
+  }
+  return u32.get();
+}
+void amg_hierarchy::apply(const double* r, double* z, int cycles) {
+  if (prm.precision == 0) {
+    union64()->apply(ctx, r, z, cycles);
+    return;
+  }
+  Union<float>* u = union32();
+  if (in32.n < (size_t)n) {
+    in32.alloc(ctx, (size_t)n);
+    out32.alloc(ctx, (size_t)n);
+  }
+  cast_copy<float, double>(ctx, in32.get(), r, (size_t)n, KC_VEC);
+  u->apply(ctx, in32.get(), out32.get(), cycles);
+  cast_copy<double, float>(ctx, z, out32.get(), (size_t)n, KC_VEC);
+}
+
+template <typename T>
+static Union<T>* union_of(amg_hierarchy* h);
+template <>
+Union<double>* union_of<double>(amg_hierarchy* h) {
+  return h->union64();
+}
+template <>
+Union<float>* union_of<float>(amg_hierarchy* h) {
+  return h->union32();
+}
+
+// ===========================================================================
+// glue kernels
+// ===========================================================================
+namespace mgd {
+
+template <typename T>
+__global__ void k_group_in(int N, const SegIn* __restrict__ tab, const double* __restrict__ r,
+                           const T* __restrict__ w, T* __restrict__ in) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const SegIn d = tab[blockIdx.y];
+  double v = r[(size_t)d.seg * N + i];
+  if (d.coef) v = v - d.coef[i] * (double)w[i];
+  in[(size_t)blockIdx.y * N + i] = (T)v;
+}
+
+template <typename T, bool SUM>
+__global__ void k_group_out(int N, int nm, const SegOut* __restrict__ tab, const T* __restrict__ out,
+                            double* __restrict__ z, T* __restrict__ sT) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double s = 0.0;
+  for (int m = 0; m < nm; ++m) {
+    const SegOut d = tab[m];
+    const double x = (double)out[(size_t)m * N + i];
+    z[(size_t)d.seg * N + i] = x;
+    if (SUM && d.coef) s = s + d.coef[i] * x;
+  }
+  if (SUM) sT[i] = (T)s;
+}
+
+// out = (T)(a - coef o w)   (coef may be null)
+template <typename T, typename W>
+__global__ void k_single_in(int N, const double* __restrict__ a, const double* __restrict__ coef,
+                            const W* __restrict__ w, T* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double v = a ? a[i] : 0.0;
+  if (coef) v = a ? v - coef[i] * (double)w[i] : coef[i] * (double)w[i];
+  out[i] = (T)v;
+}
+
+// z = p - q  (q may be null)
+template <typename T>
+__global__ void k_sub_out(int N, const T* __restrict__ p, const T* __restrict__ q,
+                          double* __restrict__ z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  z[i] = q ? (double)p[i] - (double)q[i] : (double)p[i];
+}
+
+// PCTL restriction of the block residual: rc = r_E + sum_g p_g o r_g + p_I o r_I
+template <typename T>
+__global__ void k_pctl_restrict(int G, int N, const double* __restrict__ p,
+                                const double* __restrict__ res, T* __restrict__ rc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double s = res[(size_t)G * N + i];
+  for (int g = 0; g < G; ++g) s = s + p[(size_t)g * N + i] * res[(size_t)g * N + i];
+  s = s + p[(size_t)G * N + i] * res[(size_t)(G + 1) * N + i];
+  rc[i] = (T)s;
+}
+// PCTL coarse correction: w += P w_c
+template <typename T>
+__global__ void k_pctl_correct(int G, int N, const double* __restrict__ p, const T* __restrict__ wc,
+                               double* __restrict__ z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double c = (double)wc[i];
+  z[(size_t)G * N + i] = z[(size_t)G * N + i] + c;
+  for (int g = 0; g < G; ++g) z[(size_t)g * N + i] = z[(size_t)g * N + i] + p[(size_t)g * N + i] * c;
+  z[(size_t)(G + 1) * N + i] = z[(size_t)(G + 1) * N + i] + p[(size_t)G * N + i] * c;
+}
+
+// ---------------------------------------------------------------------------
+// setup kernels
+// ---------------------------------------------------------------------------
+// a_ii <- a_ii - (d1_i d2_i) / dd_i on the stored diagonal
+__global__ void k_hat_update(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                             double* __restrict__ v, const double* __restrict__ d1,
+                             const double* __restrict__ d2, const double* __restrict__ dd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (ci[e] == i) {
+      const double t = (d1[i] * d2[i]) / dd[i];
+      v[e] = v[e] - t;
+    }
+}
+
+__global__ void k_get_diag(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const double* __restrict__ v, double* __restrict__ d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (ci[e] == i) x = v[e];
+  d[i] = x;
+}
+
+// eq. 3.3 on the shared pattern
+__global__ void k_pctl_coarse(int G, int N, BlockSysDev S, const double* __restrict__ p,
+                              double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const BlockCsr E = S.blk[G];
+  const double* pI = p + (size_t)G * N;
+  for (int e = E.rp[i]; e < E.rp[i + 1]; ++e) {
+    const int j = E.ci[e];
+    double acc = E.v[e];
+    for (int g = 0; g < G; ++g) {
+      const double* pg = p + (size_t)g * N;
+      acc = acc + (pg[i] * S.blk[g].v[e]) * pg[j];
+    }
+    acc = acc + (pI[i] * S.blk[G + 1].v[e]) * pI[j];
+    if (j == i) {
+      for (int g = 0; g < G; ++g) {
+        const double pg = p[(size_t)g * N + i];
+        acc = acc + S.d_Eg[(size_t)g * N + i] * pg;
+        acc = acc + pg * S.d_gE[(size_t)g * N + i];
+      }
+      acc = acc + S.d_EI[i] * pI[i];
+      acc = acc + pI[i] * S.d_IE[i];
+    }
+    out[e] = acc;
+  }
+}
+
+__global__ void k_pattern_diff(int n, int nnz, const int* __restrict__ rp0,
+                               const int* __restrict__ ci0, const int* __restrict__ rp1,
+                               const int* __restrict__ ci1, int* __restrict__ diff) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t <= n && rp0[t] != rp1[t]) diff[0] = 1;
+  if (t < nnz && ci0[t] != ci1[t]) diff[0] = 1;
+}
+
+__global__ void k_neg(int n, const double* __restrict__ a, double* __restrict__ b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = -a[i];
+}
+
+template <typename T>
+void Group<T>::run(Ctx* c, int N) {
+  (void)N;
+  if (batched) {
+    batched->apply(c, in.get(), out.get(), cycles);
+  } else {
+    for (size_t m = 0; m < seq.size(); ++m)
+      seq[m]->apply(c, in.get() + m * (size_t)N, out.get() + m * (size_t)N, cycles);
+  }
+}
+template struct Group<double>;
+template struct Group<float>;
+
+}  // namespace mgd
+
+// ===========================================================================
+// block_precond
+// ===========================================================================
+block_precond::~block_precond() {
+  for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+  if (aux) hipStreamDestroy(aux);
+  if (ev_in) hipEventDestroy(ev_in);
+  if (ev_out) hipEventDestroy(ev_out);
+}
+
+static void make_hierarchy(block_precond* bp, int role, Csr<double>&& M) {
+  auto h = std::make_unique<amg_hierarchy>();
+  h->ctx = bp->ctx;
+  h->prm = bp->prm.amg;
+  h->n = M.n_rows;
+  auto t0 = std::chrono::steady_clock::now();
+  amg_build(bp->ctx, std::move(M), h->prm, h->H);
+  h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if ((int)bp->hier.size() <= role) bp->hier.resize(role + 1);
+  bp->hier[role] = std::move(h);
+}
+
+static void diag_of(Ctx* c, const Csr<double>& A, double* d) {
+  hipLaunchKernelGGL(k_get_diag, dim3(cdiv(A.n_rows, 256)), dim3(256), 0, c->stream, A.n_rows,
+                     A.rp.get(), A.ci.get(), A.v.get(), d);
+  MGD_CHECK_LAUNCH();
+}
+
+static Csr<double> hat(Ctx* c, const Csr<double>& A, const double* d1, const double* d2,
+                       const double* dd) {
+  Csr<double> B;
+  csr_copy(c, A, B);
+  hipLaunchKernelGGL(k_hat_update, dim3(cdiv(B.n_rows, 256)), dim3(256), 0, c->stream, B.n_rows,
+                     B.rp.get(), B.ci.get(), B.v.get(), d1, d2, dd);
+  MGD_CHECK_LAUNCH();
+  return B;
+}
+
+// Option #3: V-cycles on the hierarchy until ||rhs - A z|| < tol ||rhs||.
+static int solve_to_tol(block_precond* bp, amg_hierarchy* h, const double* rhs, double* z,
+                        double tol, int maxc) {
+  Ctx* c = bp->ctx;
+  const int n = h->n;
+  Union<double>* U = h->union64();
+  DBuf<double> r(c, n), t(c, n), nrm(c, 2);
+  RedWork rw;
+  fill<double>(c, z, 0.0, n);
+  copy_d2d(c, r.get(), rhs, n);
+  dot_dev(c, rw, rhs, rhs, n, nrm.get());
+  const double nb = std::sqrt(read1(c, nrm.get()));
+  if (nb == 0.0) return 0;
+  const CsrView<double> A0 = view(h->H.levels[0].A);
+  const int tpr = default_tpr((double)A0.nnz / std::max(1, A0.n_rows));
+  int k = 0;
+  while (k < maxc) {
+    U->apply(c, r.get(), t.get(), 1);
+    axpy(c, z, t.get(), 1.0, n);
+    ++k;
+    spmv(c, A0, z, r.get(), tpr, KC_SPMV);
+    rsub(c, rhs, r.get(), n);
+    dot_dev(c, rw, r.get(), r.get(), n, nrm.get() + 1);
+    if (std::sqrt(read1(c, nrm.get() + 1)) < tol * nb) break;
+  }
+  return k;
+}
+
+template <typename T>
+static void build_exec(block_precond* bp, std::unique_ptr<PcExec<T>>& X) {
+  Ctx* c = bp->ctx;
+  const int G = bp->G, N = bp->N;
+  const int kind = bp->prm.kind;
+  X = std::make_unique<PcExec<T>>();
+  if (kind == MGD_PC_IDENTITY) return;
+  // every single-hierarchy union the apply uses is built here, so that an
+  // apply (possibly under graph capture) never allocates
+  std::vector<int> singles;
+  if (kind == MGD_PC_AMG_MONO) singles = {0};
+  if (kind == MGD_PC_SCHUR2 || kind == MGD_PC_SCHUR2_LOWER) singles = {G};
+  if (kind == MGD_PC_PCTL) singles = {G, G + 2};
+  if (kind == MGD_PC_SCHUR1) singles = {G, G + 1};
+  for (int r : singles) union_of<T>(bp->hier[r].get());
+  const size_t n1 = (size_t)std::max(N, 1);
+  X->a_out.alloc(c, (kind == MGD_PC_AMG_MONO) ? (size_t)(G + 2) * N : n1);
+  X->a_in.alloc(c, (kind == MGD_PC_AMG_MONO) ? (size_t)(G + 2) * N : n1);
+  X->b_in.alloc(c, n1);
+  X->b_out.alloc(c, n1);
+  X->s.alloc(c, n1);
+  if (kind == MGD_PC_PCTL) X->res.alloc(c, (size_t)(G + 2) * N);
+  if (kind == MGD_PC_AMG_MONO) return;
+  // group membership
+  std::vector<SegIn> tin;
+  std::vector<SegOut> tout;
+  std::vector<int> roles;
+  const double* dgE = bp->d_gE.get();
+  const double* dEg = bp->d_Eg.get();
+  if (kind == MGD_PC_BLOCK_DIAG) {
+    for (int a = 0; a < G + 2; ++a) {
+      roles.push_back(a);
+      tin.push_back({a, nullptr});
+      tout.push_back({a, nullptr});
+    }
+  } else if (kind == MGD_PC_SCHUR1) {
+    for (int g = 0; g < G; ++g) {
+      roles.push_back(g);
+      tin.push_back({g, dgE + (size_t)g * N});
+      tout.push_back({g, dEg + (size_t)g * N});
+    }
+  } else {  // SCHUR2, SCHUR2_LOWER, PCTL: groups and I after E
+    const bool sum = kind == MGD_PC_SCHUR2;
+    for (int g = 0; g < G; ++g) {
+      roles.push_back(g);
+      tin.push_back({g, dgE + (size_t)g * N});
+      tout.push_back({g, sum ? dEg + (size_t)g * N : nullptr});
+    }
+    roles.push_back(G + 1);
+    tin.push_back({G + 1, bp->d_IE.get()});
+    tout.push_back({G + 1, sum ? bp->d_EI.get() : nullptr});
+  }
+  Group<T>& grp = X->grp;
+  grp.roles = roles;
+  grp.cycles = bp->cycles[roles[0]];
+  bool uniform = true;
+  for (int r : roles) uniform = uniform && bp->cycles[r] == grp.cycles;
+  const size_t nm = roles.size();
+  grp.in.alloc(c, nm * N);
+  grp.out.alloc(c, nm * N);
+  grp.in_tab.alloc(c, nm);
+  grp.out_tab.alloc(c, nm);
+  copy_h2d(c, grp.in_tab.get(), tin.data(), nm);
+  copy_h2d(c, grp.out_tab.get(), tout.data(), nm);
+  if (bp->prm.batched && uniform && nm > 1) {
+    std::vector<const SetupHierarchy*> hs;
+    for (int r : roles) hs.push_back(&bp->hier[r]->H);
+    grp.batched = build_union<T>(c, hs, bp->prm.amg.n_pre, bp->prm.amg.n_post, bp->prm.amg.autotune);
+  } else {
+    for (int r : roles) grp.seq.push_back(union_of<T>(bp->hier[r].get()));
+    if (!uniform) {
+      // members with different cycle counts run one by one with their own count
+      grp.cycles = -1;
+    }
+  }
+}
+
+template <typename T>
+static const T* as_input(Ctx* c, const double* src, DBuf<T>& tmp, int N) {
+  if constexpr (std::is_same<T, double>::value) {
+    (void)c;
+    (void)tmp;
+    (void)N;
+    return src;
+  } else {
+    cast_copy<float, double>(c, tmp.get(), src, (size_t)N, KC_VEC);
+    return tmp.get();
+  }
+}
+
+template <typename T>
+static void run_group(block_precond* bp, Group<T>& grp) {
+  Ctx* c = bp->ctx;
+  const int N = bp->N;
+  if (grp.cycles >= 0) {
+    grp.run(c, N);
+    return;
+  }
+  for (size_t m = 0; m < grp.seq.size(); ++m)
+    grp.seq[m]->apply(c, grp.in.get() + m * (size_t)N, grp.out.get() + m * (size_t)N,
+                      bp->cycles[grp.roles[m]]);
+}
+
+template <typename T>
+static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double* z) {
+  Ctx* c = bp->ctx;
+  const int G = bp->G, N = bp->N, kind = bp->prm.kind;
+  const size_t nN = (size_t)N;
+  const dim3 g1(cdiv(N, 256)), b1(256);
+  int ninv = 0, nmv = 0;
+  auto U = [&](int role) { return union_of<T>(bp->hier[role].get()); };
+  Group<T>& grp = X.grp;
+  const int nm = (int)grp.roles.size();
+  auto group_in = [&](const T* w) {
+    ProfScope ps(c, KC_VEC, (double)nm * N * (8 + 8 + sizeof(T)) + N * sizeof(T));
+    hipLaunchKernelGGL(k_group_in<T>, dim3(cdiv(N, 256), nm), b1, 0, c->stream, N,
+                       (const SegIn*)grp.in_tab.get(), r, w, grp.in.get());
+    MGD_CHECK_LAUNCH();
+  };
+  auto group_out = [&](bool sum, T* sT) {
+    ProfScope ps(c, KC_VEC, (double)nm * N * (sizeof(T) + 8 + (sum ? 8 : 0)));
+    if (sum)
+      hipLaunchKernelGGL((k_group_out<T, true>), g1, b1, 0, c->stream, N, nm,
+                         (const SegOut*)grp.out_tab.get(), (const T*)grp.out.get(), z, sT);
+    else
+      hipLaunchKernelGGL((k_group_out<T, false>), g1, b1, 0, c->stream, N, nm,
+                         (const SegOut*)grp.out_tab.get(), (const T*)grp.out.get(), z, sT);
+    MGD_CHECK_LAUNCH();
+  };
+  switch (kind) {
+    case MGD_PC_IDENTITY:
+      cast_copy<double, double>(c, z, r, (size_t)(G + 2) * N, KC_VEC);
+      break;
+    case MGD_PC_AMG_MONO: {
+      const size_t n = (size_t)(G + 2) * N;
+      if constexpr (std::is_same<T, double>::value) {
+        U(0)->apply(c, r, z, bp->cycles[0]);
+      } else {
+        cast_copy<float, double>(c, X.a_in.get(), r, n, KC_VEC);
+        U(0)->apply(c, X.a_in.get(), X.a_out.get(), bp->cycles[0]);
+        cast_copy<double, float>(c, z, X.a_out.get(), n, KC_VEC);
+      }
+      ninv = 1;
+      break;
+    }
+    case MGD_PC_BLOCK_DIAG:
+      group_in(nullptr);
+      run_group(bp, grp);
+      group_out(false, nullptr);
+      ninv = G + 2;
+      break;
+    case MGD_PC_SCHUR2:
+    case MGD_PC_SCHUR2_LOWER:
+    case MGD_PC_PCTL: {
+      // step 1: w_E* = A_E^{-1} r_E
+      const T* inE = as_input<T>(c, r + (size_t)G * N, X.a_in, N);
+      U(G)->apply(c, inE, X.a_out.get(), bp->cycles[G]);
+      // step 2: groups and I against r - D_.E w_E*
+      group_in(X.a_out.get());
+      run_group(bp, grp);
+      ninv = 1 + G + 1;
+      if (kind == MGD_PC_SCHUR2) {
+        // step 3: w_E = w_E* - A_E^{-1}(sum_g D_Eg w_g + D_EI w_I)
+        group_out(true, X.b_in.get());
+        U(G)->apply(c, X.b_in.get(), X.b_out.get(), bp->cycles[G]);
+        hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.a_out.get(),
+                           (const T*)X.b_out.get(), z + (size_t)G * N);
+        MGD_CHECK_LAUNCH();
+        ninv += 1;
+      } else {
+        group_out(false, nullptr);
+        hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.a_out.get(),
+                           (const T*)nullptr, z + (size_t)G * N);
+        MGD_CHECK_LAUNCH();
+      }
+      if (kind == MGD_PC_PCTL) {
+        // coarse-grid correction: A_c w_c = P^T (b - A w); w += P w_c
+        block_matvec(c, bp->sys, z, r, X.res.get());
+        nmv = G + 2;
+        hipLaunchKernelGGL(k_pctl_restrict<T>, g1, b1, 0, c->stream, G, N,
+                           (const double*)bp->p.get(), (const double*)X.res.get(), X.b_in.get());
+        MGD_CHECK_LAUNCH();
+        U(G + 2)->apply(c, X.b_in.get(), X.b_out.get(), bp->cycles[G + 2]);
+        hipLaunchKernelGGL(k_pctl_correct<T>, g1, b1, 0, c->stream, G, N,
+                           (const double*)bp->p.get(), (const T*)X.b_out.get(), z);
+        MGD_CHECK_LAUNCH();
+        ninv += 1;
+      }
+      break;
+    }
+    case MGD_PC_SCHUR1: {
+      // 1. w_I* = A_I^{-1} r_I
+      const T* inI = as_input<T>(c, r + (size_t)(G + 1) * N, X.a_in, N);
+      U(G + 1)->apply(c, inI, X.a_out.get(), bp->cycles[G + 1]);
+      // 2. w_E* = C_E^{-1}(r_E - D_EI w_I*)
+      hipLaunchKernelGGL((k_single_in<T, T>), g1, b1, 0, c->stream, N, r + (size_t)G * N,
+                         (const double*)bp->d_EI.get(), (const T*)X.a_out.get(), X.b_in.get());
+      MGD_CHECK_LAUNCH();
+      U(G)->apply(c, X.b_in.get(), X.b_out.get(), bp->cycles[G]);
+      // 3. w_g = C_g^{-1}(r_g - D_gE w_E*)
+      group_in(X.b_out.get());
+      run_group(bp, grp);
+      // 4. w_E = w_E* - C_E^{-1} sum_g D_Eg w_g
+      group_out(true, X.b_in.get());
+      {
+        DBuf<T>& tmp = X.a_in;  // free after step 1 (FP32) / unused (FP64)
+        if (tmp.n < nN) tmp.alloc(c, nN);
+        U(G)->apply(c, X.b_in.get(), tmp.get(), bp->cycles[G]);
+        hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.b_out.get(),
+                           (const T*)tmp.get(), z + (size_t)G * N);
+        MGD_CHECK_LAUNCH();
+      }
+      // 5. w_I = w_I* - A_I^{-1} D_IE w_E
+      hipLaunchKernelGGL((k_single_in<T, double>), g1, b1, 0, c->stream, N, (const double*)nullptr,
+                         (const double*)bp->d_IE.get(), (const double*)(z + (size_t)G * N),
+                         X.b_in.get());
+      MGD_CHECK_LAUNCH();
+      U(G + 1)->apply(c, X.b_in.get(), X.b_out.get(), bp->cycles[G + 1]);
+      hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.a_out.get(),
+                         (const T*)X.b_out.get(), z + (size_t)(G + 1) * N);
+      MGD_CHECK_LAUNCH();
+      ninv = G + 4;
+      break;
+    }
+    default:
+      fail(MGD_EINVAL, "unknown preconditioner kind");
+  }
+  bp->inverses_last = ninv;
+  bp->matvecs_last = nmv;
+}
+
+void block_precond_graph_launch(block_precond* bp, const double* r, double* z);
+
+void block_precond_apply_impl(block_precond* bp, const double* r, double* z) {
+  if (bp->prm.amg.precision == 1 && bp->prm.kind != MGD_PC_IDENTITY)
+    apply_impl<float>(bp, *bp->x32, r, z);
+  else
+    apply_impl<double>(bp, *bp->x64, r, z);
+}
+
+void block_precond_apply_dispatch(block_precond* bp, const double* r, double* z) {
+  Ctx* c = bp->ctx;
+  if (!bp->prm.use_graph || c->profiling) {
+    block_precond_apply_impl(bp, r, z);
+    return;
+  }
+  // Capture and replay need a real stream: on the null stream the graph runs
+  // on a private non-blocking stream ordered after and before the caller's.
+  const hipStream_t user = c->stream;
+  if (user == nullptr) {
+    if (!bp->aux) {
+      MGD_HIP(hipStreamCreateWithFlags(&bp->aux, hipStreamNonBlocking));
+      MGD_HIP(hipEventCreateWithFlags(&bp->ev_in, hipEventDisableTiming));
+      MGD_HIP(hipEventCreateWithFlags(&bp->ev_out, hipEventDisableTiming));
+    }
+    MGD_HIP(hipEventRecord(bp->ev_in, user));
+    MGD_HIP(hipStreamWaitEvent(bp->aux, bp->ev_in, 0));
+    c->stream = bp->aux;
+    try {
+      block_precond_graph_launch(bp, r, z);
+    } catch (...) {
+      c->stream = user;
+      throw;
+    }
+    c->stream = user;
+    MGD_HIP(hipEventRecord(bp->ev_out, bp->aux));
+    MGD_HIP(hipStreamWaitEvent(user, bp->ev_out, 0));
+    return;
+  }
+  block_precond_graph_launch(bp, r, z);
+}
+
+void block_precond_graph_launch(block_precond* bp, const double* r, double* z) {
+  Ctx* c = bp->ctx;
+  auto key = std::make_pair((const void*)r, (void*)z);
+  auto it = bp->graphs.find(key);
+  if (it == bp->graphs.end()) {
+    if (bp->graphs.size() >= 256) {
+      for (auto& kv : bp->graphs) hipGraphExecDestroy(kv.second);
+      bp->graphs.clear();
+    }
+    hipGraph_t g = nullptr;
+    MGD_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+    try {
+      block_precond_apply_impl(bp, r, z);
+    } catch (...) {
+      hipStreamEndCapture(c->stream, &g);
+      if (g) hipGraphDestroy(g);
+      throw;
+    }
+    MGD_HIP(hipStreamEndCapture(c->stream, &g));
+    hipGraphExec_t ex = nullptr;
+    MGD_HIP(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    MGD_HIP(hipGraphDestroy(g));
+    it = bp->graphs.emplace(key, ex).first;
+  }
+  MGD_HIP(hipGraphLaunch(it->second, c->stream));
+}
+
+static void copy_system(block_precond* bp, const mgd_block_system* A) {
+  Ctx* c = bp->ctx;
+  const int G = A->G, N = A->N;
+  const bool tr = bp->prm.transpose != 0;
+  bp->blocks.resize(G + 2);
+  for (int a = 0; a < G + 2; ++a) {
+    if (tr) {
+      Csr<double> tmp;
+      csr_copy_from(c, &A->blocks[a], tmp);
+      transpose(c, tmp, bp->blocks[a]);
+    } else {
+      csr_copy_from(c, &A->blocks[a], bp->blocks[a]);
+    }
+  }
+  bp->d_gE.alloc(c, (size_t)G * N);
+  bp->d_Eg.alloc(c, (size_t)G * N);
+  bp->d_EI.alloc(c, (size_t)N);
+  bp->d_IE.alloc(c, (size_t)N);
+  // A^T: D_gE^T sits in the (g, E) position where D_Eg was
+  copy_d2d(c, bp->d_gE.get(), tr ? A->d_Eg : A->d_gE, (size_t)G * N);
+  copy_d2d(c, bp->d_Eg.get(), tr ? A->d_gE : A->d_Eg, (size_t)G * N);
+  copy_d2d(c, bp->d_EI.get(), tr ? A->d_IE : A->d_EI, (size_t)N);
+  copy_d2d(c, bp->d_IE.get(), tr ? A->d_EI : A->d_IE, (size_t)N);
+  c->sync();
+  mgd_block_system view{};
+  std::vector<mgd_csr> bl(G + 2);
+  for (int a = 0; a < G + 2; ++a)
+    bl[a] = {bp->blocks[a].n_rows, bp->blocks[a].n_cols, bp->blocks[a].nnz, bp->blocks[a].rp.get(),
+             bp->blocks[a].ci.get(), bp->blocks[a].v.get()};
+  view.G = G;
+  view.N = N;
+  view.blocks = bl.data();
+  view.d_gE = bp->d_gE.get();
+  view.d_Eg = bp->d_Eg.get();
+  view.d_EI = bp->d_EI.get();
+  view.d_IE = bp->d_IE.get();
+  bp->sys = make_block_sys_dev(&view);
+}
+
+// Monolithic CSR of eq. 2.2 (rows [1..G, E, I]), columns sorted.
+__global__ void k_mono_len(int G, int N, BlockSysDev S, int* __restrict__ len) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.y;
+  if (i >= N) return;
+  const int nb = S.blk[a].rp[i + 1] - S.blk[a].rp[i];
+  const int extra = a < G ? 1 : (a == G ? G + 1 : 1);
+  len[(size_t)a * N + i] = nb + extra;
+}
+__global__ void k_mono_fill(int G, int N, BlockSysDev S, const int* __restrict__ rp,
+                            int* __restrict__ ci, double* __restrict__ v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.y;
+  if (i >= N) return;
+  int p = rp[(size_t)a * N + i];
+  const BlockCsr B = S.blk[a];
+  const int base = a * N;
+  if (a == G) {  // D_Eg columns come first (segments 0..G-1)
+    for (int g = 0; g < G; ++g) {
+      ci[p] = g * N + i;
+      v[p++] = S.d_Eg[(size_t)g * N + i];
+    }
+  }
+  if (a == G + 1) {
+    ci[p] = G * N + i;
+    v[p++] = S.d_IE[i];
+  }
+  for (int e = B.rp[i]; e < B.rp[i + 1]; ++e) {
+    ci[p] = base + B.ci[e];
+    v[p++] = B.v[e];
+  }
+  if (a < G) {
+    ci[p] = G * N + i;
+    v[p++] = S.d_gE[(size_t)a * N + i];
+  }
+  if (a == G) {
+    ci[p] = (G + 1) * N + i;
+    v[p++] = S.d_EI[i];
+  }
+}
+
+static Csr<double> monolithic(Ctx* c, const BlockSysDev& S) {
+  const int G = S.G, N = S.N;
+  const long long n = (long long)(G + 2) * N;
+  MGD_REQUIRE(n < INT32_MAX, "monolithic matrix too large for int32 indices");
+  DBuf<int> len(c, (size_t)n);
+  dim3 grid(cdiv(N, 256), G + 2);
+  hipLaunchKernelGGL(k_mono_len, grid, dim3(256), 0, c->stream, G, N, S, len.get());
+  MGD_CHECK_LAUNCH();
+  Csr<double> M;
+  M.n_rows = M.n_cols = (int)n;
+  M.rp.alloc(c, (size_t)n + 1);
+  M.nnz = exclusive_scan_total(c, len.get(), M.rp.get(), (int)n);
+  M.ci.alloc(c, (size_t)M.nnz);
+  M.v.alloc(c, (size_t)M.nnz);
+  hipLaunchKernelGGL(k_mono_fill, grid, dim3(256), 0, c->stream, G, N, S, (const int*)M.rp.get(),
+                     M.ci.get(), M.v.get());
+  MGD_CHECK_LAUNCH();
+  c->sync();
+  return M;
+}
+
+block_precond* block_precond_create_impl(Ctx* c, const mgd_block_system* A, const block_params* p) {
+  auto t0 = std::chrono::steady_clock::now();
+  auto bp = std::make_unique<block_precond>();
+  bp->ctx = c;
+  bp->prm = *p;
+  const int G = A->G, N = A->N, kind = p->kind;
+  bp->G = G;
+  bp->N = N;
+  MGD_REQUIRE(kind >= 0 && kind <= MGD_PC_IDENTITY, "unknown preconditioner kind");
+  MGD_REQUIRE(p->cycles_rad >= 1 && p->cycles_E >= 1 && p->cycles_I >= 1, "cycles must be >= 1");
+  MGD_REQUIRE(p->amg.precision == 0 || p->amg.precision == 1, "precision must be 0 or 1");
+  copy_system(bp.get(), A);
+  bp->cycles.assign(G + 3, 1);
+  for (int g = 0; g < G; ++g) bp->cycles[g] = p->cycles_rad;
+  bp->cycles[G] = p->cycles_E;
+  bp->cycles[G + 1] = p->cycles_I;
+  bp->cycles[G + 2] = p->cycles_E;
+  const Csr<double>* B = bp->blocks.data();
+  if (kind == MGD_PC_AMG_MONO) {
+    bp->cycles[0] = 1;
+    make_hierarchy(bp.get(), 0, monolithic(c, bp->sys));
+  } else if (kind != MGD_PC_IDENTITY) {
+    DBuf<double> dE(c, N), dI(c, N), dCE(c, N);
+    diag_of(c, B[G], dE.get());
+    diag_of(c, B[G + 1], dI.get());
+    if (kind == MGD_PC_BLOCK_DIAG || kind == MGD_PC_PCTL) {
+      for (int a = 0; a < G + 2; ++a) {
+        Csr<double> M;
+        csr_copy(c, B[a], M);
+        make_hierarchy(bp.get(), a, std::move(M));
+      }
+    } else if (kind == MGD_PC_SCHUR1) {
+      Csr<double> CE = hat(c, B[G], bp->d_EI.get(), bp->d_IE.get(), dI.get());
+      diag_of(c, CE, dCE.get());
+      for (int g = 0; g < G; ++g)
+        make_hierarchy(bp.get(), g,
+                       hat(c, B[g], bp->d_gE.get() + (size_t)g * N, bp->d_Eg.get() + (size_t)g * N,
+                           dCE.get()));
+      make_hierarchy(bp.get(), G, std::move(CE));
+      Csr<double> AI;
+      csr_copy(c, B[G + 1], AI);
+      make_hierarchy(bp.get(), G + 1, std::move(AI));
+    } else {  // SCHUR2, SCHUR2_LOWER
+      for (int g = 0; g < G; ++g)
+        make_hierarchy(bp.get(), g,
+                       hat(c, B[g], bp->d_gE.get() + (size_t)g * N, bp->d_Eg.get() + (size_t)g * N,
+                           dE.get()));
+      Csr<double> AE;
+      csr_copy(c, B[G], AE);
+      make_hierarchy(bp.get(), G, std::move(AE));
+      make_hierarchy(bp.get(), G + 1, hat(c, B[G + 1], bp->d_IE.get(), bp->d_EI.get(), dE.get()));
+    }
+    if (kind == MGD_PC_PCTL) {
+      // all blocks must share A_E's pattern for eq. 3.3
+      DBuf<int> diff(c, 1);
+      fill<int>(c, diff.get(), 0, 1);
+      for (int a = 0; a < G + 2; ++a) {
+        MGD_REQUIRE(B[a].nnz == B[G].nnz, "PCTL needs all diagonal blocks on one pattern");
+        hipLaunchKernelGGL(k_pattern_diff, dim3(cdiv(std::max(N + 1, B[G].nnz), 256)), dim3(256), 0,
+                           c->stream, N, B[G].nnz, B[G].rp.get(), B[G].ci.get(), B[a].rp.get(),
+                           B[a].ci.get(), diff.get());
+        MGD_CHECK_LAUNCH();
+      }
+      MGD_REQUIRE(read1(c, diff.get()) == 0, "PCTL needs all diagonal blocks on one pattern");
+      bp->p.alloc(c, (size_t)(G + 1) * N);
+      DBuf<double> rhs(c, N);
+      bp->p_cycles.clear();
+      for (int g = 0; g <= G; ++g) {
+        const int role = g < G ? g : G + 1;
+        const double* dcol = g < G ? bp->d_gE.get() + (size_t)g * N : bp->d_IE.get();
+        hipLaunchKernelGGL(k_neg, dim3(cdiv(N, 256)), dim3(256), 0, c->stream, N, dcol, rhs.get());
+        MGD_CHECK_LAUNCH();
+        bp->p_cycles.push_back(solve_to_tol(bp.get(), bp->hier[role].get(), rhs.get(),
+                                            bp->p.get() + (size_t)g * N, p->pctl_p_tol,
+                                            p->pctl_p_maxcycles));
+      }
+      Csr<double> Ac;
+      csr_copy(c, B[G], Ac);
+      hipLaunchKernelGGL(k_pctl_coarse, dim3(cdiv(N, 256)), dim3(256), 0, c->stream, G, N, bp->sys,
+                         (const double*)bp->p.get(), Ac.v.get());
+      MGD_CHECK_LAUNCH();
+      make_hierarchy(bp.get(), G + 2, std::move(Ac));
+      // the FP64 unions used for the p solves are not needed by an FP32 apply
+      if (p->amg.precision == 1)
+        for (auto& h : bp->hier)
+          if (h) h->u64.reset();
+    }
+  }
+  if (p->amg.precision == 1 && kind != MGD_PC_IDENTITY)
+    build_exec<float>(bp.get(), bp->x32);
+  else
+    build_exec<double>(bp.get(), bp->x64);
+  c->sync();
+  bp->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return bp.release();
+}

@@ -1,0 +1,615 @@
+// The C ABI of libmgdamg: argument checks, context handling and conversion
+// of internal errors into status codes.  No exception crosses this file.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+
+#include "handles.hpp"
+#include "kernels.hpp"
+#include "rowdot.hpp"
+
+using namespace mgd;
+
+// implemented in other translation units
+block_precond* block_precond_create_impl(Ctx* c, const mgd_block_system* A, const block_params* p);
+void block_precond_apply_dispatch(block_precond* bp, const double* r, double* z);
+mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const double* b, double* x,
+                      const gmres_params& p, gmres_result& res);
+void assemble_impl(Ctx* c, const mgd_coeffs* cf, mgd_block_system* out);
+void system_transpose_impl(Ctx* c, const mgd_block_system* A, mgd_block_system* out);
+void system_free_impl(mgd_block_system* s);
+void adjoint_gradients_impl(Ctx* c, const mgd_coeffs* cf, const double* x, const double* lam,
+                            double* dk, double* dc);
+void check_coeffs(const mgd_coeffs* cf);
+
+namespace {
+thread_local std::string g_last_error;
+
+template <typename F>
+mgd_status guard(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return MGD_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return MGD_EHIP;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return MGD_EHIP;
+  }
+}
+}  // namespace
+
+// ===========================================================================
+// Ctx
+// ===========================================================================
+namespace mgd {
+
+const char* kernel_class_name(int c) {
+  static const char* names[KC_COUNT] = {"spmv",        "block_matvec", "smooth_l0",
+                                        "resid_l0",    "transfer_l0",  "vcycle_coarse",
+                                        "coarse_solve", "orth",        "vec"};
+  return (c >= 0 && c < KC_COUNT) ? names[c] : "?";
+}
+
+void* Ctx::dmalloc(size_t bytes) {
+  void* p = nullptr;
+  if (has_alloc) {
+    p = alloc.alloc(bytes, (void*)stream, alloc.user);
+    if (!p) fail(MGD_ENOMEM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes");
+    return p;
+  }
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(MGD_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  return p;
+}
+void Ctx::dfree(void* p) {
+  if (!p) return;
+  if (has_alloc)
+    alloc.free(p, (void*)stream, alloc.user);
+  else
+    (void)hipFree(p);
+}
+void* Ctx::host_stage(size_t bytes) {
+  if (bytes > pinned_bytes) {
+    if (pinned) (void)hipHostFree(pinned);
+    pinned = nullptr;
+    size_t sz = std::max<size_t>(bytes, 4096);
+    MGD_HIP(hipHostMalloc(&pinned, sz, hipHostMallocDefault));
+    pinned_bytes = sz;
+  }
+  return pinned;
+}
+hipEvent_t Ctx::take_event() {
+  if (!event_pool.empty()) {
+    hipEvent_t e = event_pool.back();
+    event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  MGD_HIP(hipEventCreate(&e));
+  return e;
+}
+void Ctx::prof_begin(int cls, hipEvent_t* a) {
+  (void)cls;
+  *a = take_event();
+  MGD_HIP(hipEventRecord(*a, stream));
+}
+void Ctx::prof_end(int cls, hipEvent_t a, double bytes_) {
+  hipEvent_t b = take_event();
+  MGD_HIP(hipEventRecord(b, stream));
+  pending.push_back({cls, a, b, bytes_});
+  if (pending.size() > 4096) prof_collect();
+}
+void Ctx::prof_collect() {
+  if (pending.empty()) return;
+  MGD_HIP(hipStreamSynchronize(stream));
+  for (auto& p : pending) {
+    float ms_ = 0;
+    MGD_HIP(hipEventElapsedTime(&ms_, p.a, p.b));
+    launches[p.cls] += 1;
+    ms[p.cls] += ms_;
+    bytes[p.cls] += p.bytes;
+    event_pool.push_back(p.a);
+    event_pool.push_back(p.b);
+  }
+  pending.clear();
+}
+Ctx::~Ctx() {
+  for (auto& p : pending) {
+    hipEventDestroy(p.a);
+    hipEventDestroy(p.b);
+  }
+  for (auto e : event_pool) hipEventDestroy(e);
+  if (pinned) hipHostFree(pinned);
+}
+
+void check_csr_meta(const mgd_csr* A, bool square) {
+  MGD_REQUIRE(A, "matrix is NULL");
+  MGD_REQUIRE(A->n_rows >= 0 && A->n_cols >= 0 && A->nnz >= 0, "negative matrix size");
+  MGD_REQUIRE(A->nnz < INT32_MAX, "nnz exceeds int32 indexing");
+  MGD_REQUIRE(!square || A->n_rows == A->n_cols, "matrix must be square");
+  MGD_REQUIRE(A->n_rows == 0 || A->row_ptr, "row_ptr is NULL");
+  MGD_REQUIRE(A->nnz == 0 || (A->col_idx && A->val), "col_idx or val is NULL");
+}
+
+__global__ void k_validate(int n, int ncols, long long nnz, const int* __restrict__ rp,
+                           const int* __restrict__ ci, int require_diag, int* __restrict__ bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int e0 = rp[i], e1 = rp[i + 1];
+  if (i == 0 && e0 != 0) atomicOr(bad, 1);
+  if (i == n - 1 && e1 != nnz) atomicOr(bad, 1);
+  if (e1 < e0 || e0 < 0 || e1 > nnz) {
+    atomicOr(bad, 1);
+    return;
+  }
+  bool diag = false;
+  for (int e = e0; e < e1; ++e) {
+    const int j = ci[e];
+    if (j < 0 || j >= ncols) atomicOr(bad, 2);
+    if (e > e0 && ci[e - 1] >= j) atomicOr(bad, 4);
+    if (j == i) diag = true;
+  }
+  if (require_diag && !diag) atomicOr(bad, 8);
+}
+
+void validate_csr_device(Ctx* c, const mgd_csr* A, bool require_diag) {
+  if (A->n_rows == 0) return;
+  DBuf<int> bad(c, 1);
+  fill<int>(c, bad.get(), 0, 1);
+  hipLaunchKernelGGL(k_validate, dim3(cdiv(A->n_rows, 256)), dim3(256), 0, c->stream, A->n_rows,
+                     A->n_cols, (long long)A->nnz, A->row_ptr, A->col_idx, require_diag ? 1 : 0,
+                     bad.get());
+  MGD_CHECK_LAUNCH();
+  const int b = read1(c, bad.get());
+  if (b & 1) fail(MGD_EINVAL, "row_ptr is not a monotone [0, nnz] sequence");
+  if (b & 2) fail(MGD_EINVAL, "column index out of range");
+  if (b & 4) fail(MGD_EINVAL, "columns not strictly ascending within a row");
+  if (b & 8) fail(MGD_EINVAL, "a row does not store its diagonal entry");
+}
+
+void check_block_system(const mgd_block_system* A) {
+  MGD_REQUIRE(A, "block system is NULL");
+  MGD_REQUIRE(A->G >= 1 && A->G + 2 <= kMaxBlocks, "G must be in [1, 64]");
+  MGD_REQUIRE(A->N >= 1, "N must be positive");
+  MGD_REQUIRE((long long)(A->G + 2) * A->N < INT32_MAX, "system too large for int32 indices");
+  MGD_REQUIRE(A->blocks, "blocks is NULL");
+  MGD_REQUIRE(A->d_gE && A->d_Eg && A->d_EI && A->d_IE, "coupling pointer is NULL");
+  for (int a = 0; a < A->G + 2; ++a) {
+    check_csr_meta(&A->blocks[a], true);
+    MGD_REQUIRE(A->blocks[a].n_rows == A->N, "every block must have N rows");
+  }
+}
+
+BlockSysDev make_block_sys_dev(const mgd_block_system* A) {
+  BlockSysDev S{};
+  S.G = A->G;
+  S.N = A->N;
+  long long nnz = 0;
+  for (int a = 0; a < A->G + 2; ++a) {
+    S.blk[a] = {A->blocks[a].row_ptr, A->blocks[a].col_idx, A->blocks[a].val};
+    S.nnz[a] = A->blocks[a].nnz;
+    nnz += A->blocks[a].nnz;
+  }
+  S.tpr = default_tpr((double)nnz / ((double)(A->G + 2) * A->N));
+  S.d_gE = A->d_gE;
+  S.d_Eg = A->d_Eg;
+  S.d_EI = A->d_EI;
+  S.d_IE = A->d_IE;
+  return S;
+}
+
+}  // namespace mgd
+
+// ===========================================================================
+// exported functions
+// ===========================================================================
+extern "C" {
+
+const char* mgd_last_error(void) { return g_last_error.c_str(); }
+const char* mgd_version(void) { return "mgdamg 0.1 (gfx950)"; }
+
+mgd_status mgd_ctx_create(int device, void* hip_stream, const mgd_allocator* allocator,
+                          mgd_ctx** out) {
+  return guard([&] {
+    MGD_REQUIRE(out, "out is NULL");
+    int ndev = 0;
+    MGD_HIP(hipGetDeviceCount(&ndev));
+    MGD_REQUIRE(device >= 0 && device < ndev, "device ordinal out of range");
+    auto c = std::make_unique<mgd_ctx>();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    if (allocator) {
+      MGD_REQUIRE(allocator->alloc && allocator->free, "allocator callbacks are NULL");
+      c->alloc = *allocator;
+      c->has_alloc = true;
+    }
+    c->make_current();
+    *out = c.release();
+    return MGD_OK;
+  });
+}
+
+mgd_status mgd_ctx_destroy(mgd_ctx* ctx) {
+  return guard([&] {
+    if (!ctx) return MGD_OK;
+    ctx->make_current();
+    (void)hipStreamSynchronize(ctx->stream);
+    delete ctx;
+    return MGD_OK;
+  });
+}
+
+mgd_status mgd_ctx_synchronize(mgd_ctx* ctx) {
+  return guard([&] {
+    MGD_REQUIRE(ctx, "ctx is NULL");
+    ctx->make_current();
+    ctx->sync();
+    return MGD_OK;
+  });
+}
+
+mgd_status mgd_ctx_set_profiling(mgd_ctx* ctx, int enable) {
+  return guard([&] {
+    MGD_REQUIRE(ctx, "ctx is NULL");
+    ctx->make_current();
+    if (!enable) ctx->prof_collect();
+    ctx->profiling = enable != 0;
+    return MGD_OK;
+  });
+}
+mgd_status mgd_ctx_reset_kernel_stats(mgd_ctx* ctx) {
+  return guard([&] {
+    MGD_REQUIRE(ctx, "ctx is NULL");
+    ctx->make_current();
+    ctx->prof_collect();
+    for (int i = 0; i < KC_COUNT; ++i) {
+      ctx->launches[i] = 0;
+      ctx->ms[i] = 0;
+      ctx->bytes[i] = 0;
+    }
+    return MGD_OK;
+  });
+}
+int mgd_kernel_class_count(void) { return KC_COUNT; }
+const char* mgd_kernel_class_name(int cls) { return kernel_class_name(cls); }
+mgd_status mgd_ctx_kernel_stats(mgd_ctx* ctx, int cls, int64_t* launches, double* total_ms,
+                                double* total_bytes) {
+  return guard([&] {
+    MGD_REQUIRE(ctx, "ctx is NULL");
+    MGD_REQUIRE(cls >= 0 && cls < KC_COUNT, "kernel class out of range");
+    ctx->make_current();
+    ctx->prof_collect();
+    if (launches) *launches = ctx->launches[cls];
+    if (total_ms) *total_ms = ctx->ms[cls];
+    if (total_bytes) *total_bytes = ctx->bytes[cls];
+    return MGD_OK;
+  });
+}
+
+mgd_status mgd_csr_spmv(mgd_ctx* ctx, const mgd_csr* A, const double* x, double* y) {
+  return guard([&] {
+    MGD_REQUIRE(ctx, "ctx is NULL");
+    check_csr_meta(A, false);
+    MGD_REQUIRE(A->n_rows == 0 || (x && y), "x or y is NULL");
+    MGD_REQUIRE((const void*)x != (const void*)y, "x and y must not alias");
+    ctx->make_current();
+    CsrView<double> v{A->n_rows, A->n_cols, (int)A->nnz, A->row_ptr, A->col_idx, A->val};
+    spmv(ctx, v, x, y, default_tpr(A->n_rows ? (double)A->nnz / A->n_rows : 1.0), KC_SPMV);
+    return MGD_OK;
+  });
+}
+
+void amg_params_default(amg_params* p) {
+  if (!p) return;
+  p->strength_theta = 0.25;
+  p->dominance_theta = 0.9;
+  p->seed = 1;
+  p->max_levels = 25;
+  p->coarse_max = 100;
+  p->dense_max = 2000;
+  p->n_pre = 1;
+  p->n_post = 1;
+  p->precision = 0;
+  p->autotune = 0;
+}
+
+static void check_amg_params(const amg_params* p) {
+  MGD_REQUIRE(p, "params is NULL");
+  MGD_REQUIRE(p->strength_theta > 0 && p->strength_theta < 1, "strength_theta must be in (0, 1)");
+  MGD_REQUIRE(p->max_levels >= 1 && p->max_levels <= MGD_MAX_LEVELS, "max_levels out of range");
+  MGD_REQUIRE(p->coarse_max >= 1, "coarse_max must be >= 1");
+  MGD_REQUIRE(p->dense_max >= 1 && p->dense_max <= 8192, "dense_max must be in [1, 8192]");
+  MGD_REQUIRE(p->n_pre >= 0 && p->n_post >= 0 && p->n_pre <= 16 && p->n_post <= 16,
+              "n_pre / n_post out of range");
+  MGD_REQUIRE(p->precision == 0 || p->precision == 1, "precision must be 0 or 1");
+}
+
+mgd_status amg_setup(mgd_ctx* ctx, const mgd_csr* A, const amg_params* p, amg_hierarchy** out) {
+  return guard([&] {
+    MGD_REQUIRE(ctx && out, "ctx or out is NULL");
+    check_amg_params(p);
+    check_csr_meta(A, true);
+    MGD_REQUIRE(A->n_rows >= 1, "matrix is empty");
+    ctx->make_current();
+    validate_csr_device(ctx, A, true);
+    auto t0 = std::chrono::steady_clock::now();
+    auto h = std::make_unique<amg_hierarchy>();
+    h->ctx = ctx;
+    h->prm = *p;
+    h->n = A->n_rows;
+    Csr<double> M;
+    csr_copy_from(ctx, A, M);
+    amg_build(ctx, std::move(M), h->prm, h->H);
+    if (p->precision == 0)
+      h->union64();
+    else
+      h->union32();
+    ctx->sync();
+    h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = h.release();
+    return MGD_OK;
+  });
+}
+
+mgd_status amg_apply(mgd_ctx* ctx, amg_hierarchy* h, const double* r, double* z, int n_cycles) {
+  return guard([&] {
+    MGD_REQUIRE(ctx && h, "ctx or hierarchy is NULL");
+    MGD_REQUIRE(h->ctx == ctx, "hierarchy belongs to another context");
+    MGD_REQUIRE(r && z && (const void*)r != (const void*)z, "r, z must be distinct and non-NULL");
+    MGD_REQUIRE(n_cycles >= 1, "n_cycles must be >= 1");
+    ctx->make_current();
+    h->apply(r, z, n_cycles);
+    return MGD_OK;
+  });
+}
+
+mgd_status amg_get_info(const amg_hierarchy* h, amg_info* out) {
+  return guard([&] {
+    MGD_REQUIRE(h && out, "hierarchy or out is NULL");
+    *out = amg_info{};
+    out->levels = (int)h->H.levels.size();
+    out->coarse_kind = h->H.coarse_kind;
+    double gs = 0, os_ = 0;
+    for (size_t l = 0; l < h->H.levels.size(); ++l) {
+      const auto& L = h->H.levels[l];
+      out->n[l] = L.A.n_rows;
+      out->nnz[l] = L.A.nnz;
+      out->nnz_P[l] = L.P.nnz;
+      out->pmis_rounds[l] = L.pmis_rounds;
+      gs += L.A.n_rows;
+      os_ += L.A.nnz;
+    }
+    out->grid_complexity = gs / std::max(1, h->H.levels[0].A.n_rows);
+    out->operator_complexity = os_ / std::max(1, h->H.levels[0].A.nnz);
+    return MGD_OK;
+  });
+}
+
+mgd_status amg_export_level(mgd_ctx* ctx, const amg_hierarchy* h, int level, int8_t* cf,
+                            int32_t* a_row_ptr, int32_t* a_col, double* a_val, int32_t* p_row_ptr,
+                            int32_t* p_col, double* p_val) {
+  return guard([&] {
+    MGD_REQUIRE(ctx && h, "ctx or hierarchy is NULL");
+    MGD_REQUIRE(level >= 0 && level < (int)h->H.levels.size(), "level out of range");
+    ctx->make_current();
+    const auto& L = h->H.levels[level];
+    const int n = L.A.n_rows;
+    if (cf) {
+      if (L.cf.p)
+        copy_d2h(ctx, cf, L.cf.get(), (size_t)n);
+      else
+        std::fill(cf, cf + n, (int8_t)0);
+    }
+    if (a_row_ptr) copy_d2h(ctx, a_row_ptr, L.A.rp.get(), (size_t)n + 1);
+    if (a_col) copy_d2h(ctx, a_col, L.A.ci.get(), (size_t)L.A.nnz);
+    if (a_val) copy_d2h(ctx, a_val, L.A.v.get(), (size_t)L.A.nnz);
+    if (L.P.rp.p) {
+      if (p_row_ptr) copy_d2h(ctx, p_row_ptr, L.P.rp.get(), (size_t)n + 1);
+      if (p_col) copy_d2h(ctx, p_col, L.P.ci.get(), (size_t)L.P.nnz);
+      if (p_val) copy_d2h(ctx, p_val, L.P.v.get(), (size_t)L.P.nnz);
+    }
+    return MGD_OK;
+  });
+}
+
+mgd_status amg_destroy(amg_hierarchy* h) {
+  return guard([&] {
+    if (h) {
+      h->ctx->make_current();
+      h->ctx->sync();
+      delete h;
+    }
+    return MGD_OK;
+  });
+}
+
+mgd_status mgd_block_matvec(mgd_ctx* ctx, const mgd_block_system* A, const double* x, double* y) {
+  return guard([&] {
+    MGD_REQUIRE(ctx, "ctx is NULL");
+    check_block_system(A);
+    MGD_REQUIRE(x && y && (const void*)x != (const void*)y, "x, y must be distinct and non-NULL");
+    ctx->make_current();
+    block_matvec(ctx, make_block_sys_dev(A), x, nullptr, y);
+    return MGD_OK;
+  });
+}
+
+mgd_status mgd_assemble(mgd_ctx* ctx, const mgd_coeffs* c, mgd_block_system* out) {
+  return guard([&] {
+    MGD_REQUIRE(ctx && out, "ctx or out is NULL");
+    ctx->make_current();
+    assemble_impl(ctx, c, out);
+    return MGD_OK;
+  });
+}
+
+mgd_status mgd_block_system_transpose(mgd_ctx* ctx, const mgd_block_system* A,
+                                      mgd_block_system* out) {
+  return guard([&] {
+    MGD_REQUIRE(ctx && out, "ctx or out is NULL");
+    check_block_system(A);
+    ctx->make_current();
+    system_transpose_impl(ctx, A, out);
+    return MGD_OK;
+  });
+}
+
+mgd_status mgd_block_system_free(mgd_ctx* ctx, mgd_block_system* s) {
+  return guard([&] {
+    MGD_REQUIRE(ctx && s, "ctx or system is NULL");
+    ctx->make_current();
+    ctx->sync();
+    system_free_impl(s);
+    return MGD_OK;
+  });
+}
+
+void block_params_default(block_params* p) {
+  if (!p) return;
+  p->kind = MGD_PC_SCHUR2;
+  amg_params_default(&p->amg);
+  p->cycles_rad = p->cycles_E = p->cycles_I = 1;
+  p->pctl_p_tol = 1e-2;
+  p->pctl_p_maxcycles = 100;
+  p->batched = 0;
+  p->use_graph = 0;
+  p->transpose = 0;
+}
+
+mgd_status block_precond_create(mgd_ctx* ctx, const mgd_block_system* A, const block_params* p,
+                                block_precond** out) {
+  return guard([&] {
+    MGD_REQUIRE(ctx && p && out, "ctx, params or out is NULL");
+    check_block_system(A);
+    check_amg_params(&p->amg);
+    MGD_REQUIRE(p->pctl_p_tol > 0 && p->pctl_p_maxcycles >= 1, "bad PCTL inner tolerance");
+    ctx->make_current();
+    for (int a = 0; a < A->G + 2; ++a) validate_csr_device(ctx, &A->blocks[a], true);
+    *out = block_precond_create_impl(ctx, A, p);
+    return MGD_OK;
+  });
+}
+
+mgd_status block_precond_apply(mgd_ctx* ctx, block_precond* M, const double* r, double* z) {
+  return guard([&] {
+    MGD_REQUIRE(ctx && M, "ctx or preconditioner is NULL");
+    MGD_REQUIRE(M->ctx == ctx, "preconditioner belongs to another context");
+    MGD_REQUIRE(r && z && (const void*)r != (const void*)z, "r, z must be distinct and non-NULL");
+    ctx->make_current();
+    block_precond_apply_dispatch(M, r, z);
+    return MGD_OK;
+  });
+}
+
+mgd_status block_precond_get_info(const block_precond* M, block_precond_info* out) {
+  return guard([&] {
+    MGD_REQUIRE(M && out, "preconditioner or out is NULL");
+    *out = block_precond_info{};
+    out->kind = M->prm.kind;
+    int nh = 0;
+    for (auto& h : M->hier) nh += h ? 1 : 0;
+    out->n_hierarchies = nh;
+    out->inverses_per_apply = M->inverses_last;
+    out->matvecs_per_apply = M->matvecs_last;
+    for (size_t i = 0; i < M->p_cycles.size() && i < 66; ++i) out->pctl_p_cycles[i] = M->p_cycles[i];
+    out->setup_ms = M->setup_ms;
+    return MGD_OK;
+  });
+}
+
+mgd_status block_precond_get_hierarchy(const block_precond* M, int index, const amg_hierarchy** out) {
+  return guard([&] {
+    MGD_REQUIRE(M && out, "preconditioner or out is NULL");
+    MGD_REQUIRE(index >= 0 && index < (int)M->hier.size() && M->hier[index],
+                "no hierarchy at this index");
+    *out = M->hier[index].get();
+    return MGD_OK;
+  });
+}
+
+mgd_status block_precond_destroy(block_precond* M) {
+  return guard([&] {
+    if (M) {
+      M->ctx->make_current();
+      M->ctx->sync();
+      delete M;
+    }
+    return MGD_OK;
+  });
+}
+
+void gmres_params_default(gmres_params* p) {
+  if (!p) return;
+  p->restart = 30;
+  p->max_iters = 1000;
+  p->rtol = 1e-8;
+  p->flexible = 1;
+  p->profile = 0;
+}
+
+mgd_status gmres_solve(mgd_ctx* ctx, const mgd_block_system* A, block_precond* M, const double* b,
+                       double* x, const gmres_params* p, gmres_result* out) {
+  return guard([&] {
+    MGD_REQUIRE(ctx && p && out, "ctx, params or result is NULL");
+    check_block_system(A);
+    MGD_REQUIRE(b && x && (const void*)b != (const void*)x, "b, x must be distinct and non-NULL");
+    MGD_REQUIRE(!M || M->ctx == ctx, "preconditioner belongs to another context");
+    MGD_REQUIRE(!M || (M->G == A->G && M->N == A->N), "preconditioner built for another shape");
+    MGD_REQUIRE(p->rtol >= 0, "rtol must be >= 0");
+    ctx->make_current();
+    return gmres_impl(ctx, make_block_sys_dev(A), M, b, x, *p, *out);
+  });
+}
+
+mgd_status mgd_adjoint_gradients(mgd_ctx* ctx, const mgd_coeffs* c, const double* x,
+                                 const double* lambda, double* dL_dkappa, double* dL_dc) {
+  return guard([&] {
+    MGD_REQUIRE(ctx && x && lambda, "ctx, x or lambda is NULL");
+    ctx->make_current();
+    adjoint_gradients_impl(ctx, c, x, lambda, dL_dkappa, dL_dc);
+    ctx->sync();
+    return MGD_OK;
+  });
+}
+
+mgd_status adjoint_solve(mgd_ctx* ctx, const mgd_coeffs* c, const mgd_block_system* A,
+                         block_precond* M_T, const double* x, const double* g, double* lambda,
+                         double* dL_dkappa, double* dL_dc, const gmres_params* p,
+                         gmres_result* out) {
+  return guard([&] {
+    MGD_REQUIRE(ctx && p && out && x && g && lambda, "NULL argument");
+    check_block_system(A);
+    check_coeffs(c);
+    MGD_REQUIRE(!M_T || M_T->prm.transpose, "M_T must be created with transpose = 1");
+    ctx->make_current();
+    mgd_block_system AT{};
+    system_transpose_impl(ctx, A, &AT);
+    mgd_status st;
+    try {
+      fill<double>(ctx, lambda, 0.0, (size_t)(A->G + 2) * A->N);
+      st = gmres_impl(ctx, make_block_sys_dev(&AT), M_T, g, lambda, *p, *out);
+    } catch (...) {
+      system_free_impl(&AT);
+      throw;
+    }
+    system_free_impl(&AT);
+    if (st != MGD_OK && st != MGD_ENOTCONV) return st;
+    adjoint_gradients_impl(ctx, c, x, lambda, dL_dkappa, dL_dc);
+    ctx->sync();
+    if (st == MGD_ENOTCONV) g_last_error = "adjoint GMRES reached max_iters";
+    return st;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Opaque handle types behind the C ABI.
+#pragma once
+#include <map>
+#include <memory>
+#include <utility>
+
+#include "setup.hpp"
+#include "solve.hpp"
+#include "spmv.hpp"
+
+struct amg_hierarchy {
+  mgd::Ctx* ctx = nullptr;
+  amg_params prm{};
+  mgd::SetupHierarchy H;
+  std::unique_ptr<mgd::Union<double>> u64;  // built on first use
+  std::unique_ptr<mgd::Union<float>> u32;
+  mgd::DBuf<float> in32, out32;
+  int n = 0;
+  double setup_ms = 0;
+
+  mgd::Union<double>* union64();
+  mgd::Union<float>* union32();
+  // FP64 in/out apply regardless of the stored precision
+  void apply(const double* r, double* z, int cycles);
+};
+
+namespace mgd {
+
+// Glue descriptors for a group of independent scalar solves.
+struct SegIn {
+  int seg;              // source segment of the Krylov vector (0..G+1)
+  const double* coef;   // subtract coef o w (or nullptr)
+};
+struct SegOut {
+  int seg;              // destination segment of the result
+  const double* coef;   // accumulate coef o x into s (or nullptr)
+};
+
+template <typename T>
+struct Group {
+  // one V-cycle set over several hierarchies: batched union or one per member
+  std::unique_ptr<Union<T>> batched;
+  std::vector<Union<T>*> seq;
+  std::vector<int> roles;   // hierarchy index of each member
+  int cycles = 1;
+  DBuf<T> in, out;          // members x N, member-major
+  DBuf<SegIn> in_tab;
+  DBuf<SegOut> out_tab;
+  void run(Ctx* c, int N);
+};
+
+template <typename T>
+struct PcExec {
+  Group<T> grp;                    // the batched step
+  DBuf<T> a_in, a_out, b_in, b_out;  // single-hierarchy vectors
+  DBuf<double> s, res;             // FP64 scratch
+};
+
+}  // namespace mgd
+
+struct block_precond {
+  mgd::Ctx* ctx = nullptr;
+  block_params prm{};
+  int G = 0, N = 0;
+  // owned copy of the (possibly transposed) system
+  std::vector<mgd::Csr<double>> blocks;
+  mgd::DBuf<double> d_gE, d_Eg, d_EI, d_IE;
+  mgd::BlockSysDev sys{};
+  // scalar hierarchies by role: g < G groups, G: E, G+1: I, G+2: PCTL coarse; mono: 0
+  std::vector<std::unique_ptr<amg_hierarchy>> hier;
+  std::vector<int> cycles;  // per role
+  // PCTL
+  mgd::DBuf<double> p;      // (G+1) N: p_1..p_G, p_I
+  std::vector<int> p_cycles;
+  std::unique_ptr<mgd::PcExec<double>> x64;
+  std::unique_ptr<mgd::PcExec<float>> x32;
+  // graph cache keyed by (r, z)
+  std::map<std::pair<const void*, void*>, hipGraphExec_t> graphs;
+  hipStream_t aux = nullptr;  // graph stream when the context stream is the null stream
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  int inverses_last = 0, matvecs_last = 0;
+  double setup_ms = 0;
+  ~block_precond();
+};

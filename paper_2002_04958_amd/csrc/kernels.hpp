@@ -1,0 +1,55 @@
+// Launchers shared between translation units.  All enqueue on ctx->stream.
+#pragma once
+#include "common.hpp"
+
+namespace mgd {
+
+constexpr int kBlock = 256;     // default workgroup size (4 wavefronts of 64)
+constexpr int kRedBlocks = 1024; // fixed partial count of deterministic reductions
+
+// ---- scans (int32) -----------------------------------------------------------
+// out[0..n]: out[i] = sum_{j<i} in[j], out[n] = total.  No synchronisation.
+void exclusive_scan(Ctx* c, const int* in, int* out, int n);
+// Same, then returns the total (synchronises).
+int exclusive_scan_total(Ctx* c, const int* in, int* out, int n);
+
+// ---- fills / casts ---------------------------------------------------------
+template <typename T>
+void fill(Ctx* c, T* p, T v, size_t n);
+template <typename D, typename S>
+void cast_copy(Ctx* c, D* dst, const S* src, size_t n, int cls);
+
+// ---- deterministic reductions (fixed partition, fixed order) ---------------
+struct RedWork {
+  DBuf<double> partial;  // kRedBlocks * 33
+  void ensure(Ctx* c) {
+    if (!partial.p) partial.alloc(c, (size_t)kRedBlocks * 33);
+  }
+};
+// out[0] = sum x_i y_i  (device scalar)
+void dot_dev(Ctx* c, RedWork& w, const double* x, const double* y, size_t n, double* out);
+// h[i] = V_i . w for i < J (V rows of stride ldv)
+void mdot_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* wv, size_t n,
+              double* h);
+// w -= sum_i h_i V_i, then h2[i] = V_i . w_new  (J dots)
+void update_mdot_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* h,
+                     double* wv, size_t n, double* h2);
+// w -= sum_i h_i V_i, then nrm2[0] = w_new . w_new
+void update_norm_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* h,
+                     double* wv, size_t n, double* nrm2);
+// y = x / sqrt(nrm2[0]) (y = 0 when nrm2 == 0); hcol[j+1] = sqrt(nrm2); hcol[0..j] = h1+h2
+void arnoldi_finish(Ctx* c, const double* h1, const double* h2, const double* nrm2, int J,
+                    double* hcol, double* v_next, const double* w, size_t n);
+// x += sum_i y_i Z_i (y on device)
+void combine_dev(Ctx* c, const double* Z, size_t ldz, int K, const double* y, double* x, size_t n);
+// y = b - y (in place, residual from a matvec result)
+void rsub(Ctx* c, const double* b, double* y, size_t n);
+// y = a * x
+void scale_copy(Ctx* c, double* y, const double* x, double a, size_t n);
+void axpy(Ctx* c, double* y, const double* x, double a, size_t n);
+
+// ---- sparse ------------------------------------------------------------------
+// y = A x (FP64), row groups of `tpr` lanes (1..64, power of two).
+void spmv(Ctx* c, const CsrView<double>& A, const double* x, double* y, int tpr, int cls);
+
+}  // namespace mgd

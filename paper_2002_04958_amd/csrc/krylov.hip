@@ -1,0 +1,173 @@
+// Restarted right-preconditioned (flexible) GMRES(m) on the block system of
+// eq. 2.2.  Arnoldi uses classical Gram-Schmidt applied twice; the second
+// projection is fused with the first update pass and the norm with the
+// second, so one Arnoldi step reads the basis three times.  The small
+// Hessenberg least-squares problem (Givens rotations) runs on the host from
+// one readback of the new column per step.
+#include <chrono>
+#include <cmath>
+
+#include "handles.hpp"
+#include "kernels.hpp"
+
+using namespace mgd;
+
+void block_precond_apply_dispatch(block_precond* bp, const double* r, double* z);
+
+struct EvPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EvPair() {
+    MGD_HIP(hipEventCreate(&a));
+    MGD_HIP(hipEventCreate(&b));
+  }
+  ~EvPair() {
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+  }
+  float ms() {
+    float t = 0;
+    MGD_HIP(hipEventElapsedTime(&t, a, b));
+    return t;
+  }
+};
+
+mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const double* b, double* x,
+                      const gmres_params& p, gmres_result& res) {
+  res = gmres_result{};
+  const size_t n = (size_t)(S.G + 2) * S.N;
+  const int m = p.restart;
+  MGD_REQUIRE(m >= 1 && m <= 31, "restart must be in [1, 31]");
+  MGD_REQUIRE(p.max_iters >= 0, "max_iters must be >= 0");
+  auto t_start = std::chrono::steady_clock::now();
+  const bool flex = p.flexible != 0;
+  DBuf<double> V(c, (size_t)(m + 1) * n);
+  DBuf<double> Z;
+  if (flex && M) Z.alloc(c, (size_t)m * n);
+  DBuf<double> t1, t2;
+  if (!flex && M) {
+    t1.alloc(c, n);
+    t2.alloc(c, n);
+  }
+  DBuf<double> hd(c, 200);
+  double* h1 = hd.get();
+  double* h2 = hd.get() + 40;
+  double* hc = hd.get() + 80;       // [0..J]: column, then nrm2 at 120
+  double* nrm2 = hd.get() + 120;
+  double* yd = hd.get() + 130;      // y (<= 31)
+  double* bn = hd.get() + 125;
+  RedWork rw;
+  std::unique_ptr<EvPair> evp, evm, evo;
+  if (p.profile) {
+    evp.reset(new EvPair);
+    evm.reset(new EvPair);
+    evo.reset(new EvPair);
+  }
+  double* hbuf = static_cast<double*>(c->host_stage(64 * sizeof(double)));
+
+  dot_dev(c, rw, b, b, n, bn);
+  const double bnorm = std::sqrt(read1(c, bn));
+  if (bnorm == 0.0) {
+    fill<double>(c, x, 0.0, n);
+    c->sync();
+    res.converged = 1;
+    return MGD_OK;
+  }
+  const double tol = p.rtol * bnorm;
+  double* V0 = V.get();
+  block_matvec(c, S, x, b, V0);
+  dot_dev(c, rw, V0, V0, n, bn);
+  double beta = std::sqrt(read1(c, bn));
+  res.relres_true = res.relres_est = beta / bnorm;
+  if (beta <= tol) {
+    res.converged = 1;
+    res.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    return MGD_OK;
+  }
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  auto Hij = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+  while (res.iters < p.max_iters) {
+    scale_copy(c, V0, V0, 1.0 / beta, n);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    bool breakdown = false;
+    for (int j = 0; j < m; ++j) {
+      double* vj = V.get() + (size_t)j * n;
+      double* w = V.get() + (size_t)(j + 1) * n;
+      const double* zj = vj;
+      if (M) {
+        double* zt = flex ? Z.get() + (size_t)j * n : t1.get();
+        if (evp) MGD_HIP(hipEventRecord(evp->a, c->stream));
+        block_precond_apply_dispatch(M, vj, zt);
+        if (evp) MGD_HIP(hipEventRecord(evp->b, c->stream));
+        res.precond_applies++;
+        zj = zt;
+      }
+      if (evm) MGD_HIP(hipEventRecord(evm->a, c->stream));
+      block_matvec(c, S, zj, nullptr, w);
+      if (evm) MGD_HIP(hipEventRecord(evm->b, c->stream));
+      const int J = j + 1;
+      if (evo) MGD_HIP(hipEventRecord(evo->a, c->stream));
+      mdot_dev(c, rw, V.get(), n, J, w, n, h1);
+      update_mdot_dev(c, rw, V.get(), n, J, h1, w, n, h2);
+      update_norm_dev(c, rw, V.get(), n, J, h2, w, n, nrm2);
+      arnoldi_finish(c, h1, h2, nrm2, J, hc, w, w, n);
+      if (evo) MGD_HIP(hipEventRecord(evo->b, c->stream));
+      MGD_HIP(hipMemcpyAsync(hbuf, hc, (J + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      c->sync();
+      if (evp && M) res.t_precond_ms += evp->ms();
+      if (evm) res.t_matvec_ms += evm->ms();
+      if (evo) res.t_orth_ms += evo->ms();
+      for (int i = 0; i <= J; ++i) Hij(i, j) = hbuf[i];
+      breakdown = Hij(j + 1, j) == 0.0;
+      for (int i = 0; i < j; ++i) {
+        const double tt = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
+        Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
+        Hij(i, j) = tt;
+      }
+      const double den = std::sqrt(Hij(j, j) * Hij(j, j) + Hij(j + 1, j) * Hij(j + 1, j));
+      if (den == 0.0) fail(MGD_EBREAKDOWN, "GMRES breakdown: singular Hessenberg matrix");
+      cs[j] = Hij(j, j) / den;
+      sn[j] = Hij(j + 1, j) / den;
+      Hij(j, j) = den;
+      Hij(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      res.iters++;
+      k = j + 1;
+      res.relres_est = std::fabs(g[j + 1]) / bnorm;
+      if (std::fabs(g[j + 1]) <= tol || res.iters >= p.max_iters || breakdown) break;
+    }
+    // back substitution H y = g
+    for (int i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int q = i + 1; q < k; ++q) s -= Hij(i, q) * y[q];
+      y[i] = s / Hij(i, i);
+    }
+    MGD_HIP(hipMemcpyAsync(yd, y.data(), k * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if (!M) {
+      combine_dev(c, V.get(), n, k, yd, x, n);
+    } else if (flex) {
+      combine_dev(c, Z.get(), n, k, yd, x, n);
+    } else {
+      fill<double>(c, t1.get(), 0.0, n);
+      combine_dev(c, V.get(), n, k, yd, t1.get(), n);
+      block_precond_apply_dispatch(M, t1.get(), t2.get());
+      res.precond_applies++;
+      axpy(c, x, t2.get(), 1.0, n);
+    }
+    res.restarts++;
+    block_matvec(c, S, x, b, V0);
+    dot_dev(c, rw, V0, V0, n, bn);
+    beta = std::sqrt(read1(c, bn));
+    res.relres_true = beta / bnorm;
+    if (beta <= tol) {
+      res.converged = 1;
+      break;
+    }
+    if (beta == 0.0) break;
+  }
+  c->sync();
+  res.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  return res.converged ? MGD_OK : MGD_ENOTCONV;
+}

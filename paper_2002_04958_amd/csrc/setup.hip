@@ -1,0 +1,665 @@
+// AMG setup kernels: strength of connection, PMIS, classical modified
+// interpolation, sorted transpose, canonical-order SpGEMM, l1 diagonal and
+// the dense coarsest-level inverse.
+//
+// Every floating-point sum here is evaluated left to right in a fixed order
+// with separately rounded products and additions (no contraction into fused
+// multiply-adds), so the results are reproducible bit for bit by any other
+// implementation that follows the same order.
+#pragma clang fp contract(off)
+
+#include <algorithm>
+#include <climits>
+
+#include "kernels.hpp"
+#include "setup.hpp"
+
+namespace mgd {
+
+// ---------------------------------------------------------------------------
+// copies
+// ---------------------------------------------------------------------------
+void csr_copy_from(Ctx* c, const mgd_csr* A, Csr<double>& out) {
+  out.alloc(c, A->n_rows, A->n_cols, (int)A->nnz);
+  copy_d2d(c, out.rp.get(), A->row_ptr, (size_t)A->n_rows + 1);
+  copy_d2d(c, out.ci.get(), A->col_idx, (size_t)A->nnz);
+  copy_d2d(c, out.v.get(), A->val, (size_t)A->nnz);
+}
+void csr_copy(Ctx* c, const Csr<double>& A, Csr<double>& out) {
+  out.alloc(c, A.n_rows, A.n_cols, A.nnz);
+  copy_d2d(c, out.rp.get(), A.rp.get(), (size_t)A.n_rows + 1);
+  copy_d2d(c, out.ci.get(), A.ci.get(), (size_t)A.nnz);
+  copy_d2d(c, out.v.get(), A.v.get(), (size_t)A.nnz);
+}
+
+// ---------------------------------------------------------------------------
+// strength of connection
+// ---------------------------------------------------------------------------
+__global__ void k_strength(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const double* __restrict__ v, double theta, double dom,
+                           uint8_t* __restrict__ S, int* __restrict__ stc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int e0 = rp[i], e1 = rp[i + 1];
+  double m = -INFINITY, rs = 0.0, dg = 0.0;
+  for (int e = e0; e < e1; ++e) {
+    const double a = v[e];
+    rs = rs + a;
+    if (ci[e] == i)
+      dg = a;
+    else if (-a > m)
+      m = -a;
+  }
+  bool empty = !(m > 0.0);
+  if (dom > 0.0 && rs >= dom * dg) empty = true;
+  const double thr = theta * m;
+  for (int e = e0; e < e1; ++e) {
+    const int j = ci[e];
+    const bool s = !empty && j != i && (-v[e] >= thr);
+    S[e] = s ? 1 : 0;
+    if (s) atomicAdd(&stc[j], 1);
+  }
+}
+
+void strength(Ctx* c, const Csr<double>& A, double theta, double dom, DBuf<uint8_t>& S,
+              DBuf<int>& stc) {
+  S.alloc(c, (size_t)A.nnz);
+  stc.alloc(c, (size_t)A.n_rows);
+  fill<int>(c, stc.get(), 0, (size_t)A.n_rows);
+  if (A.n_rows == 0) return;
+  hipLaunchKernelGGL(k_strength, dim3(cdiv(A.n_rows, 256)), dim3(256), 0, c->stream, A.n_rows,
+                     A.rp.get(), A.ci.get(), A.v.get(), theta, dom, S.get(), stc.get());
+  MGD_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// PMIS
+// ---------------------------------------------------------------------------
+// First output of SplitMix64 for the given state (Steele, Lea, Flood 2014).
+__device__ __forceinline__ uint64_t splitmix64_first(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_pmis_init(int n, const int* __restrict__ stc, uint64_t seed, int level,
+                            uint64_t* __restrict__ key, int8_t* __restrict__ state) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t h = splitmix64_first(seed ^ ((uint64_t)level << 56) ^ (uint64_t)i) >> 32;
+  key[i] = ((uint64_t)stc[i] << 32) | h;
+  state[i] = stc[i] == 0 ? kF : kU;
+}
+
+__global__ void k_st_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                          const uint8_t* __restrict__ S, int* __restrict__ fillpos,
+                          int* __restrict__ st_ci) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (S[e]) {
+      const int p = atomicAdd(&fillpos[ci[e]], 1);
+      st_ci[p] = i;
+    }
+}
+
+__device__ __forceinline__ bool beats(uint64_t kj, int j, uint64_t ki, int i) {
+  return kj > ki || (kj == ki && j > i);
+}
+
+__global__ void k_pmis_select(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                              const uint8_t* __restrict__ S, const int* __restrict__ st_rp,
+                              const int* __restrict__ st_ci, const uint64_t* __restrict__ key,
+                              const int8_t* __restrict__ state, uint8_t* __restrict__ newc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (state[i] != kU) {
+    newc[i] = 0;
+    return;
+  }
+  const uint64_t ki = key[i];
+  bool best = true;
+  for (int e = rp[i]; e < rp[i + 1] && best; ++e) {
+    if (!S[e]) continue;
+    const int j = ci[e];
+    if (state[j] == kU && beats(key[j], j, ki, i)) best = false;
+  }
+  for (int p = st_rp[i]; p < st_rp[i + 1] && best; ++p) {
+    const int j = st_ci[p];
+    if (state[j] == kU && beats(key[j], j, ki, i)) best = false;
+  }
+  newc[i] = best ? 1 : 0;
+}
+
+__global__ void k_pmis_update(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                              const uint8_t* __restrict__ S, const uint8_t* __restrict__ newc,
+                              int8_t* __restrict__ state, int* __restrict__ remaining) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool und = false;
+  if (i < n && state[i] == kU) {
+    if (newc[i]) {
+      state[i] = kC;
+    } else {
+      bool dep = false;
+      for (int e = rp[i]; e < rp[i + 1]; ++e)
+        if (S[e] && newc[ci[e]]) {
+          dep = true;
+          break;
+        }
+      if (dep)
+        state[i] = kF;
+      else
+        und = true;
+    }
+  }
+  const uint64_t m = __ballot(und);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(remaining, (int)__popcll(m));
+}
+
+__global__ void k_count_undecided(int n, const int8_t* __restrict__ state,
+                                  int* __restrict__ remaining) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t m = __ballot(i < n && state[i] == kU);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(remaining, (int)__popcll(m));
+}
+
+int pmis(Ctx* c, const Csr<double>& A, const DBuf<uint8_t>& S, const DBuf<int>& stc,
+         uint64_t seed, int level, DBuf<int8_t>& state) {
+  const int n = A.n_rows;
+  state.alloc(c, (size_t)n);
+  if (n == 0) return 0;
+  DBuf<uint64_t> key(c, (size_t)n);
+  DBuf<uint8_t> newc(c, (size_t)n);
+  DBuf<int> st_rp(c, (size_t)n + 1), fillpos(c, (size_t)n), remaining(c, 1);
+  const int g = cdiv(n, 256);
+  hipLaunchKernelGGL(k_pmis_init, dim3(g), dim3(256), 0, c->stream, n, stc.get(), seed, level,
+                     key.get(), state.get());
+  MGD_CHECK_LAUNCH();
+  const int nst = exclusive_scan_total(c, stc.get(), st_rp.get(), n);
+  DBuf<int> st_ci(c, (size_t)std::max(nst, 1));
+  copy_d2d(c, fillpos.get(), st_rp.get(), (size_t)n);
+  hipLaunchKernelGGL(k_st_fill, dim3(g), dim3(256), 0, c->stream, n, A.rp.get(), A.ci.get(),
+                     S.get(), fillpos.get(), st_ci.get());
+  MGD_CHECK_LAUNCH();
+  fill<int>(c, remaining.get(), 0, 1);
+  hipLaunchKernelGGL(k_count_undecided, dim3(g), dim3(256), 0, c->stream, n, state.get(),
+                     remaining.get());
+  MGD_CHECK_LAUNCH();
+  int rounds = 0;
+  while (read1(c, remaining.get()) > 0) {
+    fill<int>(c, remaining.get(), 0, 1);
+    hipLaunchKernelGGL(k_pmis_select, dim3(g), dim3(256), 0, c->stream, n, A.rp.get(), A.ci.get(),
+                       S.get(), st_rp.get(), st_ci.get(), key.get(), state.get(), newc.get());
+    MGD_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_pmis_update, dim3(g), dim3(256), 0, c->stream, n, A.rp.get(), A.ci.get(),
+                       S.get(), newc.get(), state.get(), remaining.get());
+    MGD_CHECK_LAUNCH();
+    // each round decides at least the undecided row of largest (key, index)
+    if (++rounds > n) fail(MGD_EHIP, "PMIS did not terminate");
+  }
+  return rounds;
+}
+
+// ---------------------------------------------------------------------------
+// classical modified interpolation
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int sgn(double x) { return (x > 0.0) - (x < 0.0); }
+
+// position of column j in the sorted row [e0, e1), or -1
+__device__ __forceinline__ int find_col(const int* __restrict__ ci, int e0, int e1, int j) {
+  int lo = e0, hi = e1;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (ci[mid] < j)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < e1 && ci[lo] == j) ? lo : -1;
+}
+
+__global__ void k_diag(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                       const double* __restrict__ v, double* __restrict__ d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p = find_col(ci, rp[i], rp[i + 1], i);
+  d[i] = p >= 0 ? v[p] : 0.0;
+}
+
+__global__ void k_interp_count(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                               const uint8_t* __restrict__ S, const int8_t* __restrict__ st,
+                               int* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (st[i] == kC) {
+    cnt[i] = 1;
+    return;
+  }
+  int k = 0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (S[e] && st[ci[e]] == kC) ++k;
+  cnt[i] = k;
+}
+
+__global__ void k_interp_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                              const double* __restrict__ v, const double* __restrict__ diag,
+                              const uint8_t* __restrict__ S, const int8_t* __restrict__ st,
+                              const int* __restrict__ cidx, const int* __restrict__ prp,
+                              int* __restrict__ pci, double* __restrict__ pv,
+                              double* __restrict__ sigma) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int p = prp[i];
+  if (st[i] == kC) {
+    pci[p] = cidx[i];
+    pv[p] = 1.0;
+    return;
+  }
+  const int e0 = rp[i], e1 = rp[i + 1];
+  // 1. sigma_ik = sum over j in C_i (ascending j) of ahat_kj, for strong F k
+  for (int e = e0; e < e1; ++e) {
+    const int k = ci[e];
+    if (!S[e] || st[k] != kF) continue;
+    const int f0 = rp[k], f1 = rp[k + 1];
+    const int skk = sgn(diag[k]);
+    double s = 0.0;
+    int q = e0;
+    for (int f = f0; f < f1; ++f) {
+      const int j = ci[f];
+      while (q < e1 && ci[q] < j) ++q;
+      if (q < e1 && ci[q] == j && S[q] && st[j] == kC) {
+        const double a = v[f];
+        s = s + (sgn(a) != skk ? a : 0.0);
+      }
+    }
+    sigma[e] = s;
+  }
+  // 2. modified diagonal: a_ii + weak neighbours + strong F without common C
+  double at = diag[i];
+  for (int e = e0; e < e1; ++e) {
+    const int j = ci[e];
+    if (j == i) continue;
+    if (!S[e])
+      at = at + v[e];
+    else if (st[j] == kF && sigma[e] == 0.0)
+      at = at + v[e];
+  }
+  // 3. weights for each strong C point, distribution over ascending k
+  for (int e = e0; e < e1; ++e) {
+    const int j = ci[e];
+    if (!S[e] || st[j] != kC) continue;
+    double num = v[e];
+    for (int e2 = e0; e2 < e1; ++e2) {
+      const int k = ci[e2];
+      if (!S[e2] || st[k] != kF) continue;
+      const double sg = sigma[e2];
+      if (sg == 0.0) continue;
+      const int f = find_col(ci, rp[k], rp[k + 1], j);
+      if (f < 0) continue;
+      const double a = v[f];
+      const double ah = sgn(a) != sgn(diag[k]) ? a : 0.0;
+      num = num + (v[e2] * ah) / sg;
+    }
+    pci[p] = cidx[j];
+    pv[p] = -num / at;
+    ++p;
+  }
+}
+
+__global__ void k_is_c(int n, const int8_t* __restrict__ st, int* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = st[i] == kC ? 1 : 0;
+}
+
+void interpolation(Ctx* c, const Csr<double>& A, const DBuf<uint8_t>& S,
+                   const DBuf<int8_t>& state, const DBuf<int>& cidx, int nc, Csr<double>& P) {
+  const int n = A.n_rows;
+  DBuf<int> cnt(c, (size_t)n);
+  DBuf<double> diag(c, (size_t)n), sigma(c, (size_t)std::max(A.nnz, 1));
+  const int g = cdiv(n, 256);
+  hipLaunchKernelGGL(k_diag, dim3(g), dim3(256), 0, c->stream, n, A.rp.get(), A.ci.get(), A.v.get(),
+                     diag.get());
+  MGD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_interp_count, dim3(g), dim3(256), 0, c->stream, n, A.rp.get(), A.ci.get(),
+                     S.get(), state.get(), cnt.get());
+  MGD_CHECK_LAUNCH();
+  P.n_rows = n;
+  P.n_cols = nc;
+  P.rp.alloc(c, (size_t)n + 1);
+  P.nnz = exclusive_scan_total(c, cnt.get(), P.rp.get(), n);
+  P.ci.alloc(c, (size_t)P.nnz);
+  P.v.alloc(c, (size_t)P.nnz);
+  hipLaunchKernelGGL(k_interp_fill, dim3(g), dim3(256), 0, c->stream, n, A.rp.get(), A.ci.get(),
+                     A.v.get(), diag.get(), S.get(), state.get(), cidx.get(), P.rp.get(),
+                     P.ci.get(), P.v.get(), sigma.get());
+  MGD_CHECK_LAUNCH();
+  c->sync();
+}
+
+// ---------------------------------------------------------------------------
+// sorted transpose
+// ---------------------------------------------------------------------------
+__global__ void k_count_cols(int nnz, const int* __restrict__ ci, int* __restrict__ cnt) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) atomicAdd(&cnt[ci[e]], 1);
+}
+__global__ void k_transpose_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                 const double* __restrict__ v, int* __restrict__ fillpos,
+                                 int* __restrict__ tci, double* __restrict__ tv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const int p = atomicAdd(&fillpos[ci[e]], 1);
+    tci[p] = i;
+    tv[p] = v[e];
+  }
+}
+// insertion sort of each row by column (rows of a transpose are short)
+__global__ void k_sort_rows(int n, const int* __restrict__ rp, int* __restrict__ ci,
+                            double* __restrict__ v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int e0 = rp[i], e1 = rp[i + 1];
+  for (int e = e0 + 1; e < e1; ++e) {
+    const int kc = ci[e];
+    const double kv = v[e];
+    int q = e - 1;
+    while (q >= e0 && ci[q] > kc) {
+      ci[q + 1] = ci[q];
+      v[q + 1] = v[q];
+      --q;
+    }
+    ci[q + 1] = kc;
+    v[q + 1] = kv;
+  }
+}
+
+void transpose(Ctx* c, const Csr<double>& A, Csr<double>& T) {
+  T.n_rows = A.n_cols;
+  T.n_cols = A.n_rows;
+  T.nnz = A.nnz;
+  DBuf<int> cnt(c, (size_t)std::max(A.n_cols, 1)), fillpos(c, (size_t)std::max(A.n_cols, 1));
+  fill<int>(c, cnt.get(), 0, (size_t)A.n_cols);
+  if (A.nnz)
+    hipLaunchKernelGGL(k_count_cols, dim3(cdiv(A.nnz, 256)), dim3(256), 0, c->stream, A.nnz,
+                       A.ci.get(), cnt.get());
+  MGD_CHECK_LAUNCH();
+  T.rp.alloc(c, (size_t)A.n_cols + 1);
+  exclusive_scan(c, cnt.get(), T.rp.get(), A.n_cols);
+  T.ci.alloc(c, (size_t)A.nnz);
+  T.v.alloc(c, (size_t)A.nnz);
+  copy_d2d(c, fillpos.get(), T.rp.get(), (size_t)A.n_cols);
+  if (A.n_rows)
+    hipLaunchKernelGGL(k_transpose_fill, dim3(cdiv(A.n_rows, 256)), dim3(256), 0, c->stream,
+                       A.n_rows, A.rp.get(), A.ci.get(), A.v.get(), fillpos.get(), T.ci.get(),
+                       T.v.get());
+  MGD_CHECK_LAUNCH();
+  if (T.n_rows)
+    hipLaunchKernelGGL(k_sort_rows, dim3(cdiv(T.n_rows, 256)), dim3(256), 0, c->stream, T.n_rows,
+                       T.rp.get(), T.ci.get(), T.v.get());
+  MGD_CHECK_LAUNCH();
+  c->sync();
+}
+
+// ---------------------------------------------------------------------------
+// SpGEMM: row-wise multiway merge.  Every output column of row i is produced
+// in ascending order; its value is 0 + a_ik1 b_k1j + a_ik2 b_k2j + ... over
+// the row's entries in ascending k.
+// ---------------------------------------------------------------------------
+template <bool FILL>
+__global__ void k_spgemm(int n, const int* __restrict__ arp, const int* __restrict__ aci,
+                         const double* __restrict__ av, const int* __restrict__ brp,
+                         const int* __restrict__ bci, const double* __restrict__ bv,
+                         int* __restrict__ head, int* __restrict__ hend,
+                         const int* __restrict__ crp, int* __restrict__ cnt_or_cci,
+                         double* __restrict__ cv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int e0 = arp[i], e1 = arp[i + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int k = aci[e];
+    head[e] = brp[k];
+    hend[e] = brp[k + 1];
+  }
+  int out = FILL ? crp[i] : 0;
+  for (;;) {
+    int jmin = INT_MAX;
+    for (int e = e0; e < e1; ++e)
+      if (head[e] < hend[e]) jmin = min(jmin, bci[head[e]]);
+    if (jmin == INT_MAX) break;
+    double acc = 0.0;
+    for (int e = e0; e < e1; ++e) {
+      const int h = head[e];
+      if (h < hend[e] && bci[h] == jmin) {
+        if (FILL) acc = acc + av[e] * bv[h];
+        head[e] = h + 1;
+      }
+    }
+    if (FILL) {
+      cnt_or_cci[out] = jmin;
+      cv[out] = acc;
+    }
+    ++out;
+  }
+  if (!FILL) cnt_or_cci[i] = out;
+}
+
+void spgemm(Ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>& C) {
+  MGD_REQUIRE(A.n_cols == B.n_rows, "spgemm: inner dimensions differ");
+  const int n = A.n_rows;
+  DBuf<int> head(c, (size_t)std::max(A.nnz, 1)), hend(c, (size_t)std::max(A.nnz, 1));
+  DBuf<int> cnt(c, (size_t)std::max(n, 1));
+  C.n_rows = n;
+  C.n_cols = B.n_cols;
+  C.rp.alloc(c, (size_t)n + 1);
+  const int g = cdiv(n, 128);
+  if (n)
+    hipLaunchKernelGGL(k_spgemm<false>, dim3(g), dim3(128), 0, c->stream, n, A.rp.get(),
+                       A.ci.get(), A.v.get(), B.rp.get(), B.ci.get(), B.v.get(), head.get(),
+                       hend.get(), (const int*)nullptr, cnt.get(), (double*)nullptr);
+  MGD_CHECK_LAUNCH();
+  C.nnz = exclusive_scan_total(c, cnt.get(), C.rp.get(), n);
+  C.ci.alloc(c, (size_t)C.nnz);
+  C.v.alloc(c, (size_t)C.nnz);
+  if (n)
+    hipLaunchKernelGGL(k_spgemm<true>, dim3(g), dim3(128), 0, c->stream, n, A.rp.get(), A.ci.get(),
+                       A.v.get(), B.rp.get(), B.ci.get(), B.v.get(), head.get(), hend.get(),
+                       (const int*)C.rp.get(), C.ci.get(), C.v.get());
+  MGD_CHECK_LAUNCH();
+  c->sync();
+}
+
+// ---------------------------------------------------------------------------
+// l1 diagonal
+// ---------------------------------------------------------------------------
+__global__ void k_l1diag(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                         const double* __restrict__ v, double* __restrict__ d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int e0 = rp[i], e1 = rp[i + 1];
+  double acc = 0.0;
+  for (int e = e0; e < e1; ++e)
+    if (ci[e] == i) acc = v[e];
+  for (int e = e0; e < e1; ++e)
+    if (ci[e] != i) acc = acc + fabs(v[e]);
+  d[i] = acc;
+}
+void l1_diagonal(Ctx* c, const Csr<double>& A, double* d) {
+  if (!A.n_rows) return;
+  hipLaunchKernelGGL(k_l1diag, dim3(cdiv(A.n_rows, 256)), dim3(256), 0, c->stream, A.n_rows,
+                     A.rp.get(), A.ci.get(), A.v.get(), d);
+  MGD_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// dense inverse of the coarsest matrix (FP64): LU with partial pivoting
+// (first row of maximum magnitude), then one triangular solve pair per
+// column of the identity.  One workgroup; n <= dense_max.
+// ---------------------------------------------------------------------------
+__global__ void k_csr_to_dense(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                               const double* __restrict__ v, double* __restrict__ M) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) M[(size_t)i * n + ci[e]] = v[e];
+}
+
+__global__ void __launch_bounds__(1024) k_lu(int n, double* __restrict__ M, int* __restrict__ piv,
+                                             int* __restrict__ singular) {
+  __shared__ double sval[1024];
+  __shared__ int sidx[1024];
+  const int t = threadIdx.x;
+  for (int col = 0; col < n; ++col) {
+    // pivot search: max |M[r][col]|, smallest r on ties
+    double best = -1.0;
+    int bi = INT_MAX;
+    for (int r = col + t; r < n; r += 1024) {
+      const double a = fabs(M[(size_t)r * n + col]);
+      if (a > best) {
+        best = a;
+        bi = r;
+      }
+    }
+    sval[t] = best;
+    sidx[t] = bi;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+      if (t < s) {
+        const double ov = sval[t + s];
+        const int oi = sidx[t + s];
+        if (ov > sval[t] || (ov == sval[t] && oi < sidx[t])) {
+          sval[t] = ov;
+          sidx[t] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int p = sidx[0];
+    const double pv = sval[0];
+    __syncthreads();
+    if (!(pv > 0.0)) {
+      if (t == 0) singular[0] = 1;
+      return;
+    }
+    if (t == 0) piv[col] = p;
+    if (p != col)
+      for (int j = t; j < n; j += 1024) {
+        const double tmp = M[(size_t)col * n + j];
+        M[(size_t)col * n + j] = M[(size_t)p * n + j];
+        M[(size_t)p * n + j] = tmp;
+      }
+    __syncthreads();
+    const double d = M[(size_t)col * n + col];
+    for (int r = col + 1 + t; r < n; r += 1024) M[(size_t)r * n + col] = M[(size_t)r * n + col] / d;
+    __syncthreads();
+    const int m = n - col - 1;
+    for (long q = t; q < (long)m * m; q += 1024) {
+      const int r = col + 1 + (int)(q / m);
+      const int j = col + 1 + (int)(q % m);
+      M[(size_t)r * n + j] = M[(size_t)r * n + j] - M[(size_t)r * n + col] * M[(size_t)col * n + j];
+    }
+    __syncthreads();
+  }
+}
+
+// inverse column j: solve L U x = P e_j; written column-major inv[j*n + i]
+__global__ void k_lu_inverse(int n, const double* __restrict__ M, const int* __restrict__ piv,
+                             double* __restrict__ inv) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double* x = inv + (size_t)j * n;
+  for (int i = 0; i < n; ++i) x[i] = (i == j) ? 1.0 : 0.0;
+  for (int i = 0; i < n; ++i) {  // apply the row interchanges in order
+    const int p = piv[i];
+    if (p != i) {
+      const double t = x[i];
+      x[i] = x[p];
+      x[p] = t;
+    }
+  }
+  for (int i = 0; i < n; ++i) {  // unit lower
+    double s = x[i];
+    for (int k = 0; k < i; ++k) s = s - M[(size_t)i * n + k] * x[k];
+    x[i] = s;
+  }
+  for (int i = n - 1; i >= 0; --i) {  // upper
+    double s = x[i];
+    for (int k = i + 1; k < n; ++k) s = s - M[(size_t)i * n + k] * x[k];
+    x[i] = s / M[(size_t)i * n + i];
+  }
+}
+
+bool dense_inverse(Ctx* c, const Csr<double>& A, DBuf<double>& inv) {
+  const int n = A.n_rows;
+  inv.alloc(c, (size_t)n * n);
+  if (n == 0) return true;
+  DBuf<double> M(c, (size_t)n * n);
+  DBuf<int> piv(c, (size_t)n), sing(c, 1);
+  fill<double>(c, M.get(), 0.0, (size_t)n * n);
+  fill<int>(c, sing.get(), 0, 1);
+  hipLaunchKernelGGL(k_csr_to_dense, dim3(cdiv(n, 256)), dim3(256), 0, c->stream, n, A.rp.get(),
+                     A.ci.get(), A.v.get(), M.get());
+  MGD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_lu, dim3(1), dim3(1024), 0, c->stream, n, M.get(), piv.get(), sing.get());
+  MGD_CHECK_LAUNCH();
+  if (read1(c, sing.get())) return false;
+  hipLaunchKernelGGL(k_lu_inverse, dim3(cdiv(n, 64)), dim3(64), 0, c->stream, n,
+                     (const double*)M.get(), (const int*)piv.get(), inv.get());
+  MGD_CHECK_LAUNCH();
+  c->sync();
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// hierarchy driver
+// ---------------------------------------------------------------------------
+void amg_build(Ctx* c, Csr<double>&& A0, const amg_params& p, SetupHierarchy& H) {
+  H.levels.clear();
+  Csr<double> A = std::move(A0);
+  for (int lvl = 0;; ++lvl) {
+    const int n = A.n_rows;
+    SetupLevel L;
+    if (n <= p.coarse_max || lvl == p.max_levels - 1 || lvl == MGD_MAX_LEVELS - 1) {
+      L.A = std::move(A);
+      H.levels.push_back(std::move(L));
+      break;
+    }
+    DBuf<uint8_t> S;
+    DBuf<int> stc;
+    strength(c, A, p.strength_theta, p.dominance_theta, S, stc);
+    DBuf<int8_t> state;
+    const int rounds = pmis(c, A, S, stc, p.seed, lvl, state);
+    DBuf<int> isc(c, (size_t)n), cidx(c, (size_t)n + 1);
+    hipLaunchKernelGGL(k_is_c, dim3(cdiv(n, 256)), dim3(256), 0, c->stream, n, state.get(),
+                       isc.get());
+    MGD_CHECK_LAUNCH();
+    const int nc = exclusive_scan_total(c, isc.get(), cidx.get(), n);
+    if (nc == 0 || 10LL * nc > 9LL * n) {  // stalled coarsening: this is the coarsest level
+      L.A = std::move(A);
+      H.levels.push_back(std::move(L));
+      break;
+    }
+    Csr<double> P, R, AP, Ac;
+    interpolation(c, A, S, state, cidx, nc, P);
+    transpose(c, P, R);
+    spgemm(c, A, P, AP);
+    spgemm(c, R, AP, Ac);
+    L.A = std::move(A);
+    L.cf = std::move(state);
+    L.P = std::move(P);
+    L.nc = nc;
+    L.pmis_rounds = rounds;
+    H.levels.push_back(std::move(L));
+    A = std::move(Ac);
+  }
+  SetupLevel& last = H.levels.back();
+  if (last.A.n_rows <= p.dense_max) {
+    H.coarse_kind = 0;
+    if (!dense_inverse(c, last.A, H.coarse_inv))
+      fail(MGD_ESINGULAR, "zero pivot in the coarsest-level LU");
+  } else {
+    H.coarse_kind = 1;
+  }
+}
+
+}  // namespace mgd

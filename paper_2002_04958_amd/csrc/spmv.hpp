@@ -1,0 +1,33 @@
+// Device-side description of the block system of eq. 2.2.
+#pragma once
+#include "common.hpp"
+
+namespace mgd {
+
+constexpr int kMaxBlocks = 66;  // G + 2 <= 66
+
+struct BlockCsr {
+  const int* rp;
+  const int* ci;
+  const double* v;
+};
+
+// Passed by value as a kernel argument.
+struct BlockSysDev {
+  int G, N;
+  int tpr;
+  BlockCsr blk[kMaxBlocks];
+  long long nnz[kMaxBlocks];
+  const double* d_gE;
+  const double* d_Eg;
+  const double* d_EI;
+  const double* d_IE;
+};
+
+BlockSysDev make_block_sys_dev(const mgd_block_system* A);
+void check_block_system(const mgd_block_system* A);
+// y = A x, or y = b - A x when b != nullptr.
+void block_matvec(Ctx* c, const BlockSysDev& S, const double* x, const double* b, double* y);
+double block_matvec_bytes(const BlockSysDev& S, bool resid);
+
+}  // namespace mgd

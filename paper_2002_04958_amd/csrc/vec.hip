@@ -1,0 +1,375 @@
+// Vector primitives: scans, fills, casts and deterministic reductions.
+//
+// Reductions split the index range over a FIXED number of workgroups with a
+// grid-stride loop, reduce each workgroup with wavefront shuffles and LDS,
+// and sum the per-workgroup partials in index order in a second kernel, so
+// the result depends only on n, never on scheduling.
+#include "kernels.hpp"
+
+namespace mgd {
+
+// ---------------------------------------------------------------------------
+// wavefront / workgroup reductions (wave64)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over a 256-thread workgroup; result valid in thread 0.
+__device__ __forceinline__ double block_sum256(double v, double* lds /*[4]*/) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// scan
+// ---------------------------------------------------------------------------
+constexpr int kScanTile = 2048;  // 256 threads x 8 items
+
+__global__ void __launch_bounds__(256) k_tile_sums(const int* __restrict__ in, int n,
+                                                   int* __restrict__ sums) {
+  __shared__ int lds[4];
+  const long base = (long)blockIdx.x * kScanTile;
+  int s = 0;
+  for (int k = threadIdx.x; k < kScanTile; k += 256) {
+    long i = base + k;
+    if (i < n) s += in[i];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) sums[blockIdx.x] = lds[0] + lds[1] + lds[2] + lds[3];
+}
+
+// Exclusive scan of one tile with an additive base; writes out[i] for
+// i < n and, from the block holding the last element, out[n] = total.
+__global__ void __launch_bounds__(256) k_tile_scan(const int* __restrict__ in, int n,
+                                                   const int* __restrict__ base_of_tile,
+                                                   int* __restrict__ out) {
+  __shared__ int lds[256];
+  const long base = (long)blockIdx.x * kScanTile;
+  const int t = threadIdx.x;
+  int v[8];
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    long i = base + t * 8 + k;
+    v[k] = (i < n) ? in[i] : 0;
+    s += v[k];
+  }
+  lds[t] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over 256 thread sums
+  for (int off = 1; off < 256; off <<= 1) {
+    int add = (t >= off) ? lds[t - off] : 0;
+    __syncthreads();
+    lds[t] += add;
+    __syncthreads();
+  }
+  int run = (t ? lds[t - 1] : 0) + (base_of_tile ? base_of_tile[blockIdx.x] : 0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    long i = base + t * 8 + k;
+    if (i < n) out[i] = run;
+    run += v[k];
+    if (i == n - 1) out[n] = run;
+  }
+}
+
+__global__ void k_set_zero_total(int* out) { out[0] = 0; }
+
+void exclusive_scan(Ctx* c, const int* in, int* out, int n) {
+  if (n <= 0) {
+    hipLaunchKernelGGL(k_set_zero_total, dim3(1), dim3(1), 0, c->stream, out);
+    MGD_CHECK_LAUNCH();
+    return;
+  }
+  const int tiles = cdiv(n, kScanTile);
+  if (tiles == 1) {
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(256), 0, c->stream, in, n, nullptr, out);
+    MGD_CHECK_LAUNCH();
+    return;
+  }
+  DBuf<int> sums(c, tiles), sums_scan(c, (size_t)tiles + 1);
+  hipLaunchKernelGGL(k_tile_sums, dim3(tiles), dim3(256), 0, c->stream, in, n, sums.get());
+  MGD_CHECK_LAUNCH();
+  exclusive_scan(c, sums.get(), sums_scan.get(), tiles);
+  hipLaunchKernelGGL(k_tile_scan, dim3(tiles), dim3(256), 0, c->stream, in, n,
+                     (const int*)sums_scan.get(), out);
+  MGD_CHECK_LAUNCH();
+  // temporaries are released only after the stream has consumed them
+  c->sync();
+}
+
+int exclusive_scan_total(Ctx* c, const int* in, int* out, int n) {
+  exclusive_scan(c, in, out, n);
+  return read1(c, out + (n > 0 ? n : 0));
+}
+
+// ---------------------------------------------------------------------------
+// fill / cast
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, T v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+template <typename T>
+void fill(Ctx* c, T* p, T v, size_t n) {
+  if (!n) return;
+  int g = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 65535 * 4);
+  hipLaunchKernelGGL(k_fill<T>, dim3(g), dim3(kBlock), 0, c->stream, p, v, n);
+  MGD_CHECK_LAUNCH();
+}
+template void fill<int>(Ctx*, int*, int, size_t);
+template void fill<int8_t>(Ctx*, int8_t*, int8_t, size_t);
+template void fill<double>(Ctx*, double*, double, size_t);
+template void fill<float>(Ctx*, float*, float, size_t);
+
+template <typename D, typename S>
+__global__ void k_cast(D* __restrict__ d, const S* __restrict__ s, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    d[i] = (D)s[i];
+}
+template <typename D, typename S>
+void cast_copy(Ctx* c, D* dst, const S* src, size_t n, int cls) {
+  if (!n) return;
+  ProfScope ps(c, cls, (double)n * (sizeof(D) + sizeof(S)));
+  int g = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 65535 * 4);
+  hipLaunchKernelGGL((k_cast<D, S>), dim3(g), dim3(kBlock), 0, c->stream, dst, src, n);
+  MGD_CHECK_LAUNCH();
+}
+template void cast_copy<float, double>(Ctx*, float*, const double*, size_t, int);
+template void cast_copy<double, float>(Ctx*, double*, const float*, size_t, int);
+template void cast_copy<double, double>(Ctx*, double*, const double*, size_t, int);
+template void cast_copy<float, float>(Ctx*, float*, const float*, size_t, int);
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+static int red_grid(size_t n) {
+  size_t g = (n + kBlock - 1) / kBlock;
+  return (int)std::max<size_t>(1, std::min<size_t>(g, kRedBlocks));
+}
+
+// Final stage: out[j] = sum_b partial[j*nb + b] for b ascending over a fixed
+// tree: thread t sums b = t, t+256, ...; then the workgroup tree.
+__global__ void __launch_bounds__(256) k_red_final(const double* __restrict__ partial, int nb,
+                                                   double* __restrict__ out) {
+  __shared__ double lds[4];
+  const double* p = partial + (size_t)blockIdx.x * nb;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) s += p[b];
+  s = block_sum256(s, lds);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_dot(const double* __restrict__ x,
+                                             const double* __restrict__ y, size_t n,
+                                             double* __restrict__ partial) {
+  __shared__ double lds[4];
+  double s = 0.0;
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    s += x[i] * y[i];
+  s = block_sum256(s, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+void dot_dev(Ctx* c, RedWork& w, const double* x, const double* y, size_t n, double* out) {
+  w.ensure(c);
+  ProfScope ps(c, KC_ORTH, 16.0 * n);
+  int g = red_grid(n);
+  hipLaunchKernelGGL(k_dot, dim3(g), dim3(256), 0, c->stream, x, y, n, w.partial.get());
+  MGD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_red_final, dim3(1), dim3(256), 0, c->stream, (const double*)w.partial.get(),
+                     g, out);
+  MGD_CHECK_LAUNCH();
+}
+
+constexpr int kMaxJ = 32;
+
+// mode 0: h[j] = V_j . w
+// mode 1: w -= sum h_in[j] V_j ; h[j] = V_j . w_new
+// mode 2: w -= sum h_in[j] V_j ; h[0] = w_new . w_new
+template <int MODE>
+__global__ void __launch_bounds__(256) k_mdot(const double* __restrict__ V, size_t ldv, int J,
+                                              const double* __restrict__ h_in,
+                                              double* __restrict__ w, size_t n,
+                                              double* __restrict__ partial, int nb) {
+  __shared__ double lds[4];
+  double acc[kMaxJ];
+  double hv[kMaxJ];
+#pragma unroll
+  for (int j = 0; j < kMaxJ; ++j) {
+    acc[j] = 0.0;
+    hv[j] = (MODE != 0 && j < J) ? h_in[j] : 0.0;
+  }
+  double nacc = 0.0;
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    double wi = w[i];
+    if (MODE == 0) {
+#pragma unroll
+      for (int j = 0; j < kMaxJ; ++j)
+        if (j < J) acc[j] += V[j * ldv + i] * wi;
+    } else {
+      double vj[kMaxJ];
+#pragma unroll
+      for (int j = 0; j < kMaxJ; ++j)
+        if (j < J) vj[j] = V[j * ldv + i];
+#pragma unroll
+      for (int j = 0; j < kMaxJ; ++j)
+        if (j < J) wi -= hv[j] * vj[j];
+      w[i] = wi;
+      if (MODE == 1) {
+#pragma unroll
+        for (int j = 0; j < kMaxJ; ++j)
+          if (j < J) acc[j] += vj[j] * wi;
+      } else {
+        nacc += wi * wi;
+      }
+    }
+  }
+  if (MODE == 2) {
+    double s = block_sum256(nacc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    return;
+  }
+  for (int j = 0; j < J; ++j) {
+    double s = block_sum256(acc[j], lds);
+    if (threadIdx.x == 0) partial[(size_t)j * nb + blockIdx.x] = s;
+  }
+}
+
+void mdot_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* wv, size_t n,
+              double* h) {
+  MGD_REQUIRE(J >= 1 && J <= kMaxJ, "mdot: J out of range");
+  w.ensure(c);
+  ProfScope ps(c, KC_ORTH, 8.0 * n * (J + 1));
+  int g = red_grid(n);
+  hipLaunchKernelGGL(k_mdot<0>, dim3(g), dim3(256), 0, c->stream, V, ldv, J, (const double*)nullptr,
+                     const_cast<double*>(wv), n, w.partial.get(), g);
+  MGD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_red_final, dim3(J), dim3(256), 0, c->stream, (const double*)w.partial.get(),
+                     g, h);
+  MGD_CHECK_LAUNCH();
+}
+
+void update_mdot_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* h,
+                     double* wv, size_t n, double* h2) {
+  MGD_REQUIRE(J >= 1 && J <= kMaxJ, "mdot: J out of range");
+  w.ensure(c);
+  ProfScope ps(c, KC_ORTH, 8.0 * n * (J + 2));
+  int g = red_grid(n);
+  hipLaunchKernelGGL(k_mdot<1>, dim3(g), dim3(256), 0, c->stream, V, ldv, J, h, wv, n,
+                     w.partial.get(), g);
+  MGD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_red_final, dim3(J), dim3(256), 0, c->stream, (const double*)w.partial.get(),
+                     g, h2);
+  MGD_CHECK_LAUNCH();
+}
+
+void update_norm_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* h,
+                     double* wv, size_t n, double* nrm2) {
+  MGD_REQUIRE(J >= 1 && J <= kMaxJ, "mdot: J out of range");
+  w.ensure(c);
+  ProfScope ps(c, KC_ORTH, 8.0 * n * (J + 2));
+  int g = red_grid(n);
+  hipLaunchKernelGGL(k_mdot<2>, dim3(g), dim3(256), 0, c->stream, V, ldv, J, h, wv, n,
+                     w.partial.get(), g);
+  MGD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_red_final, dim3(1), dim3(256), 0, c->stream, (const double*)w.partial.get(),
+                     g, nrm2);
+  MGD_CHECK_LAUNCH();
+}
+
+__global__ void k_arnoldi_finish_h(const double* __restrict__ h1, const double* __restrict__ h2,
+                                   const double* __restrict__ nrm2, int J,
+                                   double* __restrict__ hcol) {
+  int j = threadIdx.x;
+  if (j < J) hcol[j] = h1[j] + h2[j];
+  if (j == 0) hcol[J] = sqrt(nrm2[0]);
+}
+__global__ void k_scale_by_norm(const double* __restrict__ nrm2, const double* __restrict__ w,
+                                double* __restrict__ v, size_t n) {
+  double nr = sqrt(nrm2[0]);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    v[i] = nr > 0.0 ? w[i] / nr : 0.0;
+}
+
+void arnoldi_finish(Ctx* c, const double* h1, const double* h2, const double* nrm2, int J,
+                    double* hcol, double* v_next, const double* w, size_t n) {
+  hipLaunchKernelGGL(k_arnoldi_finish_h, dim3(1), dim3(64), 0, c->stream, h1, h2, nrm2, J, hcol);
+  MGD_CHECK_LAUNCH();
+  ProfScope ps(c, KC_ORTH, 16.0 * n);
+  int g = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 8192);
+  hipLaunchKernelGGL(k_scale_by_norm, dim3(g), dim3(kBlock), 0, c->stream, nrm2, w, v_next, n);
+  MGD_CHECK_LAUNCH();
+}
+
+__global__ void k_combine(const double* __restrict__ Z, size_t ldz, int K,
+                          const double* __restrict__ y, double* __restrict__ x, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double s = x[i];
+    for (int k = 0; k < K; ++k) s += y[k] * Z[k * ldz + i];
+    x[i] = s;
+  }
+}
+void combine_dev(Ctx* c, const double* Z, size_t ldz, int K, const double* y, double* x,
+                 size_t n) {
+  if (K <= 0) return;
+  ProfScope ps(c, KC_ORTH, 8.0 * n * (K + 2));
+  int g = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 8192);
+  hipLaunchKernelGGL(k_combine, dim3(g), dim3(kBlock), 0, c->stream, Z, ldz, K, y, x, n);
+  MGD_CHECK_LAUNCH();
+}
+
+__global__ void k_rsub(const double* __restrict__ b, double* __restrict__ y, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    y[i] = b[i] - y[i];
+}
+void rsub(Ctx* c, const double* b, double* y, size_t n) {
+  ProfScope ps(c, KC_VEC, 24.0 * n);
+  int g = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 8192);
+  hipLaunchKernelGGL(k_rsub, dim3(g), dim3(kBlock), 0, c->stream, b, y, n);
+  MGD_CHECK_LAUNCH();
+}
+
+__global__ void k_scale_copy(double* __restrict__ y, const double* __restrict__ x, double a,
+                             size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i];
+}
+void scale_copy(Ctx* c, double* y, const double* x, double a, size_t n) {
+  ProfScope ps(c, KC_VEC, 16.0 * n);
+  int g = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 8192);
+  hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(kBlock), 0, c->stream, y, x, a, n);
+  MGD_CHECK_LAUNCH();
+}
+__global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+void axpy(Ctx* c, double* y, const double* x, double a, size_t n) {
+  ProfScope ps(c, KC_VEC, 24.0 * n);
+  int g = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 8192);
+  hipLaunchKernelGGL(k_axpy, dim3(g), dim3(kBlock), 0, c->stream, y, x, a, n);
+  MGD_CHECK_LAUNCH();
+}
+
+}  // namespace mgd

@@ -1,0 +1,351 @@
+"""GPU parity against the CPU oracle, through the C ABI.
+
+Bars: bit-exact for integer/index results (C/F splittings, sparsity
+patterns) and for values computed in a fixed order without contraction
+(assembly, setup); floating-point solve results within the tolerances
+stated per test."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import synth_inputs as si
+from oracle import amg as oamg
+from oracle import krylov as okry
+from oracle import precond as opc
+
+from gpu_helpers import (csr_of, gpu_modules, gpu_system, oracle_system, rel, small_inputs,
+                         to_dev, to_host)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    api = gpu_modules()
+    c = api.Context(0)
+    yield c
+    c.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# assembly, matvec
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,inp", small_inputs() + [("g1_2d64", si.generate_workload("g1_2d64"))])
+def test_assembly_bit_exact(ctx, name, inp):
+    osys = oracle_system(inp)
+    co, gsys = gpu_system(ctx, inp)
+    for a in range(inp.G + 2):
+        rp, ci, v = gsys.block_arrays(a)
+        B = osys.blocks[a]
+        assert np.array_equal(rp, B.indptr) and np.array_equal(ci, B.indices), (name, a)
+        assert np.array_equal(v, B.data), (name, a)
+    d_gE, d_Eg, d_EI, d_IE = gsys.couplings()
+    assert np.array_equal(d_gE, osys.d_gE.reshape(-1)) and np.array_equal(d_Eg, osys.d_Eg.reshape(-1))
+    assert np.array_equal(d_EI, osys.d_EI) and np.array_equal(d_IE, osys.d_IE)
+
+
+@pytest.mark.parametrize("name,inp", small_inputs())
+def test_block_matvec(ctx, name, inp):
+    osys = oracle_system(inp)
+    co, gsys = gpu_system(ctx, inp)
+    x = np.random.default_rng(5).standard_normal(osys.n)
+    y = to_host(gsys.matvec(to_dev(ctx, x)))
+    ref = osys.monolithic() @ x
+    assert rel(y, ref) < 1e-14
+
+
+def test_csr_spmv_ragged(ctx):
+    api = gpu_modules()
+    rng = np.random.default_rng(7)
+    for n, dens in ((1, 1.0), (37, 0.2), (5000, 0.002), (3000, 0.05)):
+        A = sp.random(n, n + 3, density=dens, random_state=rng, format="csr")
+        A.sort_indices()
+        x = rng.standard_normal(n + 3)
+        y = to_host(api.csr_spmv(ctx, A.indptr, A.indices, A.data, n + 3, to_dev(ctx, x)))
+        np.testing.assert_allclose(y, A @ x, rtol=1e-13, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# AMG setup: bit-exact C/F, P and coarse operators
+# ---------------------------------------------------------------------------
+def _compare_hierarchies(gamg, H, exact_values=True):
+    info = gamg.info()
+    assert info["levels"] == len(H.levels), (info["n"], [L.A.shape[0] for L in H.levels])
+    for l, L in enumerate(H.levels):
+        g = gamg.export_level(l)
+        n = L.A.shape[0]
+        assert info["n"][l] == n
+        arp, aci, av = g["A"]
+        assert np.array_equal(arp, L.A.indptr) and np.array_equal(aci, L.A.indices), l
+        if exact_values:
+            assert np.array_equal(av, L.A.data), (l, np.abs(av - L.A.data).max())
+        else:
+            np.testing.assert_allclose(av, L.A.data, rtol=1e-12, atol=1e-12 * np.abs(L.A.data).max())
+        if L.cf is not None:
+            assert np.array_equal(g["cf"], L.cf), l
+            prp, pci, pv = g["P"]
+            assert np.array_equal(prp, L.P.indptr) and np.array_equal(pci, L.P.indices), l
+            if exact_values:
+                assert np.array_equal(pv, L.P.data), l
+            assert info["pmis_rounds"][l] == L.pmis_rounds
+
+
+@pytest.mark.parametrize("which", ["mono_g1_2d64", "block_E_g2_2d16", "block_g0_3d10",
+                                   "mono_g2_2d16_nonsym"])
+def test_amg_setup_full_chain_bit_exact(ctx, which):
+    api = gpu_modules()
+    if which == "mono_g1_2d64":
+        A = oracle_system(si.generate_workload("g1_2d64")).monolithic()
+    elif which == "block_E_g2_2d16":
+        A = oracle_system(si.generate_workload("g2_2d16")).blocks[2]
+    elif which == "block_g0_3d10":
+        A = oracle_system(si.generate(1, 3, 10, 31)).blocks[0]
+    else:
+        A = oracle_system(si.generate(2, 2, 16, 32, nonsym=True)).monolithic()
+    H = oamg.setup(A, oamg.AMGParams(seed=7))
+    g = api.AMG(ctx, A.indptr, A.indices, A.data, seed=7)
+    _compare_hierarchies(g, H, exact_values=True)
+
+
+def test_amg_levelwise_on_gpu_levels(ctx):
+    """Binding test: the oracle's strength, PMIS and interpolation applied to
+    each GPU level matrix give the GPU's C/F splitting and P bit for bit."""
+    api = gpu_modules()
+    A = oracle_system(si.generate(20, 2, 24, 33)).blocks[5]
+    g = api.AMG(ctx, A.indptr, A.indices, A.data, seed=3)
+    info = g.info()
+    for l in range(info["levels"] - 1):
+        e = g.export_level(l)
+        Al = csr_of(e["A"], info["n"][l])
+        S = oamg.strength(Al, 0.25, 0.9)
+        cf = oamg.pmis(Al, S, 3, l)
+        assert np.array_equal(cf, e["cf"]), l
+        P = oamg.interpolation(Al, S, cf)
+        prp, pci, pv = e["P"]
+        assert np.array_equal(P.indptr, prp) and np.array_equal(P.indices, pci)
+        assert np.array_equal(P.data, pv)
+
+
+def test_amg_edge_cases(ctx):
+    api = gpu_modules()
+    # single row
+    g = api.AMG(ctx, np.array([0, 1]), np.array([0]), np.array([2.0]))
+    z = to_host(g.apply(to_dev(ctx, np.array([3.0]))))
+    assert abs(z[0] - 1.5) < 1e-15
+    # small system: one direct level
+    A = oracle_system(si.generate(1, 2, 5, 3)).monolithic()
+    g = api.AMG(ctx, A.indptr, A.indices, A.data)
+    assert g.info()["levels"] == 1
+    b = np.arange(A.shape[0], dtype=float)
+    z = to_host(g.apply(to_dev(ctx, b)))
+    assert rel(z, spla.spsolve(sp.csc_matrix(A), b)) < 1e-12
+    # strongly dominant rows: stalled coarsening relaxed with Jacobi sweeps
+    n = 3000
+    A = sp.csr_matrix(sp.diags([-np.ones(n - 1), 30 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1]))
+    A.sort_indices()
+    g = api.AMG(ctx, A.indptr, A.indices, A.data)
+    inf = g.info()
+    assert inf["levels"] == 1 and inf["coarse_kind"] == 1
+    H = oamg.setup(A)
+    b = np.ones(n)
+    assert rel(to_host(g.apply(to_dev(ctx, b))), oamg.vcycle(H, b)) < 1e-14
+
+
+def test_amg_rejects_invalid_csr(ctx):
+    api = gpu_modules()
+    from paper_2002_04958_amd._lib import MgdError
+    with pytest.raises(MgdError, match="EINVAL"):  # unsorted columns
+        api.AMG(ctx, np.array([0, 2, 3]), np.array([1, 0, 1]), np.array([1.0, 2.0, 3.0]))
+    with pytest.raises(MgdError, match="EINVAL"):  # missing diagonal
+        api.AMG(ctx, np.array([0, 1, 2]), np.array([1, 0]), np.array([1.0, 2.0]))
+    with pytest.raises(MgdError, match="EINVAL"):  # column out of range
+        api.AMG(ctx, np.array([0, 1, 2]), np.array([0, 5]), np.array([1.0, 2.0]))
+
+
+# ---------------------------------------------------------------------------
+# V-cycle
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("cycles", [1, 3])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_vcycle_parity(ctx, cycles, precision):
+    api = gpu_modules()
+    A = oracle_system(si.generate_workload("g1_2d64")).monolithic()
+    H = oamg.setup(A, oamg.AMGParams(seed=1))
+    g = api.AMG(ctx, A.indptr, A.indices, A.data, seed=1, precision=precision)
+    b = np.random.default_rng(2).uniform(size=A.shape[0])
+    z = to_host(g.apply(to_dev(ctx, b), cycles=cycles))
+    ref = oamg.apply_cycles(H, b, cycles)
+    assert rel(z, ref) < (1e-12 if precision == 0 else 2e-5)
+
+
+def test_vcycle_n_pre_n_post(ctx):
+    api = gpu_modules()
+    A = oracle_system(si.generate(1, 2, 20, 9)).blocks[0]
+    for pre, post in ((2, 1), (0, 2), (1, 0)):
+        H = oamg.setup(A, oamg.AMGParams(seed=2, n_pre=pre, n_post=post))
+        g = api.AMG(ctx, A.indptr, A.indices, A.data, seed=2, n_pre=pre, n_post=post)
+        b = np.random.default_rng(3).uniform(size=A.shape[0])
+        assert rel(to_host(g.apply(to_dev(ctx, b))), oamg.vcycle(H, b)) < 1e-12, (pre, post)
+
+
+# ---------------------------------------------------------------------------
+# block preconditioners
+# ---------------------------------------------------------------------------
+KINDS = ["amg", "bdiag", "pctl", "schur1", "schur2", "schur2_lower"]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("mode", ["seq", "batched", "batched_graph"])
+def test_block_preconditioner_parity(ctx, kind, mode):
+    api = gpu_modules()
+    inp = si.generate(3, 2, 16, 41)
+    osys = oracle_system(inp)
+    M_o = opc.BlockPreconditioner(osys, opc.BlockParams(kind=kind, amg=oamg.AMGParams(seed=5)))
+    co, gsys = gpu_system(ctx, inp)
+    M_g = api.BlockPreconditioner(ctx, gsys, kind, amg_seed=5, batched=int(mode != "seq"),
+                                  use_graph=int(mode == "batched_graph"))
+    r = np.random.default_rng(4).standard_normal(osys.n)
+    rd = to_dev(ctx, r)
+    z = to_host(M_g.apply(rd))
+    ref = M_o(r)
+    assert rel(z, ref) < 1e-10, rel(z, ref)
+    z2 = to_host(M_g.apply(rd))             # replay (graph) / second call
+    assert np.array_equal(z, z2)
+    info = M_g.info()
+    G = inp.G
+    exp_inv = {"amg": 1, "bdiag": G + 2, "pctl": G + 3, "schur1": G + 4, "schur2": G + 3,
+               "schur2_lower": G + 2}[kind]
+    assert info["inverses_per_apply"] == exp_inv
+    assert info["matvecs_per_apply"] == (G + 2 if kind == "pctl" else 0)
+    if kind == "pctl":
+        assert info["pctl_p_cycles"] == M_o.setup_info["p_cycles"]
+
+
+# ---------------------------------------------------------------------------
+# GMRES
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", ["amg", "schur2", "schur1", "pctl"])
+def test_gmres_parity(ctx, kind):
+    api = gpu_modules()
+    inp = si.generate_workload("g1_2d64")
+    osys = oracle_system(inp)
+    A = osys.monolithic()
+    M_o = opc.BlockPreconditioner(osys, opc.BlockParams(kind=kind, amg=oamg.AMGParams(seed=1)))
+    xo, io = okry.gmres(A.__matmul__, M_o, inp.b, rtol=1e-8)
+    co, gsys = gpu_system(ctx, inp)
+    M_g = api.BlockPreconditioner(ctx, gsys, kind, amg_seed=1)
+    b = to_dev(ctx, inp.b)
+    xg, rg = api.gmres(ctx, gsys, M_g, b, rtol=1e-8)
+    assert rg.converged and io.converged
+    assert abs(rg.iters - io.iters) <= 1, (rg.iters, io.iters)
+    xg = to_host(xg)
+    assert np.linalg.norm(inp.b - A @ xg) <= 1e-8 * np.linalg.norm(inp.b)
+    # same number of iterations: solutions agree to 1e-10
+    xo2, _ = okry.gmres(A.__matmul__, M_o, inp.b, rtol=0.0, max_iters=io.iters)
+    xg2, r2 = api.gmres(ctx, gsys, M_g, b, rtol=0.0, max_iters=io.iters)
+    assert r2.status == -4 and r2.iters == io.iters
+    assert rel(to_host(xg2), xo2) < 1e-10
+
+
+def test_gmres_no_preconditioner_and_nonflexible(ctx):
+    api = gpu_modules()
+    inp = si.generate(1, 2, 12, 5)
+    osys = oracle_system(inp)
+    A = osys.monolithic()
+    co, gsys = gpu_system(ctx, inp)
+    b = to_dev(ctx, inp.b)
+    xg, rg = api.gmres(ctx, gsys, None, b, rtol=1e-10, max_iters=2000)
+    xo, io = okry.gmres(A.__matmul__, None, inp.b, rtol=1e-10, max_iters=2000)
+    assert rg.converged and abs(rg.iters - io.iters) <= 1
+    M_g = api.BlockPreconditioner(ctx, gsys, "schur2")
+    M_o = opc.BlockPreconditioner(osys, opc.BlockParams(kind="schur2"))
+    xg, rg = api.gmres(ctx, gsys, M_g, b, rtol=1e-10, flexible=0)
+    xo, io = okry.gmres(A.__matmul__, M_o, inp.b, rtol=1e-10, flexible=False)
+    assert rg.converged and abs(rg.iters - io.iters) <= 1
+    assert rel(to_host(xg), xo) < 1e-8
+
+
+def test_gmres_edge_cases(ctx):
+    api = gpu_modules()
+    import torch
+    inp = si.generate(1, 2, 8, 5)
+    co, gsys = gpu_system(ctx, inp)
+    M = api.BlockPreconditioner(ctx, gsys, "schur2")
+    x, r = api.gmres(ctx, gsys, M, ctx.zeros(gsys.n))
+    assert r.converged and r.iters == 0 and float(torch.abs(x).max()) == 0.0
+    x, r = api.gmres(ctx, gsys, M, to_dev(ctx, inp.b), max_iters=1, rtol=1e-14)
+    assert r.status == -4 and not r.converged and r.iters == 1
+
+
+# ---------------------------------------------------------------------------
+# FP32 hierarchy inside FP64 FGMRES
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", ["schur2", "schur1", "amg"])
+def test_fp32_vcycle_fgmres(ctx, kind):
+    api = gpu_modules()
+    inp = si.generate(4, 2, 32, 51)
+    osys = oracle_system(inp)
+    A = osys.monolithic()
+    xs = spla.spsolve(sp.csc_matrix(A), inp.b)
+    co, gsys = gpu_system(ctx, inp)
+    M = api.BlockPreconditioner(ctx, gsys, kind, amg_precision=1, batched=1, use_graph=1)
+    xg, r = api.gmres(ctx, gsys, M, to_dev(ctx, inp.b), rtol=1e-8)
+    assert r.converged
+    xg = to_host(xg)
+    assert np.linalg.norm(inp.b - A @ xg) <= 1e-8 * np.linalg.norm(inp.b)
+    assert rel(xg, xs) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+def test_adjoint_parity(ctx):
+    api = gpu_modules()
+    from oracle import adjoint as oadj
+    inp = si.generate_workload("g2_2d16")
+    osys = oracle_system(inp)
+    A = osys.monolithic()
+    x = spla.spsolve(sp.csc_matrix(A), inp.b)
+    g = x - inp.x_target
+    lam_o, (dk_o, dgE_o, dEg_o, dEI_o) = oadj.adjoint_direct(inp, osys, x, g)
+    co, gsys = gpu_system(ctx, inp)
+    MT = api.BlockPreconditioner(ctx, gsys, "schur2", transpose=1)
+    lam, dk, dc, r = api.adjoint(ctx, co, gsys, MT, to_dev(ctx, x), to_dev(ctx, g), rtol=1e-13)
+    assert r.converged
+    assert rel(to_host(lam), lam_o) < 1e-10
+    G, N = inp.G, inp.N
+    dc = to_host(dc)
+    assert rel(to_host(dk), dk_o.reshape(-1)) < 1e-9
+    assert rel(dc[:G * N], dgE_o.reshape(-1)) < 1e-9
+    assert rel(dc[G * N:2 * G * N], dEg_o.reshape(-1)) < 1e-9
+    assert rel(dc[2 * G * N:], dEI_o) < 1e-9
+
+
+def test_transposed_system(ctx):
+    inp = si.generate(2, 2, 9, 61, nonsym=True)
+    osys = oracle_system(inp)
+    co, gsys = gpu_system(ctx, inp)
+    gt = gsys.transpose()
+    x = np.random.default_rng(1).standard_normal(osys.n)
+    y = to_host(gt.matvec(to_dev(ctx, x)))
+    assert rel(y, osys.monolithic().T @ x) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# determinism
+# ---------------------------------------------------------------------------
+def test_bitwise_determinism(ctx):
+    api = gpu_modules()
+    inp = si.generate(3, 2, 24, 71)
+    outs = []
+    for _ in range(2):
+        co, gsys = gpu_system(ctx, inp)
+        M = api.BlockPreconditioner(ctx, gsys, "schur2", batched=1)
+        x, r = api.gmres(ctx, gsys, M, to_dev(ctx, inp.b), rtol=1e-9)
+        outs.append((to_host(x), r.iters))
+    assert outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][0], outs[1][0])
