@@ -196,13 +196,13 @@ mgd_status mgd_block_system_free(mgd_ctx* ctx, mgd_block_system* s);
 /* ---------------------------------------------------------------------------
  * Block preconditioners (Section 3).  apply computes z = M^{-1} r.
  *   AMG_MONO     one hierarchy on the monolithic matrix (Section 3.1)
- *   BLOCK_DIAG   A_1..A_G, A_E, A_I inverted independently (Section 3.6 remark)
+ *   BLOCK_DIAG   A_1..A_G, A_E, A_I inverted independently (Section 3.5 remark)
  *   PCTL         block relaxation E, then groups and I, then the coarse
- *                correction with A_c of eq. 3.3 (Section 3.3); the diagonal
+ *                correction with A_c of eq. 3.1 (Section 3.2); the diagonal
  *                interpolation weights come from V-cycles run to pctl_p_tol
- *   SCHUR1       five steps with C^_E, C^_g and A_I (Sections 3.4, 3.5)
- *   SCHUR2       three steps with A_E, S^_g and S^_I (Sections 3.4, 3.5)
- *   SCHUR2_LOWER Schur2 steps 1-2: the elimination factor of eq. 3.2
+ *   SCHUR1       five steps with C^_E, C^_g and A_I (Sections 3.3, 3.4)
+ *   SCHUR2       three steps with A_E, S^_g and S^_I (Sections 3.3, 3.4)
+ *   SCHUR2_LOWER Schur2 steps 1-2: the elimination factor of eq. 3.3
  *   IDENTITY     z = r
  * Each scalar inverse is a fixed number of V-cycles (option #2 of Section
  * 3.5): cycles_rad for group blocks, cycles_E for E blocks (and A_c),

@@ -443,7 +443,7 @@ def apply_cycles(H: Hierarchy, b: np.ndarray, k: int = 1) -> np.ndarray:
 
 def solve_to_tolerance(H: Hierarchy, b: np.ndarray, rtol: float,
                        max_cycles: int = 100):
-    """V-cycles until ||b - A z|| < rtol ||b|| (option #3 of Section 3.5).
+    """V-cycles until ||b - A z|| < rtol ||b|| (option #3 of Section 3.4).
     Returns (z, cycles)."""
     nb = np.linalg.norm(b)
     z = np.zeros_like(b)

@@ -3,20 +3,20 @@
 Each preconditioner acts as w = M^{-1} b on a Krylov vector b of length
 (G+2) N ordered [groups..., E, I].  The scalar inverses inside are
 "Inverse" objects; the paper's practical form uses a fixed number of AMG
-V-cycles (option #2 of Section 3.5) on:
+V-cycles (option #2 of Section 3.4) on:
 
   monolithic   one hierarchy on the whole matrix (Section 3.1)
-  bdiag        A_1..A_G, A_E, A_I (block-diagonal special case, Section 3.6)
-  pctl         A_1..A_G, A_E, A_I for the block relaxation and A_c of eq. 3.3
-               for the coarse correction (Section 3.3); the diagonal
+  bdiag        A_1..A_G, A_E, A_I (block-diagonal special case, Section 3.5)
+  pctl         A_1..A_G, A_E, A_I for the block relaxation and A_c of eq. 3.1
+               for the coarse correction (Section 3.2); the diagonal
                interpolation weights p_g = -A_g^{-1} D_gE 1, p_I = -A_I^{-1} D_IE 1
                are computed by V-cycles to a relative residual below
                pctl_p_tol (option #3)
-  schur1       A_I, C^_E, C^_g (Section 3.4, five steps; Section 3.5 hats)
-  schur2       A_E, S^_g, S^_I (Section 3.4, three steps; Section 3.5 hats)
-  schur2_lower Schur2 steps 1-2 only (the elimination factor of eq. 3.2)
+  schur1       A_I, C^_E, C^_g (Section 3.3, five steps; Section 3.4 hats)
+  schur2       A_E, S^_g, S^_I (Section 3.3, three steps; Section 3.4 hats)
+  schur2_lower Schur2 steps 1-2 only (the elimination factor of eq. 3.3)
 
-Diagonal ("hat") approximations of Section 3.5, each one entry update per
+Diagonal ("hat") approximations of Section 3.4, each one entry update per
 row, evaluated as t = (d1 * d2) / diag, new = a_ii - t:
   S^_g = A_g - D_gE diag(A_E)^-1 D_Eg       S^_I = A_I - D_IE diag(A_E)^-1 D_EI
   C^_E = A_E - D_EI diag(A_I)^-1 D_IE       C^_g = A_g - D_gE diag(C^_E)^-1 D_Eg
@@ -76,7 +76,7 @@ def amg_inverse(M, params: amg.AMGParams, cycles: int, counters: Counters,
 
 
 def exact_inverse(M, counters: Counters) -> Inverse:
-    """Direct sparse LU: for the exactness tests of Section 3.4."""
+    """Direct sparse LU: for the exactness tests of Section 3.3."""
     lu = spla.splu(sp.csc_matrix(M))
     return Inverse(M, lambda b: lu.solve(b), counters)
 
@@ -123,7 +123,7 @@ def hatted(sys: BlockSystem, kind: str):
 
 
 def pctl_coarse(sys: BlockSystem, p: np.ndarray, pI: np.ndarray) -> sp.csr_matrix:
-    """A_c of eq. 3.3 on the shared stencil pattern.  Entry order:
+    """A_c of eq. 3.1 on the shared stencil pattern.  Entry order:
     a^E_ij, then (p_g,i a^g_ij) p_g,j for g ascending, then the ion term,
     then on the diagonal d_Eg p_g and p_g d_gE for g ascending, d_EI p_I,
     p_I d_IE."""

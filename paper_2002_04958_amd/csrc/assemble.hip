@@ -166,6 +166,16 @@ void assemble_impl(Ctx* c, const mgd_coeffs* cf, mgd_block_system* out) {
   hipLaunchKernelGGL(k_pattern_fill, dim3(cdiv(N, 256)), dim3(256), 0, c->stream, N, n, dim,
                      (const int*)os->rp.get(), os->ci.get());
   MGD_CHECK_LAUNCH();
+  {
+    Csr<double> pat;  // structure check of the shared stencil pattern
+    pat.n_rows = pat.n_cols = N;
+    pat.nnz = nnz;
+    pat.rp = std::move(os->rp);
+    pat.ci = std::move(os->ci);
+    check_structure(c, pat, "assembled stencil pattern", true);
+    os->rp = std::move(pat.rp);
+    os->ci = std::move(pat.ci);
+  }
   std::vector<double*> vp(G + 2);
   os->vals.resize(G + 2);
   for (int a = 0; a < G + 2; ++a) {

@@ -1,6 +1,6 @@
 // Block preconditioners of Section 3: monolithic AMG, block-diagonal, PCTL
-// (Section 3.3, coarse operator eq. 3.3), Schur1 and Schur2 (Section 3.4)
-// with the diagonal Schur-complement approximations of Section 3.5, and the
+// (Section 3.2, coarse operator eq. 3.1), Schur1 and Schur2 (Section 3.3)
+// with the diagonal Schur-complement approximations of Section 3.4, and the
 // elimination-only factor of Schur2.  The independent scalar V-cycles of a
 // step run either as one batched set of launches over a union of
 // hierarchies or one hierarchy after another.
@@ -157,7 +157,7 @@ __global__ void k_get_diag(int n, const int* __restrict__ rp, const int* __restr
   d[i] = x;
 }
 
-// eq. 3.3 on the shared pattern
+// eq. 3.1 on the shared pattern
 __global__ void k_pctl_coarse(int G, int N, BlockSysDev S, const double* __restrict__ p,
                               double* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -591,6 +591,7 @@ static void copy_system(block_precond* bp, const mgd_block_system* A) {
     } else {
       csr_copy_from(c, &A->blocks[a], bp->blocks[a]);
     }
+    check_structure(c, bp->blocks[a], "copied diagonal block", true);
   }
   bp->d_gE.alloc(c, (size_t)G * N);
   bp->d_Eg.alloc(c, (size_t)G * N);
@@ -732,7 +733,7 @@ block_precond* block_precond_create_impl(Ctx* c, const mgd_block_system* A, cons
       make_hierarchy(bp.get(), G + 1, hat(c, B[G + 1], bp->d_IE.get(), bp->d_EI.get(), dE.get()));
     }
     if (kind == MGD_PC_PCTL) {
-      // all blocks must share A_E's pattern for eq. 3.3
+      // all blocks must share A_E's pattern for eq. 3.1
       DBuf<int> diff(c, 1);
       fill<int>(c, diff.get(), 0, 1);
       for (int a = 0; a < G + 2; ++a) {

@@ -125,6 +125,7 @@ void Ctx::prof_collect() {
   pending.clear();
 }
 Ctx::~Ctx() {
+  if (dev_err) dfree(dev_err);
   for (auto& p : pending) {
     hipEventDestroy(p.a);
     hipEventDestroy(p.b);
@@ -143,7 +144,8 @@ void check_csr_meta(const mgd_csr* A, bool square) {
 }
 
 __global__ void k_validate(int n, int ncols, long long nnz, const int* __restrict__ rp,
-                           const int* __restrict__ ci, int require_diag, int* __restrict__ bad) {
+                           const int* __restrict__ ci, int flags, int* __restrict__ bad) {
+  const int require_diag = flags & 1, unsorted = flags & 2;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int e0 = rp[i], e1 = rp[i + 1];
@@ -157,25 +159,68 @@ __global__ void k_validate(int n, int ncols, long long nnz, const int* __restric
   for (int e = e0; e < e1; ++e) {
     const int j = ci[e];
     if (j < 0 || j >= ncols) atomicOr(bad, 2);
-    if (e > e0 && ci[e - 1] >= j) atomicOr(bad, 4);
+    if (!unsorted && e > e0 && ci[e - 1] >= j) atomicOr(bad, 4);
     if (j == i) diag = true;
   }
   if (require_diag && !diag) atomicOr(bad, 8);
 }
 
-void validate_csr_device(Ctx* c, const mgd_csr* A, bool require_diag) {
-  if (A->n_rows == 0) return;
+static int csr_check_bits(Ctx* c, int n_rows, int n_cols, long long nnz, const int* rp,
+                          const int* ci, bool require_diag, bool unsorted = false) {
+  if (n_rows == 0) return 0;
   DBuf<int> bad(c, 1);
   fill<int>(c, bad.get(), 0, 1);
-  hipLaunchKernelGGL(k_validate, dim3(cdiv(A->n_rows, 256)), dim3(256), 0, c->stream, A->n_rows,
-                     A->n_cols, (long long)A->nnz, A->row_ptr, A->col_idx, require_diag ? 1 : 0,
-                     bad.get());
+  hipLaunchKernelGGL(k_validate, dim3(cdiv(n_rows, 256)), dim3(256), 0, c->stream, n_rows, n_cols,
+                     nnz, rp, ci, (require_diag ? 1 : 0) | (unsorted ? 2 : 0), bad.get());
   MGD_CHECK_LAUNCH();
-  const int b = read1(c, bad.get());
-  if (b & 1) fail(MGD_EINVAL, "row_ptr is not a monotone [0, nnz] sequence");
-  if (b & 2) fail(MGD_EINVAL, "column index out of range");
-  if (b & 4) fail(MGD_EINVAL, "columns not strictly ascending within a row");
-  if (b & 8) fail(MGD_EINVAL, "a row does not store its diagonal entry");
+  return read1(c, bad.get());
+}
+
+static std::string check_message(int b) {
+  std::string m;
+  if (b & 1) m += " row_ptr is not a monotone [0, nnz] sequence;";
+  if (b & 2) m += " column index out of range;";
+  if (b & 4) m += " columns not strictly ascending within a row;";
+  if (b & 8) m += " a row does not store its diagonal entry;";
+  return m;
+}
+
+void validate_csr_device(Ctx* c, const mgd_csr* A, bool require_diag) {
+  const int b = csr_check_bits(c, A->n_rows, A->n_cols, (long long)A->nnz, A->row_ptr, A->col_idx,
+                               require_diag);
+  if (b) fail(MGD_EINVAL, "invalid CSR:" + check_message(b));
+}
+
+template <typename V>
+void check_structure(Ctx* c, const Csr<V>& A, const char* what, bool require_diag) {
+  const int b = csr_check_bits(c, A.n_rows, A.n_cols, A.nnz, A.rp.get(), A.ci.get(), require_diag);
+  if (b) fail(MGD_EHIP, std::string("internal structure check failed for ") + what + ":" + check_message(b));
+}
+template void check_structure<double>(Ctx*, const Csr<double>&, const char*, bool);
+
+void check_index_structure(Ctx* c, int n_rows, int n_cols, long long nnz, const int* rp,
+                           const int* ci, const char* what) {
+  const int b = csr_check_bits(c, n_rows, n_cols, nnz, rp, ci, false, true);
+  if (b) fail(MGD_EHIP, std::string("internal structure check failed for ") + what + ":" + check_message(b));
+}
+template void check_structure<float>(Ctx*, const Csr<float>&, const char*, bool);
+
+int* Ctx::err_flag() {
+  if (!dev_err) {
+    dev_err = static_cast<int*>(dmalloc(sizeof(int)));
+    fill<int>(this, dev_err, 0, 1);
+  }
+  return dev_err;
+}
+
+void Ctx::check_device_errors(const char* where) {
+  if (!dev_err) return;
+  const int e = read1(this, dev_err);
+  if (e) {
+    fill<int>(this, dev_err, 0, 1);
+    sync();
+    fail(MGD_EHIP, std::string("device bounds check failed in ") + where + " (code " + std::to_string(e) + ")");
+  }
 }
 
 void check_block_system(const mgd_block_system* A) {
@@ -350,6 +395,7 @@ mgd_status amg_setup(mgd_ctx* ctx, const mgd_csr* A, const amg_params* p, amg_hi
     h->n = A->n_rows;
     Csr<double> M;
     csr_copy_from(ctx, A, M);
+    check_structure(ctx, M, "copied input matrix", true);
     amg_build(ctx, std::move(M), h->prm, h->H);
     if (p->precision == 0)
       h->union64();

@@ -77,6 +77,7 @@ struct Ctx {
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> event_pool;
+  int* dev_err = nullptr;  // set by in-kernel bounds checks
   int64_t launches[KC_COUNT] = {};
   double ms[KC_COUNT] = {};
   double bytes[KC_COUNT] = {};
@@ -86,6 +87,8 @@ struct Ctx {
   void* host_stage(size_t bytes);  // pinned buffer of at least `bytes`
   void sync() { MGD_HIP(hipStreamSynchronize(stream)); }
   void make_current() { MGD_HIP(hipSetDevice(device)); }
+  int* err_flag();                           // device int, zero until a check fails
+  void check_device_errors(const char* where);  // synchronises; throws when set
   // profiling hooks
   hipEvent_t take_event();
   void prof_begin(int cls, hipEvent_t* a);
@@ -159,10 +162,12 @@ inline void copy_h2d(Ctx* c, T* d, const T* h, size_t n) {
   MGD_HIP(hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, c->stream));
   c->sync();
 }
+// Device-to-device copies run as a library kernel on the context stream.
+void device_copy(Ctx* c, void* dst, const void* src, size_t bytes);
 template <typename T>
 inline void copy_d2d(Ctx* c, T* d, const T* s, size_t n) {
   if (!n) return;
-  MGD_HIP(hipMemcpyAsync(d, s, n * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+  device_copy(c, d, s, n * sizeof(T));
 }
 // Read a single device value (synchronises).
 template <typename T>
@@ -205,6 +210,16 @@ inline CsrView<V> view(const Csr<V>& a) {
 }
 
 inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// Structural check of an internal CSR on the device (row_ptr monotone in
+// [0, nnz], columns in range and strictly ascending, diagonal when asked);
+// throws MGD_EHIP naming `what` when a library-built structure is malformed.
+template <typename V>
+void check_structure(Ctx* c, const Csr<V>& A, const char* what, bool require_diag);
+
+// Same for an index structure whose rows need not be sorted.
+void check_index_structure(Ctx* c, int n_rows, int n_cols, long long nnz, const int* rp,
+                           const int* ci, const char* what);
 
 // Validate a caller CSR (host-side metadata only; device contents are
 // trusted to be sorted as documented, and checked by validate_csr_device).

@@ -94,13 +94,16 @@ __global__ void k_pmis_init(int n, const int* __restrict__ stc, uint64_t seed, i
 
 __global__ void k_st_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                           const uint8_t* __restrict__ S, int* __restrict__ fillpos,
-                          int* __restrict__ st_ci) {
+                          int* __restrict__ st_ci, int cap, int* __restrict__ err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   for (int e = rp[i]; e < rp[i + 1]; ++e)
     if (S[e]) {
       const int p = atomicAdd(&fillpos[ci[e]], 1);
-      st_ci[p] = i;
+      if (p >= 0 && p < cap)
+        st_ci[p] = i;
+      else
+        atomicOr(err, 1);
     }
 }
 
@@ -180,8 +183,10 @@ int pmis(Ctx* c, const Csr<double>& A, const DBuf<uint8_t>& S, const DBuf<int>& 
   DBuf<int> st_ci(c, (size_t)std::max(nst, 1));
   copy_d2d(c, fillpos.get(), st_rp.get(), (size_t)n);
   hipLaunchKernelGGL(k_st_fill, dim3(g), dim3(256), 0, c->stream, n, A.rp.get(), A.ci.get(),
-                     S.get(), fillpos.get(), st_ci.get());
+                     S.get(), fillpos.get(), st_ci.get(), nst, c->err_flag());
   MGD_CHECK_LAUNCH();
+  c->check_device_errors("transposed strength graph");
+  check_index_structure(c, n, n, nst, st_rp.get(), st_ci.get(), "transposed strength graph");
   fill<int>(c, remaining.get(), 0, 1);
   hipLaunchKernelGGL(k_count_undecided, dim3(g), dim3(256), 0, c->stream, n, state.get(),
                      remaining.get());
@@ -346,11 +351,16 @@ __global__ void k_count_cols(int nnz, const int* __restrict__ ci, int* __restric
 }
 __global__ void k_transpose_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                  const double* __restrict__ v, int* __restrict__ fillpos,
-                                 int* __restrict__ tci, double* __restrict__ tv) {
+                                 int* __restrict__ tci, double* __restrict__ tv, int cap,
+                                 int* __restrict__ err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   for (int e = rp[i]; e < rp[i + 1]; ++e) {
     const int p = atomicAdd(&fillpos[ci[e]], 1);
+    if (p < 0 || p >= cap) {
+      atomicOr(err, 1);
+      continue;
+    }
     tci[p] = i;
     tv[p] = v[e];
   }
@@ -393,13 +403,15 @@ void transpose(Ctx* c, const Csr<double>& A, Csr<double>& T) {
   if (A.n_rows)
     hipLaunchKernelGGL(k_transpose_fill, dim3(cdiv(A.n_rows, 256)), dim3(256), 0, c->stream,
                        A.n_rows, A.rp.get(), A.ci.get(), A.v.get(), fillpos.get(), T.ci.get(),
-                       T.v.get());
+                       T.v.get(), A.nnz, c->err_flag());
   MGD_CHECK_LAUNCH();
+  c->check_device_errors("transpose");
   if (T.n_rows)
-    hipLaunchKernelGGL(k_sort_rows, dim3(cdiv(T.n_rows, 256)), dim3(256), 0, c->stream, T.n_rows,
+      hipLaunchKernelGGL(k_sort_rows, dim3(cdiv(T.n_rows, 256)), dim3(256), 0, c->stream, T.n_rows,
                        T.rp.get(), T.ci.get(), T.v.get());
   MGD_CHECK_LAUNCH();
   c->sync();
+  check_structure(c, T, "transpose", false);
 }
 
 // ---------------------------------------------------------------------------
@@ -641,9 +653,12 @@ void amg_build(Ctx* c, Csr<double>&& A0, const amg_params& p, SetupHierarchy& H)
     }
     Csr<double> P, R, AP, Ac;
     interpolation(c, A, S, state, cidx, nc, P);
+    check_structure(c, P, "interpolation", false);
     transpose(c, P, R);
     spgemm(c, A, P, AP);
+    check_structure(c, AP, "A P", false);
     spgemm(c, R, AP, Ac);
+    check_structure(c, Ac, "coarse operator", true);
     L.A = std::move(A);
     L.cf = std::move(state);
     L.P = std::move(P);

@@ -217,6 +217,8 @@ std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHiera
       }
     }
     c->sync();
+    check_structure(c, Ad, "union level matrix", false);
+    check_structure(c, Wd, "union interpolation", false);
     if (ncoarse > 0) transpose(c, Wd, Wtd);
     // nnz split between the C-block and the F-block (for byte accounting)
     if (nS > 0) {

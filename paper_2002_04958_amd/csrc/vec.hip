@@ -116,6 +116,33 @@ int exclusive_scan_total(Ctx* c, const int* in, int* out, int n) {
 }
 
 // ---------------------------------------------------------------------------
+// device copy
+// ---------------------------------------------------------------------------
+__global__ void k_copy_words(uint32_t* __restrict__ d, const uint32_t* __restrict__ s, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+__global__ void k_copy_bytes(uint8_t* __restrict__ d, const uint8_t* __restrict__ s, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+void device_copy(Ctx* c, void* dst, const void* src, size_t bytes) {
+  if (!bytes) return;
+  const bool words = bytes % 4 == 0 && ((uintptr_t)dst % 4) == 0 && ((uintptr_t)src % 4) == 0;
+  const size_t n = words ? bytes / 4 : bytes;
+  const int g = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 8192);
+  if (words)
+    hipLaunchKernelGGL(k_copy_words, dim3(g), dim3(kBlock), 0, c->stream, (uint32_t*)dst,
+                       (const uint32_t*)src, n);
+  else
+    hipLaunchKernelGGL(k_copy_bytes, dim3(g), dim3(kBlock), 0, c->stream, (uint8_t*)dst,
+                       (const uint8_t*)src, n);
+  MGD_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
 // fill / cast
 // ---------------------------------------------------------------------------
 template <typename T>

@@ -84,7 +84,7 @@ def _dense_inv(M):
 
 def _exact_schur_preconditioner(sysm, kind):
     """The oracle's Schur1/Schur2 steps driven by exact inverses of the exact
-    Schur complements of Section 3.4: C_E, C~_g, A_I (Schur1) or A_E, S~_g,
+    Schur complements of Section 3.3: C_E, C~_g, A_I (Schur1) or A_E, S~_g,
     S_I (Schur2)."""
     G = sysm.G
     A = [B.toarray() for B in sysm.blocks]
@@ -111,7 +111,7 @@ def _exact_schur_preconditioner(sysm, kind):
 
 
 def test_schur1_exact_for_one_group():
-    """Section 3.4: with G = 1 the Schur1 error block set is empty."""
+    """Section 3.3: with G = 1 the Schur1 error block set is empty."""
     inp, sysm = _tiny(1)
     Mi = _exact_schur_preconditioner(sysm, "schur1")
     A = sysm.monolithic().toarray()
@@ -169,7 +169,7 @@ def test_table1_operation_counts(kind, G, inv, mv):
 
 
 def test_pctl_coarse_operator_is_galerkin():
-    """eq. 3.3 equals P^T A P with P = [diag(p_1); ...; I; diag(p_I)], and
+    """eq. 3.1 equals P^T A P with P = [diag(p_1); ...; I; diag(p_I)], and
     A_c has A_E's pattern."""
     inp, sysm = _tiny(3)
     M = precond.BlockPreconditioner(sysm, precond.BlockParams(kind="pctl"))
@@ -184,7 +184,7 @@ def test_pctl_coarse_operator_is_galerkin():
 
 def test_pctl_p_vectors_meet_tolerance():
     """Option #3: ||A_g p_g + D_gE 1|| < tol ||D_gE 1|| (constants interpolated
-    to the prescribed accuracy, Section 3.3)."""
+    to the prescribed accuracy, Section 3.2)."""
     inp, sysm = _tiny(2, n=20)
     tol = 1e-2
     M = precond.BlockPreconditioner(sysm, precond.BlockParams(kind="pctl", pctl_p_tol=tol))
@@ -221,7 +221,7 @@ def test_pctl_operator_with_exact_inverses():
 
 
 def test_zero_coupling_reduces_to_block_diagonal():
-    """Section 3.6 remark: without couplings every block preconditioner is
+    """Section 3.5 remark: without couplings every block preconditioner is
     the block-diagonal one."""
     inp = si.generate(2, 2, 10, 41)
     inp.c_gE[:] = 0
