@@ -39,7 +39,7 @@ def cpu_baseline(name: str, budget_s: float = 20.0):
     from oracle import precond as opc
 
     w = si.WORKLOADS[name]
-    n_sample = {3: 16, 2: 96}[w.dim]
+    n_sample = {3: 28, 2: 192}[w.dim]
     inp = si.generate(w.G, w.dim, n_sample, w.seed)
     t0 = time.perf_counter()
     sysm = oasm.assemble(inp)
@@ -69,6 +69,10 @@ def main():
     ap.add_argument("--workload", default="g20_3d64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--counters-run", action="store_true",
+                    help="short run for hardware-counter passes: a 256 MiB streaming "
+                         "calibration kernel (torch mul, 256 MiB read + 256 MiB written), "
+                         "then the FP32 batched setup and --steps solves; no timing lines")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is designed but "
@@ -103,6 +107,20 @@ def main():
         x = torch.zeros_like(b)
         x, r = api.gmres(ctx, sysg, M, b, x, rtol=1e-8, flexible=1)
         return x, r
+
+    if a.counters_run:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=ctx.device)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        M32, _ = build(True, True, True)
+        for _ in range(max(1, a.steps)):
+            x, r = solve(M32)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "counters", "workload": w.name, "iters": r.iters,
+                          "calibration_bytes": {"read": 256 << 20, "written": 256 << 20}}))
+        return
 
     # headline form: FP32 hierarchies, batched V-cycles, graph replay
     M32, setup32 = build(True, True, True)
@@ -140,17 +158,21 @@ def main():
         log(f"[bench] fp64 plain: {t64 * 1e3:.1f} ms/solve, iters {r64.iters}")
         del M64
 
-    # per-kernel-class timing pass (events around each launch; no graph)
+    # per-kernel timing pass: HIP events on the context stream around every
+    # launch of one solve (no graph), algorithmic bytes from the hierarchy
     ctx.reset_kernel_stats()
     ctx.set_profiling(True)
     solve(M32)
     ctx.set_profiling(False)
     stats = ctx.kernel_stats()
-    dom = max(stats, key=lambda k: stats[k]["ms"])
-    s = stats[dom]
+    syms = ctx.kernel_symbol_stats()
+    dom = max(syms, key=lambda k: syms[k]["ms"])
+    s = syms[dom]
     achieved = (s["bytes"] / 1e9) / (s["ms"] / 1e3) if s["ms"] > 0 else 0.0
     log("[bench] kernel classes: " + ", ".join(
         f"{k}={v['ms']:.1f}ms/{v['launches']}" for k, v in stats.items() if v["launches"]))
+    log("[bench] kernels: " + ", ".join(
+        f"{k}={v['ms']:.1f}ms/{v['launches']}" for k, v in sorted(syms.items(), key=lambda kv: -kv[1]["ms"])))
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -158,7 +180,7 @@ def main():
         cpu = cpu_baseline(w.name)
 
     out = {
-        "metric": "time to rtol 1e-8 (s), G=20, FP32-AMG batched",
+        "metric": "time to rtol 1e-8 (s) & SpMV HBM GB/s, G=20; FP32-AMG batched vs FP64 plain",
         "value": ms_step / 1e3,
         "unit": "s",
         "n_gpus": 1,
@@ -178,10 +200,14 @@ def main():
         "setup_s": setup32,
         "plain_fp64": plain,
         "speedup_vs_plain_fp64": (plain["s"] / (ms_step / 1e3)) if plain else None,
-        "roofline": {"bound": "hbm", "kernel_class": dom, "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None,
-                     "launches": s["launches"], "avg_launch_us": 1e3 * s["ms"] / max(1, s["launches"])},
+                     "traffic": None, "launches": s["launches"],
+                     "avg_launch_us": 1e3 * s["ms"] / max(1, s["launches"]),
+                     "bytes_per_launch": s["bytes"] / max(1, s["launches"])},
+        "kernels": {k: {"ms": v["ms"], "launches": v["launches"],
+                        "GB/s": (v["bytes"] / 1e9) / (v["ms"] / 1e3) if v["ms"] else 0.0}
+                    for k, v in syms.items()},
         "kernel_classes": {k: {"ms": v["ms"], "launches": v["launches"],
                                "GB/s": (v["bytes"] / 1e9) / (v["ms"] / 1e3) if v["ms"] else 0.0}
                            for k, v in stats.items() if v["launches"]},

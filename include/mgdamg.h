@@ -79,6 +79,14 @@ int mgd_kernel_class_count(void);
 const char* mgd_kernel_class_name(int cls);
 mgd_status mgd_ctx_kernel_stats(mgd_ctx* ctx, int cls, int64_t* launches, double* total_ms,
                                 double* total_bytes);
+/* The same statistics per kernel symbol, for the launches that a profiling
+ * scope times alone (the V-cycle kernels, SpMV and the block matvec).  Names
+ * are the kernel's name with its template arguments as a demangler prints
+ * them, e.g. "k_half<float, 1>".  mgd_ctx_kernel_symbol_count synchronises;
+ * name receives at most name_cap-1 characters and a terminating zero. */
+mgd_status mgd_ctx_kernel_symbol_count(mgd_ctx* ctx, int* count);
+mgd_status mgd_ctx_kernel_symbol_stats(mgd_ctx* ctx, int index, char* name, int name_cap,
+                                       int64_t* launches, double* total_ms, double* total_bytes);
 
 /* ---------------------------------------------------------------------------
  * Sparse matrices (CSR).  Columns sorted ascending within each row; every

@@ -80,6 +80,19 @@ class Context:
                 "launches": n.value, "ms": ms.value, "bytes": by.value}
         return out
 
+    def kernel_symbol_stats(self) -> dict:
+        """Per-kernel-symbol launches, total ms and algorithmic bytes."""
+        cnt = ctypes.c_int()
+        L.check(self.lib.mgd_ctx_kernel_symbol_count(self.h, byref(cnt)))
+        out = {}
+        buf = ctypes.create_string_buffer(256)
+        for i in range(cnt.value):
+            n, ms, by = c_int64(), c_double(), c_double()
+            L.check(self.lib.mgd_ctx_kernel_symbol_stats(self.h, i, buf, 256, byref(n), byref(ms),
+                                                         byref(by)))
+            out[buf.value.decode()] = {"launches": n.value, "ms": ms.value, "bytes": by.value}
+        return out
+
     def empty(self, n, dtype=torch.float64):
         return torch.empty(n, dtype=dtype, device=self.device)
 

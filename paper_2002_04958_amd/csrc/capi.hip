@@ -1,3 +1,4 @@
+#include <algorithm>
 // The C ABI of libmgdamg: argument checks, context handling and conversion
 // of internal errors into status codes.  No exception crosses this file.
 #include <chrono>
@@ -104,10 +105,10 @@ void Ctx::prof_begin(int cls, hipEvent_t* a) {
   *a = take_event();
   MGD_HIP(hipEventRecord(*a, stream));
 }
-void Ctx::prof_end(int cls, hipEvent_t a, double bytes_) {
+void Ctx::prof_end(int cls, hipEvent_t a, double bytes_, std::string kernel) {
   hipEvent_t b = take_event();
   MGD_HIP(hipEventRecord(b, stream));
-  pending.push_back({cls, a, b, bytes_});
+  pending.push_back({cls, a, b, bytes_, std::move(kernel)});
   if (pending.size() > 4096) prof_collect();
 }
 void Ctx::prof_collect() {
@@ -119,6 +120,17 @@ void Ctx::prof_collect() {
     launches[p.cls] += 1;
     ms[p.cls] += ms_;
     bytes[p.cls] += p.bytes;
+    if (!p.kernel.empty()) {
+      auto it = std::find_if(by_kernel.begin(), by_kernel.end(),
+                             [&](const auto& kv) { return kv.first == p.kernel; });
+      if (it == by_kernel.end()) {
+        by_kernel.push_back({p.kernel, KernelStat{}});
+        it = by_kernel.end() - 1;
+      }
+      it->second.launches += 1;
+      it->second.ms += ms_;
+      it->second.bytes += p.bytes;
+    }
     event_pool.push_back(p.a);
     event_pool.push_back(p.b);
   }
@@ -267,6 +279,7 @@ const char* mgd_version(void) { return "mgdamg 0.1 (gfx950)"; }
 mgd_status mgd_ctx_create(int device, void* hip_stream, const mgd_allocator* allocator,
                           mgd_ctx** out) {
   return guard([&] {
+    StepScope step_("mgd_ctx_create");
     MGD_REQUIRE(out, "out is NULL");
     int ndev = 0;
     MGD_HIP(hipGetDeviceCount(&ndev));
@@ -287,6 +300,7 @@ mgd_status mgd_ctx_create(int device, void* hip_stream, const mgd_allocator* all
 
 mgd_status mgd_ctx_destroy(mgd_ctx* ctx) {
   return guard([&] {
+    StepScope step_("mgd_ctx_destroy");
     if (!ctx) return MGD_OK;
     ctx->make_current();
     (void)hipStreamSynchronize(ctx->stream);
@@ -297,6 +311,7 @@ mgd_status mgd_ctx_destroy(mgd_ctx* ctx) {
 
 mgd_status mgd_ctx_synchronize(mgd_ctx* ctx) {
   return guard([&] {
+    StepScope step_("mgd_ctx_synchronize");
     MGD_REQUIRE(ctx, "ctx is NULL");
     ctx->make_current();
     ctx->sync();
@@ -306,6 +321,7 @@ mgd_status mgd_ctx_synchronize(mgd_ctx* ctx) {
 
 mgd_status mgd_ctx_set_profiling(mgd_ctx* ctx, int enable) {
   return guard([&] {
+    StepScope step_("mgd_ctx_set_profiling");
     MGD_REQUIRE(ctx, "ctx is NULL");
     ctx->make_current();
     if (!enable) ctx->prof_collect();
@@ -315,6 +331,7 @@ mgd_status mgd_ctx_set_profiling(mgd_ctx* ctx, int enable) {
 }
 mgd_status mgd_ctx_reset_kernel_stats(mgd_ctx* ctx) {
   return guard([&] {
+    StepScope step_("mgd_ctx_reset_kernel_stats");
     MGD_REQUIRE(ctx, "ctx is NULL");
     ctx->make_current();
     ctx->prof_collect();
@@ -323,6 +340,7 @@ mgd_status mgd_ctx_reset_kernel_stats(mgd_ctx* ctx) {
       ctx->ms[i] = 0;
       ctx->bytes[i] = 0;
     }
+    ctx->by_kernel.clear();
     return MGD_OK;
   });
 }
@@ -331,6 +349,7 @@ const char* mgd_kernel_class_name(int cls) { return kernel_class_name(cls); }
 mgd_status mgd_ctx_kernel_stats(mgd_ctx* ctx, int cls, int64_t* launches, double* total_ms,
                                 double* total_bytes) {
   return guard([&] {
+    StepScope step_("mgd_ctx_kernel_stats");
     MGD_REQUIRE(ctx, "ctx is NULL");
     MGD_REQUIRE(cls >= 0 && cls < KC_COUNT, "kernel class out of range");
     ctx->make_current();
@@ -342,8 +361,38 @@ mgd_status mgd_ctx_kernel_stats(mgd_ctx* ctx, int cls, int64_t* launches, double
   });
 }
 
+mgd_status mgd_ctx_kernel_symbol_count(mgd_ctx* ctx, int* count) {
+  return guard([&] {
+    StepScope step_("mgd_ctx_kernel_symbol_count");
+    MGD_REQUIRE(ctx && count, "ctx or count is NULL");
+    ctx->make_current();
+    ctx->prof_collect();
+    *count = (int)ctx->by_kernel.size();
+    return MGD_OK;
+  });
+}
+mgd_status mgd_ctx_kernel_symbol_stats(mgd_ctx* ctx, int index, char* name, int name_cap,
+                                       int64_t* launches, double* total_ms, double* total_bytes) {
+  return guard([&] {
+    StepScope step_("mgd_ctx_kernel_symbol_stats");
+    MGD_REQUIRE(ctx, "ctx is NULL");
+    MGD_REQUIRE(index >= 0 && index < (int)ctx->by_kernel.size(), "kernel index out of range");
+    const auto& kv = ctx->by_kernel[index];
+    if (name && name_cap > 0) {
+      const size_t k = std::min<size_t>(kv.first.size(), (size_t)name_cap - 1);
+      std::memcpy(name, kv.first.data(), k);
+      name[k] = 0;
+    }
+    if (launches) *launches = kv.second.launches;
+    if (total_ms) *total_ms = kv.second.ms;
+    if (total_bytes) *total_bytes = kv.second.bytes;
+    return MGD_OK;
+  });
+}
+
 mgd_status mgd_csr_spmv(mgd_ctx* ctx, const mgd_csr* A, const double* x, double* y) {
   return guard([&] {
+    StepScope step_("mgd_csr_spmv");
     MGD_REQUIRE(ctx, "ctx is NULL");
     check_csr_meta(A, false);
     MGD_REQUIRE(A->n_rows == 0 || (x && y), "x or y is NULL");
@@ -382,12 +431,14 @@ static void check_amg_params(const amg_params* p) {
 
 mgd_status amg_setup(mgd_ctx* ctx, const mgd_csr* A, const amg_params* p, amg_hierarchy** out) {
   return guard([&] {
+    StepScope step_("amg_setup");
     MGD_REQUIRE(ctx && out, "ctx or out is NULL");
     check_amg_params(p);
     check_csr_meta(A, true);
     MGD_REQUIRE(A->n_rows >= 1, "matrix is empty");
     ctx->make_current();
     validate_csr_device(ctx, A, true);
+    StepScope st_copy("amg_setup: input copy");
     auto t0 = std::chrono::steady_clock::now();
     auto h = std::make_unique<amg_hierarchy>();
     h->ctx = ctx;
@@ -410,6 +461,7 @@ mgd_status amg_setup(mgd_ctx* ctx, const mgd_csr* A, const amg_params* p, amg_hi
 
 mgd_status amg_apply(mgd_ctx* ctx, amg_hierarchy* h, const double* r, double* z, int n_cycles) {
   return guard([&] {
+    StepScope step_("amg_apply");
     MGD_REQUIRE(ctx && h, "ctx or hierarchy is NULL");
     MGD_REQUIRE(h->ctx == ctx, "hierarchy belongs to another context");
     MGD_REQUIRE(r && z && (const void*)r != (const void*)z, "r, z must be distinct and non-NULL");
@@ -422,6 +474,7 @@ mgd_status amg_apply(mgd_ctx* ctx, amg_hierarchy* h, const double* r, double* z,
 
 mgd_status amg_get_info(const amg_hierarchy* h, amg_info* out) {
   return guard([&] {
+    StepScope step_("amg_get_info");
     MGD_REQUIRE(h && out, "hierarchy or out is NULL");
     *out = amg_info{};
     out->levels = (int)h->H.levels.size();
@@ -446,6 +499,7 @@ mgd_status amg_export_level(mgd_ctx* ctx, const amg_hierarchy* h, int level, int
                             int32_t* a_row_ptr, int32_t* a_col, double* a_val, int32_t* p_row_ptr,
                             int32_t* p_col, double* p_val) {
   return guard([&] {
+    StepScope step_("amg_export_level");
     MGD_REQUIRE(ctx && h, "ctx or hierarchy is NULL");
     MGD_REQUIRE(level >= 0 && level < (int)h->H.levels.size(), "level out of range");
     ctx->make_current();
@@ -471,6 +525,7 @@ mgd_status amg_export_level(mgd_ctx* ctx, const amg_hierarchy* h, int level, int
 
 mgd_status amg_destroy(amg_hierarchy* h) {
   return guard([&] {
+    StepScope step_("amg_destroy");
     if (h) {
       h->ctx->make_current();
       h->ctx->sync();
@@ -482,6 +537,7 @@ mgd_status amg_destroy(amg_hierarchy* h) {
 
 mgd_status mgd_block_matvec(mgd_ctx* ctx, const mgd_block_system* A, const double* x, double* y) {
   return guard([&] {
+    StepScope step_("mgd_block_matvec");
     MGD_REQUIRE(ctx, "ctx is NULL");
     check_block_system(A);
     MGD_REQUIRE(x && y && (const void*)x != (const void*)y, "x, y must be distinct and non-NULL");
@@ -493,6 +549,7 @@ mgd_status mgd_block_matvec(mgd_ctx* ctx, const mgd_block_system* A, const doubl
 
 mgd_status mgd_assemble(mgd_ctx* ctx, const mgd_coeffs* c, mgd_block_system* out) {
   return guard([&] {
+    StepScope step_("mgd_assemble");
     MGD_REQUIRE(ctx && out, "ctx or out is NULL");
     ctx->make_current();
     assemble_impl(ctx, c, out);
@@ -503,6 +560,7 @@ mgd_status mgd_assemble(mgd_ctx* ctx, const mgd_coeffs* c, mgd_block_system* out
 mgd_status mgd_block_system_transpose(mgd_ctx* ctx, const mgd_block_system* A,
                                       mgd_block_system* out) {
   return guard([&] {
+    StepScope step_("mgd_block_system_transpose");
     MGD_REQUIRE(ctx && out, "ctx or out is NULL");
     check_block_system(A);
     ctx->make_current();
@@ -513,6 +571,7 @@ mgd_status mgd_block_system_transpose(mgd_ctx* ctx, const mgd_block_system* A,
 
 mgd_status mgd_block_system_free(mgd_ctx* ctx, mgd_block_system* s) {
   return guard([&] {
+    StepScope step_("mgd_block_system_free");
     MGD_REQUIRE(ctx && s, "ctx or system is NULL");
     ctx->make_current();
     ctx->sync();
@@ -536,6 +595,7 @@ void block_params_default(block_params* p) {
 mgd_status block_precond_create(mgd_ctx* ctx, const mgd_block_system* A, const block_params* p,
                                 block_precond** out) {
   return guard([&] {
+    StepScope step_("block_precond_create");
     MGD_REQUIRE(ctx && p && out, "ctx, params or out is NULL");
     check_block_system(A);
     check_amg_params(&p->amg);
@@ -549,6 +609,7 @@ mgd_status block_precond_create(mgd_ctx* ctx, const mgd_block_system* A, const b
 
 mgd_status block_precond_apply(mgd_ctx* ctx, block_precond* M, const double* r, double* z) {
   return guard([&] {
+    StepScope step_("block_precond_apply");
     MGD_REQUIRE(ctx && M, "ctx or preconditioner is NULL");
     MGD_REQUIRE(M->ctx == ctx, "preconditioner belongs to another context");
     MGD_REQUIRE(r && z && (const void*)r != (const void*)z, "r, z must be distinct and non-NULL");
@@ -560,6 +621,7 @@ mgd_status block_precond_apply(mgd_ctx* ctx, block_precond* M, const double* r, 
 
 mgd_status block_precond_get_info(const block_precond* M, block_precond_info* out) {
   return guard([&] {
+    StepScope step_("block_precond_get_info");
     MGD_REQUIRE(M && out, "preconditioner or out is NULL");
     *out = block_precond_info{};
     out->kind = M->prm.kind;
@@ -576,6 +638,7 @@ mgd_status block_precond_get_info(const block_precond* M, block_precond_info* ou
 
 mgd_status block_precond_get_hierarchy(const block_precond* M, int index, const amg_hierarchy** out) {
   return guard([&] {
+    StepScope step_("block_precond_get_hierarchy");
     MGD_REQUIRE(M && out, "preconditioner or out is NULL");
     MGD_REQUIRE(index >= 0 && index < (int)M->hier.size() && M->hier[index],
                 "no hierarchy at this index");
@@ -586,6 +649,7 @@ mgd_status block_precond_get_hierarchy(const block_precond* M, int index, const 
 
 mgd_status block_precond_destroy(block_precond* M) {
   return guard([&] {
+    StepScope step_("block_precond_destroy");
     if (M) {
       M->ctx->make_current();
       M->ctx->sync();
@@ -607,6 +671,7 @@ void gmres_params_default(gmres_params* p) {
 mgd_status gmres_solve(mgd_ctx* ctx, const mgd_block_system* A, block_precond* M, const double* b,
                        double* x, const gmres_params* p, gmres_result* out) {
   return guard([&] {
+    StepScope step_("gmres_solve");
     MGD_REQUIRE(ctx && p && out, "ctx, params or result is NULL");
     check_block_system(A);
     MGD_REQUIRE(b && x && (const void*)b != (const void*)x, "b, x must be distinct and non-NULL");
@@ -621,6 +686,7 @@ mgd_status gmres_solve(mgd_ctx* ctx, const mgd_block_system* A, block_precond* M
 mgd_status mgd_adjoint_gradients(mgd_ctx* ctx, const mgd_coeffs* c, const double* x,
                                  const double* lambda, double* dL_dkappa, double* dL_dc) {
   return guard([&] {
+    StepScope step_("mgd_adjoint_gradients");
     MGD_REQUIRE(ctx && x && lambda, "ctx, x or lambda is NULL");
     ctx->make_current();
     adjoint_gradients_impl(ctx, c, x, lambda, dL_dkappa, dL_dc);
@@ -634,6 +700,7 @@ mgd_status adjoint_solve(mgd_ctx* ctx, const mgd_coeffs* c, const mgd_block_syst
                          double* dL_dkappa, double* dL_dc, const gmres_params* p,
                          gmres_result* out) {
   return guard([&] {
+    StepScope step_("adjoint_solve");
     MGD_REQUIRE(ctx && p && out && x && g && lambda, "NULL argument");
     check_block_system(A);
     check_coeffs(c);

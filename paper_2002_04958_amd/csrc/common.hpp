@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <initializer_list>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -25,12 +26,29 @@ struct Error : std::runtime_error {
 
 [[noreturn]] inline void fail(mgd_status c, const std::string& m) { throw Error(c, m); }
 
-#define MGD_HIP(call)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (call);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      ::mgd::fail(e_ == hipErrorOutOfMemory ? MGD_ENOMEM : MGD_EHIP,                    \
-                  std::string(#call) + ": " + hipGetErrorString(e_) + " (" __FILE__ ")"); \
+// The library step in progress on this thread (set by StepScope); HIP errors
+// name it, so an asynchronous device fault reported at a later synchronisation
+// still says which step's kernels were in flight.
+inline std::string& current_step() {
+  static thread_local std::string s;
+  return s;
+}
+struct StepScope {
+  std::string prev;
+  explicit StepScope(const std::string& step) : prev(current_step()) { current_step() = step; }
+  ~StepScope() { current_step() = prev; }
+};
+inline std::string step_suffix() {
+  return current_step().empty() ? std::string() : " [step: " + current_step() + "]";
+}
+
+#define MGD_HIP(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      ::mgd::fail(e_ == hipErrorOutOfMemory ? MGD_ENOMEM : MGD_EHIP,                      \
+                  std::string(#call) + ": " + hipGetErrorString(e_) + " (" __FILE__ ")" + \
+                      ::mgd::step_suffix());                                              \
   } while (0)
 
 #define MGD_CHECK_LAUNCH() MGD_HIP(hipGetLastError())
@@ -74,6 +92,11 @@ struct Ctx {
     int cls;
     hipEvent_t a, b;
     double bytes;
+    std::string kernel;  // symbol of the single kernel timed, or empty
+  };
+  struct KernelStat {
+    int64_t launches = 0;
+    double ms = 0, bytes = 0;
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> event_pool;
@@ -81,6 +104,7 @@ struct Ctx {
   int64_t launches[KC_COUNT] = {};
   double ms[KC_COUNT] = {};
   double bytes[KC_COUNT] = {};
+  std::vector<std::pair<std::string, KernelStat>> by_kernel;  // first-seen order
 
   void* dmalloc(size_t bytes);
   void dfree(void* p);
@@ -92,24 +116,47 @@ struct Ctx {
   // profiling hooks
   hipEvent_t take_event();
   void prof_begin(int cls, hipEvent_t* a);
-  void prof_end(int cls, hipEvent_t a, double bytes);
+  void prof_end(int cls, hipEvent_t a, double bytes, std::string kernel);
   void prof_collect();  // synchronises
   ~Ctx();
 };
 
-// RAII scope: events around one launch when profiling is on.
+// RAII scope: events around one launch (or a short fixed sequence) when
+// profiling is on.  `kernel` names the kernel symbol when the scope holds
+// exactly one launch, so per-kernel averages can be compared with a trace.
 struct ProfScope {
   Ctx* c;
   int cls;
   double bytes;
+  std::string kernel;
   hipEvent_t a = nullptr;
-  ProfScope(Ctx* c_, int cls_, double bytes_) : c(c_), cls(cls_), bytes(bytes_) {
+  ProfScope(Ctx* c_, int cls_, double bytes_, std::string kernel_ = std::string())
+      : c(c_), cls(cls_), bytes(bytes_), kernel(std::move(kernel_)) {
     if (c->profiling) c->prof_begin(cls, &a);
   }
   ~ProfScope() {
-    if (c->profiling && a) c->prof_end(cls, a, bytes);
+    if (c->profiling && a) c->prof_end(cls, a, bytes, std::move(kernel));
   }
 };
+
+// Kernel symbol with template arguments as a demangler prints them
+// ("k_half<float, 1>"); empty unless profiling, so launches pay nothing.
+template <typename T>
+inline const char* type_name() {
+  return sizeof(T) == 4 ? "float" : "double";
+}
+inline std::string ksym(const Ctx* c, const char* base, std::initializer_list<std::string> args) {
+  if (!c->profiling) return std::string();
+  std::string s(base);
+  const char* sep = "<";
+  for (const auto& a : args) {
+    s += sep;
+    s += a;
+    sep = ", ";
+  }
+  return args.size() ? s + ">" : s;
+}
+
 
 // ---------------------------------------------------------------------------
 // device buffer owned through the context allocator

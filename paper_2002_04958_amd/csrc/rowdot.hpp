@@ -34,6 +34,11 @@ inline void dispatch_tpr(int tpr, Args&&... args) {
   }
 }
 
+// The group width dispatch_tpr actually launches for a requested width.
+inline int tpr_of(int tpr) {
+  return (tpr == 1 || tpr == 2 || tpr == 4 || tpr == 8 || tpr == 16 || tpr == 32) ? tpr : 64;
+}
+
 // Group width for an average row length (used when no tuned value exists).
 inline int default_tpr(double avg_row) {
   if (avg_row <= 12) return 1;

@@ -636,11 +636,15 @@ void amg_build(Ctx* c, Csr<double>&& A0, const amg_params& p, SetupHierarchy& H)
       H.levels.push_back(std::move(L));
       break;
     }
+    const std::string at = " (level " + std::to_string(lvl) + ", " + std::to_string(n) + " rows)";
     DBuf<uint8_t> S;
     DBuf<int> stc;
+    StepScope st_strength("amg setup: strength" + at);
     strength(c, A, p.strength_theta, p.dominance_theta, S, stc);
     DBuf<int8_t> state;
+    StepScope st_pmis("amg setup: pmis" + at);
     const int rounds = pmis(c, A, S, stc, p.seed, lvl, state);
+    StepScope st_cnum("amg setup: coarse numbering" + at);
     DBuf<int> isc(c, (size_t)n), cidx(c, (size_t)n + 1);
     hipLaunchKernelGGL(k_is_c, dim3(cdiv(n, 256)), dim3(256), 0, c->stream, n, state.get(),
                        isc.get());
@@ -652,13 +656,25 @@ void amg_build(Ctx* c, Csr<double>&& A0, const amg_params& p, SetupHierarchy& H)
       break;
     }
     Csr<double> P, R, AP, Ac;
-    interpolation(c, A, S, state, cidx, nc, P);
-    check_structure(c, P, "interpolation", false);
-    transpose(c, P, R);
-    spgemm(c, A, P, AP);
-    check_structure(c, AP, "A P", false);
-    spgemm(c, R, AP, Ac);
-    check_structure(c, Ac, "coarse operator", true);
+    {
+      StepScope st("amg setup: interpolation" + at);
+      interpolation(c, A, S, state, cidx, nc, P);
+      check_structure(c, P, "interpolation", false);
+    }
+    {
+      StepScope st("amg setup: transpose of P" + at);
+      transpose(c, P, R);
+    }
+    {
+      StepScope st("amg setup: A P" + at);
+      spgemm(c, A, P, AP);
+      check_structure(c, AP, "A P", false);
+    }
+    {
+      StepScope st("amg setup: R (A P)" + at);
+      spgemm(c, R, AP, Ac);
+      check_structure(c, Ac, "coarse operator", true);
+    }
     L.A = std::move(A);
     L.cf = std::move(state);
     L.P = std::move(P);
@@ -669,6 +685,7 @@ void amg_build(Ctx* c, Csr<double>&& A0, const amg_params& p, SetupHierarchy& H)
   }
   SetupLevel& last = H.levels.back();
   if (last.A.n_rows <= p.dense_max) {
+    StepScope st("amg setup: coarsest LU (" + std::to_string(last.A.n_rows) + " rows)");
     H.coarse_kind = 0;
     if (!dense_inverse(c, last.A, H.coarse_inv))
       fail(MGD_ESINGULAR, "zero pivot in the coarsest-level LU");

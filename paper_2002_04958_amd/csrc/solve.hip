@@ -109,6 +109,8 @@ std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHiera
   size_t maxL = 0;
   for (auto* H : members) maxL = std::max(maxL, H->levels.size());
   for (size_t l = 0; l < maxL; ++l) {
+    StepScope st("solve-phase build: level " + std::to_string(l) + " of " +
+                 std::to_string(members.size()) + " hierarchies");
     std::vector<MemberAtLevel> ms;
     int off = 0, nCtot = 0, nFtot = 0, ncoarse = 0;
     for (auto* H : members) {
@@ -256,7 +258,10 @@ std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHiera
   }
   U->t0.alloc(c, (size_t)std::max(U->n0, 1));
   U->t1.alloc(c, (size_t)std::max(U->n0, 1));
-  for (size_t l = 0; l < nl; ++l) U->L[l].tpr = tune_level(c, U->L[l], autotune, sizeof(T) == 4);
+  for (size_t l = 0; l < nl; ++l) {
+    StepScope st("solve-phase build: row-group tuning, level " + std::to_string(l));
+    U->L[l].tpr = tune_level(c, U->L[l], autotune, sizeof(T) == 4);
+  }
   c->sync();
   return U;
 }
@@ -449,6 +454,14 @@ static double resid_bytes(const ULevel<T>& lv) {
 }
 
 static inline int cls_of(int l, int cls0) { return l == 0 ? cls0 : KC_VCYCLE_COARSE; }
+template <typename T>
+static std::string khalf(const Ctx* c, int tpr) {
+  return ksym(c, "k_half", {type_name<T>(), std::to_string(tpr_of(tpr))});
+}
+template <typename T>
+static std::string kresid(const Ctx* c, int tpr, bool natural) {
+  return ksym(c, "k_resid", {type_name<T>(), std::to_string(tpr_of(tpr)), natural ? "true" : "false"});
+}
 
 template <typename T>
 void Union<T>::vcycle(Ctx* c, const T* b0, T* x0) {
@@ -469,30 +482,33 @@ void Union<T>::vcycle(Ctx* c, const T* b0, T* x0) {
       for (int s = 0; s < n_pre; ++s) {
         if (s == 0) {
           ProfScope ps(c, cls_of(l, KC_SMOOTH_L0),
-                       (double)lv.nS * (4 + 2 * sizeof(T)) + lv.nC * (sizeof(T)));
+                       (double)lv.nS * (4 + 2 * sizeof(T)) + lv.nC * (sizeof(T)),
+                       ksym(c, "k_pre_c", {type_name<T>()}));
           hipLaunchKernelGGL(k_pre_c<T>, dim3(cdiv(lv.nS, 256)), dim3(256), 0, c->stream, lv.nS,
                              lv.nC, lv.perm.get(), lv.dinv.get(), bl, xw);
           MGD_CHECK_LAUNCH();
         } else {
-          ProfScope ps(c, cls_of(l, KC_SMOOTH_L0), half_bytes(lv, true));
+          ProfScope ps(c, cls_of(l, KC_SMOOTH_L0), half_bytes(lv, true), khalf<T>(c, lv.tpr));
           dispatch<HalfLaunchD>(lv.tpr, c, HalfArgs<T>{&lv, 0, lv.nC, bl, x1, xw});
         }
-        ProfScope ps(c, cls_of(l, KC_SMOOTH_L0), half_bytes(lv, false));
+        ProfScope ps(c, cls_of(l, KC_SMOOTH_L0), half_bytes(lv, false), khalf<T>(c, lv.tpr));
         dispatch<HalfLaunchD>(lv.tpr, c, HalfArgs<T>{&lv, lv.nC, lv.nS, bl, xw, x1});
       }
       if (lv.n_coarse > 0) {
         {
-          ProfScope ps(c, cls_of(l, KC_RESID_L0), resid_bytes(lv));
+          ProfScope ps(c, cls_of(l, KC_RESID_L0), resid_bytes(lv), kresid<T>(c, lv.tpr, false));
           dispatch<ResidLaunch>(lv.tpr, c, &lv, bl, (const T*)x1, r[l].get(), false);
         }
         ProfScope ps(c, cls_of(l, KC_TRANSFER_L0),
                      (double)lv.Wt.nnz * (sizeof(T) + 4) + lv.n_coarse * (4 + sizeof(T)) +
-                         (double)lv.nS * sizeof(T));
+                         (double)lv.nS * sizeof(T),
+                     ksym(c, "k_restrict", {type_name<T>(), std::to_string(tpr_of(lv.tpr_wt))}));
         dispatch<RestrictLaunch>(lv.tpr_wt, c, &lv, (const T*)r[l].get(), b[l + 1].get());
       }
     }
     if (!lv.dense.empty()) {
-      ProfScope ps(c, KC_COARSE_SOLVE, 8.0 * lv.dense_entries + 2.0 * sizeof(T) * lv.n);
+      ProfScope ps(c, KC_COARSE_SOLVE, 8.0 * lv.dense_entries + 2.0 * sizeof(T) * lv.n,
+                   ksym(c, "k_dense", {type_name<T>()}));
       dim3 grid(cdiv(lv.dense_max_n, 64), (unsigned)lv.dense.size());
       hipLaunchKernelGGL(k_dense<T>, grid, dim3(64), 0, c->stream,
                          (const DenseDev*)lv.dense_dev.get(), bl, x1);
@@ -508,15 +524,16 @@ void Union<T>::vcycle(Ctx* c, const T* b0, T* x0) {
     if (lv.n_coarse > 0) {
       ProfScope ps(c, cls_of(l, KC_TRANSFER_L0),
                    (double)lv.W.nnz * (sizeof(T) + 4) + lv.nS * (4 + 2.0 * sizeof(T)) +
-                       lv.n_coarse * (double)sizeof(T));
+                       lv.n_coarse * (double)sizeof(T),
+                   ksym(c, "k_prolong", {type_name<T>(), std::to_string(tpr_of(lv.tpr_w))}));
       dispatch<ProlongLaunch>(lv.tpr_w, c, &lv, (const T*)X1p(l + 1), x1);
     }
     for (int s = 0; s < n_post; ++s) {
       {
-        ProfScope ps(c, cls_of(l, KC_SMOOTH_L0), half_bytes(lv, false));
+        ProfScope ps(c, cls_of(l, KC_SMOOTH_L0), half_bytes(lv, false), khalf<T>(c, lv.tpr));
         dispatch<HalfLaunchD>(lv.tpr, c, HalfArgs<T>{&lv, lv.nC, lv.nS, bl, x1, xw});
       }
-      ProfScope ps(c, cls_of(l, KC_SMOOTH_L0), half_bytes(lv, true));
+      ProfScope ps(c, cls_of(l, KC_SMOOTH_L0), half_bytes(lv, true), khalf<T>(c, lv.tpr));
       dispatch<HalfLaunchD>(lv.tpr, c, HalfArgs<T>{&lv, 0, lv.nC, bl, xw, x1});
     }
   }
@@ -529,7 +546,7 @@ void Union<T>::apply(Ctx* c, const T* bvec, T* z, int cycles) {
     ULevel<T>& lv = L[0];
     if (!lv.dense.empty()) fill<T>(c, t0.get(), (T)0, (size_t)n0);
     if (lv.nS > 0) {
-      ProfScope ps(c, KC_RESID_L0, resid_bytes(lv));
+      ProfScope ps(c, KC_RESID_L0, resid_bytes(lv), kresid<T>(c, lv.tpr, true));
       dispatch<ResidLaunch>(lv.tpr, c, &lv, bvec, (const T*)z, t0.get(), true);
     }
     vcycle(c, t0.get(), t1.get());

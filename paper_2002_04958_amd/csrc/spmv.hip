@@ -31,7 +31,8 @@ struct SpmvLaunch {
 
 void spmv(Ctx* c, const CsrView<double>& A, const double* x, double* y, int tpr, int cls) {
   if (A.n_rows == 0) return;
-  ProfScope ps(c, cls, 12.0 * A.nnz + 4.0 * (A.n_rows + 1) + 8.0 * A.n_rows + 8.0 * A.n_cols);
+  ProfScope ps(c, cls, 12.0 * A.nnz + 4.0 * (A.n_rows + 1) + 8.0 * A.n_rows + 8.0 * A.n_cols,
+               ksym(c, "k_spmv", {std::to_string(tpr_of(tpr))}));
   dispatch_tpr<SpmvLaunch>(tpr, c, A, x, y);
 }
 
@@ -89,7 +90,8 @@ double block_matvec_bytes(const BlockSysDev& S, bool resid) {
 }
 
 void block_matvec(Ctx* c, const BlockSysDev& S, const double* x, const double* b, double* y) {
-  ProfScope ps(c, KC_BLOCK_MATVEC, block_matvec_bytes(S, b != nullptr));
+  ProfScope ps(c, KC_BLOCK_MATVEC, block_matvec_bytes(S, b != nullptr),
+               ksym(c, "k_block_matvec", {std::to_string(tpr_of(S.tpr)), b ? "true" : "false"}));
   dispatch_tpr<BlockMatvecLaunch>(S.tpr, c, S, x, b, y);
 }
 
