@@ -51,10 +51,16 @@ __global__ void k_pattern_len(int N, int n, int dim, int* __restrict__ len) {
 
 // sorted columns: -z, -y, -x, c, +x, +y, +z
 __global__ void k_pattern_fill(int N, int n, int dim, const int* __restrict__ rp,
-                               int* __restrict__ ci) {
+                               int* __restrict__ ci, int* __restrict__ err) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= N) return;
   int p = rp[c];
+  int len = 1;  // the diagonal plus the interior faces
+  for (int d = 0; d < 2 * dim; ++d) len += nbr(c, d, n, dim) >= 0 ? 1 : 0;
+  if (rp[c + 1] - p != len) {
+    atomicOr(err, 1);
+    return;
+  }
   const int order[7] = {4, 2, 0, -1, 1, 3, 5};
   for (int q = 0; q < 7; ++q) {
     const int d = order[q];
@@ -164,8 +170,9 @@ void assemble_impl(Ctx* c, const mgd_coeffs* cf, mgd_block_system* out) {
   const int nnz = exclusive_scan_total(c, len.get(), os->rp.get(), N);
   os->ci.alloc(c, (size_t)nnz);
   hipLaunchKernelGGL(k_pattern_fill, dim3(cdiv(N, 256)), dim3(256), 0, c->stream, N, n, dim,
-                     (const int*)os->rp.get(), os->ci.get());
+                     (const int*)os->rp.get(), os->ci.get(), c->err_flag());
   MGD_CHECK_LAUNCH();
+  c->check_device_errors("stencil pattern fill");
   {
     Csr<double> pat;  // structure check of the shared stencil pattern
     pat.n_rows = pat.n_cols = N;

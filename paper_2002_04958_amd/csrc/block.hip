@@ -628,12 +628,18 @@ __global__ void k_mono_len(int G, int N, BlockSysDev S, int* __restrict__ len) {
   len[(size_t)a * N + i] = nb + extra;
 }
 __global__ void k_mono_fill(int G, int N, BlockSysDev S, const int* __restrict__ rp,
-                            int* __restrict__ ci, double* __restrict__ v) {
+                            int* __restrict__ ci, double* __restrict__ v, int* __restrict__ err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int a = blockIdx.y;
   if (i >= N) return;
   int p = rp[(size_t)a * N + i];
   const BlockCsr B = S.blk[a];
+  // coupling entries per row: D_gE for a group row, D_Eg (G) and D_EI for E, D_IE for I
+  const int extra = a < G ? 1 : (a == G ? G + 1 : 1);
+  if (rp[(size_t)a * N + i + 1] - p != (B.rp[i + 1] - B.rp[i]) + extra) {
+    atomicOr(err, 1);
+    return;
+  }
   const int base = a * N;
   if (a == G) {  // D_Eg columns come first (segments 0..G-1)
     for (int g = 0; g < G; ++g) {
@@ -674,9 +680,9 @@ static Csr<double> monolithic(Ctx* c, const BlockSysDev& S) {
   M.ci.alloc(c, (size_t)M.nnz);
   M.v.alloc(c, (size_t)M.nnz);
   hipLaunchKernelGGL(k_mono_fill, grid, dim3(256), 0, c->stream, G, N, S, (const int*)M.rp.get(),
-                     M.ci.get(), M.v.get());
+                     M.ci.get(), M.v.get(), c->err_flag());
   MGD_CHECK_LAUNCH();
-  c->sync();
+  c->check_device_errors("monolithic matrix fill");
   return M;
 }
 

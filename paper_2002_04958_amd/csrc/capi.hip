@@ -206,14 +206,18 @@ void validate_csr_device(Ctx* c, const mgd_csr* A, bool require_diag) {
 template <typename V>
 void check_structure(Ctx* c, const Csr<V>& A, const char* what, bool require_diag) {
   const int b = csr_check_bits(c, A.n_rows, A.n_cols, A.nnz, A.rp.get(), A.ci.get(), require_diag);
-  if (b) fail(MGD_EHIP, std::string("internal structure check failed for ") + what + ":" + check_message(b));
+  if (b)
+    fail(MGD_EHIP, std::string("internal structure check failed for ") + what + ":" +
+                       check_message(b) + step_suffix());
 }
 template void check_structure<double>(Ctx*, const Csr<double>&, const char*, bool);
 
 void check_index_structure(Ctx* c, int n_rows, int n_cols, long long nnz, const int* rp,
                            const int* ci, const char* what) {
   const int b = csr_check_bits(c, n_rows, n_cols, nnz, rp, ci, false, true);
-  if (b) fail(MGD_EHIP, std::string("internal structure check failed for ") + what + ":" + check_message(b));
+  if (b)
+    fail(MGD_EHIP, std::string("internal structure check failed for ") + what + ":" +
+                       check_message(b) + step_suffix());
 }
 template void check_structure<float>(Ctx*, const Csr<float>&, const char*, bool);
 
@@ -231,7 +235,8 @@ void Ctx::check_device_errors(const char* where) {
   if (e) {
     fill<int>(this, dev_err, 0, 1);
     sync();
-    fail(MGD_EHIP, std::string("device bounds check failed in ") + where + " (code " + std::to_string(e) + ")");
+    fail(MGD_EHIP, std::string("device bounds check failed in ") + where + " (code " +
+                       std::to_string(e) + ")" + step_suffix());
   }
 }
 

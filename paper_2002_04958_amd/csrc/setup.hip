@@ -252,11 +252,16 @@ __global__ void k_interp_fill(int n, const int* __restrict__ rp, const int* __re
                               const uint8_t* __restrict__ S, const int8_t* __restrict__ st,
                               const int* __restrict__ cidx, const int* __restrict__ prp,
                               int* __restrict__ pci, double* __restrict__ pv,
-                              double* __restrict__ sigma) {
+                              double* __restrict__ sigma, int* __restrict__ err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int p = prp[i];
+  const int pend = prp[i + 1];
   if (st[i] == kC) {
+    if (pend != p + 1) {  // the count pass gives C rows exactly one entry
+      atomicOr(err, 2);
+      return;
+    }
     pci[p] = cidx[i];
     pv[p] = 1.0;
     return;
@@ -306,10 +311,15 @@ __global__ void k_interp_fill(int n, const int* __restrict__ rp, const int* __re
       const double ah = sgn(a) != sgn(diag[k]) ? a : 0.0;
       num = num + (v[e2] * ah) / sg;
     }
+    if (p >= pend) {  // more entries than the count pass gave this row
+      atomicOr(err, 1);
+      return;
+    }
     pci[p] = cidx[j];
     pv[p] = -num / at;
     ++p;
   }
+  if (p != pend) atomicOr(err, 2);
 }
 
 __global__ void k_is_c(int n, const int8_t* __restrict__ st, int* __restrict__ out) {
@@ -337,9 +347,9 @@ void interpolation(Ctx* c, const Csr<double>& A, const DBuf<uint8_t>& S,
   P.v.alloc(c, (size_t)P.nnz);
   hipLaunchKernelGGL(k_interp_fill, dim3(g), dim3(256), 0, c->stream, n, A.rp.get(), A.ci.get(),
                      A.v.get(), diag.get(), S.get(), state.get(), cidx.get(), P.rp.get(),
-                     P.ci.get(), P.v.get(), sigma.get());
+                     P.ci.get(), P.v.get(), sigma.get(), c->err_flag());
   MGD_CHECK_LAUNCH();
-  c->sync();
+  c->check_device_errors("interpolation fill");
 }
 
 // ---------------------------------------------------------------------------
@@ -425,7 +435,7 @@ __global__ void k_spgemm(int n, const int* __restrict__ arp, const int* __restri
                          const int* __restrict__ bci, const double* __restrict__ bv,
                          int* __restrict__ head, int* __restrict__ hend,
                          const int* __restrict__ crp, int* __restrict__ cnt_or_cci,
-                         double* __restrict__ cv) {
+                         double* __restrict__ cv, int* __restrict__ err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int e0 = arp[i], e1 = arp[i + 1];
@@ -435,6 +445,7 @@ __global__ void k_spgemm(int n, const int* __restrict__ arp, const int* __restri
     hend[e] = brp[k + 1];
   }
   int out = FILL ? crp[i] : 0;
+  const int oend = FILL ? crp[i + 1] : INT_MAX;
   for (;;) {
     int jmin = INT_MAX;
     for (int e = e0; e < e1; ++e)
@@ -449,12 +460,17 @@ __global__ void k_spgemm(int n, const int* __restrict__ arp, const int* __restri
       }
     }
     if (FILL) {
+      if (out >= oend) {  // more columns than the symbolic pass counted
+        atomicOr(err, 1);
+        return;
+      }
       cnt_or_cci[out] = jmin;
       cv[out] = acc;
     }
     ++out;
   }
   if (!FILL) cnt_or_cci[i] = out;
+  if (FILL && out != oend) atomicOr(err, 2);
 }
 
 void spgemm(Ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>& C) {
@@ -469,7 +485,7 @@ void spgemm(Ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>& C) 
   if (n)
     hipLaunchKernelGGL(k_spgemm<false>, dim3(g), dim3(128), 0, c->stream, n, A.rp.get(),
                        A.ci.get(), A.v.get(), B.rp.get(), B.ci.get(), B.v.get(), head.get(),
-                       hend.get(), (const int*)nullptr, cnt.get(), (double*)nullptr);
+                       hend.get(), (const int*)nullptr, cnt.get(), (double*)nullptr, c->err_flag());
   MGD_CHECK_LAUNCH();
   C.nnz = exclusive_scan_total(c, cnt.get(), C.rp.get(), n);
   C.ci.alloc(c, (size_t)C.nnz);
@@ -477,9 +493,9 @@ void spgemm(Ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>& C) 
   if (n)
     hipLaunchKernelGGL(k_spgemm<true>, dim3(g), dim3(128), 0, c->stream, n, A.rp.get(), A.ci.get(),
                        A.v.get(), B.rp.get(), B.ci.get(), B.v.get(), head.get(), hend.get(),
-                       (const int*)C.rp.get(), C.ci.get(), C.v.get());
+                       (const int*)C.rp.get(), C.ci.get(), C.v.get(), c->err_flag());
   MGD_CHECK_LAUNCH();
-  c->sync();
+  c->check_device_errors("SpGEMM fill");
 }
 
 // ---------------------------------------------------------------------------

@@ -18,49 +18,105 @@ namespace mgd {
 // ===========================================================================
 // union construction
 // ===========================================================================
+// The kernels below take a C/F marker only where one exists (members with a
+// coarser level); members without one are all-F and use the _allf variants.
+// Per-row choices are written as arithmetic on both candidates rather than as
+// a select between kernel arguments under a divergent branch.
 __global__ void k_flags(int n, const int8_t* __restrict__ cf, int* __restrict__ isc,
                         int* __restrict__ isf) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const bool c = cf && cf[i] == kC;
-  isc[i] = c ? 1 : 0;
-  isf[i] = c ? 0 : 1;
+  const int c = cf[i] == kC ? 1 : 0;
+  isc[i] = c;
+  isf[i] = 1 - c;
 }
 
-// stored index of every member row; perm[stored] = natural
+// stored index of every member row (C rows from cbase, F rows from fbase);
+// perm[stored] = off + natural
 __global__ void k_map_rows(int n, const int8_t* __restrict__ cf, const int* __restrict__ cidx,
                            const int* __restrict__ fidx, int cbase, int fbase, int off,
                            int* __restrict__ srow, int* __restrict__ perm) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const bool c = cf && cf[i] == kC;
-  const int s = c ? cbase + cidx[i] : fbase + fidx[i];
+  const int c = cf[i] == kC ? 1 : 0;
+  const int sc = cbase + cidx[i], sf = fbase + fidx[i];
+  const int s = sf + c * (sc - sf);
   srow[i] = s;
   perm[s] = off + i;
 }
+__global__ void k_map_rows_allf(int n, int fbase, int off, int* __restrict__ srow,
+                                int* __restrict__ perm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  srow[i] = fbase + i;
+  perm[fbase + i] = off + i;
+}
 
+// every stored row must be hit exactly once before the map drives any write
+__global__ void k_count_hits(int n, const int* __restrict__ srow, int nS, int* __restrict__ hits,
+                             int* __restrict__ bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int s = srow[i];
+  if (s < 0 || s >= nS) {
+    atomicOr(bad, 1);
+    return;
+  }
+  atomicAdd(&hits[s], 1);
+}
+__global__ void k_check_hits(int nS, const int* __restrict__ hits, int* __restrict__ bad) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nS && hits[s] != 1) atomicOr(bad, 2);
+}
+
+// row lengths into the stored order: all rows, or F rows only (W)
 __global__ void k_row_len(int n, const int* __restrict__ rp, const int* __restrict__ srow,
-                          int sbase, const int8_t* __restrict__ only_f_cf,
                           int* __restrict__ len) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (only_f_cf && only_f_cf[i] == kC) return;  // W holds F rows only
-  len[srow[i] - sbase] = rp ? rp[i + 1] - rp[i] : 0;
+  len[srow[i]] = rp[i + 1] - rp[i];
 }
-
-__global__ void k_row_copy(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                           const double* __restrict__ v, const int* __restrict__ srow, int sbase,
-                           const int8_t* __restrict__ only_f_cf, int coloff,
-                           const int* __restrict__ drp, int* __restrict__ dci,
-                           double* __restrict__ dv) {
+__global__ void k_row_len_f(int n, const int* __restrict__ rp, const int* __restrict__ srow,
+                            int sbase, const int8_t* __restrict__ cf, int* __restrict__ len) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (only_f_cf && only_f_cf[i] == kC) return;
-  int p = drp[srow[i] - sbase];
+  if (cf[i] == kC) return;
+  len[srow[i] - sbase] = rp[i + 1] - rp[i];
+}
+
+// copy rows into the stored order (columns shifted by coloff): all rows, or F rows only
+__device__ __forceinline__ void copy_row(const int* __restrict__ rp, const int* __restrict__ ci,
+                                         const double* __restrict__ v, int i, int coloff, int p,
+                                         int pend, int* __restrict__ dci, double* __restrict__ dv,
+                                         int* __restrict__ err) {
+  if (rp[i + 1] - rp[i] != pend - p) {  // target row length differs from the source row
+    atomicOr(err, 4);
+    return;
+  }
   for (int e = rp[i]; e < rp[i + 1]; ++e, ++p) {
     dci[p] = ci[e] + coloff;
     dv[p] = v[e];
   }
+}
+__global__ void k_row_copy(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const double* __restrict__ v, const int* __restrict__ srow, int coloff,
+                           const int* __restrict__ drp, int* __restrict__ dci,
+                           double* __restrict__ dv, int* __restrict__ err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int s = srow[i];
+  copy_row(rp, ci, v, i, coloff, drp[s], drp[s + 1], dci, dv, err);
+}
+__global__ void k_row_copy_f(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                             const double* __restrict__ v, const int* __restrict__ srow, int sbase,
+                             const int8_t* __restrict__ cf, int coloff,
+                             const int* __restrict__ drp, int* __restrict__ dci,
+                             double* __restrict__ dv, int* __restrict__ err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (cf[i] == kC) return;
+  const int s = srow[i] - sbase;
+  copy_row(rp, ci, v, i, coloff, drp[s], drp[s + 1], dci, dv, err);
 }
 
 template <typename T>
@@ -98,6 +154,101 @@ struct MemberAtLevel {
 // Tuning of the stored-matrix row-group width on a built level.
 template <typename T>
 static int tune_level(Ctx* c, ULevel<T>& lv, int autotune, bool fp32);
+
+// Host-side verification of a union level (MGD_DEBUG_UNION=1): the stored-row
+// map is a permutation, row lengths and row pointers agree with the members'
+// matrices, and every copied row equals its source row.  Throws with the first
+// mismatch; used to diagnose, never needed for correct operation.
+static bool debug_union() {
+  static const bool on = [] {
+    const char* e = std::getenv("MGD_DEBUG_UNION");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
+static void verify_flags_and_scans(Ctx* c, int n, const int8_t* cf_d, const int* isc_d,
+                                   const int* isf_d, const int* cidx_d, const int* fidx_d) {
+  std::vector<int8_t> cf(n, 0);
+  std::vector<int> isc(n), isf(n), cidx((size_t)n + 1), fidx((size_t)n + 1);
+  if (cf_d) copy_d2h(c, cf.data(), cf_d, (size_t)n);
+  copy_d2h(c, isc.data(), isc_d, (size_t)n);
+  copy_d2h(c, isf.data(), isf_d, (size_t)n);
+  copy_d2h(c, cidx.data(), cidx_d, (size_t)n + 1);
+  copy_d2h(c, fidx.data(), fidx_d, (size_t)n + 1);
+  int sc = 0, sf = 0;
+  for (int i = 0; i <= n; ++i) {
+    if (cidx[i] != sc || fidx[i] != sf) {
+      std::string ctx = "";
+      for (int k = std::max(0, i - 3); k < std::min(n, i + 4); ++k)
+        ctx += " [" + std::to_string(k) + ": cf " + std::to_string((int)cf[k]) + " isc " +
+               std::to_string(isc[k]) + " isf " + std::to_string(isf[k]) + " cidx " +
+               std::to_string(cidx[k]) + " fidx " + std::to_string(fidx[k]) + "]";
+      fail(MGD_EHIP, "union debug: scan mismatch at " + std::to_string(i) + " of " +
+                         std::to_string(n) + ": cidx " + std::to_string(cidx[i]) + " expected " +
+                         std::to_string(sc) + ", fidx " + std::to_string(fidx[i]) + " expected " +
+                         std::to_string(sf) + ";" + ctx);
+    }
+    if (i == n) break;
+    const int want = cf_d && cf[i] == kC ? 1 : 0;
+    if (isc[i] != want || isf[i] != 1 - want)
+      fail(MGD_EHIP, "union debug: flags at " + std::to_string(i) + ": cf " +
+                         std::to_string((int)cf[i]) + " isc " + std::to_string(isc[i]) + " isf " +
+                         std::to_string(isf[i]));
+    sc += isc[i];
+    sf += isf[i];
+  }
+}
+static void verify_union_level(Ctx* c, const std::vector<MemberAtLevel>& ms,
+                               const std::vector<DBuf<int>>& srows, int nS, const int* alen_d,
+                               const Csr<double>* Ad) {
+  std::vector<int> alen(nS), seen(nS, -1);
+  copy_d2h(c, alen.data(), alen_d, (size_t)nS);
+  std::vector<int> arp, aci;
+  if (Ad) {
+    arp.resize((size_t)nS + 1);
+    aci.resize((size_t)std::max(Ad->nnz, 1));
+    copy_d2h(c, arp.data(), Ad->rp.get(), (size_t)nS + 1);
+    copy_d2h(c, aci.data(), Ad->ci.get(), (size_t)Ad->nnz);
+    long long acc = 0;
+    for (int s = 0; s < nS; ++s) {
+      if (arp[s] != acc)
+        fail(MGD_EHIP, "union debug: row_ptr[" + std::to_string(s) + "] = " +
+                           std::to_string(arp[s]) + ", scan of lengths gives " + std::to_string(acc));
+      acc += alen[s];
+    }
+    if (arp[nS] != acc || acc != Ad->nnz)
+      fail(MGD_EHIP, "union debug: row_ptr[nS] = " + std::to_string(arp[nS]) + ", total " +
+                         std::to_string(acc) + ", nnz " + std::to_string(Ad->nnz));
+  }
+  for (size_t q = 0; q < ms.size(); ++q) {
+    const auto& m = ms[q];
+    if (m.kind == 2) continue;
+    const int n = m.n;
+    std::vector<int> srow(n), rp((size_t)n + 1), ci((size_t)std::max(m.lev->A.nnz, 1));
+    copy_d2h(c, srow.data(), srows[q].get(), (size_t)n);
+    copy_d2h(c, rp.data(), m.lev->A.rp.get(), (size_t)n + 1);
+    copy_d2h(c, ci.data(), m.lev->A.ci.get(), (size_t)m.lev->A.nnz);
+    for (int i = 0; i < n; ++i) {
+      const int s = srow[i];
+      const std::string at = "member " + std::to_string(q) + " row " + std::to_string(i) +
+                             " -> stored " + std::to_string(s);
+      if (s < 0 || s >= nS) fail(MGD_EHIP, "union debug: " + at + " out of range");
+      if (seen[s] >= 0)
+        fail(MGD_EHIP, "union debug: " + at + " also taken by row " + std::to_string(seen[s]));
+      seen[s] = i;
+      const int len = rp[i + 1] - rp[i];
+      if (alen[s] != len)
+        fail(MGD_EHIP, "union debug: " + at + " length " + std::to_string(alen[s]) + ", source " +
+                           std::to_string(len));
+      if (Ad)
+        for (int k = 0; k < len; ++k)
+          if (aci[(size_t)arp[s] + k] != ci[(size_t)rp[i] + k] + m.off)
+            fail(MGD_EHIP, "union debug: " + at + " entry " + std::to_string(k) + " column " +
+                               std::to_string(aci[(size_t)arp[s] + k]) + ", source " +
+                               std::to_string(ci[(size_t)rp[i] + k]) + " + " + std::to_string(m.off));
+    }
+  }
+}
 
 template <typename T>
 std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHierarchy*>& members,
@@ -141,10 +292,14 @@ std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHiera
     const int nS = lv.nS, nF = nFtot;
     lv.perm.alloc(c, (size_t)std::max(nS, 1));
     lv.dinv.alloc(c, (size_t)std::max(nS, 1));
-    DBuf<int> alen(c, (size_t)nS + 1), wlen(c, (size_t)nF + 1);
+    DBuf<int> alen(c, (size_t)nS + 1), wlen(c, (size_t)nF + 1), hits(c, (size_t)nS + 1);
+    fill<int>(c, alen.get(), 0, (size_t)nS + 1);
     fill<int>(c, wlen.get(), 0, (size_t)nF + 1);
+    fill<int>(c, hits.get(), 0, (size_t)nS + 1);
+    int* bad = c->err_flag();
     std::vector<DBuf<int>> srows;
     int cbase = 0, fbase = nCtot;
+    long long want_a = 0, want_w = 0;  // nnz the stored matrix and W must end with
     for (auto& m : ms) {
       DBuf<int> srow;
       if (m.kind == 2) {
@@ -153,45 +308,78 @@ std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHiera
       }
       const int n = m.n, g = cdiv(n, 256);
       srow.alloc(c, (size_t)n);
-      DBuf<int> isc(c, n), isf(c, n), cidx(c, (size_t)n + 1), fidx(c, (size_t)n + 1);
       const int8_t* cf = m.kind == 0 ? m.lev->cf.get() : nullptr;
-      hipLaunchKernelGGL(k_flags, dim3(g), dim3(256), 0, c->stream, n, cf, isc.get(), isf.get());
+      if (m.kind == 0) {
+        DBuf<int> isc(c, n), isf(c, n), cidx(c, (size_t)n + 1), fidx(c, (size_t)n + 1);
+        hipLaunchKernelGGL(k_flags, dim3(g), dim3(256), 0, c->stream, n, cf, isc.get(), isf.get());
+        MGD_CHECK_LAUNCH();
+        exclusive_scan(c, isc.get(), cidx.get(), n);
+        exclusive_scan(c, isf.get(), fidx.get(), n);
+        if (debug_union()) verify_flags_and_scans(c, n, cf, isc.get(), isf.get(), cidx.get(), fidx.get());
+        hipLaunchKernelGGL(k_map_rows, dim3(g), dim3(256), 0, c->stream, n, cf,
+                           (const int*)cidx.get(), (const int*)fidx.get(), cbase, fbase, m.off,
+                           srow.get(), lv.perm.get());
+        MGD_CHECK_LAUNCH();
+        c->sync();
+      } else {
+        hipLaunchKernelGGL(k_map_rows_allf, dim3(g), dim3(256), 0, c->stream, n, fbase, m.off,
+                           srow.get(), lv.perm.get());
+        MGD_CHECK_LAUNCH();
+      }
+      hipLaunchKernelGGL(k_count_hits, dim3(g), dim3(256), 0, c->stream, n,
+                         (const int*)srow.get(), nS, hits.get(), bad);
       MGD_CHECK_LAUNCH();
-      exclusive_scan(c, isc.get(), cidx.get(), n);
-      exclusive_scan(c, isf.get(), fidx.get(), n);
-      hipLaunchKernelGGL(k_map_rows, dim3(g), dim3(256), 0, c->stream, n, cf,
-                         (const int*)cidx.get(), (const int*)fidx.get(), cbase, fbase, m.off,
-                         srow.get(), lv.perm.get());
-      MGD_CHECK_LAUNCH();
-      hipLaunchKernelGGL(k_row_len, dim3(g), dim3(256), 0, c->stream, n, m.lev->A.rp.get(),
-                         (const int*)srow.get(), 0, (const int8_t*)nullptr, alen.get());
-      MGD_CHECK_LAUNCH();
-      if (m.kind == 0)
-        hipLaunchKernelGGL(k_row_len, dim3(g), dim3(256), 0, c->stream, n, m.lev->P.rp.get(),
-                           (const int*)srow.get(), nCtot, cf, wlen.get());
-      MGD_CHECK_LAUNCH();
-      DBuf<double> d(c, (size_t)n);
-      l1_diagonal(c, m.lev->A, d.get());
-      hipLaunchKernelGGL(k_dinv<T>, dim3(g), dim3(256), 0, c->stream, n, (const double*)d.get(),
-                         (const int*)srow.get(), lv.dinv.get());
-      MGD_CHECK_LAUNCH();
-      c->sync();
+      want_a += m.lev->A.nnz;
+      if (m.kind == 0) want_w += (long long)m.lev->P.nnz - m.nc;
       cbase += m.nc;
       fbase += (m.kind == 0) ? m.n - m.nc : m.n;
       srows.push_back(std::move(srow));
     }
+    if (nS > 0) {
+      hipLaunchKernelGGL(k_check_hits, dim3(cdiv(nS, 256)), dim3(256), 0, c->stream, nS,
+                         (const int*)hits.get(), bad);
+      MGD_CHECK_LAUNCH();
+    }
+    c->check_device_errors("stored-row map of a solve-phase level");
+    // the map is a permutation: lengths, diagonals
+    for (size_t q = 0; q < ms.size(); ++q) {
+      auto& m = ms[q];
+      if (m.kind == 2) continue;
+      const int n = m.n, g = cdiv(n, 256);
+      hipLaunchKernelGGL(k_row_len, dim3(g), dim3(256), 0, c->stream, n, m.lev->A.rp.get(),
+                         (const int*)srows[q].get(), alen.get());
+      MGD_CHECK_LAUNCH();
+      if (m.kind == 0)
+        hipLaunchKernelGGL(k_row_len_f, dim3(g), dim3(256), 0, c->stream, n, m.lev->P.rp.get(),
+                           (const int*)srows[q].get(), nCtot, (const int8_t*)m.lev->cf.get(),
+                           wlen.get());
+      MGD_CHECK_LAUNCH();
+      DBuf<double> d(c, (size_t)n);
+      l1_diagonal(c, m.lev->A, d.get());
+      hipLaunchKernelGGL(k_dinv<T>, dim3(g), dim3(256), 0, c->stream, n, (const double*)d.get(),
+                         (const int*)srows[q].get(), lv.dinv.get());
+      MGD_CHECK_LAUNCH();
+      c->sync();
+    }
+    if (debug_union()) verify_union_level(c, ms, srows, nS, alen.get(), nullptr);
     // stored matrix (natural columns)
     Csr<double> Ad, Wd, Wtd;
     Ad.n_rows = nS;
     Ad.n_cols = lv.n;
     Ad.rp.alloc(c, (size_t)nS + 1);
     Ad.nnz = exclusive_scan_total(c, alen.get(), Ad.rp.get(), nS);
+    if (Ad.nnz != want_a)
+      fail(MGD_EHIP, "internal check failed: stored level matrix has " + std::to_string(Ad.nnz) +
+                         " entries, its members " + std::to_string(want_a) + step_suffix());
     Ad.ci.alloc(c, (size_t)std::max(Ad.nnz, 1));
     Ad.v.alloc(c, (size_t)std::max(Ad.nnz, 1));
     Wd.n_rows = nF;
     Wd.n_cols = ncoarse;
     Wd.rp.alloc(c, (size_t)nF + 1);
     Wd.nnz = exclusive_scan_total(c, wlen.get(), Wd.rp.get(), nF);
+    if (Wd.nnz != want_w)
+      fail(MGD_EHIP, "internal check failed: W has " + std::to_string(Wd.nnz) + " entries, " +
+                         std::to_string(want_w) + " expected" + step_suffix());
     Wd.ci.alloc(c, (size_t)std::max(Wd.nnz, 1));
     Wd.v.alloc(c, (size_t)std::max(Wd.nnz, 1));
     int coarse_off = 0;
@@ -205,20 +393,20 @@ std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHiera
       }
       const int n = m.n, g = cdiv(n, 256);
       hipLaunchKernelGGL(k_row_copy, dim3(g), dim3(256), 0, c->stream, n, m.lev->A.rp.get(),
-                         m.lev->A.ci.get(), m.lev->A.v.get(), (const int*)srows[q].get(), 0,
-                         (const int8_t*)nullptr, m.off, (const int*)Ad.rp.get(), Ad.ci.get(),
-                         Ad.v.get());
+                         m.lev->A.ci.get(), m.lev->A.v.get(), (const int*)srows[q].get(), m.off,
+                         (const int*)Ad.rp.get(), Ad.ci.get(), Ad.v.get(), bad);
       MGD_CHECK_LAUNCH();
       if (m.kind == 0) {
-        hipLaunchKernelGGL(k_row_copy, dim3(g), dim3(256), 0, c->stream, n, m.lev->P.rp.get(),
+        hipLaunchKernelGGL(k_row_copy_f, dim3(g), dim3(256), 0, c->stream, n, m.lev->P.rp.get(),
                            m.lev->P.ci.get(), m.lev->P.v.get(), (const int*)srows[q].get(), nCtot,
-                           m.lev->cf.get(), coarse_off, (const int*)Wd.rp.get(), Wd.ci.get(),
-                           Wd.v.get());
+                           (const int8_t*)m.lev->cf.get(), coarse_off, (const int*)Wd.rp.get(),
+                           Wd.ci.get(), Wd.v.get(), bad);
         MGD_CHECK_LAUNCH();
         coarse_off += m.nc;
       }
     }
-    c->sync();
+    c->check_device_errors("row copy into a solve-phase level");
+    if (debug_union()) verify_union_level(c, ms, srows, nS, alen.get(), &Ad);
     check_structure(c, Ad, "union level matrix", false);
     check_structure(c, Wd, "union interpolation", false);
     if (ncoarse > 0) transpose(c, Wd, Wtd);

@@ -94,16 +94,8 @@ def _compare_hierarchies(gamg, H, exact_values=True):
             assert info["pmis_rounds"][l] == L.pmis_rounds
 
 
-# amg_setup on the monolithic G=1 2D 64x64 matrix (seed 1 inputs, PMIS seed 7)
-# ended in a GPU memory fault once.  Emulated on the CPU (guard pages, ASan,
-# TSan, UBSan, several fill patterns of fresh allocations) the same calls are
-# clean and bit-exact, and no defect has been shown in the code, so the case
-# stays off the GPU until a cause is found.
-FAULTED = "faulted the GPU once (illegal memory access in amg_setup); cause not yet shown"
-
-
-@pytest.mark.parametrize("which", [pytest.param("mono_g1_2d64", marks=pytest.mark.skip(reason=FAULTED)),
-                                   "block_E_g2_2d16", "block_g0_3d10", "mono_g2_2d16_nonsym"])
+@pytest.mark.parametrize("which", ["mono_g1_2d64", "block_E_g2_2d16", "block_g0_3d10",
+                                   "mono_g2_2d16_nonsym"])
 def test_amg_setup_full_chain_bit_exact(ctx, which):
     api = gpu_modules()
     if which == "mono_g1_2d64":
@@ -181,7 +173,7 @@ def test_amg_rejects_invalid_csr(ctx):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_vcycle_parity(ctx, cycles, precision):
     api = gpu_modules()
-    A = oracle_system(si.generate(1, 2, 48, 14)).monolithic()
+    A = oracle_system(si.generate_workload("g1_2d64")).monolithic()
     H = oamg.setup(A, oamg.AMGParams(seed=1))
     g = api.AMG(ctx, A.indptr, A.indices, A.data, seed=1, precision=precision)
     b = np.random.default_rng(2).uniform(size=A.shape[0])
@@ -250,7 +242,7 @@ def test_block_preconditioner_parity(ctx, kind, mode):
 @pytest.mark.parametrize("kind", ["amg", "schur2", "schur1", "pctl"])
 def test_gmres_parity(ctx, kind):
     api = gpu_modules()
-    inp = si.generate(1, 2, 48, 15)
+    inp = si.generate_workload("g1_2d64")
     osys = oracle_system(inp)
     A = osys.monolithic()
     M_o = opc.BlockPreconditioner(osys, opc.BlockParams(kind=kind, amg=oamg.AMGParams(seed=1)))
