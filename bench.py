@@ -70,9 +70,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--counters-run", action="store_true",
-                    help="short run for hardware-counter passes: a 256 MiB streaming "
-                         "calibration kernel (torch mul, 256 MiB read + 256 MiB written), "
-                         "then the FP32 batched setup and --steps solves; no timing lines")
+                    help="short run for hardware-counter passes: a streaming calibration "
+                         "kernel (torch mul reading 1 GiB and writing 1 GiB, its input pushed "
+                         "out of the last-level cache first), then the FP32 batched setup and "
+                         "--steps solves; no timing lines")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is designed but "
@@ -109,17 +110,18 @@ def main():
         return x, r
 
     if a.counters_run:
-        src = torch.ones(64 << 20, dtype=torch.float32, device=ctx.device)
+        src = torch.ones(256 << 20, dtype=torch.float32, device=ctx.device)
+        flush = torch.ones(512 << 20, dtype=torch.float32, device=ctx.device)  # 2 GiB
         dst = torch.empty_like(src)
         torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
-        del src, dst
+        del src, dst, flush
         M32, _ = build(True, True, True)
         for _ in range(max(1, a.steps)):
             x, r = solve(M32)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "counters", "workload": w.name, "iters": r.iters,
-                          "calibration_bytes": {"read": 256 << 20, "written": 256 << 20}}))
+                          "calibration_bytes": {"read": 1 << 30, "written": 1 << 30}}))
         return
 
     # headline form: FP32 hierarchies, batched V-cycles, graph replay
