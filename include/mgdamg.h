@@ -288,6 +288,7 @@ typedef struct gmres_result {
   double relres_true; /* ||b - A x|| / ||b|| at exit */
   double t_total_ms;
   double t_precond_ms, t_matvec_ms, t_orth_ms; /* when profile = 1 */
+  int32_t reorths;    /* Arnoldi steps that needed the second Gram-Schmidt pass */
 } gmres_result;
 
 /* Solve A x = b.  x [dev] holds the initial guess on entry.  M may be NULL

@@ -69,7 +69,7 @@ class gmres_result(Structure):
     _fields_ = [("iters", c_int32), ("restarts", c_int32), ("converged", c_int32),
                 ("precond_applies", c_int32), ("relres_est", c_double),
                 ("relres_true", c_double), ("t_total_ms", c_double), ("t_precond_ms", c_double),
-                ("t_matvec_ms", c_double), ("t_orth_ms", c_double)]
+                ("t_matvec_ms", c_double), ("t_orth_ms", c_double), ("reorths", c_int32)]
 
 
 ALLOC_FN = CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p, c_void_p)

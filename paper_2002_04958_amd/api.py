@@ -400,6 +400,7 @@ class GmresResult:
     t_precond_ms: float
     t_matvec_ms: float
     t_orth_ms: float
+    reorths: int = 0
 
 
 def gmres_params(**kw) -> L.gmres_params:
@@ -415,7 +416,7 @@ def gmres_params(**kw) -> L.gmres_params:
 def _result(st, r) -> GmresResult:
     return GmresResult(st, r.iters, r.restarts, bool(r.converged), r.precond_applies,
                        r.relres_est, r.relres_true, r.t_total_ms, r.t_precond_ms,
-                       r.t_matvec_ms, r.t_orth_ms)
+                       r.t_matvec_ms, r.t_orth_ms, r.reorths)
 
 
 def gmres(ctx: Context, system: BlockSystem, M: Optional[BlockPreconditioner], b: torch.Tensor,

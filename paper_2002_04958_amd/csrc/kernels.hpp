@@ -28,16 +28,19 @@ struct RedWork {
 };
 // out[0] = sum x_i y_i  (device scalar)
 void dot_dev(Ctx* c, RedWork& w, const double* x, const double* y, size_t n, double* out);
-// h[i] = V_i . w for i < J (V rows of stride ldv)
+// Arnoldi orthogonalisation of w against V_0..V_{J-1} (rows of stride ldv),
+// classical Gram-Schmidt with selective reorthogonalisation (J < 32):
+//   mdot_dev:        h[i] = V_i . w (i < J), h[J] = w . w
+//   update_mdot_dev: w -= sum h_i V_i; h2[i] = V_i . w_new, h2[J] = w_new . w_new
+//   update_norm_dev: only if h2[J] < h1[J] / 2: w -= sum h2_i V_i; nrm2[0] = w_new . w_new
+//   arnoldi_finish:  hcol[0..J-1] = h1 (+ h2 if the second pass ran), hcol[J] = the
+//                    norm, hcol[J+1] = 1 if the second pass ran; v_next = w / hcol[J]
 void mdot_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* wv, size_t n,
               double* h);
-// w -= sum_i h_i V_i, then h2[i] = V_i . w_new  (J dots)
 void update_mdot_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* h,
                      double* wv, size_t n, double* h2);
-// w -= sum_i h_i V_i, then nrm2[0] = w_new . w_new
-void update_norm_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* h,
-                     double* wv, size_t n, double* nrm2);
-// y = x / sqrt(nrm2[0]) (y = 0 when nrm2 == 0); hcol[j+1] = sqrt(nrm2); hcol[0..j] = h1+h2
+void update_norm_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* h1,
+                     const double* h2, double* wv, size_t n, double* nrm2);
 void arnoldi_finish(Ctx* c, const double* h1, const double* h2, const double* nrm2, int J,
                     double* hcol, double* v_next, const double* w, size_t n);
 // x += sum_i y_i Z_i (y on device)

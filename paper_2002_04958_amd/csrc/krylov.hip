@@ -1,9 +1,12 @@
 // Restarted right-preconditioned (flexible) GMRES(m) on the block system of
-// eq. 2.2.  Arnoldi uses classical Gram-Schmidt applied twice; the second
-// projection is fused with the first update pass and the norm with the
-// second, so one Arnoldi step reads the basis three times.  The small
+// eq. 2.2.  Arnoldi uses classical Gram-Schmidt with selective
+// reorthogonalisation: the projection coefficients and the norm come from one
+// pass over the basis, the update is fused with the second projection, and a
+// third pass (second update) runs only when the first projection removed more
+// than half of the norm.  The small
 // Hessenberg least-squares problem (Givens rotations) runs on the host from
 // one readback of the new column per step.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 
@@ -110,15 +113,16 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
       if (evo) MGD_HIP(hipEventRecord(evo->a, c->stream));
       mdot_dev(c, rw, V.get(), n, J, w, n, h1);
       update_mdot_dev(c, rw, V.get(), n, J, h1, w, n, h2);
-      update_norm_dev(c, rw, V.get(), n, J, h2, w, n, nrm2);
+      update_norm_dev(c, rw, V.get(), n, J, h1, h2, w, n, nrm2);
       arnoldi_finish(c, h1, h2, nrm2, J, hc, w, w, n);
       if (evo) MGD_HIP(hipEventRecord(evo->b, c->stream));
-      MGD_HIP(hipMemcpyAsync(hbuf, hc, (J + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      MGD_HIP(hipMemcpyAsync(hbuf, hc, (J + 2) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
       c->sync();
       if (evp && M) res.t_precond_ms += evp->ms();
       if (evm) res.t_matvec_ms += evm->ms();
       if (evo) res.t_orth_ms += evo->ms();
       for (int i = 0; i <= J; ++i) Hij(i, j) = hbuf[i];
+      if (hbuf[J + 1] != 0.0) res.reorths++;
       breakdown = Hij(j + 1, j) == 0.0;
       for (int i = 0; i < j; ++i) {
         const double tt = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
@@ -144,7 +148,8 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
       for (int q = i + 1; q < k; ++q) s -= Hij(i, q) * y[q];
       y[i] = s / Hij(i, i);
     }
-    MGD_HIP(hipMemcpyAsync(yd, y.data(), k * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    std::copy(y.begin(), y.begin() + k, hbuf + 32);  // pinned staging (k <= 31)
+    MGD_HIP(hipMemcpyAsync(yd, hbuf + 32, k * sizeof(double), hipMemcpyHostToDevice, c->stream));
     if (!M) {
       combine_dev(c, V.get(), n, k, yd, x, n);
     } else if (flex) {

@@ -540,14 +540,30 @@ __global__ void __launch_bounds__(256) k_prolong(int nS, int nC, const int* __re
 }
 
 // x = A^{-1} b for every dense-solved member (FP64 arithmetic)
+// One workgroup column of 64 rows per member; the loop is unrolled so that
+// eight coalesced column loads are in flight per step (the sum stays in
+// ascending j).
 template <typename T>
 __global__ void __launch_bounds__(64) k_dense(const DenseDev* __restrict__ tab,
                                               const T* __restrict__ b, T* __restrict__ X) {
   const DenseDev d = tab[blockIdx.y];
   const int i = blockIdx.x * 64 + threadIdx.x;
   if (i >= d.n) return;
+  const double* __restrict__ col = d.inv + i;
+  const T* __restrict__ bb = b + d.off;
   double s = 0.0;
-  for (int j = 0; j < d.n; ++j) s += d.inv[(size_t)j * d.n + i] * (double)b[d.off + j];
+  int j = 0;
+  for (; j + 8 <= d.n; j += 8) {
+    double a[8], x[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      a[q] = col[(size_t)(j + q) * d.n];
+      x[q] = (double)bb[j + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += a[q] * x[q];
+  }
+  for (; j < d.n; ++j) s += col[(size_t)j * d.n] * (double)bb[j];
   X[d.off + i] = (T)s;
 }
 

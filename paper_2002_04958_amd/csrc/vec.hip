@@ -202,6 +202,19 @@ __global__ void __launch_bounds__(256) k_red_final(const double* __restrict__ pa
   if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
+// k_red_final for the reorthogonalisation pass: skipped with it
+__global__ void __launch_bounds__(256) k_red_final_if(const double* __restrict__ partial, int nb,
+                                                      const double* __restrict__ h1,
+                                                      const double* __restrict__ h2, int J,
+                                                      double* __restrict__ out) {
+  __shared__ double lds[4];
+  if (!(h2[J] < 0.5 * h1[J])) return;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) s += partial[b];
+  s = block_sum256(s, lds);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
 __global__ void __launch_bounds__(256) k_dot(const double* __restrict__ x,
                                              const double* __restrict__ y, size_t n,
                                              double* __restrict__ partial) {
@@ -226,45 +239,51 @@ void dot_dev(Ctx* c, RedWork& w, const double* x, const double* y, size_t n, dou
 
 constexpr int kMaxJ = 32;
 
-// mode 0: h[j] = V_j . w
-// mode 1: w -= sum h_in[j] V_j ; h[j] = V_j . w_new
-// mode 2: w -= sum h_in[j] V_j ; h[0] = w_new . w_new
-template <int MODE>
+// Arnoldi orthogonalisation passes (classical Gram-Schmidt with selective
+// reorthogonalisation, Daniel-Gragg-Kaufman-Stewart criterion eta = 1/sqrt 2):
+// mode 0: h[j] = V_j . w,                            h[J] = w . w
+// mode 1: w -= sum h_in[j] V_j;  h[j] = V_j . w_new, h[J] = w_new . w_new
+// mode 2: only when h2[J] < h1[J] / 2 (the first projection lost more than
+//         half the norm): w -= sum h2[j] V_j;        h[0] = w_new . w_new
+template <int MODE, int JB>
 __global__ void __launch_bounds__(256) k_mdot(const double* __restrict__ V, size_t ldv, int J,
                                               const double* __restrict__ h_in,
+                                              const double* __restrict__ h_first,
                                               double* __restrict__ w, size_t n,
                                               double* __restrict__ partial, int nb) {
   __shared__ double lds[4];
-  double acc[kMaxJ];
-  double hv[kMaxJ];
+  if (MODE == 2 && !(h_in[J] < 0.5 * h_first[J])) return;  // no reorthogonalisation needed
+  double acc[JB + 1];
+  double hv[JB];
 #pragma unroll
-  for (int j = 0; j < kMaxJ; ++j) {
+  for (int j = 0; j < JB; ++j) {
     acc[j] = 0.0;
     hv[j] = (MODE != 0 && j < J) ? h_in[j] : 0.0;
   }
+  acc[JB] = 0.0;
   double nacc = 0.0;
   for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
     double wi = w[i];
     if (MODE == 0) {
 #pragma unroll
-      for (int j = 0; j < kMaxJ; ++j)
+      for (int j = 0; j < JB; ++j)
         if (j < J) acc[j] += V[j * ldv + i] * wi;
+      nacc += wi * wi;
     } else {
-      double vj[kMaxJ];
+      double vj[JB];
 #pragma unroll
-      for (int j = 0; j < kMaxJ; ++j)
+      for (int j = 0; j < JB; ++j)
         if (j < J) vj[j] = V[j * ldv + i];
 #pragma unroll
-      for (int j = 0; j < kMaxJ; ++j)
+      for (int j = 0; j < JB; ++j)
         if (j < J) wi -= hv[j] * vj[j];
       w[i] = wi;
       if (MODE == 1) {
 #pragma unroll
-        for (int j = 0; j < kMaxJ; ++j)
+        for (int j = 0; j < JB; ++j)
           if (j < J) acc[j] += vj[j] * wi;
-      } else {
-        nacc += wi * wi;
       }
+      nacc += wi * wi;
     }
   }
   if (MODE == 2) {
@@ -272,64 +291,106 @@ __global__ void __launch_bounds__(256) k_mdot(const double* __restrict__ V, size
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
     return;
   }
-  for (int j = 0; j < J; ++j) {
-    double s = block_sum256(acc[j], lds);
-    if (threadIdx.x == 0) partial[(size_t)j * nb + blockIdx.x] = s;
+#pragma unroll
+  for (int j = 0; j < JB; ++j) {
+    if (j < J) {  // J is uniform: every thread takes the same branches around the barriers
+      double s = block_sum256(acc[j], lds);
+      if (threadIdx.x == 0) partial[(size_t)j * nb + blockIdx.x] = s;
+    }
   }
+  double s = block_sum256(nacc, lds);
+  if (threadIdx.x == 0) partial[(size_t)J * nb + blockIdx.x] = s;
+}
+
+struct MdotArgs {
+  const double* V;
+  size_t ldv;
+  int J;
+  const double* h_in;
+  const double* h_first;
+  double* w;
+  size_t n;
+  double* partial;
+  int nb;
+};
+// register arrays sized to the next power of two >= J keep occupancy up for short bases
+static int mdot_jb(int J) { return J <= 4 ? 4 : J <= 8 ? 8 : J <= 16 ? 16 : 32; }
+template <int MODE>
+static void launch_mdot(Ctx* c, const MdotArgs& a) {
+  const dim3 g(a.nb), b(256);
+#define MGD_MDOT(JB)                                                                             \
+  hipLaunchKernelGGL((k_mdot<MODE, JB>), g, b, 0, c->stream, a.V, a.ldv, a.J, a.h_in, a.h_first, \
+                     a.w, a.n, a.partial, a.nb)
+  if (a.J <= 4)
+    MGD_MDOT(4);
+  else if (a.J <= 8)
+    MGD_MDOT(8);
+  else if (a.J <= 16)
+    MGD_MDOT(16);
+  else
+    MGD_MDOT(32);
+#undef MGD_MDOT
+  MGD_CHECK_LAUNCH();
 }
 
 void mdot_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* wv, size_t n,
               double* h) {
-  MGD_REQUIRE(J >= 1 && J <= kMaxJ, "mdot: J out of range");
+  MGD_REQUIRE(J >= 1 && J < kMaxJ, "mdot: J out of range");
   w.ensure(c);
-  ProfScope ps(c, KC_ORTH, 8.0 * n * (J + 1));
+  ProfScope ps(c, KC_ORTH, 8.0 * n * (J + 1), ksym(c, "k_mdot", {"0", std::to_string(mdot_jb(J))}));
   int g = red_grid(n);
-  hipLaunchKernelGGL(k_mdot<0>, dim3(g), dim3(256), 0, c->stream, V, ldv, J, (const double*)nullptr,
-                     const_cast<double*>(wv), n, w.partial.get(), g);
+  MdotArgs a{V, ldv, J, nullptr, nullptr, const_cast<double*>(wv), n, w.partial.get(), g};
+  launch_mdot<0>(c, a);
   MGD_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_red_final, dim3(J), dim3(256), 0, c->stream, (const double*)w.partial.get(),
-                     g, h);
+  hipLaunchKernelGGL(k_red_final, dim3(J + 1), dim3(256), 0, c->stream,
+                     (const double*)w.partial.get(), g, h);
   MGD_CHECK_LAUNCH();
 }
 
 void update_mdot_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* h,
                      double* wv, size_t n, double* h2) {
-  MGD_REQUIRE(J >= 1 && J <= kMaxJ, "mdot: J out of range");
+  MGD_REQUIRE(J >= 1 && J < kMaxJ, "mdot: J out of range");
   w.ensure(c);
-  ProfScope ps(c, KC_ORTH, 8.0 * n * (J + 2));
+  ProfScope ps(c, KC_ORTH, 8.0 * n * (J + 2), ksym(c, "k_mdot", {"1", std::to_string(mdot_jb(J))}));
   int g = red_grid(n);
-  hipLaunchKernelGGL(k_mdot<1>, dim3(g), dim3(256), 0, c->stream, V, ldv, J, h, wv, n,
-                     w.partial.get(), g);
+  MdotArgs a{V, ldv, J, h, nullptr, wv, n, w.partial.get(), g};
+  launch_mdot<1>(c, a);
   MGD_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_red_final, dim3(J), dim3(256), 0, c->stream, (const double*)w.partial.get(),
-                     g, h2);
+  hipLaunchKernelGGL(k_red_final, dim3(J + 1), dim3(256), 0, c->stream,
+                     (const double*)w.partial.get(), g, h2);
   MGD_CHECK_LAUNCH();
 }
 
-void update_norm_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* h,
-                     double* wv, size_t n, double* nrm2) {
-  MGD_REQUIRE(J >= 1 && J <= kMaxJ, "mdot: J out of range");
+void update_norm_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* h1,
+                     const double* h2, double* wv, size_t n, double* nrm2) {
+  MGD_REQUIRE(J >= 1 && J < kMaxJ, "mdot: J out of range");
   w.ensure(c);
-  ProfScope ps(c, KC_ORTH, 8.0 * n * (J + 2));
+  ProfScope ps(c, KC_ORTH, 8.0 * n * (J + 2), ksym(c, "k_mdot", {"2", std::to_string(mdot_jb(J))}));
   int g = red_grid(n);
-  hipLaunchKernelGGL(k_mdot<2>, dim3(g), dim3(256), 0, c->stream, V, ldv, J, h, wv, n,
-                     w.partial.get(), g);
+  MdotArgs a{V, ldv, J, h2, h1, wv, n, w.partial.get(), g};
+  launch_mdot<2>(c, a);
   MGD_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_red_final, dim3(1), dim3(256), 0, c->stream, (const double*)w.partial.get(),
-                     g, nrm2);
+  hipLaunchKernelGGL(k_red_final_if, dim3(1), dim3(256), 0, c->stream,
+                     (const double*)w.partial.get(), g, h1, h2, J, nrm2);
   MGD_CHECK_LAUNCH();
 }
 
+// Arnoldi column: h = h1 (+ h2 when reorthogonalised), h[J] = the new norm;
+// hcol[J+1] = 1 when the second pass ran.
 __global__ void k_arnoldi_finish_h(const double* __restrict__ h1, const double* __restrict__ h2,
                                    const double* __restrict__ nrm2, int J,
                                    double* __restrict__ hcol) {
-  int j = threadIdx.x;
-  if (j < J) hcol[j] = h1[j] + h2[j];
-  if (j == 0) hcol[J] = sqrt(nrm2[0]);
+  const bool re = h2[J] < 0.5 * h1[J];
+  const int j = threadIdx.x;
+  if (j < J) hcol[j] = re ? h1[j] + h2[j] : h1[j];
+  if (j == 0) {
+    hcol[J] = sqrt(re ? nrm2[0] : h2[J]);
+    hcol[J + 1] = re ? 1.0 : 0.0;
+  }
 }
-__global__ void k_scale_by_norm(const double* __restrict__ nrm2, const double* __restrict__ w,
-                                double* __restrict__ v, size_t n) {
-  double nr = sqrt(nrm2[0]);
+__global__ void k_scale_by_norm(const double* __restrict__ hcol, int J,
+                                const double* __restrict__ w, double* __restrict__ v, size_t n) {
+  const double nr = hcol[J];
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)
     v[i] = nr > 0.0 ? w[i] / nr : 0.0;
@@ -339,9 +400,10 @@ void arnoldi_finish(Ctx* c, const double* h1, const double* h2, const double* nr
                     double* hcol, double* v_next, const double* w, size_t n) {
   hipLaunchKernelGGL(k_arnoldi_finish_h, dim3(1), dim3(64), 0, c->stream, h1, h2, nrm2, J, hcol);
   MGD_CHECK_LAUNCH();
-  ProfScope ps(c, KC_ORTH, 16.0 * n);
+  ProfScope ps(c, KC_ORTH, 16.0 * n, ksym(c, "k_scale_by_norm", {}));
   int g = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 8192);
-  hipLaunchKernelGGL(k_scale_by_norm, dim3(g), dim3(kBlock), 0, c->stream, nrm2, w, v_next, n);
+  hipLaunchKernelGGL(k_scale_by_norm, dim3(g), dim3(kBlock), 0, c->stream, (const double*)hcol, J,
+                     w, v_next, n);
   MGD_CHECK_LAUNCH();
 }
 
