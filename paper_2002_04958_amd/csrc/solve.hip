@@ -119,29 +119,76 @@ __global__ void k_row_copy_f(int n, const int* __restrict__ rp, const int* __res
   copy_row(rp, ci, v, i, coloff, drp[s], drp[s + 1], dci, dv, err);
 }
 
+__global__ void k_iota(int n, int first, int* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = first + i;
+}
+// inverse of a permutation given as perm[k] (k < n), with a range check
+__global__ void k_invert(int n, const int* __restrict__ perm, int* __restrict__ inv,
+                         int* __restrict__ err) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int i = perm[k];
+  if (i < 0 || i >= n) {
+    atomicOr(err, 8);
+    return;
+  }
+  inv[i] = k;
+}
+// columns through a map (entry order kept)
+__global__ void k_remap(long long nnz, const int* __restrict__ map, int ncols_map,
+                        int* __restrict__ ci, int* __restrict__ err) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const int j = ci[e];
+  if (j < 0 || j >= ncols_map) {
+    atomicOr(err, 16);
+    return;
+  }
+  ci[e] = map[j];
+}
+// row gather: out row k = in row src[k]
+__global__ void k_gather_len(int n, const int* __restrict__ rp, const int* __restrict__ src,
+                             int* __restrict__ len) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) len[k] = rp[src[k] + 1] - rp[src[k]];
+}
+__global__ void k_gather_rows(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                              const double* __restrict__ v, const int* __restrict__ src,
+                              const int* __restrict__ orp, int* __restrict__ oci,
+                              double* __restrict__ ov, int* __restrict__ err) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int i = src[k];
+  int p = orp[k];
+  if (orp[k + 1] - p != rp[i + 1] - rp[i]) {
+    atomicOr(err, 32);
+    return;
+  }
+  for (int e = rp[i]; e < rp[i + 1]; ++e, ++p) {
+    oci[p] = ci[e];
+    ov[p] = v[e];
+  }
+}
+// out[i] = a[b[i]] with b[i] in [0, na)
+__global__ void k_compose(int n, const int* __restrict__ a, int na, const int* __restrict__ bidx,
+                          int* __restrict__ out, int* __restrict__ err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int j = bidx[i];
+  if (j < 0 || j >= na) {
+    atomicOr(err, 64);
+    return;
+  }
+  out[i] = a[j];
+}
+
 template <typename T>
 __global__ void k_dinv(int n, const double* __restrict__ d, const int* __restrict__ srow,
                        T* __restrict__ dinv) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   dinv[srow[i]] = (T)(1.0 / d[i]);
-}
-
-template <typename T>
-static void csr_to(Ctx* c, Csr<double>& src, Csr<T>& dst) {
-  if constexpr (std::is_same<T, double>::value) {
-    dst = std::move(src);
-  } else {
-    dst.n_rows = src.n_rows;
-    dst.n_cols = src.n_cols;
-    dst.nnz = src.nnz;
-    dst.rp = std::move(src.rp);
-    dst.ci = std::move(src.ci);
-    dst.v.alloc(c, (size_t)src.nnz);
-    cast_copy<T, double>(c, dst.v.get(), src.v.get(), (size_t)src.nnz, KC_VEC);
-    c->sync();
-    src.v.reset();
-  }
 }
 
 struct MemberAtLevel {
@@ -151,9 +198,25 @@ struct MemberAtLevel {
   int off, n, nc;
 };
 
-// Tuning of the stored-matrix row-group width on a built level.
+// Level products of the construction pass, before the stored-order finalisation.
 template <typename T>
-static int tune_level(Ctx* c, ULevel<T>& lv, int autotune, bool fp32);
+struct BuildLevel {
+  int n = 0, nS = 0, nC = 0, n_coarse = 0;
+  Csr<double> A;   // nS rows (stored order), natural columns
+  Csr<double> W;   // nS - nC rows, coarse natural columns
+  Csr<double> Wt;  // n_coarse rows (coarse natural), F-index columns
+  DBuf<int> perm;  // stored -> natural (nS)
+  DBuf<int> cnat;  // C-block position -> coarse natural index (nC); empty: identity
+  DBuf<T> dinv;    // nS
+  long long nnz_C = 0;
+  struct Dense {
+    int off, n;
+    const double* inv;
+  };
+  std::vector<Dense> dense;  // natural offsets
+};
+template <typename T>
+static void finalize_levels(Ctx* c, std::vector<BuildLevel<T>>& bl, Union<T>& U, int autotune);
 
 // Host-side verification of a union level (MGD_DEBUG_UNION=1): the stored-row
 // map is a permutation, row lengths and row pointers agree with the members'
@@ -250,6 +313,8 @@ static void verify_union_level(Ctx* c, const std::vector<MemberAtLevel>& ms,
   }
 }
 
+constexpr int kSortWindow = 512;
+
 template <typename T>
 std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHierarchy*>& members,
                                       int n_pre, int n_post, int autotune) {
@@ -257,6 +322,7 @@ std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHiera
   U->n_pre = n_pre;
   U->n_post = n_post;
   U->members = (int)members.size();
+  std::vector<BuildLevel<T>> built;
   size_t maxL = 0;
   for (auto* H : members) maxL = std::max(maxL, H->levels.size());
   for (size_t l = 0; l < maxL; ++l) {
@@ -284,7 +350,7 @@ std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHiera
       }
       ms.push_back(m);
     }
-    ULevel<T> lv;
+    BuildLevel<T> lv;
     lv.n = off;
     lv.nC = nCtot;
     lv.nS = nCtot + nFtot;
@@ -341,6 +407,51 @@ std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHiera
       MGD_CHECK_LAUNCH();
     }
     c->check_device_errors("stored-row map of a solve-phase level");
+    // Below the finest level, rows of the C-block and of the F-block are ordered
+    // by decreasing length (stable) within windows of kSortWindow rows, so that
+    // 64-row slices hold rows of similar length while neighbouring rows stay
+    // close; the coarse numbering stays member order and is kept in cnat.
+    if (l > 0 && nS > 0) {
+      for (size_t q = 0; q < ms.size(); ++q) {
+        const auto& m = ms[q];
+        if (m.kind == 2) continue;
+        hipLaunchKernelGGL(k_row_len, dim3(cdiv(m.n, 256)), dim3(256), 0, c->stream, m.n,
+                           m.lev->A.rp.get(), (const int*)srows[q].get(), alen.get());
+        MGD_CHECK_LAUNCH();
+      }
+      std::vector<int> len(nS), pm(nS), qpos(nS), cn(std::max(nCtot, 1));
+      copy_d2h(c, len.data(), alen.get(), (size_t)nS);
+      copy_d2h(c, pm.data(), lv.perm.get(), (size_t)nS);
+      std::vector<int> order(nS);
+      for (int k = 0; k < nS; ++k) order[k] = k;
+      // windows of kSortWindow rows keep neighbouring rows close together
+      auto by_len = [&](int a, int b2) { return len[a] > len[b2]; };
+      for (int w0 = 0; w0 < nCtot; w0 += kSortWindow)
+        std::stable_sort(order.begin() + w0, order.begin() + std::min(nCtot, w0 + kSortWindow),
+                         by_len);
+      for (int w0 = nCtot; w0 < nS; w0 += kSortWindow)
+        std::stable_sort(order.begin() + w0, order.begin() + std::min(nS, w0 + kSortWindow),
+                         by_len);
+      std::vector<int> pm2(nS);
+      for (int k = 0; k < nS; ++k) {
+        qpos[order[k]] = k;  // old position -> new position
+        pm2[k] = pm[order[k]];
+      }
+      for (int k = 0; k < nCtot; ++k) cn[k] = order[k];  // coarse index of C position k
+      DBuf<int> qd(c, (size_t)nS);
+      copy_h2d(c, qd.get(), qpos.data(), (size_t)nS);
+      copy_h2d(c, lv.perm.get(), pm2.data(), (size_t)nS);
+      lv.cnat.alloc(c, (size_t)std::max(nCtot, 1));
+      copy_h2d(c, lv.cnat.get(), cn.data(), (size_t)std::max(nCtot, 1));
+      for (size_t q = 0; q < ms.size(); ++q) {
+        if (ms[q].kind == 2) continue;
+        hipLaunchKernelGGL(k_remap, dim3(cdiv(ms[q].n, 256)), dim3(256), 0, c->stream,
+                           (long long)ms[q].n, (const int*)qd.get(), nS, srows[q].get(), bad);
+        MGD_CHECK_LAUNCH();
+      }
+      fill<int>(c, alen.get(), 0, (size_t)nS + 1);
+      c->check_device_errors("length order of a solve-phase level");
+    }
     // the map is a permutation: lengths, diagonals
     for (size_t q = 0; q < ms.size(); ++q) {
       auto& m = ms[q];
@@ -387,8 +498,6 @@ std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHiera
       auto& m = ms[q];
       if (m.kind == 2) {
         lv.dense.push_back({m.off, m.n, m.H->coarse_inv.get()});
-        lv.dense_max_n = std::max(lv.dense_max_n, m.n);
-        lv.dense_entries += (long long)m.n * m.n;
         continue;
       }
       const int n = m.n, g = cdiv(n, 256);
@@ -410,139 +519,293 @@ std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHiera
     check_structure(c, Ad, "union level matrix", false);
     check_structure(c, Wd, "union interpolation", false);
     if (ncoarse > 0) transpose(c, Wd, Wtd);
-    // nnz split between the C-block and the F-block (for byte accounting)
-    if (nS > 0) {
-      int rpC = read1(c, Ad.rp.get() + nCtot);
-      lv.nnz_S_C = rpC;
-      lv.nnz_S_F = Ad.nnz - rpC;
-    }
-    csr_to<T>(c, Ad, lv.A);
-    csr_to<T>(c, Wd, lv.W);
-    if (ncoarse > 0) csr_to<T>(c, Wtd, lv.Wt);
-    if (!lv.dense.empty()) {
-      lv.dense_dev.alloc(c, lv.dense.size());
-      copy_h2d(c, lv.dense_dev.get(), lv.dense.data(), lv.dense.size());
-    }
-    lv.tpr_w = default_tpr(nF ? (double)lv.W.nnz / nF : 1.0);
-    lv.tpr_wt = default_tpr(ncoarse ? (double)lv.Wt.nnz / ncoarse : 1.0);
-    U->L.push_back(std::move(lv));
+    if (nS > 0) lv.nnz_C = read1(c, Ad.rp.get() + nCtot);
+    lv.A = std::move(Ad);
+    lv.W = std::move(Wd);
+    lv.Wt = std::move(Wtd);
+    built.push_back(std::move(lv));
     if (ncoarse == 0) break;
   }
-  // workspace
-  const size_t nl = U->L.size();
-  U->b.resize(nl);
-  U->X0.resize(nl);
-  U->X1.resize(nl);
-  U->r.resize(nl);
-  U->n0 = U->L.empty() ? 0 : U->L[0].n;
-  for (size_t l = 0; l < nl; ++l) {
-    auto& lv = U->L[l];
-    if (l > 0) {
-      U->b[l].alloc(c, (size_t)std::max(lv.n, 1));
-      U->X1[l].alloc(c, (size_t)std::max(lv.n, 1));
-    }
-    U->X0[l].alloc(c, (size_t)std::max(lv.n, 1));
-    U->r[l].alloc(c, (size_t)std::max(lv.nS, 1));
-  }
-  U->t0.alloc(c, (size_t)std::max(U->n0, 1));
-  U->t1.alloc(c, (size_t)std::max(U->n0, 1));
-  for (size_t l = 0; l < nl; ++l) {
-    StepScope st("solve-phase build: row-group tuning, level " + std::to_string(l));
-    U->L[l].tpr = tune_level(c, U->L[l], autotune, sizeof(T) == 4);
-  }
+  finalize_levels(c, built, *U, autotune);
   c->sync();
   return U;
 }
 
 // ===========================================================================
-// solve kernels
+// solve kernels (stored order)
 // ===========================================================================
+// Iterate gathers.  A level's iterate has a C region [0, nC) and an F region
+// [nC, nS) that alternate independently between two buffers, and a dense
+// region [nS, nX) kept in the first buffer.  The region is chosen by index
+// arithmetic on a buffer distance (a select of values, never a branch).
 template <typename T>
-__global__ void k_pre_c(int nS, int nC, const int* __restrict__ perm, const T* __restrict__ dinv,
-                        const T* __restrict__ b, T* __restrict__ X) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nS) return;
-  const int i = perm[k];
-  X[i] = k < nC ? b[i] * dinv[k] : (T)0;
-}
-
-template <typename T>
-__global__ void k_zero_stored(int nS, const int* __restrict__ perm, T* __restrict__ X) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < nS) X[perm[k]] = (T)0;
-}
-
-// Xout_S = Xin_S + (b_S - (A Xin)_S) / d_S on stored rows [s0, s1); the
-// other stored rows are copied.
-template <typename T, int TPR>
-__global__ void __launch_bounds__(256) k_half(int nS, int s0, int s1, const int* __restrict__ rp,
-                                              const int* __restrict__ ci, const T* __restrict__ v,
-                                              const int* __restrict__ perm,
-                                              const T* __restrict__ dinv, const T* __restrict__ b,
-                                              const T* __restrict__ Xin, T* __restrict__ Xout) {
-  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const int k = (int)(t / TPR), lane = (int)(t % TPR);
-  if (k >= nS) return;
-  const int i = perm[k];
-  if (k >= s0 && k < s1) {
-    const T s = row_dot<TPR, T>(rp, ci, v, Xin, k, lane);
-    if (lane == 0) Xout[i] = Xin[i] + (b[i] - s) * dinv[k];
-  } else if (lane == 0) {
-    Xout[i] = Xin[i];
+struct GatherCF {
+  const T* base;        // buffer holding the C region
+  ptrdiff_t f_minus_c;  // (buffer holding the F region) - base, in elements
+  int nC;
+  __device__ __forceinline__ T operator()(int j) const {
+    return base[j + (j < nC ? 0 : f_minus_c)];
   }
+};
+template <typename T>
+struct GatherCFD {
+  const T* base;  // C region buffer
+  ptrdiff_t f_minus_c, d_minus_c;
+  int nC, nS;
+  __device__ __forceinline__ T operator()(int j) const {
+    const ptrdiff_t o = j < nC ? 0 : (j < nS ? f_minus_c : d_minus_c);
+    return base[j + o];
+  }
+};
+template <typename T>
+struct Gather1 {
+  const T* x;
+  __device__ __forceinline__ T operator()(int j) const { return x[j]; }
+};
+template <typename T>
+struct GatherPerm {  // natural vector seen in stored order
+  const T* x;
+  const int* perm;
+  __device__ __forceinline__ T operator()(int j) const { return x[perm[j]]; }
+};
+template <typename T>
+struct GatherCOnly {  // first F half-sweep: F values are still zero
+  const T* xc;
+  int nC;
+};
+
+// sum over row `row` of a_rj g(j), entries in stored order; SELL uses one
+// lane per row, CSR `TPR` lanes of a wavefront per row (butterfly combine)
+template <int FMT, int TPR, typename T, typename G>
+__device__ __forceinline__ T mrow(const int* __restrict__ rp, const int* __restrict__ ci,
+                                  const T* __restrict__ v, const G& g, int row, int lane) {
+  T s = 0;
+  if (FMT == kFmtSELL) {
+    const int o = rp[row >> 6] + (row & 63);
+    const int w = (rp[(row >> 6) + 1] - rp[row >> 6]) >> 6;
+    int e = 0;
+    for (; e + 4 <= w; e += 4) {  // four entries' loads in flight (sum order unchanged)
+      int j[4];
+      T a[4], x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) j[q] = ci[o + 64 * (e + q)];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = v[o + 64 * (e + q)];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = g(j[q]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s += a[q] * x[q];
+    }
+    for (; e < w; ++e) s += v[o + 64 * e] * g(ci[o + 64 * e]);
+  } else {
+    const int e1 = rp[row + 1];
+    int e = rp[row] + lane;
+    for (; e + 3 * TPR < e1; e += 4 * TPR) {
+      int j[4];
+      T a[4], x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) j[q] = ci[e + q * TPR];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = v[e + q * TPR];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = g(j[q]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s += a[q] * x[q];
+    }
+    for (; e < e1; e += TPR) s += v[e] * g(ci[e]);
+    if (TPR > 1) {
+#pragma unroll
+      for (int off = TPR / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, TPR);
+    }
+  }
+  return s;
+}
+// the same, with only C columns (the F part of the iterate is zero): F columns
+// read the first C value with weight zero, so every lane issues the same loads
+template <int FMT, int TPR, typename T>
+__device__ __forceinline__ T mrow_c(const int* __restrict__ rp, const int* __restrict__ ci,
+                                    const T* __restrict__ v, const T* __restrict__ xc, int nC,
+                                    int row, int lane) {
+  T s = 0;
+  if (nC == 0) return s;
+  if (FMT == kFmtSELL) {
+    const int o = rp[row >> 6] + (row & 63);
+    const int w = (rp[(row >> 6) + 1] - rp[row >> 6]) >> 6;
+    int e = 0;
+    for (; e + 4 <= w; e += 4) {
+      int j[4];
+      T a[4], x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) j[q] = ci[o + 64 * (e + q)];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = j[q] < nC ? v[o + 64 * (e + q)] : (T)0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = xc[j[q] < nC ? j[q] : 0];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s += a[q] * x[q];
+    }
+    for (; e < w; ++e) {
+      const int j = ci[o + 64 * e];
+      if (j < nC) s += v[o + 64 * e] * xc[j];
+    }
+  } else {
+    const int e1 = rp[row + 1];
+    for (int e = rp[row] + lane; e < e1; e += TPR) {
+      const int j = ci[e];
+      if (j < nC) s += v[e] * xc[j];
+    }
+    if (TPR > 1) {
+#pragma unroll
+      for (int off = TPR / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, TPR);
+    }
+  }
+  return s;
 }
 
-template <typename T, int TPR, bool NATURAL>
-__global__ void __launch_bounds__(256) k_resid(int nS, const int* __restrict__ rp,
-                                               const int* __restrict__ ci,
-                                               const T* __restrict__ v,
-                                               const int* __restrict__ perm,
-                                               const T* __restrict__ b, const T* __restrict__ X,
-                                               T* __restrict__ r) {
-  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const int k = (int)(t / TPR), lane = (int)(t % TPR);
-  if (k >= nS) return;
-  const T s = row_dot<TPR, T>(rp, ci, v, X, k, lane);
+#define MGD_ROWS_TPR                                             \
+  const long t_ = blockIdx.x * (long)blockDim.x + threadIdx.x;   \
+  const int lane = (int)(t_ % TPR);                              \
+  const int k = r0 + (int)(t_ / TPR);                            \
+  if (k >= r1) return;
+
+// level-0 entry: B[k] = b[perm[k]]; C values of the first sweep X_C = B_C / d_C
+template <typename T, bool PRE>
+__global__ void k_entry(int nX, int nC, const int* __restrict__ perm, const T* __restrict__ dinv,
+                        const T* __restrict__ b, T* __restrict__ B, T* __restrict__ XC) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nX) return;
+  const T bb = b[perm[k]];
+  B[k] = bb;
+  if (k < nC) XC[k] = PRE ? bb * dinv[k] : (T)0;
+}
+// later cycles: B = (b - A z) in stored order (dense rows: 0), X_C as above
+template <typename T, int FMT, int TPR, bool PRE>
+__global__ void __launch_bounds__(256) k_entry_resid(int r0, int r1, int nS, int nC,
+                                                     const int* __restrict__ rp,
+                                                     const int* __restrict__ ci,
+                                                     const T* __restrict__ v,
+                                                     const int* __restrict__ perm,
+                                                     const T* __restrict__ dinv,
+                                                     const T* __restrict__ b,
+                                                     const T* __restrict__ z, T* __restrict__ B,
+                                                     T* __restrict__ XC) {
+  MGD_ROWS_TPR
+  if (k >= nS) {
+    if (lane == 0) B[k] = (T)0;
+    return;
+  }
+  const T s = mrow<FMT, TPR>(rp, ci, v, GatherPerm<T>{z, perm}, k, lane);
   if (lane == 0) {
-    const int i = perm[k];
-    r[NATURAL ? i : k] = b[i] - s;
+    const T bb = b[perm[k]] - s;
+    B[k] = bb;
+    if (k < nC) XC[k] = PRE ? bb * dinv[k] : (T)0;
   }
 }
 
-template <typename T, int TPR>
-__global__ void __launch_bounds__(256) k_restrict(int nc, int nC, const int* __restrict__ rp,
+// first F half-sweep of a cycle (F iterate zero): X_F = (B_F - A_FC X_C) / d_F
+template <typename T, int FMT, int TPR>
+__global__ void __launch_bounds__(256) k_fhalf0(int r0, int r1, int nC, const int* __restrict__ rp,
+                                                const int* __restrict__ ci,
+                                                const T* __restrict__ v,
+                                                const T* __restrict__ dinv,
+                                                const T* __restrict__ B, const T* __restrict__ XC,
+                                                T* __restrict__ Xout) {
+  MGD_ROWS_TPR
+  const T s = mrow_c<FMT, TPR>(rp, ci, v, XC, nC, k, lane);
+  if (lane == 0) Xout[k] = (T)0 + (B[k] - s) * dinv[k];
+}
+
+// half-sweep on rows [r0, r1): Xout = Xold + (B - A X) / d
+template <typename T, int FMT, int TPR>
+__global__ void __launch_bounds__(256) k_half(int r0, int r1, const int* __restrict__ rp,
+                                              const int* __restrict__ ci, const T* __restrict__ v,
+                                              const T* __restrict__ dinv, const T* __restrict__ B,
+                                              GatherCF<T> X, const T* __restrict__ Xold,
+                                              T* __restrict__ Xout) {
+  MGD_ROWS_TPR
+  const T s = mrow<FMT, TPR>(rp, ci, v, X, k, lane);
+  if (lane == 0) Xout[k] = Xold[k] + (B[k] - s) * dinv[k];
+}
+
+// level-0 final C half-sweep fused with the output: z[perm[k]] = new X_C on
+// C rows, the current F and dense values on the other rows
+template <typename T, int FMT, int TPR>
+__global__ void __launch_bounds__(256) k_half_out(int r0, int r1, int nC, int nS,
+                                                  const int* __restrict__ rp,
                                                   const int* __restrict__ ci,
                                                   const T* __restrict__ v,
-                                                  const T* __restrict__ r, T* __restrict__ bc) {
-  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const int I = (int)(t / TPR), lane = (int)(t % TPR);
-  if (I >= nc) return;
-  const T s = row_dot<TPR, T>(rp, ci, v, r + nC, I, lane);
-  if (lane == 0) bc[I] = r[I] + s;
+                                                  const T* __restrict__ dinv,
+                                                  const T* __restrict__ B, GatherCF<T> X,
+                                                  const T* __restrict__ XD,
+                                                  const int* __restrict__ perm, T* __restrict__ z) {
+  MGD_ROWS_TPR
+  if (k < nC) {
+    const T s = mrow<FMT, TPR>(rp, ci, v, X, k, lane);
+    if (lane == 0) z[perm[k]] = X.base[k] + (B[k] - s) * dinv[k];
+  } else if (lane == 0) {
+    if (k < nS)
+      z[perm[k]] = X.base[k + X.f_minus_c];
+    else
+      z[perm[k]] = XD[k];
+  }
+}
+// level-0 output without post-smoothing
+template <typename T>
+__global__ void k_out(int nX, GatherCFD<T> X, const int* __restrict__ perm, T* __restrict__ z) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nX) z[perm[k]] = X(k);
 }
 
-template <typename T, int TPR>
-__global__ void __launch_bounds__(256) k_prolong(int nS, int nC, const int* __restrict__ rp,
+template <typename T, int FMT, int TPR>
+__global__ void __launch_bounds__(256) k_resid(int r0, int r1, const int* __restrict__ rp,
+                                               const int* __restrict__ ci,
+                                               const T* __restrict__ v, const T* __restrict__ B,
+                                               GatherCF<T> X, T* __restrict__ R) {
+  MGD_ROWS_TPR
+  const T s = mrow<FMT, TPR>(rp, ci, v, X, k, lane);
+  if (lane == 0) R[k] = B[k] - s;
+}
+
+// restriction into level l+1 (rows in its extended order):
+// Bn[k] = R[cpos[k]] + sum_f Wt[k, f] R[nC + f], and its first-sweep C values
+template <typename T, int FMT, int TPR, bool PRE>
+__global__ void __launch_bounds__(256) k_restrict(int r0, int r1, int nC, int nCn,
+                                                  const int* __restrict__ rp,
+                                                  const int* __restrict__ ci,
+                                                  const T* __restrict__ v,
+                                                  const int* __restrict__ cpos,
+                                                  const T* __restrict__ R,
+                                                  const T* __restrict__ dinv_n,
+                                                  T* __restrict__ Bn, T* __restrict__ XCn) {
+  MGD_ROWS_TPR
+  const T s = mrow<FMT, TPR>(rp, ci, v, Gather1<T>{R + nC}, k, lane);
+  if (lane == 0) {
+    const T bb = R[cpos[k]] + s;
+    Bn[k] = bb;
+    if (k < nCn) XCn[k] = PRE ? bb * dinv_n[k] : (T)0;
+  }
+}
+
+// prolongation: X_C[k] += E(cmap[k]) (k < nC); X_F[k] += W[k - nC, :] E
+template <typename T, int FMT, int TPR>
+__global__ void __launch_bounds__(256) k_prolong(int r0, int r1, int nC,
+                                                 const int* __restrict__ rp,
                                                  const int* __restrict__ ci,
                                                  const T* __restrict__ v,
-                                                 const int* __restrict__ perm,
-                                                 const T* __restrict__ e, T* __restrict__ X) {
-  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const int k = (int)(t / TPR), lane = (int)(t % TPR);
-  if (k >= nS) return;
-  T s;
+                                                 const int* __restrict__ cmap, GatherCFD<T> E,
+                                                 T* __restrict__ XC, T* __restrict__ XF) {
+  MGD_ROWS_TPR
   if (k < nC) {
-    s = e[k];
+    if (lane == 0) XC[k] += E(cmap[k]);
   } else {
-    s = row_dot<TPR, T>(rp, ci, v, e, k - nC, lane);
+    const T s = mrow<FMT, TPR>(rp, ci, v, E, k - nC, lane);
+    if (lane == 0) XF[k] += s;
   }
-  if (lane == 0) X[perm[k]] += s;
 }
 
-// x = A^{-1} b for every dense-solved member (FP64 arithmetic)
-// One workgroup column of 64 rows per member; the loop is unrolled so that
-// eight coalesced column loads are in flight per step (the sum stays in
-// ascending j).
+// x = A^{-1} b for every dense-solved member (FP64 arithmetic); one workgroup
+// column of 64 rows per member, eight column loads in flight per step (the sum
+// stays in ascending j)
 template <typename T>
 __global__ void __launch_bounds__(64) k_dense(const DenseDev* __restrict__ tab,
                                               const T* __restrict__ b, T* __restrict__ X) {
@@ -574,186 +837,351 @@ __global__ void k_axpy_t(int n, const T* __restrict__ x, T* __restrict__ y) {
 }
 
 // ---------------------------------------------------------------------------
-// launchers
+// launchers: one row per lane (SELL) or TPR lanes per row (CSR)
 // ---------------------------------------------------------------------------
 template <typename T>
-struct HalfArgs {
-  const ULevel<T>* lv;
-  int s0, s1;
-  const T *b, *Xin;
-  T* Xout;
+struct MatArgs {
+  const LMat<T>* m;
 };
-template <int TPR>
-struct HalfLaunchD {
-  template <typename T>
-  static void run(Ctx* c, const HalfArgs<T>& a) {
-    const auto& lv = *a.lv;
-    const int grid = cdiv((long long)lv.nS * TPR, 256);
-    hipLaunchKernelGGL((k_half<T, TPR>), dim3(grid), dim3(256), 0, c->stream, lv.nS, a.s0, a.s1,
-                       lv.A.rp.get(), lv.A.ci.get(), lv.A.v.get(), lv.perm.get(), lv.dinv.get(),
-                       a.b, a.Xin, a.Xout);
-    MGD_CHECK_LAUNCH();
-  }
-};
-template <int TPR>
-struct ResidLaunch {
-  template <typename T>
-  static void run(Ctx* c, const ULevel<T>* lv, const T* b, const T* X, T* r, bool natural) {
-    const int grid = cdiv((long long)lv->nS * TPR, 256);
-    if (natural)
-      hipLaunchKernelGGL((k_resid<T, TPR, true>), dim3(grid), dim3(256), 0, c->stream, lv->nS,
-                         lv->A.rp.get(), lv->A.ci.get(), lv->A.v.get(), lv->perm.get(), b, X, r);
-    else
-      hipLaunchKernelGGL((k_resid<T, TPR, false>), dim3(grid), dim3(256), 0, c->stream, lv->nS,
-                         lv->A.rp.get(), lv->A.ci.get(), lv->A.v.get(), lv->perm.get(), b, X, r);
-    MGD_CHECK_LAUNCH();
-  }
-};
-template <int TPR>
-struct RestrictLaunch {
-  template <typename T>
-  static void run(Ctx* c, const ULevel<T>* lv, const T* r, T* bc) {
-    const int grid = cdiv((long long)lv->n_coarse * TPR, 256);
-    hipLaunchKernelGGL((k_restrict<T, TPR>), dim3(grid), dim3(256), 0, c->stream, lv->n_coarse,
-                       lv->nC, lv->Wt.rp.get(), lv->Wt.ci.get(), lv->Wt.v.get(), r, bc);
-    MGD_CHECK_LAUNCH();
-  }
-};
-template <int TPR>
-struct ProlongLaunch {
-  template <typename T>
-  static void run(Ctx* c, const ULevel<T>* lv, const T* e, T* X) {
-    const int grid = cdiv((long long)lv->nS * TPR, 256);
-    hipLaunchKernelGGL((k_prolong<T, TPR>), dim3(grid), dim3(256), 0, c->stream, lv->nS, lv->nC,
-                       lv->W.rp.get(), lv->W.ci.get(), lv->W.v.get(), lv->perm.get(), e, X);
-    MGD_CHECK_LAUNCH();
-  }
-};
+static inline dim3 rows_grid(int rows, int tpr) { return dim3(cdiv((long long)rows * tpr, 256)); }
 
-template <template <int> class K, typename... Args>
-static void dispatch(int tpr, Args&&... args) {
+// Calls F.template go<FMT, TPR>() for the matrix's layout.
+template <typename F>
+static void with_layout(int fmt, int tpr, F&& f) {
+  if (fmt == kFmtSELL) {
+    f.template go<kFmtSELL, 1>();
+    return;
+  }
   switch (tpr) {
-    case 1: K<1>::run(args...); break;
-    case 2: K<2>::run(args...); break;
-    case 4: K<4>::run(args...); break;
-    case 8: K<8>::run(args...); break;
-    case 16: K<16>::run(args...); break;
-    case 32: K<32>::run(args...); break;
-    default: K<64>::run(args...); break;
+    case 1: f.template go<kFmtCSR, 1>(); break;
+    case 2: f.template go<kFmtCSR, 2>(); break;
+    case 4: f.template go<kFmtCSR, 4>(); break;
+    case 8: f.template go<kFmtCSR, 8>(); break;
+    case 16: f.template go<kFmtCSR, 16>(); break;
+    case 32: f.template go<kFmtCSR, 32>(); break;
+    default: f.template go<kFmtCSR, 64>(); break;
   }
 }
-
-// algorithmic bytes (each entry/index/vector element once per launch)
 template <typename T>
-static double half_bytes(const ULevel<T>& lv, bool c_half) {
-  const double ts = sizeof(T);
-  const long long rows = c_half ? lv.nC : lv.nS - lv.nC;
-  const long long nnz = c_half ? lv.nnz_S_C : lv.nnz_S_F;
-  return nnz * (ts + 4) + rows * (4 + 2 * ts) + lv.nS * (4 + 2 * ts) + (double)lv.n * 0;
-}
-template <typename T>
-static double resid_bytes(const ULevel<T>& lv) {
-  const double ts = sizeof(T);
-  return (double)lv.A.nnz * (ts + 4) + lv.nS * (4 + 4 + 2 * ts) + (double)lv.n * ts;
+static std::string kname(const Ctx* c, const char* base, const LMat<T>& m,
+                         std::initializer_list<std::string> extra = {}) {
+  if (!c->profiling) return std::string();
+  std::vector<std::string> a{type_name<T>(), std::to_string(m.fmt),
+                             std::to_string(m.fmt == kFmtSELL ? 1 : tpr_of(m.tpr))};
+  for (const auto& e : extra) a.push_back(e);
+  std::string s(base);
+  const char* sep = "<";
+  for (const auto& x : a) {
+    s += sep;
+    s += x;
+    sep = ", ";
+  }
+  return s + ">";
 }
 
+template <typename T>
+struct HalfL {
+  Ctx* c;
+  const LMat<T>& A;
+  int r0, r1;
+  const T *dinv, *B;
+  GatherCF<T> X;
+  const T* Xold;
+  T* Xout;
+  template <int FMT, int TPR>
+  void go() const {
+    if (r1 <= r0) return;
+    hipLaunchKernelGGL((k_half<T, FMT, TPR>), rows_grid(r1 - r0, TPR), dim3(256), 0, c->stream,
+                       r0, r1, A.rp.get(), A.ci.get(), A.v.get(), dinv, B, X, Xold, Xout);
+    MGD_CHECK_LAUNCH();
+  }
+};
+template <typename T>
+struct FHalf0L {
+  Ctx* c;
+  const LMat<T>& A;
+  int r0, r1, nC;
+  const T *dinv, *B, *XC;
+  T* Xout;
+  template <int FMT, int TPR>
+  void go() const {
+    if (r1 <= r0) return;
+    hipLaunchKernelGGL((k_fhalf0<T, FMT, TPR>), rows_grid(r1 - r0, TPR), dim3(256), 0, c->stream,
+                       r0, r1, nC, A.rp.get(), A.ci.get(), A.v.get(), dinv, B, XC, Xout);
+    MGD_CHECK_LAUNCH();
+  }
+};
+template <typename T>
+struct HalfOutL {
+  Ctx* c;
+  const LMat<T>& A;
+  int nX, nC, nS;
+  const T *dinv, *B;
+  GatherCF<T> X;
+  const T* XD;
+  const int* perm;
+  T* z;
+  template <int FMT, int TPR>
+  void go() const {
+    if (nX <= 0) return;
+    hipLaunchKernelGGL((k_half_out<T, FMT, TPR>), rows_grid(nX, TPR), dim3(256), 0, c->stream, 0,
+                       nX, nC, nS, A.rp.get(), A.ci.get(), A.v.get(), dinv, B, X, XD, perm, z);
+    MGD_CHECK_LAUNCH();
+  }
+};
+template <typename T>
+struct ResidL {
+  Ctx* c;
+  const LMat<T>& A;
+  int nS;
+  const T* B;
+  GatherCF<T> X;
+  T* R;
+  template <int FMT, int TPR>
+  void go() const {
+    if (nS <= 0) return;
+    hipLaunchKernelGGL((k_resid<T, FMT, TPR>), rows_grid(nS, TPR), dim3(256), 0, c->stream, 0, nS,
+                       A.rp.get(), A.ci.get(), A.v.get(), B, X, R);
+    MGD_CHECK_LAUNCH();
+  }
+};
+template <typename T>
+struct EntryResidL {
+  Ctx* c;
+  const LMat<T>& A;
+  int nX, nS, nC;
+  const int* perm;
+  const T *dinv, *b, *z;
+  T *B, *XC;
+  bool pre;
+  template <int FMT, int TPR>
+  void go() const {
+    if (nX <= 0) return;
+    if (pre)
+      hipLaunchKernelGGL((k_entry_resid<T, FMT, TPR, true>), rows_grid(nX, TPR), dim3(256), 0,
+                         c->stream, 0, nX, nS, nC, A.rp.get(), A.ci.get(), A.v.get(), perm, dinv,
+                         b, z, B, XC);
+    else
+      hipLaunchKernelGGL((k_entry_resid<T, FMT, TPR, false>), rows_grid(nX, TPR), dim3(256), 0,
+                         c->stream, 0, nX, nS, nC, A.rp.get(), A.ci.get(), A.v.get(), perm, dinv,
+                         b, z, B, XC);
+    MGD_CHECK_LAUNCH();
+  }
+};
+template <typename T>
+struct RestrictL {
+  Ctx* c;
+  const LMat<T>& Wt;
+  int nXn, nC, nCn;
+  const int* cpos;
+  const T *R, *dinv_n;
+  T *Bn, *XCn;
+  bool pre;
+  template <int FMT, int TPR>
+  void go() const {
+    if (nXn <= 0) return;
+    if (pre)
+      hipLaunchKernelGGL((k_restrict<T, FMT, TPR, true>), rows_grid(nXn, TPR), dim3(256), 0,
+                         c->stream, 0, nXn, nC, nCn, Wt.rp.get(), Wt.ci.get(), Wt.v.get(), cpos, R,
+                         dinv_n, Bn, XCn);
+    else
+      hipLaunchKernelGGL((k_restrict<T, FMT, TPR, false>), rows_grid(nXn, TPR), dim3(256), 0,
+                         c->stream, 0, nXn, nC, nCn, Wt.rp.get(), Wt.ci.get(), Wt.v.get(), cpos, R,
+                         dinv_n, Bn, XCn);
+    MGD_CHECK_LAUNCH();
+  }
+};
+template <typename T>
+struct ProlongL {
+  Ctx* c;
+  const LMat<T>& W;
+  int nS, nC;
+  const int* cmap;
+  GatherCFD<T> E;
+  T *XC, *XF;
+  template <int FMT, int TPR>
+  void go() const {
+    if (nS <= 0) return;
+    hipLaunchKernelGGL((k_prolong<T, FMT, TPR>), rows_grid(nS, TPR), dim3(256), 0, c->stream, 0,
+                       nS, nC, W.rp.get(), W.ci.get(), W.v.get(), cmap, E, XC, XF);
+    MGD_CHECK_LAUNCH();
+  }
+};
+
+// algorithmic bytes per launch: every matrix entry (value + column), every
+// per-row vector element read or written, and the gathered iterate once
+template <typename T>
+static double mat_bytes(long long nnz) {
+  return (double)nnz * (sizeof(T) + 4);
+}
 static inline int cls_of(int l, int cls0) { return l == 0 ? cls0 : KC_VCYCLE_COARSE; }
+
 template <typename T>
-static std::string khalf(const Ctx* c, int tpr) {
-  return ksym(c, "k_half", {type_name<T>(), std::to_string(tpr_of(tpr))});
+static GatherCF<T> gather_cf(const T* xc, const T* xf, int nC) {
+  return GatherCF<T>{xc, (ptrdiff_t)(xf - xc), nC};
 }
 template <typename T>
-static std::string kresid(const Ctx* c, int tpr, bool natural) {
-  return ksym(c, "k_resid", {type_name<T>(), std::to_string(tpr_of(tpr)), natural ? "true" : "false"});
+static GatherCFD<T> gather_cfd(const T* xc, const T* xf, const T* xd, int nC, int nS) {
+  return GatherCFD<T>{xc, (ptrdiff_t)(xf - xc), (ptrdiff_t)(xd - xc), nC, nS};
 }
 
 template <typename T>
-void Union<T>::vcycle(Ctx* c, const T* b0, T* x0) {
+void Union<T>::vcycle(Ctx* c, T* z) {
   const int nl = (int)L.size();
-  auto Bp = [&](int l) -> const T* { return l == 0 ? b0 : b[l].get(); };
-  auto X1p = [&](int l) -> T* { return l == 0 ? x0 : X1[l].get(); };
+  const size_t ts = sizeof(T);
+  // current buffer (0: X0, 1: X1) of the C and the F region, per level
+  std::vector<int> cc(nl, 0), cf(nl, 0);
+  auto Xb = [&](int l, int which) -> T* { return which ? X1[l].get() : X0[l].get(); };
   for (int l = 0; l < nl; ++l) {
     ULevel<T>& lv = L[l];
-    T* x1 = X1p(l);
-    T* xw = X0[l].get();
-    const T* bl = Bp(l);
+    const int nF = lv.nS - lv.nC;
+    // the C values of the first sweep were written with B (entry / restriction)
     if (lv.nS > 0) {
-      if (n_pre == 0) {
-        hipLaunchKernelGGL(k_zero_stored<T>, dim3(cdiv(lv.nS, 256)), dim3(256), 0, c->stream,
-                           lv.nS, lv.perm.get(), x1);
-        MGD_CHECK_LAUNCH();
-      }
       for (int s = 0; s < n_pre; ++s) {
-        if (s == 0) {
+        if (s > 0) {  // C half of a later sweep
           ProfScope ps(c, cls_of(l, KC_SMOOTH_L0),
-                       (double)lv.nS * (4 + 2 * sizeof(T)) + lv.nC * (sizeof(T)),
-                       ksym(c, "k_pre_c", {type_name<T>()}));
-          hipLaunchKernelGGL(k_pre_c<T>, dim3(cdiv(lv.nS, 256)), dim3(256), 0, c->stream, lv.nS,
-                             lv.nC, lv.perm.get(), lv.dinv.get(), bl, xw);
-          MGD_CHECK_LAUNCH();
-        } else {
-          ProfScope ps(c, cls_of(l, KC_SMOOTH_L0), half_bytes(lv, true), khalf<T>(c, lv.tpr));
-          dispatch<HalfLaunchD>(lv.tpr, c, HalfArgs<T>{&lv, 0, lv.nC, bl, x1, xw});
+                       mat_bytes<T>(lv.nnz_C) + (double)lv.nC * 4 * ts + lv.nS * ts,
+                       kname(c, "k_half", lv.A));
+          with_layout(lv.A.fmt, lv.A.tpr,
+                      HalfL<T>{c, lv.A, 0, lv.nC, lv.dinv.get(), B[l].get(),
+                               gather_cf<T>(Xb(l, cc[l]), Xb(l, cf[l]), lv.nC), Xb(l, cc[l]),
+                               Xb(l, 1 - cc[l])});
+          cc[l] = 1 - cc[l];
         }
-        ProfScope ps(c, cls_of(l, KC_SMOOTH_L0), half_bytes(lv, false), khalf<T>(c, lv.tpr));
-        dispatch<HalfLaunchD>(lv.tpr, c, HalfArgs<T>{&lv, lv.nC, lv.nS, bl, xw, x1});
+        if (nF > 0) {
+          if (s == 0) {
+            ProfScope ps(c, cls_of(l, KC_SMOOTH_L0),
+                         mat_bytes<T>(lv.nnz_F) + (double)nF * 3 * ts + lv.nC * ts,
+                         kname(c, "k_fhalf0", lv.A));
+            with_layout(lv.A.fmt, lv.A.tpr,
+                        FHalf0L<T>{c, lv.A, lv.nC, lv.nS, lv.nC, lv.dinv.get(), B[l].get(),
+                                   Xb(l, cc[l]), Xb(l, 1 - cf[l])});
+          } else {
+            ProfScope ps(c, cls_of(l, KC_SMOOTH_L0),
+                         mat_bytes<T>(lv.nnz_F) + (double)nF * 4 * ts + lv.nS * ts,
+                         kname(c, "k_half", lv.A));
+            with_layout(lv.A.fmt, lv.A.tpr,
+                        HalfL<T>{c, lv.A, lv.nC, lv.nS, lv.dinv.get(), B[l].get(),
+                                 gather_cf<T>(Xb(l, cc[l]), Xb(l, cf[l]), lv.nC), Xb(l, cf[l]),
+                                 Xb(l, 1 - cf[l])});
+          }
+          cf[l] = 1 - cf[l];
+        }
       }
-      if (lv.n_coarse > 0) {
+      if (n_pre == 0 && nF > 0) fill<T>(c, Xb(l, cf[l]) + lv.nC, (T)0, (size_t)nF);
+      if (lv.nX_next > 0) {
         {
-          ProfScope ps(c, cls_of(l, KC_RESID_L0), resid_bytes(lv), kresid<T>(c, lv.tpr, false));
-          dispatch<ResidLaunch>(lv.tpr, c, &lv, bl, (const T*)x1, r[l].get(), false);
+          ProfScope ps(c, cls_of(l, KC_RESID_L0),
+                       mat_bytes<T>(lv.A.nnz) + (double)lv.nS * 3 * ts,
+                       kname(c, "k_resid", lv.A));
+          with_layout(lv.A.fmt, lv.A.tpr,
+                      ResidL<T>{c, lv.A, lv.nS, B[l].get(),
+                                gather_cf<T>(Xb(l, cc[l]), Xb(l, cf[l]), lv.nC), R[l].get()});
         }
+        const ULevel<T>& nx = L[l + 1];
         ProfScope ps(c, cls_of(l, KC_TRANSFER_L0),
-                     (double)lv.Wt.nnz * (sizeof(T) + 4) + lv.n_coarse * (4 + sizeof(T)) +
-                         (double)lv.nS * sizeof(T),
-                     ksym(c, "k_restrict", {type_name<T>(), std::to_string(tpr_of(lv.tpr_wt))}));
-        dispatch<RestrictLaunch>(lv.tpr_wt, c, &lv, (const T*)r[l].get(), b[l + 1].get());
+                     mat_bytes<T>(lv.Wt.nnz) + (double)lv.nX_next * (4 + ts) +
+                         (double)nx.nC * 2 * ts + lv.nS * ts,
+                     kname(c, "k_restrict", lv.Wt, {n_pre > 0 ? "true" : "false"}));
+        with_layout(lv.Wt.fmt, lv.Wt.tpr,
+                    RestrictL<T>{c, lv.Wt, lv.nX_next, lv.nC, nx.nC, lv.cpos.get(), R[l].get(),
+                                 nx.dinv.get(), B[l + 1].get(), Xb(l + 1, 0), n_pre > 0});
       }
     }
     if (!lv.dense.empty()) {
-      ProfScope ps(c, KC_COARSE_SOLVE, 8.0 * lv.dense_entries + 2.0 * sizeof(T) * lv.n,
+      ProfScope ps(c, KC_COARSE_SOLVE, 8.0 * lv.dense_entries + 2.0 * ts * (lv.nX - lv.nS),
                    ksym(c, "k_dense", {type_name<T>()}));
       dim3 grid(cdiv(lv.dense_max_n, 64), (unsigned)lv.dense.size());
       hipLaunchKernelGGL(k_dense<T>, grid, dim3(64), 0, c->stream,
-                         (const DenseDev*)lv.dense_dev.get(), bl, x1);
+                         (const DenseDev*)lv.dense_dev.get(), (const T*)B[l].get(), X0[l].get());
       MGD_CHECK_LAUNCH();
     }
   }
   for (int l = nl - 1; l >= 0; --l) {
     ULevel<T>& lv = L[l];
-    if (lv.nS == 0) continue;
-    T* x1 = X1p(l);
-    T* xw = X0[l].get();
-    const T* bl = Bp(l);
-    if (lv.n_coarse > 0) {
+    const int nF = lv.nS - lv.nC;
+    if (lv.nS > 0 && lv.nX_next > 0) {
+      const ULevel<T>& nx = L[l + 1];
       ProfScope ps(c, cls_of(l, KC_TRANSFER_L0),
-                   (double)lv.W.nnz * (sizeof(T) + 4) + lv.nS * (4 + 2.0 * sizeof(T)) +
-                       lv.n_coarse * (double)sizeof(T),
-                   ksym(c, "k_prolong", {type_name<T>(), std::to_string(tpr_of(lv.tpr_w))}));
-      dispatch<ProlongLaunch>(lv.tpr_w, c, &lv, (const T*)X1p(l + 1), x1);
+                   mat_bytes<T>(lv.W.nnz) + (double)lv.nC * 4 + lv.nS * 2.0 * ts +
+                       (double)lv.nX_next * ts,
+                   kname(c, "k_prolong", lv.W));
+      with_layout(lv.W.fmt, lv.W.tpr,
+                  ProlongL<T>{c, lv.W, lv.nS, lv.nC, lv.cmap.get(),
+                              gather_cfd<T>(Xb(l + 1, cc[l + 1]), Xb(l + 1, cf[l + 1]),
+                                            X0[l + 1].get(), nx.nC, nx.nS),
+                              Xb(l, cc[l]), Xb(l, cf[l])});
     }
-    for (int s = 0; s < n_post; ++s) {
-      {
-        ProfScope ps(c, cls_of(l, KC_SMOOTH_L0), half_bytes(lv, false), khalf<T>(c, lv.tpr));
-        dispatch<HalfLaunchD>(lv.tpr, c, HalfArgs<T>{&lv, lv.nC, lv.nS, bl, x1, xw});
+    const bool last_out = (l == 0);
+    if (lv.nS > 0) {
+      for (int s = 0; s < n_post; ++s) {
+        if (nF > 0) {
+          ProfScope ps(c, cls_of(l, KC_SMOOTH_L0),
+                       mat_bytes<T>(lv.nnz_F) + (double)nF * 4 * ts + lv.nS * ts,
+                       kname(c, "k_half", lv.A));
+          with_layout(lv.A.fmt, lv.A.tpr,
+                      HalfL<T>{c, lv.A, lv.nC, lv.nS, lv.dinv.get(), B[l].get(),
+                               gather_cf<T>(Xb(l, cc[l]), Xb(l, cf[l]), lv.nC), Xb(l, cf[l]),
+                               Xb(l, 1 - cf[l])});
+          cf[l] = 1 - cf[l];
+        }
+        if (last_out && s == n_post - 1) {  // final C half writes the natural result
+          ProfScope ps(c, KC_SMOOTH_L0,
+                       mat_bytes<T>(lv.nnz_C) + (double)lv.nC * 3 * ts + lv.nS * ts +
+                           (double)lv.nX * (4 + ts),
+                       kname(c, "k_half_out", lv.A));
+          with_layout(lv.A.fmt, lv.A.tpr,
+                      HalfOutL<T>{c, lv.A, lv.nX, lv.nC, lv.nS, lv.dinv.get(), B[l].get(),
+                                  gather_cf<T>(Xb(l, cc[l]), Xb(l, cf[l]), lv.nC), X0[l].get(),
+                                  lv.perm.get(), z});
+          return;
+        }
+        ProfScope ps(c, cls_of(l, KC_SMOOTH_L0),
+                     mat_bytes<T>(lv.nnz_C) + (double)lv.nC * 4 * ts + lv.nS * ts,
+                     kname(c, "k_half", lv.A));
+        with_layout(lv.A.fmt, lv.A.tpr,
+                    HalfL<T>{c, lv.A, 0, lv.nC, lv.dinv.get(), B[l].get(),
+                             gather_cf<T>(Xb(l, cc[l]), Xb(l, cf[l]), lv.nC), Xb(l, cc[l]),
+                             Xb(l, 1 - cc[l])});
+        cc[l] = 1 - cc[l];
       }
-      ProfScope ps(c, cls_of(l, KC_SMOOTH_L0), half_bytes(lv, true), khalf<T>(c, lv.tpr));
-      dispatch<HalfLaunchD>(lv.tpr, c, HalfArgs<T>{&lv, 0, lv.nC, bl, xw, x1});
+    }
+    if (last_out) {  // no post-smoothing (or no stored rows): copy out
+      hipLaunchKernelGGL(k_out<T>, dim3(cdiv(lv.nX, 256)), dim3(256), 0, c->stream, lv.nX,
+                         gather_cfd<T>(Xb(0, cc[0]), Xb(0, cf[0]), X0[0].get(), lv.nC, lv.nS),
+                         (const int*)lv.perm.get(), z);
+      MGD_CHECK_LAUNCH();
     }
   }
 }
 
 template <typename T>
 void Union<T>::apply(Ctx* c, const T* bvec, T* z, int cycles) {
-  vcycle(c, bvec, z);
+  ULevel<T>& l0 = L[0];
+  {
+    ProfScope ps(c, KC_TRANSFER_L0, (double)l0.nX * (4 + 2.0 * sizeof(T)) + l0.nC * 2.0 * sizeof(T),
+                 ksym(c, "k_entry", {type_name<T>(), n_pre > 0 ? "true" : "false"}));
+    if (n_pre > 0)
+      hipLaunchKernelGGL((k_entry<T, true>), dim3(cdiv(l0.nX, 256)), dim3(256), 0, c->stream,
+                         l0.nX, l0.nC, (const int*)l0.perm.get(), (const T*)l0.dinv.get(), bvec,
+                         B[0].get(), X0[0].get());
+    else
+      hipLaunchKernelGGL((k_entry<T, false>), dim3(cdiv(l0.nX, 256)), dim3(256), 0, c->stream,
+                         l0.nX, l0.nC, (const int*)l0.perm.get(), (const T*)l0.dinv.get(), bvec,
+                         B[0].get(), X0[0].get());
+    MGD_CHECK_LAUNCH();
+  }
+  vcycle(c, z);
   for (int k = 1; k < cycles; ++k) {
-    ULevel<T>& lv = L[0];
-    if (!lv.dense.empty()) fill<T>(c, t0.get(), (T)0, (size_t)n0);
-    if (lv.nS > 0) {
-      ProfScope ps(c, KC_RESID_L0, resid_bytes(lv), kresid<T>(c, lv.tpr, true));
-      dispatch<ResidLaunch>(lv.tpr, c, &lv, bvec, (const T*)z, t0.get(), true);
+    {
+      ProfScope ps(c, KC_RESID_L0,
+                   mat_bytes<T>(l0.A.nnz) + (double)l0.nX * (8 + 3.0 * sizeof(T)),
+                   kname(c, "k_entry_resid", l0.A, {n_pre > 0 ? "true" : "false"}));
+      with_layout(l0.A.fmt, l0.A.tpr,
+                  EntryResidL<T>{c, l0.A, l0.nX, l0.nS, l0.nC, l0.perm.get(), l0.dinv.get(), bvec,
+                                 z, B[0].get(), X0[0].get(), n_pre > 0});
     }
-    vcycle(c, t0.get(), t1.get());
+    vcycle(c, t1.get());
     hipLaunchKernelGGL(k_axpy_t<T>, dim3(cdiv(n0, 256)), dim3(256), 0, c->stream, n0,
                        (const T*)t1.get(), z);
     MGD_CHECK_LAUNCH();
@@ -762,17 +1190,19 @@ void Union<T>::apply(Ctx* c, const T* bvec, T* z, int cycles) {
 
 template <typename T>
 double Union<T>::bytes_per_vcycle() const {
+  const double ts = sizeof(T);
   double s = 0;
-  for (auto& lv : L) {
+  for (size_t l = 0; l < L.size(); ++l) {
+    const auto& lv = L[l];
+    const double nF = lv.nS - lv.nC;
     if (lv.nS > 0) {
-      s += (double)lv.nS * (4 + 2 * sizeof(T)) + lv.nC * sizeof(T);
-      s += half_bytes(lv, false) * (n_pre + n_post) + half_bytes(lv, true) * (n_pre + n_post - 1);
-      if (lv.n_coarse > 0) {
-        s += resid_bytes(lv);
-        s += (double)lv.Wt.nnz * (sizeof(T) + 4) + lv.n_coarse * (4 + sizeof(T)) +
-             (double)lv.nS * sizeof(T);
-        s += (double)lv.W.nnz * (sizeof(T) + 4) + lv.nS * (4 + 2.0 * sizeof(T)) +
-             lv.n_coarse * (double)sizeof(T);
+      s += mat_bytes<T>(lv.nnz_F) * (n_pre + n_post) + mat_bytes<T>(lv.nnz_C) * (n_pre + n_post - 1);
+      s += (nF * 4 * ts + lv.nS * ts) * (n_pre + n_post) +
+           (lv.nC * 4 * ts + lv.nS * ts) * (n_pre + n_post - 1);
+      if (lv.nX_next > 0) {
+        s += mat_bytes<T>(lv.A.nnz) + lv.nS * 3 * ts;
+        s += mat_bytes<T>(lv.Wt.nnz) + lv.nX_next * (4 + ts) + lv.nS * ts;
+        s += mat_bytes<T>(lv.W.nnz) + lv.nC * 4.0 + lv.nS * 2.0 * ts + lv.nX_next * ts;
       }
     }
     s += 8.0 * lv.dense_entries;
@@ -780,9 +1210,6 @@ double Union<T>::bytes_per_vcycle() const {
   return s;
 }
 
-// ===========================================================================
-// autotuning of row-group widths
-// ===========================================================================
 static std::mutex g_tune_mu;
 static std::map<std::string, int> g_tune;
 static bool g_tune_loaded = false;
@@ -845,36 +1272,297 @@ __global__ void k_max_row(int n, const int* __restrict__ rp, int* __restrict__ o
   if ((threadIdx.x & 63) == 0 && m > 0) atomicMax(out, m);
 }
 
+// ---------------------------------------------------------------------------
+// stored-order finalisation and level layouts
+// ---------------------------------------------------------------------------
+// SELL slice widths (64 x the longest row of each 64-row slice)
+__global__ void k_slice_width(int rows, const int* __restrict__ rp, int* __restrict__ w64) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ns = (rows + 63) / 64;
+  if (s >= ns) return;
+  int m = 0;
+  const int r1 = min(rows, 64 * s + 64);
+  for (int r = 64 * s; r < r1; ++r) m = max(m, rp[r + 1] - rp[r]);
+  w64[s] = 64 * m;
+}
 template <typename T>
-static int tune_level(Ctx* c, ULevel<T>& lv, int autotune, bool fp32) {
-  if (lv.nS == 0) return 1;
+__global__ void k_sell_fill(int rows, const int* __restrict__ rp, const int* __restrict__ ci,
+                            const double* __restrict__ v, const int* __restrict__ off,
+                            int self_pad, int* __restrict__ sci, T* __restrict__ sv) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int o = off[r >> 6] + (r & 63), w = (off[(r >> 6) + 1] - off[r >> 6]) >> 6;
+  const int e0 = rp[r], len = rp[r + 1] - e0;
+  const int pad = self_pad ? r : 0;  // padding reads a defined element with weight zero
+  for (int e = 0; e < w; ++e) {
+    const bool in = e < len;
+    sci[o + 64 * e] = in ? ci[e0 + e] : pad;
+    sv[o + 64 * e] = in ? (T)v[e0 + e] : (T)0;
+  }
+}
+
+// CSR (FP64 values) -> layout `fmt` with values in T; `self_pad` pads SELL rows
+// with their own index as column (square stored-order matrices), else column 0
+template <typename T>
+static void to_layout(Ctx* c, const Csr<double>& M, int fmt, int tpr, bool self_pad,
+                      LMat<T>& out) {
+  out.rows = M.n_rows;
+  out.nnz = M.nnz;
+  out.fmt = fmt;
+  out.tpr = tpr;
+  if (fmt == kFmtCSR || M.n_rows == 0) {
+    out.fmt = kFmtCSR;
+    out.stored = M.nnz;
+    out.rp.alloc(c, (size_t)M.n_rows + 1);
+    copy_d2d(c, out.rp.get(), M.rp.get(), (size_t)M.n_rows + 1);
+    out.ci.alloc(c, (size_t)std::max(M.nnz, 1));
+    copy_d2d(c, out.ci.get(), M.ci.get(), (size_t)M.nnz);
+    out.v.alloc(c, (size_t)std::max(M.nnz, 1));
+    cast_copy<T, double>(c, out.v.get(), M.v.get(), (size_t)M.nnz, KC_VEC);
+    c->sync();
+    return;
+  }
+  const int ns = cdiv(M.n_rows, 64);
+  DBuf<int> w64(c, (size_t)ns);
+  hipLaunchKernelGGL(k_slice_width, dim3(cdiv(ns, 256)), dim3(256), 0, c->stream, M.n_rows,
+                     (const int*)M.rp.get(), w64.get());
+  MGD_CHECK_LAUNCH();
+  out.rp.alloc(c, (size_t)ns + 1);
+  out.stored = exclusive_scan_total(c, w64.get(), out.rp.get(), ns);
+  out.ci.alloc(c, (size_t)std::max(out.stored, 1LL));
+  out.v.alloc(c, (size_t)std::max(out.stored, 1LL));
+  hipLaunchKernelGGL(k_sell_fill<T>, dim3(cdiv(M.n_rows, 256)), dim3(256), 0, c->stream,
+                     M.n_rows, (const int*)M.rp.get(), (const int*)M.ci.get(),
+                     (const double*)M.v.get(), (const int*)out.rp.get(), self_pad ? 1 : 0,
+                     out.ci.get(), out.v.get());
+  MGD_CHECK_LAUNCH();
+  c->sync();
+}
+// padded size of the SELL layout of M (host-side estimate through the device widths)
+static long long sell_stored(Ctx* c, const Csr<double>& M) {
+  if (M.n_rows == 0) return 0;
+  const int ns = cdiv(M.n_rows, 64);
+  DBuf<int> w64(c, (size_t)ns), tmp(c, (size_t)ns + 1);
+  hipLaunchKernelGGL(k_slice_width, dim3(cdiv(ns, 256)), dim3(256), 0, c->stream, M.n_rows,
+                     (const int*)M.rp.get(), w64.get());
+  MGD_CHECK_LAUNCH();
+  return exclusive_scan_total(c, w64.get(), tmp.get(), ns);
+}
+
+template <typename T>
+static void tune_layout(Ctx* c, ULevel<T>& lv, const Csr<double>& A, int autotune, bool fp32);
+
+template <typename T>
+static void finalize_levels(Ctx* c, std::vector<BuildLevel<T>>& bl, Union<T>& U, int autotune) {
+  const int nl = (int)bl.size();
+  int* err = c->err_flag();
+  // extended stored order (stored rows, then dense members' rows) and its inverse
+  std::vector<DBuf<int>> pext(nl), sinv(nl);
+  for (int l = 0; l < nl; ++l) {
+    auto& b = bl[l];
+    pext[l].alloc(c, (size_t)std::max(b.n, 1));
+    sinv[l].alloc(c, (size_t)std::max(b.n, 1));
+    copy_d2d(c, pext[l].get(), b.perm.get(), (size_t)b.nS);
+    int pos = b.nS;
+    for (auto& d : b.dense) {
+      hipLaunchKernelGGL(k_iota, dim3(cdiv(d.n, 256)), dim3(256), 0, c->stream, d.n, d.off,
+                         pext[l].get() + pos);
+      MGD_CHECK_LAUNCH();
+      pos += d.n;
+    }
+    MGD_REQUIRE(pos == b.n, "internal: extended order does not cover the level");
+    if (b.n > 0) {
+      hipLaunchKernelGGL(k_invert, dim3(cdiv(b.n, 256)), dim3(256), 0, c->stream, b.n,
+                         (const int*)pext[l].get(), sinv[l].get(), err);
+      MGD_CHECK_LAUNCH();
+    }
+  }
+  c->check_device_errors("extended stored order");
+  U.L.clear();
+  U.L.resize(nl);
+  for (int l = 0; l < nl; ++l) {
+    StepScope st("solve-phase build: stored-order level " + std::to_string(l));
+    auto& b = bl[l];
+    ULevel<T>& lv = U.L[l];
+    lv.n = lv.nX = b.n;
+    lv.nS = b.nS;
+    lv.nC = b.nC;
+    lv.nnz_C = b.nnz_C;
+    lv.nnz_F = b.A.nnz - b.nnz_C;
+    lv.perm = std::move(pext[l]);
+    lv.dinv = std::move(b.dinv);
+    // columns of A in stored order (each member's rows only reference its own rows)
+    if (b.A.nnz > 0) {
+      hipLaunchKernelGGL(k_remap, dim3(cdiv(b.A.nnz, 256)), dim3(256), 0, c->stream,
+                         (long long)b.A.nnz, (const int*)sinv[l].get(), b.n, b.A.ci.get(), err);
+      MGD_CHECK_LAUNCH();
+    }
+    check_index_structure(c, b.A.n_rows, b.nS, b.A.nnz, b.A.rp.get(), b.A.ci.get(),
+                          "stored-order level matrix");
+    // dense members: offsets in the extended order
+    int pos = b.nS;
+    for (auto& d : b.dense) {
+      lv.dense.push_back({pos, d.n, d.inv});
+      lv.dense_max_n = std::max(lv.dense_max_n, d.n);
+      lv.dense_entries += (long long)d.n * d.n;
+      pos += d.n;
+    }
+    if (!lv.dense.empty()) {
+      lv.dense_dev.alloc(c, lv.dense.size());
+      copy_h2d(c, lv.dense_dev.get(), lv.dense.data(), lv.dense.size());
+    }
+    if (l + 1 < nl && b.n_coarse > 0) {
+      auto& nb = bl[l + 1];
+      MGD_REQUIRE(nb.n == b.n_coarse && b.nC == b.n_coarse,
+                  "internal: coarse level size differs from the C-block");
+      lv.nX_next = nb.n;
+      lv.nC_next = nb.nC;
+      lv.nS_next = nb.nS;
+      // W: columns to level l+1 extended order
+      if (b.W.nnz > 0) {
+        hipLaunchKernelGGL(k_remap, dim3(cdiv(b.W.nnz, 256)), dim3(256), 0, c->stream,
+                           (long long)b.W.nnz, (const int*)sinv[l + 1].get(), nb.n, b.W.ci.get(),
+                           err);
+        MGD_CHECK_LAUNCH();
+      }
+      // C-block position -> level l+1 index; level l+1 index -> C-block position
+      lv.cmap.alloc(c, (size_t)std::max(b.nC, 1));
+      lv.cpos.alloc(c, (size_t)std::max(nb.n, 1));
+      DBuf<int> cinv;
+      if (b.cnat.p) {
+        hipLaunchKernelGGL(k_compose, dim3(cdiv(b.nC, 256)), dim3(256), 0, c->stream, b.nC,
+                           (const int*)sinv[l + 1].get(), nb.n, (const int*)b.cnat.get(),
+                           lv.cmap.get(), err);
+        MGD_CHECK_LAUNCH();
+        cinv.alloc(c, (size_t)std::max(b.nC, 1));
+        hipLaunchKernelGGL(k_invert, dim3(cdiv(b.nC, 256)), dim3(256), 0, c->stream, b.nC,
+                           (const int*)b.cnat.get(), cinv.get(), err);
+        MGD_CHECK_LAUNCH();
+      } else {
+        copy_d2d(c, lv.cmap.get(), sinv[l + 1].get(), (size_t)b.nC);
+      }
+      // rows of W^T in level l+1 extended order
+      Csr<double> Wt2;
+      Wt2.n_rows = nb.n;
+      Wt2.n_cols = b.Wt.n_cols;
+      Wt2.nnz = b.Wt.nnz;
+      Wt2.rp.alloc(c, (size_t)nb.n + 1);
+      Wt2.ci.alloc(c, (size_t)std::max(b.Wt.nnz, 1));
+      Wt2.v.alloc(c, (size_t)std::max(b.Wt.nnz, 1));
+      {
+        // level l+1's extended order is pext[l+1] (moved into U.L[l+1] later)
+        const int* src = pext[l + 1].get();
+        if (b.cnat.p) {
+          hipLaunchKernelGGL(k_compose, dim3(cdiv(nb.n, 256)), dim3(256), 0, c->stream, nb.n,
+                             (const int*)cinv.get(), b.nC, src, lv.cpos.get(), err);
+          MGD_CHECK_LAUNCH();
+        } else {
+          copy_d2d(c, lv.cpos.get(), src, (size_t)nb.n);
+        }
+        DBuf<int> len(c, (size_t)nb.n + 1);
+        hipLaunchKernelGGL(k_gather_len, dim3(cdiv(nb.n, 256)), dim3(256), 0, c->stream, nb.n,
+                           (const int*)b.Wt.rp.get(), src, len.get());
+        MGD_CHECK_LAUNCH();
+        const int tot = exclusive_scan_total(c, len.get(), Wt2.rp.get(), nb.n);
+        MGD_REQUIRE(tot == b.Wt.nnz, "internal: permuted W^T lost entries");
+        hipLaunchKernelGGL(k_gather_rows, dim3(cdiv(nb.n, 256)), dim3(256), 0, c->stream, nb.n,
+                           (const int*)b.Wt.rp.get(), (const int*)b.Wt.ci.get(),
+                           (const double*)b.Wt.v.get(), src, (const int*)Wt2.rp.get(),
+                           Wt2.ci.get(), Wt2.v.get(), err);
+        MGD_CHECK_LAUNCH();
+      }
+      c->check_device_errors("transfer operators in stored order");
+      check_index_structure(c, b.W.n_rows, nb.n, b.W.nnz, b.W.rp.get(), b.W.ci.get(),
+                            "stored-order interpolation");
+      check_index_structure(c, Wt2.n_rows, b.nS - b.nC, Wt2.nnz, Wt2.rp.get(), Wt2.ci.get(),
+                            "stored-order restriction");
+      const double aw = b.W.n_rows ? (double)b.W.nnz / b.W.n_rows : 1.0;
+      const double at = nb.n ? (double)b.Wt.nnz / nb.n : 1.0;
+      const long long sw = sell_stored(c, b.W), st2 = sell_stored(c, Wt2);
+      if (b.W.nnz > 0 && sw <= (long long)(1.5 * b.W.nnz))
+        to_layout<T>(c, b.W, kFmtSELL, 1, false, lv.W);
+      else
+        to_layout<T>(c, b.W, kFmtCSR, default_tpr(aw), false, lv.W);
+      if (Wt2.nnz > 0 && st2 <= (long long)(1.5 * Wt2.nnz))
+        to_layout<T>(c, Wt2, kFmtSELL, 1, false, lv.Wt);
+      else
+        to_layout<T>(c, Wt2, kFmtCSR, default_tpr(at), false, lv.Wt);
+    }
+    c->check_device_errors("stored-order level");
+    tune_layout<T>(c, lv, b.A, autotune, sizeof(T) == 4);
+  }
+  // workspace
+  U.B.resize(nl);
+  U.X0.resize(nl);
+  U.X1.resize(nl);
+  U.R.resize(nl);
+  U.n0 = nl ? U.L[0].nX : 0;
+  for (int l = 0; l < nl; ++l) {
+    auto& lv = U.L[l];
+    U.B[l].alloc(c, (size_t)std::max(lv.nX, 1));
+    U.X0[l].alloc(c, (size_t)std::max(lv.nX, 1));
+    U.X1[l].alloc(c, (size_t)std::max(lv.nX, 1));
+    U.R[l].alloc(c, (size_t)std::max(lv.nS, 1));
+  }
+  U.t1.alloc(c, (size_t)std::max(U.n0, 1));
+}
+
+// Layout of a level matrix: the tuned choice cached per (rows, nnz, longest
+// row) key (1000 = SELL, t = CSR with t lanes per row); without a cached
+// choice and with autotuning off, SELL when padding stays within 30%, else
+// CSR with a lane count from the mean row length.
+constexpr int kTuneSell = 1000;
+template <typename T>
+static void tune_layout(Ctx* c, ULevel<T>& lv, const Csr<double>& A, int autotune, bool fp32) {
+  if (lv.nS == 0) {
+    to_layout<T>(c, A, kFmtCSR, 1, true, lv.A);
+    return;
+  }
   DBuf<int> mr(c, 1);
   fill<int>(c, mr.get(), 0, 1);
   hipLaunchKernelGGL(k_max_row, dim3(cdiv(lv.nS, 256)), dim3(256), 0, c->stream, lv.nS,
-                     lv.A.rp.get(), mr.get());
+                     (const int*)A.rp.get(), mr.get());
   MGD_CHECK_LAUNCH();
   const int maxrow = read1(c, mr.get());
-  const double avg = (double)lv.A.nnz / lv.nS;
-  int t = autotune_lookup(lv.nS, lv.A.nnz, maxrow, fp32);
-  if (t > 0) return t;
-  if (!autotune) return default_tpr(avg);
-  DBuf<T> x(c, (size_t)lv.n), y(c, (size_t)lv.nS);
-  fill<T>(c, x.get(), (T)1, (size_t)lv.n);
+  const double avg = (double)A.nnz / lv.nS;
+  const long long st = sell_stored(c, A);
+  auto apply = [&](int code) {
+    if (code == kTuneSell)
+      to_layout<T>(c, A, kFmtSELL, 1, true, lv.A);
+    else
+      to_layout<T>(c, A, kFmtCSR, code, true, lv.A);
+  };
+  const int cached = autotune_lookup(lv.nS, A.nnz, maxrow, fp32);
+  if (cached > 0) {
+    apply(cached);
+    return;
+  }
+  const int dflt = st <= (long long)(1.3 * A.nnz) ? kTuneSell : default_tpr(avg);
+  if (!autotune) {
+    apply(dflt);
+    return;
+  }
+  std::vector<int> cands;
+  if (st <= 2 * A.nnz) cands.push_back(kTuneSell);
+  for (int t : {1, 2, 4, 8, 16, 32})
+    if (t == 1 || t <= 2 * std::max(avg, 1.0)) cands.push_back(t);
+  DBuf<T> x(c, (size_t)std::max(lv.nX, 1)), bb(c, (size_t)lv.nS), r(c, (size_t)lv.nS);
+  fill<T>(c, x.get(), (T)1, (size_t)std::max(lv.nX, 1));
+  fill<T>(c, bb.get(), (T)1, (size_t)lv.nS);
   hipEvent_t e0, e1;
   MGD_HIP(hipEventCreate(&e0));
   MGD_HIP(hipEventCreate(&e1));
   float best = 1e30f;
-  int bt = default_tpr(avg);
+  int bt = dflt;
   const bool prof = c->profiling;
   c->profiling = false;
-  for (int cand : {1, 2, 4, 8, 16, 32}) {
-    if (cand > 1 && cand > 2 * std::max(avg, 1.0)) break;
-    dispatch<ResidLaunch>(cand, c, (const ULevel<T>*)&lv, (const T*)x.get(), (const T*)x.get(),
-                          y.get(), false);
+  for (int cand : cands) {
+    apply(cand);
+    const auto g = gather_cf<T>(x.get(), x.get(), lv.nC);
+    ResidL<T> run{c, lv.A, lv.nS, bb.get(), g, r.get()};
+    with_layout(lv.A.fmt, lv.A.tpr, run);
     MGD_HIP(hipEventRecord(e0, c->stream));
-    for (int rep = 0; rep < 5; ++rep)
-      dispatch<ResidLaunch>(cand, c, (const ULevel<T>*)&lv, (const T*)x.get(), (const T*)x.get(),
-                            y.get(), false);
+    for (int rep = 0; rep < 5; ++rep) with_layout(lv.A.fmt, lv.A.tpr, run);
     MGD_HIP(hipEventRecord(e1, c->stream));
     MGD_HIP(hipEventSynchronize(e1));
     float ms = 0;
@@ -887,8 +1575,8 @@ static int tune_level(Ctx* c, ULevel<T>& lv, int autotune, bool fp32) {
   c->profiling = prof;
   MGD_HIP(hipEventDestroy(e0));
   MGD_HIP(hipEventDestroy(e1));
-  autotune_store(lv.nS, lv.A.nnz, maxrow, fp32, bt);
-  return bt;
+  apply(bt);
+  autotune_store(lv.nS, A.nnz, maxrow, fp32, bt);
 }
 
 template struct Union<double>;

@@ -21,24 +21,47 @@
 namespace mgd {
 
 struct DenseDev {
-  int off;  // natural offset at this level
+  int off;  // first row of the member in the level's extended stored order
   int n;
   const double* inv;  // column-major n x n
 };
 
+// A level matrix in one of two layouts chosen per level:
+//   SELL: slices of 64 consecutive rows, each stored column-major with the
+//         slice's longest row as its width (entry e of row 64 s + t at
+//         off[s] + 64 e + t; padding entries are zero with the row's own
+//         column), so one lane per row reads consecutive addresses;
+//   CSR:  row pointers, and `tpr` lanes of a wavefront per row.
+template <typename T>
+struct LMat {
+  int rows = 0, fmt = 0, tpr = 1;  // fmt: 0 CSR, 1 SELL
+  long long nnz = 0;               // entries (without padding)
+  long long stored = 0;            // stored entries (with padding)
+  DBuf<int> rp;                    // CSR: rows + 1 row pointers; SELL: slices + 1 offsets
+  DBuf<int> ci;
+  DBuf<T> v;
+};
+enum { kFmtCSR = 0, kFmtSELL = 1 };
+
+// One level of a union in extended stored order: [0, nC) the C-block, [nC, nS)
+// the F-block (rows smoothed, F points and relaxed coarsest rows), [nS, nX)
+// rows of members solved densely at this level.  Every vector of the level is
+// kept in this order; columns of A are stored-order indices.
 template <typename T>
 struct ULevel {
-  int n = 0;         // natural rows (including dense-solved members)
-  int nS = 0;        // stored rows
-  int nC = 0;        // C-block size
-  int n_coarse = 0;  // rows of level l+1 (0: no coarser level)
-  long long nnz_S_C = 0, nnz_S_F = 0;
-  Csr<T> A;          // nS rows, natural columns
-  DBuf<int> perm;    // stored -> natural
-  DBuf<T> dinv;      // 1 / l1 diagonal, per stored row
-  Csr<T> W;          // nS - nC rows, n_coarse columns
-  Csr<T> Wt;         // n_coarse rows, nS - nC columns
-  int tpr = 1, tpr_w = 1, tpr_wt = 1;
+  int n = 0;          // rows (== nX)
+  int nS = 0, nC = 0; // stored rows, C-block size
+  int nX = 0;         // extended rows
+  int nX_next = 0;    // rows of level l+1 (0: last level)
+  int nC_next = 0, nS_next = 0;
+  long long nnz_C = 0, nnz_F = 0;  // entries of C rows and of F rows
+  LMat<T> A;          // nS rows, stored-order columns
+  DBuf<T> dinv;       // 1 / l1 diagonal, stored rows
+  DBuf<int> perm;     // extended stored order -> natural union numbering (nX)
+  LMat<T> W;          // F rows of P (nS - nC rows), columns in level l+1 extended order
+  LMat<T> Wt;         // W transposed, rows in level l+1 extended order, columns F index
+  DBuf<int> cmap;     // C row I -> its level l+1 extended index (nC)
+  DBuf<int> cpos;     // level l+1 extended index k -> C row of this level (nX_next)
   std::vector<DenseDev> dense;
   DBuf<DenseDev> dense_dev;
   int dense_max_n = 0;
@@ -48,16 +71,22 @@ struct ULevel {
 template <typename T>
 struct Union {
   std::vector<ULevel<T>> L;
-  std::vector<DBuf<T>> b, X0, X1, r;  // per level (b[0], X1[0] unused: caller's)
-  DBuf<T> t0, t1;                     // finest-level scratch for extra cycles
+  // per level: right-hand side (nX), two iterate buffers (nX; the C and F
+  // regions alternate between them independently), residual (nS)
+  std::vector<DBuf<T>> B, X0, X1, R;
+  DBuf<T> t1;  // natural level-0 scratch for extra cycles
   int n0 = 0;
   int n_pre = 1, n_post = 1;
   int members = 0;
 
   // z = k V-cycles on b (zero initial guess); b, z natural level-0 vectors.
   void apply(Ctx* c, const T* b, T* z, int cycles);
-  void vcycle(Ctx* c, const T* b, T* z);
   double bytes_per_vcycle() const;
+
+ private:
+  // one V-cycle on B[0] (already in stored order, C values of X0[0] set)
+  // ending with z (natural) = the result
+  void vcycle(Ctx* c, T* z);
 };
 
 template <typename T>
