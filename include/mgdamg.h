@@ -122,7 +122,10 @@ typedef struct amg_params {
   int32_t n_pre, n_post;  /* 1, 1 */
   int32_t precision;      /* 0: FP64 solve phase; 1: FP32 matrices and vectors
                              (coarsest solve stays FP64) */
-  int32_t autotune;       /* 1: time SpMV row-group widths per level once and cache */
+  int32_t autotune;       /* 1: time the level matrix layouts once per shape and cache */
+  int32_t coarsening;     /* 0: PMIS; 1: HMIS (Ruge-Stueben first pass inside tiles of
+                             hmis_tile consecutive rows, then PMIS for the rest) */
+  int32_t hmis_tile;      /* 1024, in [1, 1024] */
 } amg_params;
 void amg_params_default(amg_params* p);
 

@@ -135,7 +135,7 @@ def pmis_keys(A: sp.csr_matrix, S: np.ndarray, seed: int, level: int) -> np.ndar
 
 
 def pmis_with_keys(A: sp.csr_matrix, S: np.ndarray, key: np.ndarray,
-                   return_rounds: bool = False):
+                   return_rounds: bool = False, initial: Optional[np.ndarray] = None):
     """PMIS rounds (De Sterck, Yang, Heys 2006) for given integer keys.
 
     Rows nobody depends on (|S^T_i| = 0) start as F, all others undecided.
@@ -149,8 +149,11 @@ def pmis_with_keys(A: sp.csr_matrix, S: np.ndarray, key: np.ndarray,
     rows = csr_rows(A)[S]
     cols = A.indices[S].astype(np.int64)
     stc = strength_transpose_counts(A, S)
-    state = np.zeros(n, dtype=np.int8)
-    state[stc == 0] = F_PT
+    if initial is None:
+        state = np.zeros(n, dtype=np.int8)
+        state[stc == 0] = F_PT
+    else:
+        state = initial.astype(np.int8).copy()
     ei = np.concatenate([rows, cols])
     ej = np.concatenate([cols, rows])
     rounds = 0
@@ -176,6 +179,75 @@ def pmis(A: sp.csr_matrix, S: np.ndarray, seed: int, level: int,
          return_rounds: bool = False):
     """C/F splitting by PMIS.  Returns int8 array (1 = C, -1 = F)."""
     return pmis_with_keys(A, S, pmis_keys(A, S, seed, level), return_rounds)
+
+
+# ----------------------------------------------------------------------------
+# HMIS coarsening
+# ----------------------------------------------------------------------------
+def rs_first_pass_tiles(A: sp.csr_matrix, S: np.ndarray, seed: int, level: int,
+                        tile: int) -> np.ndarray:
+    """C points of the Ruge-Stueben first pass run independently on each tile
+    of `tile` consecutive rows, on the strength graph restricted to the tile.
+
+    The measure of a point is the number of undecided tile points that depend
+    strongly on it (initially the tile-internal |S^T_i|).  While some undecided
+    point has a positive measure, the undecided point with the largest
+    (measure, hash32(seed, level, i), i) becomes C; every undecided tile point
+    depending strongly on it becomes F, and for each such new F point the
+    measures of its undecided tile dependencies rise by one; then the measures
+    of the new C point's own undecided tile dependencies drop by one.  Points
+    left undecided (measure 0) are not C.  Plain loops: small inputs only."""
+    n = A.shape[0]
+    rows = csr_rows(A)
+    cols = A.indices.astype(np.int64)
+    hk = hash32(seed, level, np.arange(n)).astype(np.int64)
+    isC = np.zeros(n, dtype=bool)
+    for t0 in range(0, n, tile):
+        t1 = min(n, t0 + tile)
+        dep = {i: [] for i in range(t0, t1)}     # S_i within the tile
+        rdep = {i: [] for i in range(t0, t1)}    # S^T_i within the tile
+        for e in np.nonzero(S & (rows >= t0) & (rows < t1) & (cols >= t0) & (cols < t1))[0]:
+            i, j = int(rows[e]), int(cols[e])
+            dep[i].append(j)
+            rdep[j].append(i)
+        lam = {i: len(rdep[i]) for i in range(t0, t1)}
+        state = {i: 0 for i in range(t0, t1)}      # 0 undecided, 1 C, -1 F
+        while True:
+            cand = [i for i in range(t0, t1) if state[i] == 0 and lam[i] > 0]
+            if not cand:
+                break
+            p = max(cand, key=lambda i: (lam[i], int(hk[i]), i))
+            state[p] = 1
+            isC[p] = True
+            newf = [j for j in rdep[p] if state[j] == 0]
+            for j in newf:
+                state[j] = -1
+            for j in newf:
+                for k in dep[j]:
+                    if state[k] == 0:
+                        lam[k] += 1
+            for k in dep[p]:
+                if state[k] == 0:
+                    lam[k] -= 1
+    return isC
+
+
+def hmis(A: sp.csr_matrix, S: np.ndarray, seed: int, level: int, tile: int = 1024,
+         return_rounds: bool = False):
+    """Hybrid MIS (De Sterck, Yang, Heys 2006): the tile-local Ruge-Stueben
+    first pass fixes its C points; every other point that depends strongly on
+    one of them, or that nobody depends on, is F; PMIS rounds with the usual
+    keys decide the rest."""
+    c0 = rs_first_pass_tiles(A, S, seed, level, tile)
+    rows = csr_rows(A)[S]
+    cols = A.indices[S].astype(np.int64)
+    stc = strength_transpose_counts(A, S)
+    state = np.zeros(A.shape[0], dtype=np.int8)
+    depc = np.zeros(A.shape[0], dtype=bool)
+    depc[rows[c0[cols]]] = True
+    state[(stc == 0) | depc] = F_PT
+    state[c0] = C_PT
+    return pmis_with_keys(A, S, pmis_keys(A, S, seed, level), return_rounds, initial=state)
 
 
 # ----------------------------------------------------------------------------
@@ -328,6 +400,8 @@ class AMGParams:
     dense_max: int = 2000
     n_pre: int = 1
     n_post: int = 1
+    coarsening: str = "pmis"           # "pmis" or "hmis"
+    hmis_tile: int = 1024
 
 
 @dataclass
@@ -374,7 +448,10 @@ def setup(A: sp.csr_matrix, params: Optional[AMGParams] = None) -> Hierarchy:
             levels.append(Level(A, d))
             break
         S = strength(A, p.strength_theta, p.dominance_theta)
-        cf, rounds = pmis(A, S, p.seed, lvl, return_rounds=True)
+        if p.coarsening == "hmis":
+            cf, rounds = hmis(A, S, p.seed, lvl, p.hmis_tile, return_rounds=True)
+        else:
+            cf, rounds = pmis(A, S, p.seed, lvl, return_rounds=True)
         nc = int(np.count_nonzero(cf == C_PT))
         if nc == 0 or 10 * nc > 9 * n:
             levels.append(Level(A, d))

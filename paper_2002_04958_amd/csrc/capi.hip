@@ -421,6 +421,8 @@ void amg_params_default(amg_params* p) {
   p->n_post = 1;
   p->precision = 0;
   p->autotune = 0;
+  p->coarsening = 0;
+  p->hmis_tile = 1024;
 }
 
 static void check_amg_params(const amg_params* p) {
@@ -432,6 +434,9 @@ static void check_amg_params(const amg_params* p) {
   MGD_REQUIRE(p->n_pre >= 0 && p->n_post >= 0 && p->n_pre <= 16 && p->n_post <= 16,
               "n_pre / n_post out of range");
   MGD_REQUIRE(p->precision == 0 || p->precision == 1, "precision must be 0 or 1");
+  MGD_REQUIRE(p->coarsening == 0 || p->coarsening == 1, "coarsening must be 0 (PMIS) or 1 (HMIS)");
+  MGD_REQUIRE(p->coarsening == 0 || (p->hmis_tile >= 1 && p->hmis_tile <= 1024),
+              "hmis_tile must be in [1, 1024]");
 }
 
 mgd_status amg_setup(mgd_ctx* ctx, const mgd_csr* A, const amg_params* p, amg_hierarchy** out) {

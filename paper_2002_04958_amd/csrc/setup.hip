@@ -167,8 +167,119 @@ __global__ void k_count_undecided(int n, const int8_t* __restrict__ state,
   if ((threadIdx.x & 63) == 0 && m) atomicAdd(remaining, (int)__popcll(m));
 }
 
+// ---------------------------------------------------------------------------
+// HMIS: Ruge-Stueben first pass inside tiles of consecutive rows (one
+// workgroup per tile, state in LDS), then PMIS for the points it leaves open
+// ---------------------------------------------------------------------------
+constexpr int kMaxHmisTile = 1024;
+
+__device__ __forceinline__ uint64_t block_max_u64(uint64_t v, uint64_t* red) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint64_t m = red[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = red[w] > m ? red[w] : m;
+  __syncthreads();
+  return m;
+}
+
+// One workgroup (256 threads) per tile [t0, t1).  The measure of a point is
+// the number of undecided tile points depending strongly on it; the point of
+// largest (measure, hash, index) with a positive measure becomes C, the
+// undecided tile points depending on it become F, the measures of those new F
+// points' undecided tile dependencies rise by one, then the measures of the new
+// C point's undecided tile dependencies drop by one.  c0[i] = 1 for the C points.
+__global__ void __launch_bounds__(256) k_rs_tiles(int n, int tile, uint64_t seed, int level,
+                                                  const int* __restrict__ rp,
+                                                  const int* __restrict__ ci,
+                                                  const uint8_t* __restrict__ S,
+                                                  const int* __restrict__ st_rp,
+                                                  const int* __restrict__ st_ci,
+                                                  int8_t* __restrict__ c0) {
+  __shared__ int lam[kMaxHmisTile];
+  __shared__ int8_t st[kMaxHmisTile];
+  __shared__ uint8_t newf[kMaxHmisTile];
+  __shared__ uint32_t hk[kMaxHmisTile];
+  __shared__ uint64_t red[4];
+  const int t0 = blockIdx.x * tile, t1 = min(n, t0 + tile), nt = t1 - t0;
+  for (int i = threadIdx.x; i < nt; i += 256) {
+    st[i] = 0;
+    newf[i] = 0;
+    hk[i] = (uint32_t)(splitmix64_first(seed ^ ((uint64_t)level << 56) ^ (uint64_t)(t0 + i)) >> 32);
+    int m = 0;
+    for (int e = st_rp[t0 + i]; e < st_rp[t0 + i + 1]; ++e) {
+      const int j = st_ci[e];
+      m += (j >= t0 && j < t1) ? 1 : 0;
+    }
+    lam[i] = m;
+  }
+  __syncthreads();
+  for (int step = 0; step < nt; ++step) {
+    uint64_t best = 0;
+    for (int i = threadIdx.x; i < nt; i += 256) {
+      if (st[i] == 0 && lam[i] > 0) {
+        const uint64_t k = ((uint64_t)lam[i] << 48) | ((uint64_t)hk[i] << 16) | (uint64_t)i;
+        best = k > best ? k : best;
+      }
+    }
+    best = block_max_u64(best, red);
+    if (best == 0) break;  // the same value in every thread
+    const int pl = (int)(best & 0xffff), pg = t0 + pl;
+    if (threadIdx.x == 0) st[pl] = 1;
+    __syncthreads();
+    // undecided tile points depending on the new C point become F
+    for (int e = st_rp[pg] + threadIdx.x; e < st_rp[pg + 1]; e += 256) {
+      const int j = st_ci[e] - t0;
+      if (j >= 0 && j < nt && st[j] == 0) {
+        st[j] = -1;
+        newf[j] = 1;
+      }
+    }
+    __syncthreads();
+    // their undecided tile dependencies gain one
+    for (int e = st_rp[pg] + threadIdx.x; e < st_rp[pg + 1]; e += 256) {
+      const int j = st_ci[e] - t0;
+      if (j >= 0 && j < nt && newf[j]) {
+        newf[j] = 0;
+        for (int f = rp[t0 + j]; f < rp[t0 + j + 1]; ++f) {
+          const int k = ci[f] - t0;
+          if (S[f] && k >= 0 && k < nt && st[k] == 0) atomicAdd(&lam[k], 1);
+        }
+      }
+    }
+    __syncthreads();
+    // the new C point's undecided tile dependencies lose one
+    for (int f = rp[pg] + threadIdx.x; f < rp[pg + 1]; f += 256) {
+      const int k = ci[f] - t0;
+      if (S[f] && k >= 0 && k < nt && st[k] == 0) atomicAdd(&lam[k], -1);
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < nt; i += 256) c0[t0 + i] = st[i] == 1 ? 1 : 0;
+}
+
+// HMIS initial state: first-pass C points; F for points nobody depends on or
+// that depend strongly on a first-pass C point; undecided otherwise
+__global__ void k_hmis_init(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                            const uint8_t* __restrict__ S, const int* __restrict__ stc,
+                            const int8_t* __restrict__ c0, int8_t* __restrict__ state) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (c0[i]) {
+    state[i] = kC;
+    return;
+  }
+  bool dep = stc[i] == 0;
+  for (int e = rp[i]; e < rp[i + 1] && !dep; ++e)
+    if (S[e] && c0[ci[e]]) dep = true;
+  state[i] = dep ? kF : kU;
+}
+
 int pmis(Ctx* c, const Csr<double>& A, const DBuf<uint8_t>& S, const DBuf<int>& stc,
-         uint64_t seed, int level, DBuf<int8_t>& state) {
+         uint64_t seed, int level, DBuf<int8_t>& state, int hmis_tile) {
   const int n = A.n_rows;
   state.alloc(c, (size_t)n);
   if (n == 0) return 0;
@@ -187,6 +298,17 @@ int pmis(Ctx* c, const Csr<double>& A, const DBuf<uint8_t>& S, const DBuf<int>& 
   MGD_CHECK_LAUNCH();
   c->check_device_errors("transposed strength graph");
   check_index_structure(c, n, n, nst, st_rp.get(), st_ci.get(), "transposed strength graph");
+  if (hmis_tile > 0) {
+    DBuf<int8_t> c0(c, (size_t)n);
+    hipLaunchKernelGGL(k_rs_tiles, dim3(cdiv(n, hmis_tile)), dim3(256), 0, c->stream, n, hmis_tile,
+                       seed, level, A.rp.get(), A.ci.get(), S.get(), (const int*)st_rp.get(),
+                       (const int*)st_ci.get(), c0.get());
+    MGD_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_hmis_init, dim3(g), dim3(256), 0, c->stream, n, A.rp.get(), A.ci.get(),
+                       S.get(), stc.get(), (const int8_t*)c0.get(), state.get());
+    MGD_CHECK_LAUNCH();
+    c->sync();
+  }
   fill<int>(c, remaining.get(), 0, 1);
   hipLaunchKernelGGL(k_count_undecided, dim3(g), dim3(256), 0, c->stream, n, state.get(),
                      remaining.get());
@@ -659,7 +781,7 @@ void amg_build(Ctx* c, Csr<double>&& A0, const amg_params& p, SetupHierarchy& H)
     strength(c, A, p.strength_theta, p.dominance_theta, S, stc);
     DBuf<int8_t> state;
     StepScope st_pmis("amg setup: pmis" + at);
-    const int rounds = pmis(c, A, S, stc, p.seed, lvl, state);
+    const int rounds = pmis(c, A, S, stc, p.seed, lvl, state, p.coarsening == 1 ? p.hmis_tile : 0);
     StepScope st_cnum("amg setup: coarse numbering" + at);
     DBuf<int> isc(c, (size_t)n), cidx(c, (size_t)n + 1);
     hipLaunchKernelGGL(k_is_c, dim3(cdiv(n, 256)), dim3(256), 0, c->stream, n, state.get(),

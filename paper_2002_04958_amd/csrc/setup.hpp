@@ -29,8 +29,9 @@ void amg_build(Ctx* c, Csr<double>&& A0, const amg_params& p, SetupHierarchy& H)
 // Pieces exposed for testing and for the union builder.
 void strength(Ctx* c, const Csr<double>& A, double theta, double dom, DBuf<uint8_t>& S,
               DBuf<int>& stc);
+// hmis_tile > 0: HMIS with tiles of that many rows (<= 1024), else PMIS
 int pmis(Ctx* c, const Csr<double>& A, const DBuf<uint8_t>& S, const DBuf<int>& stc,
-         uint64_t seed, int level, DBuf<int8_t>& state);
+         uint64_t seed, int level, DBuf<int8_t>& state, int hmis_tile);
 void interpolation(Ctx* c, const Csr<double>& A, const DBuf<uint8_t>& S,
                    const DBuf<int8_t>& state, const DBuf<int>& cidx, int nc, Csr<double>& P);
 // Sorted transpose (values copied).

@@ -111,6 +111,25 @@ def test_amg_setup_full_chain_bit_exact(ctx, which):
     _compare_hierarchies(g, H, exact_values=True)
 
 
+@pytest.mark.parametrize("which,tile", [("block_E_g2_2d16", 64), ("mono_g2_2d16_nonsym", 128),
+                                        ("block_g0_3d10", 1024)])
+def test_amg_setup_hmis_bit_exact(ctx, which, tile):
+    """HMIS (tile-local Ruge-Stueben first pass, then PMIS): the whole hierarchy
+    equals the oracle's bit for bit, and one V-cycle agrees to 1e-12."""
+    api = gpu_modules()
+    if which == "block_E_g2_2d16":
+        A = oracle_system(si.generate_workload("g2_2d16")).blocks[2]
+    elif which == "block_g0_3d10":
+        A = oracle_system(si.generate(1, 3, 10, 31)).blocks[0]
+    else:
+        A = oracle_system(si.generate(2, 2, 16, 32, nonsym=True)).monolithic()
+    H = oamg.setup(A, oamg.AMGParams(seed=5, coarsening="hmis", hmis_tile=tile))
+    g = api.AMG(ctx, A.indptr, A.indices, A.data, seed=5, coarsening=1, hmis_tile=tile)
+    _compare_hierarchies(g, H, exact_values=True)
+    b = np.random.default_rng(6).uniform(size=A.shape[0])
+    assert rel(to_host(g.apply(to_dev(ctx, b))), oamg.vcycle(H, b)) < 1e-12
+
+
 def test_amg_levelwise_on_gpu_levels(ctx):
     """Binding test: the oracle's strength, PMIS and interpolation applied to
     each GPU level matrix give the GPU's C/F splitting and P bit for bit."""

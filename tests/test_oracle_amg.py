@@ -342,3 +342,60 @@ def test_solve_to_tolerance_reaches_tolerance():
     assert np.linalg.norm(b - A @ z) < 1e-6 * np.linalg.norm(b)
     z2, k2 = amg.solve_to_tolerance(H, b, 1e-2)
     assert k2 <= k
+
+
+# --- HMIS ---------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(5))
+def test_rs_first_pass_1d_chain_alternates(seed):
+    """Ruge-Stueben coarsening of the 1D Poisson chain (textbook result): C and
+    F points alternate, whichever interior point the tie-break picks first."""
+    n = 17
+    A = sp.csr_matrix(sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1]))
+    A.sort_indices()
+    S = amg.strength(A, 0.25, 0.0)
+    c = amg.rs_first_pass_tiles(A, S, seed, 0, 1024)
+    assert not np.any(c[1:] & c[:-1])          # no two neighbouring C points
+    assert not np.any(~c[1:-1] & ~c[2:] & ~c[:-2])  # no interior F run of three
+    cf = amg.hmis(A, S, seed, 0, 1024)
+    assert np.array_equal(cf == 1, c)           # PMIS has nothing left to decide
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_hmis_single_row_tiles_is_pmis(seed):
+    """With one-row tiles the first pass finds no tile-internal dependency, so
+    HMIS reduces to PMIS exactly."""
+    A = _random_mmatrix(70, seed)
+    S = amg.strength(A, 0.25, 0.9)
+    assert np.array_equal(amg.hmis(A, S, seed, 1, tile=1), amg.pmis(A, S, seed, 1))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_hmis_splitting_invariants(seed):
+    A = _random_mmatrix(90, seed + 10)
+    S = amg.strength(A, 0.25, 0.9)
+    rows = amg.csr_rows(A)
+    cols = A.indices.astype(np.int64)
+    stc = amg.strength_transpose_counts(A, S)
+    c0 = amg.rs_first_pass_tiles(A, S, seed, 0, 32)
+    cf = amg.hmis(A, S, seed, 0, tile=32)
+    isC = cf == 1
+    assert set(np.unique(cf)) <= {1, -1}
+    assert np.all(isC[c0])                      # first-pass C points stay C
+    hasC = np.zeros(A.shape[0], dtype=bool)
+    hasC[rows[S & isC[cols]]] = True
+    assert np.all(hasC[(cf == -1) & (stc > 0)])  # F points interpolate from a C point
+    assert np.all(cf[stc == 0] == -1)
+
+
+def test_hmis_2d_laplacian_one_tile_halves_points():
+    """On the 2D 5-point Laplacian one RS first pass over the whole grid gives
+    the red-black pattern (every C point's four neighbours are F)."""
+    A = _laplace2d(8)
+    S = amg.strength(A, 0.25, 0.0)
+    cf = amg.hmis(A, S, 2, 0, tile=1024)
+    isC = cf == 1
+    rows = amg.csr_rows(A)
+    cols = A.indices.astype(np.int64)
+    off = rows != cols
+    assert not np.any(isC[rows[off]] & isC[cols[off]])   # C points independent
+    assert abs(int(isC.sum()) - 32) <= 4
