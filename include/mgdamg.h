@@ -126,6 +126,9 @@ typedef struct amg_params {
   int32_t coarsening;     /* 0: PMIS; 1: HMIS (Ruge-Stueben first pass inside tiles of
                              hmis_tile consecutive rows, then PMIS for the rest) */
   int32_t hmis_tile;      /* 1024, in [1, 1024] */
+  int32_t smoother;       /* 0: CF-ordered l1-Jacobi; 1: multicolour Gauss-Seidel (Jones-
+                             Plassmann colours, ascending going down, descending going up;
+                             a stalled coarsest level is relaxed the same way) */
 } amg_params;
 void amg_params_default(amg_params* p);
 

@@ -387,6 +387,44 @@ def l1_diagonal(A: sp.csr_matrix) -> np.ndarray:
                            add, init=diagonal_of(A))
 
 
+def jp_colours(A: sp.csr_matrix, seed: int, level: int) -> np.ndarray:
+    """Jones-Plassmann colouring of the structural graph of A (every stored
+    off-diagonal entry is an edge, in both directions).  In round c every
+    uncoloured vertex whose (hash32(seed, level, i), i) exceeds that of all its
+    uncoloured neighbours gets colour c."""
+    n = A.shape[0]
+    rows = csr_rows(A)
+    cols = A.indices.astype(np.int64)
+    off = rows != cols
+    ei = np.concatenate([rows[off], cols[off]])
+    ej = np.concatenate([cols[off], rows[off]])
+    key = hash32(seed, level, np.arange(n)).astype(np.int64)
+    colour = np.full(n, -1, dtype=np.int64)
+    c = 0
+    while np.any(colour < 0):
+        unc = colour < 0
+        live = unc[ei] & unc[ej]
+        beaten = (key[ej] > key[ei]) | ((key[ej] == key[ei]) & (ej > ei))
+        lose = np.zeros(n, dtype=bool)
+        lose[ei[live & beaten]] = True
+        colour[unc & ~lose] = c
+        c += 1
+    return colour
+
+
+def gs_sweep(A, dg, b, x, colour, descending=False):
+    """Multicolour Gauss-Seidel: colour by colour (ascending, or descending),
+    x_c += (b_c - (A x)_c) / a_cc with A x taken after the previous colours."""
+    x = x.copy()
+    ncol = int(colour.max()) + 1 if len(colour) else 0
+    order = range(ncol - 1, -1, -1) if descending else range(ncol)
+    for c in order:
+        mask = colour == c
+        r = b - A @ x
+        x[mask] = x[mask] + r[mask] / dg[mask]
+    return x
+
+
 # ----------------------------------------------------------------------------
 # hierarchy
 # ----------------------------------------------------------------------------
@@ -402,6 +440,7 @@ class AMGParams:
     n_post: int = 1
     coarsening: str = "pmis"           # "pmis" or "hmis"
     hmis_tile: int = 1024
+    smoother: str = "cf_l1_jacobi"     # or "mc_gs" (multicolour Gauss-Seidel)
 
 
 @dataclass
@@ -412,6 +451,8 @@ class Level:
     P: Optional[sp.csr_matrix] = None
     R: Optional[sp.csr_matrix] = None
     pmis_rounds: int = 0
+    colour: Optional[np.ndarray] = None  # multicolour Gauss-Seidel colours
+    dg: Optional[np.ndarray] = None      # a_ii, for Gauss-Seidel
 
 
 @dataclass
@@ -461,6 +502,10 @@ def setup(A: sp.csr_matrix, params: Optional[AMGParams] = None) -> Hierarchy:
         levels.append(Level(A, d, cf, P, R, rounds))
         A = Ac
         lvl += 1
+    if p.smoother == "mc_gs":
+        for k, L in enumerate(levels):
+            L.colour = jp_colours(L.A, p.seed, k)
+            L.dg = diagonal_of(L.A)
     H = Hierarchy(levels, p)
     Ac = levels[-1].A
     if Ac.shape[0] <= p.dense_max:
@@ -487,10 +532,17 @@ def vcycle(H: Hierarchy, b: np.ndarray, lvl: int = 0) -> np.ndarray:
     """One V(n_pre, n_post) cycle with zero initial guess (Section 3.1)."""
     L = H.levels[lvl]
     p = H.params
+    gs = p.smoother == "mc_gs"
     if lvl == len(H.levels) - 1:
         if H.coarse_kind == "lu":
             return sla.lu_solve(H.lu, b)
         x = np.zeros_like(b)
+        if gs:                               # ascending, then descending colours
+            for _ in range(p.n_pre):
+                x = gs_sweep(L.A, L.dg, b, x, L.colour)
+            for _ in range(p.n_post):
+                x = gs_sweep(L.A, L.dg, b, x, L.colour, descending=True)
+            return x
         allrows = np.ones(len(b), dtype=bool)
         for _ in range(p.n_pre + p.n_post):
             x = half_sweep(L.A, L.d, b, x, allrows)
@@ -498,15 +550,21 @@ def vcycle(H: Hierarchy, b: np.ndarray, lvl: int = 0) -> np.ndarray:
     isC = L.cf == C_PT
     isF = ~isC
     x = np.zeros_like(b)
-    for _ in range(p.n_pre):                 # going down: C then F
-        x = half_sweep(L.A, L.d, b, x, isC)
-        x = half_sweep(L.A, L.d, b, x, isF)
+    for _ in range(p.n_pre):                 # going down: C then F (or ascending colours)
+        if gs:
+            x = gs_sweep(L.A, L.dg, b, x, L.colour)
+        else:
+            x = half_sweep(L.A, L.d, b, x, isC)
+            x = half_sweep(L.A, L.d, b, x, isF)
     r = b - L.A @ x
     e = vcycle(H, L.R @ r, lvl + 1)
     x = x + L.P @ e
-    for _ in range(p.n_post):                # going up: F then C
-        x = half_sweep(L.A, L.d, b, x, isF)
-        x = half_sweep(L.A, L.d, b, x, isC)
+    for _ in range(p.n_post):                # going up: F then C (or descending colours)
+        if gs:
+            x = gs_sweep(L.A, L.dg, b, x, L.colour, descending=True)
+        else:
+            x = half_sweep(L.A, L.d, b, x, isF)
+            x = half_sweep(L.A, L.d, b, x, isC)
     return x
 
 

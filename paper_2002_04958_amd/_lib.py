@@ -26,7 +26,8 @@ class amg_params(Structure):
     _fields_ = [("strength_theta", c_double), ("dominance_theta", c_double), ("seed", c_uint64),
                 ("max_levels", c_int32), ("coarse_max", c_int32), ("dense_max", c_int32),
                 ("n_pre", c_int32), ("n_post", c_int32), ("precision", c_int32),
-                ("autotune", c_int32), ("coarsening", c_int32), ("hmis_tile", c_int32)]
+                ("autotune", c_int32), ("coarsening", c_int32), ("hmis_tile", c_int32),
+                ("smoother", c_int32)]
 
 
 class amg_info(Structure):

@@ -20,14 +20,14 @@ using namespace mgd;
 Union<double>* amg_hierarchy::union64() {
   if (!u64) {
     std::vector<const SetupHierarchy*> m{&H};
-    u64 = build_union<double>(ctx, m, prm.n_pre, prm.n_post, prm.autotune);
+    u64 = build_union<double>(ctx, m, prm.n_pre, prm.n_post, prm.autotune, prm.smoother);
   }
   return u64.get();
 }
 Union<float>* amg_hierarchy::union32() {
   if (!u32) {
     std::vector<const SetupHierarchy*> m{&H};
-    u32 = build_union<float>(ctx, m, prm.n_pre, prm.n_post, prm.autotune);
+    u32 = build_union<float>(ctx, m, prm.n_pre, prm.n_post, prm.autotune, prm.smoother);
   }
   return u32.get();
 }
@@ -346,7 +346,8 @@ static void build_exec(block_precond* bp, std::unique_ptr<PcExec<T>>& X) {
   if (bp->prm.batched && uniform && nm > 1) {
     std::vector<const SetupHierarchy*> hs;
     for (int r : roles) hs.push_back(&bp->hier[r]->H);
-    grp.batched = build_union<T>(c, hs, bp->prm.amg.n_pre, bp->prm.amg.n_post, bp->prm.amg.autotune);
+    grp.batched = build_union<T>(c, hs, bp->prm.amg.n_pre, bp->prm.amg.n_post, bp->prm.amg.autotune,
+                                bp->prm.amg.smoother);
   } else {
     for (int r : roles) grp.seq.push_back(union_of<T>(bp->hier[r].get()));
     if (!uniform) {

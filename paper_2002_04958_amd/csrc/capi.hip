@@ -423,6 +423,7 @@ void amg_params_default(amg_params* p) {
   p->autotune = 0;
   p->coarsening = 0;
   p->hmis_tile = 1024;
+  p->smoother = 0;
 }
 
 static void check_amg_params(const amg_params* p) {
@@ -437,6 +438,7 @@ static void check_amg_params(const amg_params* p) {
   MGD_REQUIRE(p->coarsening == 0 || p->coarsening == 1, "coarsening must be 0 (PMIS) or 1 (HMIS)");
   MGD_REQUIRE(p->coarsening == 0 || (p->hmis_tile >= 1 && p->hmis_tile <= 1024),
               "hmis_tile must be in [1, 1024]");
+  MGD_REQUIRE(p->smoother == 0 || p->smoother == 1, "smoother must be 0 (CF-l1-Jacobi) or 1 (MC-GS)");
 }
 
 mgd_status amg_setup(mgd_ctx* ctx, const mgd_csr* A, const amg_params* p, amg_hierarchy** out) {

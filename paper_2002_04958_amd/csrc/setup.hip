@@ -635,6 +635,86 @@ __global__ void k_l1diag(int n, const int* __restrict__ rp, const int* __restric
     if (ci[e] != i) acc = acc + fabs(v[e]);
   d[i] = acc;
 }
+void plain_diagonal(Ctx* c, const Csr<double>& A, double* d) {
+  if (!A.n_rows) return;
+  hipLaunchKernelGGL(k_diag, dim3(cdiv(A.n_rows, 256)), dim3(256), 0, c->stream, A.n_rows,
+                     A.rp.get(), A.ci.get(), A.v.get(), d);
+  MGD_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// Jones-Plassmann colouring (multicolour Gauss-Seidel): every stored
+// off-diagonal entry of A is an edge in both directions; in round c every
+// uncoloured row whose (hash32(seed, level, i), i) beats all uncoloured
+// neighbours gets colour c
+// ---------------------------------------------------------------------------
+__global__ void k_jp_select(int n, int round, uint64_t seed, int level,
+                            const int* __restrict__ rp, const int* __restrict__ ci,
+                            const int* __restrict__ trp, const int* __restrict__ tci,
+                            const int* __restrict__ colour, uint8_t* __restrict__ win) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (colour[i] >= 0) {
+    win[i] = 0;
+    return;
+  }
+  const uint64_t salt = seed ^ ((uint64_t)level << 56);
+  const uint32_t ki = (uint32_t)(splitmix64_first(salt ^ (uint64_t)i) >> 32);
+  bool best = true;
+  for (int e = rp[i]; e < rp[i + 1] && best; ++e) {
+    const int j = ci[e];
+    if (j == i || colour[j] >= 0) continue;
+    const uint32_t kj = (uint32_t)(splitmix64_first(salt ^ (uint64_t)j) >> 32);
+    if (kj > ki || (kj == ki && j > i)) best = false;
+  }
+  for (int e = trp[i]; e < trp[i + 1] && best; ++e) {
+    const int j = tci[e];
+    if (j == i || colour[j] >= 0) continue;
+    const uint32_t kj = (uint32_t)(splitmix64_first(salt ^ (uint64_t)j) >> 32);
+    if (kj > ki || (kj == ki && j > i)) best = false;
+  }
+  win[i] = best ? 1 : 0;
+}
+__global__ void k_jp_assign(int n, int round, const uint8_t* __restrict__ win,
+                            int* __restrict__ colour, int* __restrict__ remaining) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool left = false;
+  if (i < n) {
+    if (win[i]) colour[i] = round;
+    left = colour[i] < 0;
+  }
+  const uint64_t m = __ballot(left);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(remaining, (int)__popcll(m));
+}
+
+int jp_colouring(Ctx* c, const Csr<double>& A, uint64_t seed, int level, DBuf<int>& colour) {
+  const int n = A.n_rows;
+  colour.alloc(c, (size_t)std::max(n, 1));
+  if (n == 0) return 0;
+  fill<int>(c, colour.get(), -1, (size_t)n);
+  Csr<double> T;
+  transpose(c, A, T);
+  DBuf<uint8_t> win(c, (size_t)n);
+  DBuf<int> remaining(c, 1);
+  const int g = cdiv(n, 256);
+  int round = 0;
+  for (;;) {
+    fill<int>(c, remaining.get(), 0, 1);
+    hipLaunchKernelGGL(k_jp_select, dim3(g), dim3(256), 0, c->stream, n, round, seed, level,
+                       A.rp.get(), A.ci.get(), (const int*)T.rp.get(), (const int*)T.ci.get(),
+                       (const int*)colour.get(), win.get());
+    MGD_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_jp_assign, dim3(g), dim3(256), 0, c->stream, n, round,
+                       (const uint8_t*)win.get(), colour.get(), remaining.get());
+    MGD_CHECK_LAUNCH();
+    ++round;
+    if (read1(c, remaining.get()) == 0) break;
+    // every round colours at least the uncoloured row of largest (key, index)
+    if (round > n) fail(MGD_EHIP, "colouring did not terminate");
+  }
+  return round;
+}
+
 void l1_diagonal(Ctx* c, const Csr<double>& A, double* d) {
   if (!A.n_rows) return;
   hipLaunchKernelGGL(k_l1diag, dim3(cdiv(A.n_rows, 256)), dim3(256), 0, c->stream, A.n_rows,
@@ -820,6 +900,13 @@ void amg_build(Ctx* c, Csr<double>&& A0, const amg_params& p, SetupHierarchy& H)
     L.pmis_rounds = rounds;
     H.levels.push_back(std::move(L));
     A = std::move(Ac);
+  }
+  if (p.smoother == 1) {
+    for (size_t l = 0; l < H.levels.size(); ++l) {
+      StepScope st("amg setup: colouring (level " + std::to_string(l) + ")");
+      auto& L = H.levels[l];
+      L.ncolours = jp_colouring(c, L.A, p.seed, (int)l, L.colour);
+    }
   }
   SetupLevel& last = H.levels.back();
   if (last.A.n_rows <= p.dense_max) {

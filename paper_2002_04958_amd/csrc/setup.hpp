@@ -12,6 +12,8 @@ struct SetupLevel {
   Csr<double> P;    // n x nc; empty on the coarsest level
   int nc = 0;
   int pmis_rounds = 0;
+  DBuf<int> colour;  // Jones-Plassmann colours (multicolour Gauss-Seidel only)
+  int ncolours = 0;
 };
 
 struct SetupHierarchy {
@@ -40,6 +42,10 @@ void transpose(Ctx* c, const Csr<double>& A, Csr<double>& T);
 void spgemm(Ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>& C);
 // d_i = a_ii + sum_{j != i} |a_ij| (ascending column order)
 void l1_diagonal(Ctx* c, const Csr<double>& A, double* d);
+// d_i = a_ii
+void plain_diagonal(Ctx* c, const Csr<double>& A, double* d);
+// Jones-Plassmann colouring of the structural graph of A; returns the number of colours
+int jp_colouring(Ctx* c, const Csr<double>& A, uint64_t seed, int level, DBuf<int>& colour);
 // Explicit inverse via LU with partial pivoting; returns false on a zero pivot.
 bool dense_inverse(Ctx* c, const Csr<double>& A, DBuf<double>& inv_colmajor);
 

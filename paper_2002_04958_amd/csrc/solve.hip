@@ -2,6 +2,7 @@
 // half-sweeps, residual, restriction, prolongation, dense coarsest solve,
 // and the V(n_pre, n_post) cycle driver.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -170,6 +171,13 @@ __global__ void k_gather_rows(int n, const int* __restrict__ rp, const int* __re
     ov[p] = v[e];
   }
 }
+// out[idx[i]] = v[i]
+__global__ void k_scatter_int(int n, const int* __restrict__ idx, const int* __restrict__ v,
+                              int* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[idx[i]] = v[i];
+}
+
 // out[i] = a[b[i]] with b[i] in [0, na)
 __global__ void k_compose(int n, const int* __restrict__ a, int na, const int* __restrict__ bidx,
                           int* __restrict__ out, int* __restrict__ err) {
@@ -208,6 +216,8 @@ struct BuildLevel {
   DBuf<int> perm;  // stored -> natural (nS)
   DBuf<int> cnat;  // C-block position -> coarse natural index (nC); empty: identity
   DBuf<T> dinv;    // nS
+  DBuf<T> dgs;     // 1 / a_ii (multicolour Gauss-Seidel)
+  std::vector<std::array<int, 4>> cranges;  // per colour: C-block [lo, hi), F-block [lo, hi)
   long long nnz_C = 0;
   struct Dense {
     int off, n;
@@ -317,10 +327,11 @@ constexpr int kSortWindow = 512;
 
 template <typename T>
 std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHierarchy*>& members,
-                                      int n_pre, int n_post, int autotune) {
+                                      int n_pre, int n_post, int autotune, int smoother) {
   auto U = std::make_unique<Union<T>>();
   U->n_pre = n_pre;
   U->n_post = n_post;
+  U->gs = smoother == 1;
   U->members = (int)members.size();
   std::vector<BuildLevel<T>> built;
   size_t maxL = 0;
@@ -358,6 +369,7 @@ std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHiera
     const int nS = lv.nS, nF = nFtot;
     lv.perm.alloc(c, (size_t)std::max(nS, 1));
     lv.dinv.alloc(c, (size_t)std::max(nS, 1));
+    if (smoother == 1) lv.dgs.alloc(c, (size_t)std::max(nS, 1));
     DBuf<int> alen(c, (size_t)nS + 1), wlen(c, (size_t)nF + 1), hits(c, (size_t)nS + 1);
     fill<int>(c, alen.get(), 0, (size_t)nS + 1);
     fill<int>(c, wlen.get(), 0, (size_t)nF + 1);
@@ -411,12 +423,21 @@ std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHiera
     // by decreasing length (stable) within windows of kSortWindow rows, so that
     // 64-row slices hold rows of similar length while neighbouring rows stay
     // close; the coarse numbering stays member order and is kept in cnat.
-    if (l > 0 && nS > 0) {
+    // With multicolour Gauss-Seidel the blocks are ordered by colour instead, so
+    // each colour is one range of the C-block and one of the F-block.
+    if (nS > 0 && (smoother == 1 || l > 0)) {
       for (size_t q = 0; q < ms.size(); ++q) {
         const auto& m = ms[q];
         if (m.kind == 2) continue;
-        hipLaunchKernelGGL(k_row_len, dim3(cdiv(m.n, 256)), dim3(256), 0, c->stream, m.n,
-                           m.lev->A.rp.get(), (const int*)srows[q].get(), alen.get());
+        if (smoother == 1) {
+          MGD_REQUIRE(m.lev->colour.p, "internal: level without colours");
+          hipLaunchKernelGGL(k_scatter_int, dim3(cdiv(m.n, 256)), dim3(256), 0, c->stream, m.n,
+                             (const int*)srows[q].get(), (const int*)m.lev->colour.get(),
+                             alen.get());
+        } else {
+          hipLaunchKernelGGL(k_row_len, dim3(cdiv(m.n, 256)), dim3(256), 0, c->stream, m.n,
+                             m.lev->A.rp.get(), (const int*)srows[q].get(), alen.get());
+        }
         MGD_CHECK_LAUNCH();
       }
       std::vector<int> len(nS), pm(nS), qpos(nS), cn(std::max(nCtot, 1));
@@ -424,14 +445,36 @@ std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHiera
       copy_d2h(c, pm.data(), lv.perm.get(), (size_t)nS);
       std::vector<int> order(nS);
       for (int k = 0; k < nS; ++k) order[k] = k;
-      // windows of kSortWindow rows keep neighbouring rows close together
-      auto by_len = [&](int a, int b2) { return len[a] > len[b2]; };
-      for (int w0 = 0; w0 < nCtot; w0 += kSortWindow)
-        std::stable_sort(order.begin() + w0, order.begin() + std::min(nCtot, w0 + kSortWindow),
-                         by_len);
-      for (int w0 = nCtot; w0 < nS; w0 += kSortWindow)
-        std::stable_sort(order.begin() + w0, order.begin() + std::min(nS, w0 + kSortWindow),
-                         by_len);
+      if (smoother == 1) {  // ascending colour (len holds colours here)
+        auto by_col = [&](int a, int b2) { return len[a] < len[b2]; };
+        std::stable_sort(order.begin(), order.begin() + nCtot, by_col);
+        std::stable_sort(order.begin() + nCtot, order.end(), by_col);
+        int ncol = 0;
+        for (int k = 0; k < nS; ++k) ncol = std::max(ncol, len[k] + 1);
+        lv.cranges.assign(ncol, {0, 0, 0, 0});
+        for (int cc = 0; cc < ncol; ++cc) lv.cranges[cc] = {nCtot, nCtot, nS, nS};
+        for (int k = nS - 1; k >= 0; --k) {  // first and last position of each colour
+          const int cc = len[order[k]], blk = k < nCtot ? 0 : 2;
+          lv.cranges[cc][blk] = k;
+        }
+        for (int k = 0; k < nS; ++k) {
+          const int cc = len[order[k]], blk = k < nCtot ? 1 : 3;
+          lv.cranges[cc][blk] = k + 1;
+        }
+        for (auto& r : lv.cranges) {  // colours absent from a block: empty range
+          if (r[1] <= r[0]) r[0] = r[1] = 0;
+          if (r[3] <= r[2]) r[2] = r[3] = 0;
+        }
+      } else {
+        // windows of kSortWindow rows keep neighbouring rows close together
+        auto by_len = [&](int a, int b2) { return len[a] > len[b2]; };
+        for (int w0 = 0; w0 < nCtot; w0 += kSortWindow)
+          std::stable_sort(order.begin() + w0, order.begin() + std::min(nCtot, w0 + kSortWindow),
+                           by_len);
+        for (int w0 = nCtot; w0 < nS; w0 += kSortWindow)
+          std::stable_sort(order.begin() + w0, order.begin() + std::min(nS, w0 + kSortWindow),
+                           by_len);
+      }
       std::vector<int> pm2(nS);
       for (int k = 0; k < nS; ++k) {
         qpos[order[k]] = k;  // old position -> new position
@@ -470,6 +513,12 @@ std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHiera
       hipLaunchKernelGGL(k_dinv<T>, dim3(g), dim3(256), 0, c->stream, n, (const double*)d.get(),
                          (const int*)srows[q].get(), lv.dinv.get());
       MGD_CHECK_LAUNCH();
+      if (smoother == 1) {
+        plain_diagonal(c, m.lev->A, d.get());
+        hipLaunchKernelGGL(k_dinv<T>, dim3(g), dim3(256), 0, c->stream, n, (const double*)d.get(),
+                           (const int*)srows[q].get(), lv.dgs.get());
+        MGD_CHECK_LAUNCH();
+      }
       c->sync();
     }
     if (debug_union()) verify_union_level(c, ms, srows, nS, alen.get(), nullptr);
@@ -749,6 +798,23 @@ __global__ void __launch_bounds__(256) k_half_out(int r0, int r1, int nC, int nS
       z[perm[k]] = XD[k];
   }
 }
+// multicolour Gauss-Seidel on the rows of one colour, [r0, r0+n1) u [r2, r2+n2),
+// in place: no two rows of a colour are coupled
+template <typename T, int FMT, int TPR>
+__global__ void __launch_bounds__(256) k_gs(int r0, int n1, int r2, int n2,
+                                            const int* __restrict__ rp,
+                                            const int* __restrict__ ci, const T* __restrict__ v,
+                                            const T* __restrict__ dg, const T* __restrict__ B,
+                                            T* __restrict__ X) {
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const int lane = (int)(t % TPR);
+  const int q = (int)(t / TPR);
+  if (q >= n1 + n2) return;
+  const int k = q < n1 ? r0 + q : r2 + (q - n1);
+  const T s = mrow<FMT, TPR>(rp, ci, v, Gather1<T>{X}, k, lane);
+  if (lane == 0) X[k] = X[k] + (B[k] - s) * dg[k];
+}
+
 // level-0 output without post-smoothing
 template <typename T>
 __global__ void k_out(int nX, GatherCFD<T> X, const int* __restrict__ perm, T* __restrict__ z) {
@@ -926,6 +992,21 @@ struct HalfOutL {
     if (nX <= 0) return;
     hipLaunchKernelGGL((k_half_out<T, FMT, TPR>), rows_grid(nX, TPR), dim3(256), 0, c->stream, 0,
                        nX, nC, nS, A.rp.get(), A.ci.get(), A.v.get(), dinv, B, X, XD, perm, z);
+    MGD_CHECK_LAUNCH();
+  }
+};
+template <typename T>
+struct GsL {
+  Ctx* c;
+  const LMat<T>& A;
+  int r0, n1, r2, n2;
+  const T *dg, *B;
+  T* X;
+  template <int FMT, int TPR>
+  void go() const {
+    if (n1 + n2 <= 0) return;
+    hipLaunchKernelGGL((k_gs<T, FMT, TPR>), rows_grid(n1 + n2, TPR), dim3(256), 0, c->stream, r0,
+                       n1, r2, n2, A.rp.get(), A.ci.get(), A.v.get(), dg, B, X);
     MGD_CHECK_LAUNCH();
   }
 };
@@ -1156,12 +1237,81 @@ void Union<T>::vcycle(Ctx* c, T* z) {
 }
 
 template <typename T>
+void Union<T>::gs_sweep(Ctx* c, int l, bool descending) {
+  ULevel<T>& lv = L[l];
+  const int nc = (int)lv.cranges.size();
+  for (int q = 0; q < nc; ++q) {
+    const auto& r = lv.cranges[descending ? nc - 1 - q : q];
+    const int n1 = r[1] - r[0], n2 = r[3] - r[2];
+    if (n1 + n2 == 0) continue;
+    ProfScope ps(c, cls_of(l, KC_SMOOTH_L0), 0.0, kname(c, "k_gs", lv.A));
+    with_layout(lv.A.fmt, lv.A.tpr,
+                GsL<T>{c, lv.A, r[0], n1, r[2], n2, lv.dgs.get(), B[l].get(), X0[l].get()});
+  }
+}
+
+// V-cycle with multicolour Gauss-Seidel: one iterate buffer per level, updated
+// in place colour by colour (ascending going down, descending going up)
+template <typename T>
+void Union<T>::vcycle_gs(Ctx* c, T* z) {
+  const int nl = (int)L.size();
+  for (int l = 0; l < nl; ++l) {
+    ULevel<T>& lv = L[l];
+    const int nF = lv.nS - lv.nC;
+    if (lv.nS > 0) {
+      if (nF > 0) fill<T>(c, X0[l].get() + lv.nC, (T)0, (size_t)nF);  // C part zeroed with B
+      for (int s = 0; s < n_pre; ++s) gs_sweep(c, l, false);
+      if (lv.nX_next > 0) {
+        {
+          ProfScope ps(c, cls_of(l, KC_RESID_L0), 0.0, kname(c, "k_resid", lv.A));
+          with_layout(lv.A.fmt, lv.A.tpr,
+                      ResidL<T>{c, lv.A, lv.nS, B[l].get(),
+                                gather_cf<T>(X0[l].get(), X0[l].get(), lv.nC), R[l].get()});
+        }
+        const ULevel<T>& nx = L[l + 1];
+        ProfScope ps(c, cls_of(l, KC_TRANSFER_L0), 0.0, kname(c, "k_restrict", lv.Wt, {"false"}));
+        with_layout(lv.Wt.fmt, lv.Wt.tpr,
+                    RestrictL<T>{c, lv.Wt, lv.nX_next, lv.nC, nx.nC, lv.cpos.get(), R[l].get(),
+                                 nx.dinv.get(), B[l + 1].get(), X0[l + 1].get(), false});
+      }
+    }
+    if (!lv.dense.empty()) {
+      ProfScope ps(c, KC_COARSE_SOLVE, 8.0 * lv.dense_entries, ksym(c, "k_dense", {type_name<T>()}));
+      dim3 grid(cdiv(lv.dense_max_n, 64), (unsigned)lv.dense.size());
+      hipLaunchKernelGGL(k_dense<T>, grid, dim3(64), 0, c->stream,
+                         (const DenseDev*)lv.dense_dev.get(), (const T*)B[l].get(), X0[l].get());
+      MGD_CHECK_LAUNCH();
+    }
+  }
+  for (int l = nl - 1; l >= 0; --l) {
+    ULevel<T>& lv = L[l];
+    if (lv.nS > 0 && lv.nX_next > 0) {
+      const ULevel<T>& nx = L[l + 1];
+      ProfScope ps(c, cls_of(l, KC_TRANSFER_L0), 0.0, kname(c, "k_prolong", lv.W));
+      with_layout(lv.W.fmt, lv.W.tpr,
+                  ProlongL<T>{c, lv.W, lv.nS, lv.nC, lv.cmap.get(),
+                              gather_cfd<T>(X0[l + 1].get(), X0[l + 1].get(), X0[l + 1].get(),
+                                            nx.nC, nx.nS),
+                              X0[l].get(), X0[l].get()});
+    }
+    if (lv.nS > 0)
+      for (int s = 0; s < n_post; ++s) gs_sweep(c, l, true);
+  }
+  ULevel<T>& l0 = L[0];
+  hipLaunchKernelGGL(k_out<T>, dim3(cdiv(l0.nX, 256)), dim3(256), 0, c->stream, l0.nX,
+                     gather_cfd<T>(X0[0].get(), X0[0].get(), X0[0].get(), l0.nC, l0.nS),
+                     (const int*)l0.perm.get(), z);
+  MGD_CHECK_LAUNCH();
+}
+
+template <typename T>
 void Union<T>::apply(Ctx* c, const T* bvec, T* z, int cycles) {
   ULevel<T>& l0 = L[0];
+  const bool pre = n_pre > 0 && !gs;  // first-sweep C values (CF-l1-Jacobi only)
   {
     ProfScope ps(c, KC_TRANSFER_L0, (double)l0.nX * (4 + 2.0 * sizeof(T)) + l0.nC * 2.0 * sizeof(T),
-                 ksym(c, "k_entry", {type_name<T>(), n_pre > 0 ? "true" : "false"}));
-    if (n_pre > 0)
+                 ksym(c, "k_entry", {type_name<T>(), pre ? "true" : "false"}));
+    if (pre)
       hipLaunchKernelGGL((k_entry<T, true>), dim3(cdiv(l0.nX, 256)), dim3(256), 0, c->stream,
                          l0.nX, l0.nC, (const int*)l0.perm.get(), (const T*)l0.dinv.get(), bvec,
                          B[0].get(), X0[0].get());
@@ -1171,17 +1321,23 @@ void Union<T>::apply(Ctx* c, const T* bvec, T* z, int cycles) {
                          B[0].get(), X0[0].get());
     MGD_CHECK_LAUNCH();
   }
-  vcycle(c, z);
+  if (gs)
+    vcycle_gs(c, z);
+  else
+    vcycle(c, z);
   for (int k = 1; k < cycles; ++k) {
     {
       ProfScope ps(c, KC_RESID_L0,
                    mat_bytes<T>(l0.A.nnz) + (double)l0.nX * (8 + 3.0 * sizeof(T)),
-                   kname(c, "k_entry_resid", l0.A, {n_pre > 0 ? "true" : "false"}));
+                   kname(c, "k_entry_resid", l0.A, {pre ? "true" : "false"}));
       with_layout(l0.A.fmt, l0.A.tpr,
                   EntryResidL<T>{c, l0.A, l0.nX, l0.nS, l0.nC, l0.perm.get(), l0.dinv.get(), bvec,
-                                 z, B[0].get(), X0[0].get(), n_pre > 0});
+                                 z, B[0].get(), X0[0].get(), pre});
     }
-    vcycle(c, t1.get());
+    if (gs)
+      vcycle_gs(c, t1.get());
+    else
+      vcycle(c, t1.get());
     hipLaunchKernelGGL(k_axpy_t<T>, dim3(cdiv(n0, 256)), dim3(256), 0, c->stream, n0,
                        (const T*)t1.get(), z);
     MGD_CHECK_LAUNCH();
@@ -1391,6 +1547,8 @@ static void finalize_levels(Ctx* c, std::vector<BuildLevel<T>>& bl, Union<T>& U,
     lv.nnz_F = b.A.nnz - b.nnz_C;
     lv.perm = std::move(pext[l]);
     lv.dinv = std::move(b.dinv);
+    lv.dgs = std::move(b.dgs);
+    lv.cranges = std::move(b.cranges);
     // columns of A in stored order (each member's rows only reference its own rows)
     if (b.A.nnz > 0) {
       hipLaunchKernelGGL(k_remap, dim3(cdiv(b.A.nnz, 256)), dim3(256), 0, c->stream,
@@ -1581,11 +1739,9 @@ static void tune_layout(Ctx* c, ULevel<T>& lv, const Csr<double>& A, int autotun
 
 template struct Union<double>;
 template struct Union<float>;
-template std::unique_ptr<Union<double>> build_union<double>(Ctx*,
-                                                            const std::vector<const SetupHierarchy*>&,
-                                                            int, int, int);
-template std::unique_ptr<Union<float>> build_union<float>(Ctx*,
-                                                          const std::vector<const SetupHierarchy*>&,
-                                                          int, int, int);
+template std::unique_ptr<Union<double>> build_union<double>(
+    Ctx*, const std::vector<const SetupHierarchy*>&, int, int, int, int);
+template std::unique_ptr<Union<float>> build_union<float>(
+    Ctx*, const std::vector<const SetupHierarchy*>&, int, int, int, int);
 
 }  // namespace mgd

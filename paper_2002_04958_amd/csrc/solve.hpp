@@ -12,6 +12,7 @@
 // with only W and W^T stored.  Columns stay in natural numbering, so vectors
 // are never permuted.
 #pragma once
+#include <array>
 #include <map>
 #include <memory>
 
@@ -62,6 +63,8 @@ struct ULevel {
   LMat<T> Wt;         // W transposed, rows in level l+1 extended order, columns F index
   DBuf<int> cmap;     // C row I -> its level l+1 extended index (nC)
   DBuf<int> cpos;     // level l+1 extended index k -> C row of this level (nX_next)
+  DBuf<T> dgs;        // 1 / a_ii (multicolour Gauss-Seidel)
+  std::vector<std::array<int, 4>> cranges;  // per colour: C-block [lo, hi), F-block [lo, hi)
   std::vector<DenseDev> dense;
   DBuf<DenseDev> dense_dev;
   int dense_max_n = 0;
@@ -78,6 +81,7 @@ struct Union {
   int n0 = 0;
   int n_pre = 1, n_post = 1;
   int members = 0;
+  bool gs = false;  // multicolour Gauss-Seidel instead of CF-l1-Jacobi
 
   // z = k V-cycles on b (zero initial guess); b, z natural level-0 vectors.
   void apply(Ctx* c, const T* b, T* z, int cycles);
@@ -87,11 +91,13 @@ struct Union {
   // one V-cycle on B[0] (already in stored order, C values of X0[0] set)
   // ending with z (natural) = the result
   void vcycle(Ctx* c, T* z);
+  void vcycle_gs(Ctx* c, T* z);
+  void gs_sweep(Ctx* c, int l, bool descending);
 };
 
 template <typename T>
 std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHierarchy*>& members,
-                                      int n_pre, int n_post, int autotune);
+                                      int n_pre, int n_post, int autotune, int smoother);
 
 // Tuned row-group widths, keyed by (rows, nnz, max row length); persisted to
 // the JSON file named by MGD_AUTOTUNE_CACHE when set.

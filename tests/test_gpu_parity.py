@@ -211,6 +211,45 @@ def test_vcycle_n_pre_n_post(ctx):
         assert rel(to_host(g.apply(to_dev(ctx, b))), oamg.vcycle(H, b)) < 1e-12, (pre, post)
 
 
+@pytest.mark.parametrize("which", ["mono_g2_2d16_nonsym", "block_g0_3d10", "mono_g1_2d64"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_vcycle_multicolour_gauss_seidel(ctx, which, precision):
+    """Multicolour Gauss-Seidel smoothing (Jones-Plassmann colours): V-cycles
+    and 3-cycle applications against the oracle."""
+    api = gpu_modules()
+    if which == "block_g0_3d10":
+        A = oracle_system(si.generate(1, 3, 10, 31)).blocks[0]
+    elif which == "mono_g1_2d64":
+        A = oracle_system(si.generate_workload("g1_2d64")).monolithic()
+    else:
+        A = oracle_system(si.generate(2, 2, 16, 32, nonsym=True)).monolithic()
+    tol = 1e-12 if precision == 0 else 2e-5
+    for pre, post in ((1, 1), (2, 1), (0, 2)):
+        H = oamg.setup(A, oamg.AMGParams(seed=3, smoother="mc_gs", n_pre=pre, n_post=post))
+        g = api.AMG(ctx, A.indptr, A.indices, A.data, seed=3, smoother=1, n_pre=pre, n_post=post,
+                    precision=precision)
+        b = np.random.default_rng(9).uniform(size=A.shape[0])
+        assert rel(to_host(g.apply(to_dev(ctx, b))), oamg.vcycle(H, b)) < tol, (pre, post)
+        assert rel(to_host(g.apply(to_dev(ctx, b), cycles=3)), oamg.apply_cycles(H, b, 3)) < tol
+
+
+@pytest.mark.parametrize("mode", ["seq", "batched_graph"])
+def test_schur2_with_multicolour_gauss_seidel(ctx, mode):
+    api = gpu_modules()
+    inp = si.generate(3, 2, 16, 41)
+    osys = oracle_system(inp)
+    M_o = opc.BlockPreconditioner(osys, opc.BlockParams(
+        kind="schur2", amg=oamg.AMGParams(seed=5, smoother="mc_gs")))
+    co, gsys = gpu_system(ctx, inp)
+    M_g = api.BlockPreconditioner(ctx, gsys, "schur2", amg_seed=5, amg_smoother=1,
+                                  batched=int(mode != "seq"), use_graph=int(mode == "batched_graph"))
+    r = np.random.default_rng(4).standard_normal(osys.n)
+    assert rel(to_host(M_g.apply(to_dev(ctx, r))), M_o(r)) < 1e-10
+    x, res = api.gmres(ctx, gsys, M_g, to_dev(ctx, inp.b), rtol=1e-8)
+    xo, io = okry.gmres(osys.matvec, M_o, inp.b, rtol=1e-8)
+    assert res.converged and abs(res.iters - io.iters) <= 1
+
+
 # ---------------------------------------------------------------------------
 # block preconditioners
 # ---------------------------------------------------------------------------

@@ -399,3 +399,66 @@ def test_hmis_2d_laplacian_one_tile_halves_points():
     off = rows != cols
     assert not np.any(isC[rows[off]] & isC[cols[off]])   # C points independent
     assert abs(int(isC.sum()) - 32) <= 4
+
+
+# --- multicolour Gauss-Seidel -------------------------------------------------
+@pytest.mark.parametrize("seed", range(4))
+def test_jp_colouring_is_proper_and_brute_force(seed):
+    A = _random_mmatrix(60, seed)
+    col = amg.jp_colours(A, seed, 0)
+    rows = amg.csr_rows(A)
+    cols = A.indices.astype(np.int64)
+    off = rows != cols
+    assert np.all(col >= 0)
+    assert not np.any(col[rows[off]] == col[cols[off]])
+    # round rule with Python sets
+    n = A.shape[0]
+    nb = [set() for _ in range(n)]
+    for e in np.nonzero(off)[0]:
+        nb[int(rows[e])].add(int(cols[e]))
+        nb[int(cols[e])].add(int(rows[e]))
+    key = [int(k) for k in amg.hash32(seed, 0, np.arange(n))]
+    ref = [-1] * n
+    c = 0
+    while -1 in ref:
+        new = [i for i in range(n) if ref[i] < 0 and
+               all((key[i], i) > (key[j], j) for j in nb[i] if ref[j] < 0)]
+        for i in new:
+            ref[i] = c
+        c += 1
+    assert np.array_equal(col, np.array(ref))
+
+
+def test_mc_gs_sweep_is_pointwise_gauss_seidel_in_colour_order():
+    """With a proper colouring, one multicolour sweep equals point Gauss-Seidel
+    visiting the rows by (colour, index), written as a plain loop."""
+    A = _random_mmatrix(50, 3)
+    col = amg.jp_colours(A, 7, 0)
+    dg = A.diagonal()
+    b = np.random.default_rng(1).uniform(size=50)
+    x0 = np.random.default_rng(2).uniform(size=50)
+    for desc in (False, True):
+        x = x0.copy()
+        order = sorted(range(50), key=lambda i: (-col[i] if desc else col[i], i))
+        for i in order:
+            s = sum(A.data[e] * x[A.indices[e]] for e in range(A.indptr[i], A.indptr[i + 1]))
+            x[i] = x[i] + (b[i] - s) / dg[i]
+        np.testing.assert_allclose(amg.gs_sweep(A, dg, b, x0, col, descending=desc), x,
+                                   rtol=1e-13, atol=1e-13)
+
+
+def test_mc_gs_vcycle_converges_faster_than_jacobi_on_laplacian():
+    """Gauss-Seidel smoothing gives a smaller V-cycle error reduction than
+    l1-Jacobi on the 2D Laplacian (both below one)."""
+    A = sp.csr_matrix(_laplace2d(24) + sp.eye(576) * 1e-3)
+    rates = {}
+    for sm in ("cf_l1_jacobi", "mc_gs"):
+        H = amg.setup(A, amg.AMGParams(seed=3, smoother=sm))
+        b = np.zeros(576)
+        x = np.random.default_rng(4).uniform(size=576)
+        for _ in range(6):
+            x = x + amg.vcycle(H, b - A @ x)
+        e5 = np.linalg.norm(x)
+        x = x + amg.vcycle(H, b - A @ x)
+        rates[sm] = np.linalg.norm(x) / e5
+    assert rates["mc_gs"] < rates["cf_l1_jacobi"] < 1.0
