@@ -167,7 +167,12 @@ def main():
     solve(M32)
     ctx.set_profiling(False)
     stats = ctx.kernel_stats()
-    syms = ctx.kernel_symbol_stats()
+    tagged = ctx.kernel_symbol_stats()  # "symbol@L<level>/<members>"
+    syms = {}
+    for k, v in tagged.items():
+        agg = syms.setdefault(k.split("@")[0], {"launches": 0, "ms": 0.0, "bytes": 0.0})
+        for f in agg:
+            agg[f] += v[f]
     dom = max(syms, key=lambda k: syms[k]["ms"])
     s = syms[dom]
     achieved = (s["bytes"] / 1e9) / (s["ms"] / 1e3) if s["ms"] > 0 else 0.0
@@ -175,6 +180,9 @@ def main():
         f"{k}={v['ms']:.1f}ms/{v['launches']}" for k, v in stats.items() if v["launches"]))
     log("[bench] kernels: " + ", ".join(
         f"{k}={v['ms']:.1f}ms/{v['launches']}" for k, v in sorted(syms.items(), key=lambda kv: -kv[1]["ms"])))
+    log("[bench] by level: " + ", ".join(
+        f"{k}={v['ms']:.1f}ms/{v['launches']}({(v['bytes'] / 1e9) / (v['ms'] / 1e3) if v['ms'] else 0:.0f}GB/s)"
+        for k, v in sorted(tagged.items(), key=lambda kv: -kv[1]["ms"])[:40]))
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -210,6 +218,9 @@ def main():
         "kernels": {k: {"ms": v["ms"], "launches": v["launches"],
                         "GB/s": (v["bytes"] / 1e9) / (v["ms"] / 1e3) if v["ms"] else 0.0}
                     for k, v in syms.items()},
+        "kernels_by_level": {k: {"ms": v["ms"], "launches": v["launches"],
+                                 "GB/s": (v["bytes"] / 1e9) / (v["ms"] / 1e3) if v["ms"] else 0.0}
+                             for k, v in tagged.items()},
         "kernel_classes": {k: {"ms": v["ms"], "launches": v["launches"],
                                "GB/s": (v["bytes"] / 1e9) / (v["ms"] / 1e3) if v["ms"] else 0.0}
                            for k, v in stats.items() if v["launches"]},

@@ -928,6 +928,13 @@ static void with_layout(int fmt, int tpr, F&& f) {
     default: f.template go<kFmtCSR, 64>(); break;
   }
 }
+// Level and union size of the launches being profiled, appended to the kernel
+// symbol as "@L<level>/<members>" (the symbol itself comes before the '@').
+static thread_local int t_prof_level = -1, t_prof_members = 0;
+static std::string level_tag() {
+  return t_prof_level < 0 ? std::string()
+                          : "@L" + std::to_string(t_prof_level) + "/" + std::to_string(t_prof_members);
+}
 template <typename T>
 static std::string kname(const Ctx* c, const char* base, const LMat<T>& m,
                          std::initializer_list<std::string> extra = {}) {
@@ -942,7 +949,7 @@ static std::string kname(const Ctx* c, const char* base, const LMat<T>& m,
     s += x;
     sep = ", ";
   }
-  return s + ">";
+  return s + ">" + level_tag();
 }
 
 template <typename T>
@@ -1113,7 +1120,9 @@ void Union<T>::vcycle(Ctx* c, T* z) {
   // current buffer (0: X0, 1: X1) of the C and the F region, per level
   std::vector<int> cc(nl, 0), cf(nl, 0);
   auto Xb = [&](int l, int which) -> T* { return which ? X1[l].get() : X0[l].get(); };
+  t_prof_members = members;
   for (int l = 0; l < nl; ++l) {
+    t_prof_level = l;
     ULevel<T>& lv = L[l];
     const int nF = lv.nS - lv.nC;
     // the C values of the first sweep were written with B (entry / restriction)
@@ -1179,6 +1188,7 @@ void Union<T>::vcycle(Ctx* c, T* z) {
     }
   }
   for (int l = nl - 1; l >= 0; --l) {
+    t_prof_level = l;
     ULevel<T>& lv = L[l];
     const int nF = lv.nS - lv.nC;
     if (lv.nS > 0 && lv.nX_next > 0) {
@@ -1342,6 +1352,7 @@ void Union<T>::apply(Ctx* c, const T* bvec, T* z, int cycles) {
                        (const T*)t1.get(), z);
     MGD_CHECK_LAUNCH();
   }
+  t_prof_level = -1;
 }
 
 template <typename T>
@@ -1508,6 +1519,26 @@ static long long sell_stored(Ctx* c, const Csr<double>& M) {
 template <typename T>
 static void tune_layout(Ctx* c, ULevel<T>& lv, const Csr<double>& A, int autotune, bool fp32);
 
+constexpr long long kFillLanes = 1 << 17;  // lanes that keep all compute units busy
+constexpr int kSellMinRows = 1 << 17;
+// lanes per row so that a small matrix still spreads over the device
+static int small_level_tpr(long long rows, double avg) {
+  int t = 1;
+  while (t < 64 && rows * t < kFillLanes && t < avg) t *= 2;
+  return t;
+}
+// interpolation / restriction layout: SELL for large matrices with little
+// padding, otherwise CSR with enough lanes per row
+template <typename T>
+static void layout_transfer(Ctx* c, const Csr<double>& M, LMat<T>& out) {
+  const double avg = M.n_rows ? (double)M.nnz / M.n_rows : 1.0;
+  if (M.nnz > 0 && M.n_rows >= kSellMinRows && sell_stored(c, M) <= (long long)(1.5 * M.nnz))
+    to_layout<T>(c, M, kFmtSELL, 1, false, out);
+  else
+    to_layout<T>(c, M, kFmtCSR, std::max(small_level_tpr(M.n_rows, avg), default_tpr(avg)), false,
+                 out);
+}
+
 template <typename T>
 static void finalize_levels(Ctx* c, std::vector<BuildLevel<T>>& bl, Union<T>& U, int autotune) {
   const int nl = (int)bl.size();
@@ -1634,17 +1665,8 @@ static void finalize_levels(Ctx* c, std::vector<BuildLevel<T>>& bl, Union<T>& U,
                             "stored-order interpolation");
       check_index_structure(c, Wt2.n_rows, b.nS - b.nC, Wt2.nnz, Wt2.rp.get(), Wt2.ci.get(),
                             "stored-order restriction");
-      const double aw = b.W.n_rows ? (double)b.W.nnz / b.W.n_rows : 1.0;
-      const double at = nb.n ? (double)b.Wt.nnz / nb.n : 1.0;
-      const long long sw = sell_stored(c, b.W), st2 = sell_stored(c, Wt2);
-      if (b.W.nnz > 0 && sw <= (long long)(1.5 * b.W.nnz))
-        to_layout<T>(c, b.W, kFmtSELL, 1, false, lv.W);
-      else
-        to_layout<T>(c, b.W, kFmtCSR, default_tpr(aw), false, lv.W);
-      if (Wt2.nnz > 0 && st2 <= (long long)(1.5 * Wt2.nnz))
-        to_layout<T>(c, Wt2, kFmtSELL, 1, false, lv.Wt);
-      else
-        to_layout<T>(c, Wt2, kFmtCSR, default_tpr(at), false, lv.Wt);
+      layout_transfer<T>(c, b.W, lv.W);
+      layout_transfer<T>(c, Wt2, lv.Wt);
     }
     c->check_device_errors("stored-order level");
     tune_layout<T>(c, lv, b.A, autotune, sizeof(T) == 4);
@@ -1695,7 +1717,11 @@ static void tune_layout(Ctx* c, ULevel<T>& lv, const Csr<double>& A, int autotun
     apply(cached);
     return;
   }
-  const int dflt = st <= (long long)(1.3 * A.nnz) ? kTuneSell : default_tpr(avg);
+  // enough lanes to occupy the device on small levels (a lane per row serialises
+  // long rows), SELL when the level is large and its padding small
+  const int dflt = (lv.nS >= kSellMinRows && st <= (long long)(1.3 * A.nnz))
+                       ? kTuneSell
+                       : std::max(small_level_tpr(lv.nS, avg), default_tpr(avg));
   if (!autotune) {
     apply(dflt);
     return;
