@@ -239,10 +239,22 @@ void system_transpose_impl(Ctx* c, const mgd_block_system* A, mgd_block_system* 
   copy_d2d(c, os->d_EI.get(), A->d_IE, (size_t)N);
   copy_d2d(c, os->d_IE.get(), A->d_EI, (size_t)N);
   c->sync();
+  // Blocks that share one pattern keep sharing it: the transposes of equal
+  // patterns are equal (every transposed row is sorted by column), so block
+  // 0's row pointers and column indices serve all blocks.
+  bool shared = true;
+  for (int a = 1; a < G + 2; ++a)
+    shared = shared && A->blocks[a].row_ptr == A->blocks[0].row_ptr &&
+             A->blocks[a].col_idx == A->blocks[0].col_idx && A->blocks[a].nnz == A->blocks[0].nnz;
   os->desc.resize(G + 2);
   for (int a = 0; a < G + 2; ++a) {
     auto& B = os->blocks[a];
-    os->desc[a] = {B.n_rows, B.n_cols, B.nnz, B.rp.get(), B.ci.get(), B.v.get()};
+    if (shared && a > 0) {
+      B.rp.reset();
+      B.ci.reset();
+    }
+    const auto& P = shared ? os->blocks[0] : B;
+    os->desc[a] = {B.n_rows, B.n_cols, B.nnz, P.rp.get(), P.ci.get(), B.v.get()};
   }
   out->G = G;
   out->N = N;

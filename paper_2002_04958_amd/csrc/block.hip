@@ -604,11 +604,19 @@ static void copy_system(block_precond* bp, const mgd_block_system* A) {
   copy_d2d(c, bp->d_EI.get(), tr ? A->d_IE : A->d_EI, (size_t)N);
   copy_d2d(c, bp->d_IE.get(), tr ? A->d_EI : A->d_IE, (size_t)N);
   c->sync();
+  // Blocks given with one shared pattern keep one in the preconditioner's
+  // matvec (copies and sorted transposes of equal patterns are equal).
+  bool shared = true;
+  for (int a = 1; a < G + 2; ++a)
+    shared = shared && A->blocks[a].row_ptr == A->blocks[0].row_ptr &&
+             A->blocks[a].col_idx == A->blocks[0].col_idx && A->blocks[a].nnz == A->blocks[0].nnz;
   mgd_block_system view{};
   std::vector<mgd_csr> bl(G + 2);
-  for (int a = 0; a < G + 2; ++a)
-    bl[a] = {bp->blocks[a].n_rows, bp->blocks[a].n_cols, bp->blocks[a].nnz, bp->blocks[a].rp.get(),
-             bp->blocks[a].ci.get(), bp->blocks[a].v.get()};
+  for (int a = 0; a < G + 2; ++a) {
+    const auto& P = bp->blocks[shared ? 0 : a];
+    bl[a] = {bp->blocks[a].n_rows, bp->blocks[a].n_cols, bp->blocks[a].nnz, P.rp.get(), P.ci.get(),
+             bp->blocks[a].v.get()};
+  }
   view.G = G;
   view.N = N;
   view.blocks = bl.data();

@@ -264,6 +264,11 @@ BlockSysDev make_block_sys_dev(const mgd_block_system* A) {
     nnz += A->blocks[a].nnz;
   }
   S.tpr = default_tpr((double)nnz / ((double)(A->G + 2) * A->N));
+  S.shared = 1;
+  for (int a = 1; a < A->G + 2; ++a)
+    if (A->blocks[a].row_ptr != A->blocks[0].row_ptr ||
+        A->blocks[a].col_idx != A->blocks[0].col_idx || A->blocks[a].nnz != A->blocks[0].nnz)
+      S.shared = 0;
   S.d_gE = A->d_gE;
   S.d_Eg = A->d_Eg;
   S.d_EI = A->d_EI;

@@ -82,14 +82,112 @@ struct BlockMatvecLaunch {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Block matvec of eq. 2.2 when every block has the same sparsity pattern (the
+// assembled stencil, and its transpose).  A workgroup takes R consecutive
+// rows of all G+2 blocks.  It stages the pattern segment of those rows (row
+// pointers and column indices) in LDS once; then, block after block, every
+// thread issues all of its coalesced loads of the block's values for the
+// segment into registers before the barrier, the values go to LDS, and each
+// thread sums its own row over its entries in stored order.  The column
+// indices are read from HBM once per matvec instead of once per block.  A
+// segment longer than the LDS capacity is walked in chunks, re-staging the
+// column indices per chunk.  The E row's coupling sum  sum_g d_Eg[g] o x_g
+// is accumulated while the thread passes block g, where x_g[i] was just
+// gathered.
+// ---------------------------------------------------------------------------
+template <int R, bool RESID>
+__global__ void __launch_bounds__(R) k_block_matvec_shared(BlockSysDev S,
+                                                           const double* __restrict__ x,
+                                                           const double* __restrict__ b,
+                                                           double* __restrict__ y) {
+  constexpr int CAP = 7 * R + 64;        // staged pattern entries per chunk
+  constexpr int PT = (CAP + R - 1) / R;  // staging loads per thread and block
+  __shared__ int s_rp[R + 1];
+  __shared__ int s_ci[CAP];
+  __shared__ double s_v[CAP];
+  const int G = S.G, N = S.N, nb = S.G + 2;
+  const int t = threadIdx.x;
+  const int i0 = blockIdx.x * R;
+  const int nr = min(R, N - i0);
+  const int* __restrict__ rp = S.blk[0].rp;
+  const int* __restrict__ ci = S.blk[0].ci;
+  for (int k = t; k <= nr; k += R) s_rp[k] = rp[i0 + k];
+  __syncthreads();
+  const int beg = s_rp[0], end = s_rp[nr];
+  const bool active = t < nr;
+  const int i = i0 + t;
+  const int rb = active ? s_rp[t] : 0, re = active ? s_rp[t + 1] : 0;
+  const bool one_chunk = end - beg <= CAP;
+  if (one_chunk)
+    for (int k = t; k < end - beg; k += R) s_ci[k] = ci[beg + k];
+  const double xE = active ? x[(size_t)G * N + i] : 0.0;
+  double sE = 0.0;
+  for (int a = 0; a < nb; ++a) {
+    const double* __restrict__ xa = x + (size_t)a * N;
+    double s = 0.0;
+    for (int cb = beg; cb < end; cb += CAP) {
+      const int cl = min(CAP, end - cb);
+      const double* __restrict__ v = S.blk[a].v + cb;
+      double r[PT];
+#pragma unroll
+      for (int j = 0; j < PT; ++j) {
+        const int k = t + j * R;
+        r[j] = k < cl ? v[k] : 0.0;
+      }
+      __syncthreads();  // every thread is done with the previous chunk
+      if (!one_chunk)
+        for (int k = t; k < cl; k += R) s_ci[k] = ci[cb + k];
+#pragma unroll
+      for (int j = 0; j < PT; ++j) {
+        const int k = t + j * R;
+        if (k < cl) s_v[k] = r[j];
+      }
+      __syncthreads();
+      const int kb = max(rb, cb), ke = min(re, cb + cl);
+      for (int k = kb; k < ke; ++k) s += s_v[k - cb] * xa[s_ci[k - cb]];
+    }
+    if (!active) continue;
+    if (a < G) {
+      s += S.d_gE[(size_t)a * N + i] * xE;
+      sE += S.d_Eg[(size_t)a * N + i] * xa[i];
+    } else if (a == G) {
+      s += sE;
+      s += S.d_EI[i] * x[(size_t)(G + 1) * N + i];
+    } else {
+      s += S.d_IE[i] * xE;
+    }
+    const size_t ro = (size_t)a * N + i;
+    y[ro] = RESID ? b[ro] - s : s;
+  }
+}
+
+constexpr int kSharedRows = 512;
+
 double block_matvec_bytes(const BlockSysDev& S, bool resid) {
   const double n = (double)(S.G + 2) * S.N;
   double nnz = 0;
   for (int a = 0; a < S.G + 2; ++a) nnz += S.nnz[a];
-  return 12.0 * nnz + 4.0 * n + 8.0 * (2.0 * S.G + 2.0) * S.N + 8.0 * n * (resid ? 3 : 2);
+  // values, pattern (once when shared), x, couplings, y (and b)
+  const double pattern = S.shared ? 4.0 * S.nnz[0] + 4.0 * (S.N + 1)
+                                  : 4.0 * nnz + 4.0 * n;
+  return 8.0 * nnz + pattern + 8.0 * (2.0 * S.G + 2.0) * S.N + 8.0 * n * (resid ? 3 : 2);
 }
 
 void block_matvec(Ctx* c, const BlockSysDev& S, const double* x, const double* b, double* y) {
+  if (S.shared) {
+    constexpr int R = kSharedRows;
+    ProfScope ps(c, KC_BLOCK_MATVEC, block_matvec_bytes(S, b != nullptr),
+                 ksym(c, "k_block_matvec_shared", {std::to_string(R), b ? "true" : "false"}));
+    const dim3 grid(cdiv(S.N, R));
+    if (b)
+      hipLaunchKernelGGL((k_block_matvec_shared<R, true>), grid, dim3(R), 0, c->stream, S, x, b, y);
+    else
+      hipLaunchKernelGGL((k_block_matvec_shared<R, false>), grid, dim3(R), 0, c->stream, S, x, b,
+                         y);
+    MGD_CHECK_LAUNCH();
+    return;
+  }
   ProfScope ps(c, KC_BLOCK_MATVEC, block_matvec_bytes(S, b != nullptr),
                ksym(c, "k_block_matvec", {std::to_string(tpr_of(S.tpr)), b ? "true" : "false"}));
   dispatch_tpr<BlockMatvecLaunch>(S.tpr, c, S, x, b, y);

@@ -16,6 +16,7 @@ struct BlockCsr {
 struct BlockSysDev {
   int G, N;
   int tpr;
+  int shared;  // 1: every block uses blk[0].rp / blk[0].ci (one pattern)
   BlockCsr blk[kMaxBlocks];
   long long nnz[kMaxBlocks];
   const double* d_gE;

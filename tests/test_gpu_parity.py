@@ -58,6 +58,72 @@ def test_block_matvec(ctx, name, inp):
     assert rel(y, ref) < 1e-14
 
 
+@pytest.mark.parametrize("name,inp", [("g2_2d37", si.generate(2, 2, 37, 31)),
+                                      ("g3_3d11", si.generate(3, 3, 11, 32)),
+                                      ("g2_2d37_nonsym", si.generate(2, 2, 37, 33, nonsym=True))])
+def test_block_matvec_multi_tile(ctx, name, inp):
+    """Assembled systems share one pattern across blocks; 1369 and 1331 rows
+    span several 512-row tiles of the shared-pattern kernel with a ragged
+    last tile.  The transpose keeps one pattern too."""
+    osys = oracle_system(inp)
+    co, gsys = gpu_system(ctx, inp)
+    x = np.random.default_rng(6).standard_normal(osys.n)
+    y = to_host(gsys.matvec(to_dev(ctx, x)))
+    assert rel(y, osys.monolithic() @ x) < 1e-14
+    yt = to_host(gsys.transpose().matvec(to_dev(ctx, x)))
+    assert rel(yt, osys.monolithic().T @ x) < 1e-14
+
+
+def _shared_pattern_system(G, N, seed, max_len):
+    """G+2 blocks on one random pattern (rows of 0..max_len sorted distinct
+    columns, some rows empty), distinct values per block, random couplings."""
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(0, max_len + 1, size=N)
+    lens[rng.choice(N, size=N // 10, replace=False)] = 0
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = np.concatenate([np.sort(rng.choice(N, size=int(l), replace=False)) for l in lens]
+                        + [np.zeros(0, dtype=np.int64)]).astype(np.int32)
+    vals = [rng.standard_normal(int(rp[-1])) for _ in range(G + 2)]
+    cpl = [rng.standard_normal(G * N), rng.standard_normal(G * N), rng.standard_normal(N),
+           rng.standard_normal(N)]
+    return rp, ci, vals, cpl
+
+
+def _monolithic(G, N, rp, ci, vals, cpl):
+    from oracle import assemble as oasm
+    blocks = [sp.csr_matrix((v, ci, rp), shape=(N, N)) for v in vals]
+    return oasm.BlockSystem(G, N, blocks, cpl[0].reshape(G, N), cpl[1].reshape(G, N), cpl[2],
+                            cpl[3]).monolithic()
+
+
+@pytest.mark.parametrize("G,N,max_len", [(3, 1500, 60), (1, 1777, 5), (2, 700, 250)])
+def test_block_matvec_shared_pattern_given(ctx, G, N, max_len):
+    """A caller's system whose blocks point at one row_ptr / col_idx takes
+    the shared-pattern kernel.  Long rows make a tile's pattern segment exceed
+    the kernel's LDS capacity, so it is walked in chunks; empty rows and a
+    ragged last tile are covered.  The same system with a separate pattern
+    copy per block (general kernel) agrees to rounding."""
+    import torch
+    api = gpu_modules()
+    rp, ci, vals, cpl = _shared_pattern_system(G, N, 40 + N, max_len)
+    dev = ctx.device
+    trp = torch.as_tensor(rp).to(dev)
+    tci = torch.as_tensor(ci).to(dev)
+    shared = api.BlockSystem.from_tensors(ctx, G, N, [(trp, tci, torch.as_tensor(v).to(dev))
+                                                      for v in vals], *cpl)
+    separate = api.BlockSystem.from_tensors(ctx, G, N, [(trp.clone(), tci.clone(),
+                                                         torch.as_tensor(v).to(dev))
+                                                        for v in vals], *cpl)
+    M = _monolithic(G, N, rp, ci, vals, cpl)
+    x = np.random.default_rng(9).standard_normal((G + 2) * N)
+    ys = to_host(shared.matvec(to_dev(ctx, x)))
+    yp = to_host(separate.matvec(to_dev(ctx, x)))
+    ref = M @ x
+    assert rel(ys, ref) < 1e-14
+    assert rel(yp, ref) < 1e-14
+    assert rel(ys, yp) < 1e-14
+
+
 def test_csr_spmv_ragged(ctx):
     api = gpu_modules()
     rng = np.random.default_rng(7)
