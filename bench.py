@@ -127,6 +127,9 @@ def main():
     # headline form: FP32 hierarchies, batched V-cycles, graph replay
     M32, setup32 = build(True, True, True)
     log(f"[bench] fp32 batched setup {setup32:.2f}s")
+    for idx, label in ((0, "group 1"), (w.G, "E"), (w.G + 1, "I")):
+        hi = M32.hierarchy(idx).info()
+        log(f"[bench] hierarchy {label}: rows per level {hi['n']}, nnz {hi['nnz']}")
     for _ in range(a.warmup):
         solve(M32)
     torch.cuda.synchronize()

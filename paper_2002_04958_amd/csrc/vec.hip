@@ -264,16 +264,17 @@ __global__ void __launch_bounds__(256) k_mdot(const double* __restrict__ V, size
   double nacc = 0.0;
   for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
     double wi = w[i];
+    // all loads of the basis column first, so they are in flight together
+    double vj[JB];
+#pragma unroll
+    for (int j = 0; j < JB; ++j)
+      if (j < J) vj[j] = V[j * ldv + i];
     if (MODE == 0) {
 #pragma unroll
       for (int j = 0; j < JB; ++j)
-        if (j < J) acc[j] += V[j * ldv + i] * wi;
+        if (j < J) acc[j] += vj[j] * wi;
       nacc += wi * wi;
     } else {
-      double vj[JB];
-#pragma unroll
-      for (int j = 0; j < JB; ++j)
-        if (j < J) vj[j] = V[j * ldv + i];
 #pragma unroll
       for (int j = 0; j < JB; ++j)
         if (j < J) wi -= hv[j] * vj[j];
