@@ -16,6 +16,12 @@ V-cycles (option #2 of Section 3.4) on:
   schur2       A_E, S^_g, S^_I (Section 3.3, three steps; Section 3.4 hats)
   schur2_lower Schur2 steps 1-2 only (the elimination factor of eq. 3.3)
 
+With `adaptive` (PCTL, Schur1, Schur2: the alpha-variants of Section 3.5)
+the preconditioner is formed from the system with its weak couplings
+neglected (Definition 1) and each inverse whose matrix is strongly
+diagonally dominant (Definition 2) is a fixed number of Jacobi iterations;
+see oracle/adaptive.py for the rules and their readings.
+
 Diagonal ("hat") approximations of Section 3.4, each one entry update per
 row, evaluated as t = (d1 * d2) / diag, new = a_ii - t:
   S^_g = A_g - D_gE diag(A_E)^-1 D_Eg       S^_I = A_I - D_IE diag(A_E)^-1 D_EI
@@ -30,6 +36,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
+from . import adaptive as adp
 from . import amg
 from .assemble import BlockSystem
 
@@ -45,6 +52,11 @@ class BlockParams:
     cycles_I: int = 1
     pctl_p_tol: float = 1e-2           # inner tolerance, Section 4
     pctl_p_maxcycles: int = 100
+    adaptive: bool = False             # Section 3.5 strategy + options #1/#2
+    theta_wc: float = 1e-2             # Definition 1
+    sigma_wc: float = 0.5
+    theta_wd: float = 0.9              # Definition 2
+    jacobi_sweeps: int = 2             # option #1
 
 
 class Counters:
@@ -166,16 +178,35 @@ class BlockPreconditioner:
         fac = inverse_factory or self._amg_factory
         self.inv = {}
         self.setup_info = {}
+        self.plan = None
+        self.jacobi_roles = set()
         if self.kind == "amg":
             self.Amono = sys.monolithic()
             self.inv["mono"] = fac(self.Amono, "mono")
             return
+        if params.adaptive:
+            if self.kind not in ("pctl", "schur1", "schur2"):
+                raise ValueError("the adaptive strategy applies to pctl, schur1 and schur2")
+            self.plan = adp.coupling_plan(sys, params.theta_wc, params.sigma_wc)
+            sys = adp.drop_weak(sys, self.plan)
+            self.sys = sys
         mats = hatted(sys, self.kind)
         self.mats = mats
         for key, M in mats.items():
             self.inv[key] = fac(M, key)
         if self.kind == "pctl":
             self._pctl_setup(fac)
+        if params.adaptive:
+            # second level: option #1 where the matrix is strongly diagonally dominant
+            self.setup_info["wd_counts"] = {}
+            for key, M in mats.items():
+                cnt = adp.weak_dominance_count(M, params.theta_wd)
+                self.setup_info["wd_counts"][key] = cnt
+                if cnt == 0:
+                    self.jacobi_roles.add(key)
+                    sweeps = params.jacobi_sweeps
+                    self.inv[key] = Inverse(M, lambda b, M=M, k=sweeps: adp.jacobi(M, b, k),
+                                            self.counters)
 
     # -- scalar inverse construction -----------------------------------------
     def _amg_factory(self, M, key):
@@ -228,6 +259,8 @@ class BlockPreconditioner:
             for g in range(G):
                 W[g] = inv[("g", g)](B[g] - sys.d_gE[g] * W[G])
             W[G + 1] = inv["I"](B[G + 1] - sys.d_IE * W[G])
+            if self.plan is not None and self.plan.all_into_E_rows_weak:
+                return W.reshape(-1)   # no coarse-grid correction needed
             self.counters.matvecs += G + 2
             Rr = (b - sys.matvec(W.reshape(-1))).reshape(G + 2, N)
             rc = Rr[G].copy()
@@ -240,21 +273,49 @@ class BlockPreconditioner:
                 W[g] = W[g] + self.p[g] * wc
             W[G + 1] = W[G + 1] + self.pI * wc
         elif self.kind == "schur1":
+            plan = self.plan
             wI = inv["I"](B[G + 1])
-            wE = inv["E"](B[G] - sys.d_EI * wI)
-            for g in range(G):
-                W[g] = inv[("g", g)](B[g] - sys.d_gE[g] * wE)
-            s = np.zeros(N)
-            for g in range(G):
-                s = s + sys.d_Eg[g] * W[g]
-            W[G] = wE - inv["E"](s)
-            W[G + 1] = wI - inv["I"](sys.d_IE * W[G])
+            if plan is not None and bool(np.all(plan.gE)):
+                # groups independent of E: one C^_E inverse after them
+                for g in range(G):
+                    W[g] = inv[("g", g)](B[g])
+                s = np.zeros(N)
+                for g in range(G):
+                    s = s + sys.d_Eg[g] * W[g]
+                W[G] = inv["E"]((B[G] - sys.d_EI * wI) - s)
+            else:
+                wE = inv["E"](B[G] - sys.d_EI * wI)
+                for g in range(G):
+                    W[g] = inv[("g", g)](B[g] - sys.d_gE[g] * wE)
+                if plan is not None and bool(np.all(plan.Eg)):
+                    W[G] = wE
+                else:
+                    s = np.zeros(N)
+                    for g in range(G):
+                        s = s + sys.d_Eg[g] * W[g]
+                    W[G] = wE - inv["E"](s)
+            if plan is not None and plan.IE:
+                W[G + 1] = wI
+            else:
+                W[G + 1] = wI - inv["I"](sys.d_IE * W[G])
         elif self.kind in ("schur2", "schur2_lower"):
+            plan = self.plan
+            if plan is not None and plan.all_from_E_weak:
+                # every row block independent of E: block lower triangular
+                for g in range(G):
+                    W[g] = inv[("g", g)](B[g])
+                W[G + 1] = inv["I"](B[G + 1])
+                s = np.zeros(N)
+                for g in range(G):
+                    s = s + sys.d_Eg[g] * W[g]
+                s = s + sys.d_EI * W[G + 1]
+                W[G] = inv["E"](B[G] - s)
+                return W.reshape(-1)
             wE = inv["E"](B[G])
             for g in range(G):
                 W[g] = inv[("g", g)](B[g] - sys.d_gE[g] * wE)
             W[G + 1] = inv["I"](B[G + 1] - sys.d_IE * wE)
-            if self.kind == "schur2":
+            if self.kind == "schur2" and not (plan is not None and plan.all_into_E_rows_weak):
                 s = np.zeros(N)
                 for g in range(G):
                     s = s + sys.d_Eg[g] * W[g]

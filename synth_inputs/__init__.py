@@ -99,11 +99,18 @@ def _patch_index(n: int, dim: int) -> np.ndarray:
 
 
 def generate(G: int, dim: int, n: int, seed: int, *, nonsym: bool = False,
-             zero_row_sum: bool = False) -> Inputs:
+             zero_row_sum: bool = False, c_scale=(1.0, 1.0, 1.0),
+             log_kappa_shift=(0.0, 0.0, 0.0)) -> Inputs:
     """Draw one synthetic instance.
 
     ``zero_row_sum`` keeps the draws but sets the mass term and all couplings
     to zero (the zero-flux Laplacian test variant).
+
+    ``c_scale`` = (s_gE, s_Eg, s_EI) multiplies the drawn coupling magnitudes
+    after all draws (s_gE and s_Eg may be per-group arrays of length G), and
+    ``log_kappa_shift`` = (radiation, E, I) is added to the drawn log10 kappa
+    exponents: the weakly coupled and strongly diagonally dominant test
+    variants.  The draws themselves are unchanged.
     """
     if dim not in (2, 3):
         raise ValueError("dim must be 2 or 3")
@@ -123,12 +130,17 @@ def generate(G: int, dim: int, n: int, seed: int, *, nonsym: bool = False,
     x_target = rng.uniform(0.0, 1.0, size=(G + 2) * N)
     xi = rng.uniform(0.0, 1.0, size=(G + 2, N, 2 * dim)) if nonsym else None
 
+    sgE, sEg, sEI = c_scale
+    c_gE = c_gE * np.reshape(np.asarray(sgE, dtype=np.float64), (-1, 1))
+    c_Eg = c_Eg * np.reshape(np.asarray(sEg, dtype=np.float64), (-1, 1))
+    c_EI = c_EI * float(sEI)
+    kR, kE, kI = log_kappa_shift
     patch = _patch_index(n, dim)
     kappa = np.empty((G + 2, N))
     for g in range(G):
-        kappa[g] = 10.0 ** (u_R[patch] + u_s[g])
-    kappa[G] = 10.0 ** u_E[patch]
-    kappa[G + 1] = 10.0 ** u_I[patch]
+        kappa[g] = 10.0 ** (u_R[patch] + u_s[g] + kR)
+    kappa[G] = 10.0 ** (u_E[patch] + kE)
+    kappa[G + 1] = 10.0 ** (u_I[patch] + kI)
     mass = 1.0
     if zero_row_sum:
         c_gE[:] = 0.0
