@@ -69,6 +69,7 @@ def main():
     ap.add_argument("--workload", default="g20_3d64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--counters-run", action="store_true",
                     help="short run for hardware-counter passes: a streaming calibration "
                          "kernel (torch mul reading 1 GiB and writing 1 GiB, its input pushed "
@@ -95,12 +96,12 @@ def main():
     b = torch.as_tensor(inp.b, device=ctx.device)
     bnorm = float(torch.linalg.vector_norm(b))
 
-    def build(batched, fp32, graph):
+    def build(batched, fp32, graph, adaptive=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         M = api.BlockPreconditioner(ctx, sysg, "schur2", amg_seed=w.seed,
                                     amg_precision=1 if fp32 else 0, batched=int(batched),
-                                    use_graph=int(graph))
+                                    use_graph=int(graph), adaptive=int(adaptive))
         torch.cuda.synchronize()
         return M, time.perf_counter() - t0
 
@@ -146,6 +147,35 @@ def main():
     ms_step = e0.elapsed_time(e1) / a.steps
     relres = float(torch.linalg.vector_norm(b - sysg.matvec(x))) / bnorm
     log(f"[bench] fp32 batched: {ms_step:.1f} ms/solve, iters {iters}, relres {relres:.2e}")
+
+    # the adaptive variant of the same preconditioner (alpha-Schur2, Section 3.5)
+    alpha = None
+    if not a.no_adaptive:
+        Ma, setup_a = build(True, True, True, adaptive=True)
+        ia = Ma.info()
+        solve(Ma)
+        torch.cuda.synchronize()
+        ea0, ea1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ea0.record()
+        iters_a = []
+        for _ in range(a.steps):
+            xa, ra = solve(Ma)
+            iters_a.append(ra.iters)
+        ea1.record()
+        torch.cuda.synchronize()
+        ms_a = ea0.elapsed_time(ea1) / a.steps
+        relres_a = float(torch.linalg.vector_norm(b - sysg.matvec(xa))) / bnorm
+        weak = ia["weak"]
+        alpha = {"s": ms_a / 1e3, "iters": iters_a, "relres": relres_a, "setup_s": setup_a,
+                 "neglected": {"gE": [g for g, v in enumerate(weak["gE"]) if v],
+                               "Eg": [g for g, v in enumerate(weak["Eg"]) if v],
+                               "EI": weak["EI"], "IE": weak["IE"]},
+                 "jacobi_roles": [r for r, v in enumerate(ia["jacobi"]) if v],
+                 "inverses_per_apply": ia["inverses_per_apply"]}
+        log(f"[bench] alpha-schur2 fp32 batched: {ms_a:.1f} ms/solve, iters {iters_a}, "
+            f"relres {relres_a:.2e}, neglected {alpha['neglected']}, "
+            f"jacobi roles {alpha['jacobi_roles']}")
+        del Ma, xa
 
     # plain FP64 form: sequential launches, no graph
     plain = None
@@ -213,6 +243,7 @@ def main():
         "setup_s": setup32,
         "plain_fp64": plain,
         "speedup_vs_plain_fp64": (plain["s"] / (ms_step / 1e3)) if plain else None,
+        "alpha_schur2_fp32": alpha,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "launches": s["launches"],

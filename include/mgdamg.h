@@ -224,6 +224,19 @@ mgd_status mgd_block_system_free(mgd_ctx* ctx, mgd_block_system* s);
  * step (the group blocks, plus I where the step has it) as one set of
  * launches over all hierarchies; use_graph = 1 replays the whole apply from
  * a captured HIP graph.  transpose = 1 builds the preconditioner on A^T.
+ *
+ * adaptive = 1 (PCTL, SCHUR1, SCHUR2: the alpha-variants of Section 3.5)
+ * forms the preconditioner from the system with its weak couplings
+ * neglected: a coupling block D_ab is weak when more than sigma_wc N of its
+ * rows have -d_kk <= theta_wc a_kk, a_kk the diagonal of the row block A_a
+ * (Definition 1).  A row block whose coupling to E is neglected is solved
+ * independently of E; when every row block's coupling to E is neglected the
+ * two E inverses of Schur1/Schur2 become one after the independent solves,
+ * and when every coupling in E's row is neglected the E correction step (and
+ * PCTL's coarse-grid correction) is skipped.  Each scalar inverse whose
+ * matrix has no row with sum_j a_kj < theta_wd a_kk (Definition 2) uses
+ * jacobi_sweeps Jacobi iterations from zero (option #1 of Section 3.4)
+ * instead of V-cycles; PCTL's interpolation weights keep option #3.
  * ------------------------------------------------------------------------- */
 enum {
   MGD_PC_AMG_MONO = 0,
@@ -244,6 +257,11 @@ typedef struct block_params {
   int32_t batched;                        /* 0 sequential launches, 1 batched */
   int32_t use_graph;                      /* 0 / 1 */
   int32_t transpose;                      /* 0 / 1 */
+  int32_t adaptive;                       /* 0 / 1 (PCTL, SCHUR1, SCHUR2) */
+  double theta_wc;                        /* 1e-2, Definition 1 */
+  double sigma_wc;                        /* 0.5 */
+  double theta_wd;                        /* 0.9, Definition 2 */
+  int32_t jacobi_sweeps;                  /* 2, option #1 */
 } block_params;
 void block_params_default(block_params* p);
 
@@ -260,6 +278,14 @@ typedef struct block_precond_info {
   int32_t matvecs_per_apply;    /* block SpMVs per apply (PCTL step 2) */
   int32_t pctl_p_cycles[66];    /* V-cycles used for p_1..p_G, p_I */
   double setup_ms;
+  /* adaptive = 1 only (zero otherwise): Definition 1 counts and the
+   * neglected couplings, Definition 2 counts per inverse role (g < G, G: E,
+   * G+1: I; -1 where not evaluated) and the roles that use Jacobi */
+  int32_t wc_count_gE[64], wc_count_Eg[64], wc_count_EI, wc_count_IE;
+  uint8_t weak_gE[64], weak_Eg[64];
+  int32_t weak_EI, weak_IE;
+  int32_t wd_count[66];
+  uint8_t jacobi[66];
 } block_precond_info;
 mgd_status block_precond_get_info(const block_precond* M, block_precond_info* out);
 /* Hierarchy of one scalar inverse: index g < G for group g, G for the E

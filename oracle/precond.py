@@ -164,6 +164,19 @@ def pctl_coarse(sys: BlockSystem, p: np.ndarray, pI: np.ndarray) -> sp.csr_matri
     return Ac
 
 
+def adaptive_decisions(sys: BlockSystem, kind: str, params: "BlockParams"):
+    """Both levels of the adaptive strategy without building any inverse:
+    the Definition 1 plan, the modified system, the matrices of the kind's
+    inverses on it, and their Definition 2 counts (option #1 where zero)."""
+    if kind not in ("pctl", "schur1", "schur2"):
+        raise ValueError("the adaptive strategy applies to pctl, schur1 and schur2")
+    plan = adp.coupling_plan(sys, params.theta_wc, params.sigma_wc)
+    At = adp.drop_weak(sys, plan)
+    mats = hatted(At, kind)
+    wd = {key: adp.weak_dominance_count(M, params.theta_wd) for key, M in mats.items()}
+    return plan, At, mats, wd
+
+
 class BlockPreconditioner:
     """M^{-1} for one of KINDS built on a BlockSystem."""
 
@@ -184,13 +197,12 @@ class BlockPreconditioner:
             self.Amono = sys.monolithic()
             self.inv["mono"] = fac(self.Amono, "mono")
             return
+        wd = None
         if params.adaptive:
-            if self.kind not in ("pctl", "schur1", "schur2"):
-                raise ValueError("the adaptive strategy applies to pctl, schur1 and schur2")
-            self.plan = adp.coupling_plan(sys, params.theta_wc, params.sigma_wc)
-            sys = adp.drop_weak(sys, self.plan)
+            self.plan, sys, mats, wd = adaptive_decisions(sys, self.kind, params)
             self.sys = sys
-        mats = hatted(sys, self.kind)
+        else:
+            mats = hatted(sys, self.kind)
         self.mats = mats
         for key, M in mats.items():
             self.inv[key] = fac(M, key)
@@ -198,11 +210,9 @@ class BlockPreconditioner:
             self._pctl_setup(fac)
         if params.adaptive:
             # second level: option #1 where the matrix is strongly diagonally dominant
-            self.setup_info["wd_counts"] = {}
+            self.setup_info["wd_counts"] = wd
             for key, M in mats.items():
-                cnt = adp.weak_dominance_count(M, params.theta_wd)
-                self.setup_info["wd_counts"][key] = cnt
-                if cnt == 0:
+                if wd[key] == 0:
                     self.jacobi_roles.add(key)
                     sweeps = params.jacobi_sweeps
                     self.inv[key] = Inverse(M, lambda b, M=M, k=sweeps: adp.jacobi(M, b, k),

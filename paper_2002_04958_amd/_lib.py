@@ -4,7 +4,7 @@ from __future__ import annotations
 import ctypes
 import os
 from ctypes import (POINTER, Structure, c_char_p, c_double, c_int, c_int8, c_int32, c_int64,
-                    c_uint64, c_void_p, CFUNCTYPE)
+                    c_uint8, c_uint64, c_void_p, CFUNCTYPE)
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmgdamg.so")
 
@@ -52,13 +52,17 @@ class block_params(Structure):
     _fields_ = [("kind", c_int32), ("amg", amg_params), ("cycles_rad", c_int32),
                 ("cycles_E", c_int32), ("cycles_I", c_int32), ("pctl_p_tol", c_double),
                 ("pctl_p_maxcycles", c_int32), ("batched", c_int32), ("use_graph", c_int32),
-                ("transpose", c_int32)]
+                ("transpose", c_int32), ("adaptive", c_int32), ("theta_wc", c_double),
+                ("sigma_wc", c_double), ("theta_wd", c_double), ("jacobi_sweeps", c_int32)]
 
 
 class block_precond_info(Structure):
     _fields_ = [("kind", c_int32), ("n_hierarchies", c_int32), ("inverses_per_apply", c_int32),
                 ("matvecs_per_apply", c_int32), ("pctl_p_cycles", c_int32 * 66),
-                ("setup_ms", c_double)]
+                ("setup_ms", c_double), ("wc_count_gE", c_int32 * 64),
+                ("wc_count_Eg", c_int32 * 64), ("wc_count_EI", c_int32), ("wc_count_IE", c_int32),
+                ("weak_gE", c_uint8 * 64), ("weak_Eg", c_uint8 * 64), ("weak_EI", c_int32),
+                ("weak_IE", c_int32), ("wd_count", c_int32 * 66), ("jacobi", c_uint8 * 66)]
 
 
 class gmres_params(Structure):

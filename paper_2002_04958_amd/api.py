@@ -365,10 +365,20 @@ class BlockPreconditioner:
     def info(self) -> dict:
         i = L.block_precond_info()
         L.check(self.ctx.lib.block_precond_get_info(self.h, byref(i)))
+        G = self.G
         return {"kind": i.kind, "n_hierarchies": i.n_hierarchies,
                 "inverses_per_apply": i.inverses_per_apply,
                 "matvecs_per_apply": i.matvecs_per_apply,
-                "pctl_p_cycles": list(i.pctl_p_cycles[:self.G + 1]), "setup_ms": i.setup_ms}
+                "pctl_p_cycles": list(i.pctl_p_cycles[:G + 1]), "setup_ms": i.setup_ms,
+                # adaptive strategy: Definition 1 counts and neglected couplings,
+                # Definition 2 counts per inverse role and the Jacobi roles
+                "wc_counts": {"gE": list(i.wc_count_gE[:G]), "Eg": list(i.wc_count_Eg[:G]),
+                              "EI": i.wc_count_EI, "IE": i.wc_count_IE},
+                "weak": {"gE": [bool(v) for v in i.weak_gE[:G]],
+                         "Eg": [bool(v) for v in i.weak_Eg[:G]],
+                         "EI": bool(i.weak_EI), "IE": bool(i.weak_IE)},
+                "wd_count": list(i.wd_count[:G + 2]),
+                "jacobi": [bool(v) for v in i.jacobi[:G + 2]]}
 
     def hierarchy(self, index: int) -> AMG:
         h = c_void_p()

@@ -108,6 +108,60 @@ __global__ void k_sub_out(int N, const T* __restrict__ p, const T* __restrict__ 
   z[i] = q ? (double)p[i] - (double)q[i] : (double)p[i];
 }
 
+// E input after independent solves: out = (T)((r - coef o w) - s)  (coef may be null)
+template <typename T>
+__global__ void k_lower_E_in(int N, const double* __restrict__ r, const double* __restrict__ coef,
+                             const T* __restrict__ w, const T* __restrict__ s, T* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double v = r[i];
+  if (coef) v = v - coef[i] * (double)w[i];
+  v = v - (double)s[i];
+  out[i] = (T)v;
+}
+// One Jacobi iteration (option #1 of Section 3.4) for member blockIdx.y:
+// x_out = x_in + (b - A x_in) / d, and x_out = b / d for the first from zero.
+template <typename T, bool FIRST>
+__global__ void k_jacobi(int N, const JacMember* __restrict__ tab, const T* __restrict__ b,
+                         const T* __restrict__ xin, T* __restrict__ xout) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const JacMember J = tab[blockIdx.y];
+  const size_t off = (size_t)blockIdx.y * N;
+  double r = (double)b[off + i];
+  if (FIRST) {
+    xout[off + i] = (T)(r / J.d[i]);
+    return;
+  }
+  const T* __restrict__ x = xin + off;
+  for (int e = J.rp[i]; e < J.rp[i + 1]; ++e) r = r - J.v[e] * (double)x[J.ci[e]];
+  xout[off + i] = (T)((double)x[i] + r / J.d[i]);
+}
+// Definition 1 count: rows with -d_k <= theta a_k
+__global__ void k_weak_count(int n, const double* __restrict__ d, const double* __restrict__ a,
+                             double theta, int* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool hit = i < n && -d[i] <= theta * a[i];
+  const unsigned long long m = __ballot(hit);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(cnt, (int)__popcll(m));
+}
+// Definition 2 count: rows with sum_j a_kj < theta a_kk, the sum taken left
+// to right in stored (ascending column) order
+__global__ void k_wd_count(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const double* __restrict__ v, double theta, int* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool hit = false;
+  if (i < n) {
+    double s = 0.0, dg = 0.0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+      s = s + v[e];
+      if (ci[e] == i) dg = v[e];
+    }
+    hit = s < theta * dg;
+  }
+  const unsigned long long m = __ballot(hit);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(cnt, (int)__popcll(m));
+}
 // PCTL restriction of the block residual: rc = r_E + sum_g p_g o r_g + p_I o r_I
 template <typename T>
 __global__ void k_pctl_restrict(int G, int N, const double* __restrict__ p,
@@ -199,14 +253,46 @@ __global__ void k_neg(int n, const double* __restrict__ a, double* __restrict__ 
 }
 
 template <typename T>
-void Group<T>::run(Ctx* c, int N) {
-  (void)N;
-  if (batched) {
-    batched->apply(c, in.get(), out.get(), cycles);
-  } else {
-    for (size_t m = 0; m < seq.size(); ++m)
-      seq[m]->apply(c, in.get() + m * (size_t)N, out.get() + m * (size_t)N, cycles);
+void jacobi_run(Ctx* c, int N, const JacMember* tab, int nm, int sweeps, double nnz, const T* b,
+                T* x, T* tmp) {
+  if (nm <= 0 || N <= 0) return;
+  const dim3 grid(cdiv(N, 256), nm);
+  // first sweep: b, d, x; later ones: the matrix, the row pointers, b, d, x in and out
+  const double first = (double)nm * N * (2.0 * sizeof(T) + 8.0);
+  const double later = 12.0 * nnz + (double)nm * N * (4.0 + 3.0 * sizeof(T) + 8.0);
+  ProfScope ps(c, KC_SMOOTH_L0, first + (sweeps - 1) * later, ksym(c, "k_jacobi", {type_name<T>()}));
+  // sweep s writes x when (sweeps - s) is even, so the last one lands in x
+  const T* src = nullptr;
+  for (int s = 1; s <= sweeps; ++s) {
+    T* dst = ((sweeps - s) % 2 == 0) ? x : tmp;
+    if (s == 1)
+      hipLaunchKernelGGL((k_jacobi<T, true>), grid, dim3(256), 0, c->stream, N, tab, b,
+                         (const T*)nullptr, dst);
+    else
+      hipLaunchKernelGGL((k_jacobi<T, false>), grid, dim3(256), 0, c->stream, N, tab, b, src, dst);
+    MGD_CHECK_LAUNCH();
+    src = dst;
   }
+}
+template void jacobi_run<double>(Ctx*, int, const JacMember*, int, int, double, const double*,
+                                 double*, double*);
+template void jacobi_run<float>(Ctx*, int, const JacMember*, int, int, double, const float*, float*,
+                                float*);
+
+template <typename T>
+void Group<T>::run(Ctx* c, int N) {
+  if (n_amg > 0) {
+    if (batched) {
+      batched->apply(c, in.get(), out.get(), cycles);
+    } else {
+      for (size_t m = 0; m < seq.size(); ++m)
+        seq[m]->apply(c, in.get() + m * (size_t)N, out.get() + m * (size_t)N, cycles);
+    }
+  }
+  const int nj = (int)roles.size() - n_amg;
+  if (nj > 0)
+    jacobi_run<T>(c, N, jac_tab.get(), nj, jac_sweeps, jac_nnz, in.get() + (size_t)n_amg * N,
+                  out.get() + (size_t)n_amg * N, jac_tmp.get());
 }
 template struct Group<double>;
 template struct Group<float>;
@@ -293,7 +379,18 @@ static void build_exec(block_precond* bp, std::unique_ptr<PcExec<T>>& X) {
   if (kind == MGD_PC_SCHUR2 || kind == MGD_PC_SCHUR2_LOWER) singles = {G};
   if (kind == MGD_PC_PCTL) singles = {G, G + 2};
   if (kind == MGD_PC_SCHUR1) singles = {G, G + 1};
-  for (int r : singles) union_of<T>(bp->hier[r].get());
+  X->jac_one.resize(G + 3);
+  for (int r : singles) {
+    if (bp->jacobi[r]) {
+      const Csr<double>& A = bp->hier[r]->H.levels[0].A;
+      JacMember jm{A.rp.get(), A.ci.get(), A.v.get(), bp->jac_diag[r].get()};
+      X->jac_one[r].alloc(c, 1);
+      copy_h2d(c, X->jac_one[r].get(), &jm, 1);
+      if (X->jac_tmp1.n < (size_t)N) X->jac_tmp1.alloc(c, (size_t)std::max(N, 1));
+    } else {
+      union_of<T>(bp->hier[r].get());
+    }
+  }
   const size_t n1 = (size_t)std::max(N, 1);
   X->a_out.alloc(c, (kind == MGD_PC_AMG_MONO) ? (size_t)(G + 2) * N : n1);
   X->a_in.alloc(c, (kind == MGD_PC_AMG_MONO) ? (size_t)(G + 2) * N : n1);
@@ -308,6 +405,12 @@ static void build_exec(block_precond* bp, std::unique_ptr<PcExec<T>>& X) {
   std::vector<int> roles;
   const double* dgE = bp->d_gE.get();
   const double* dEg = bp->d_Eg.get();
+  // a neglected coupling (adaptive strategy) contributes no term at all
+  const bool adp = bp->prm.adaptive != 0;
+  auto gE = [&](int g) { return (adp && bp->weak_gE[g]) ? nullptr : dgE + (size_t)g * N; };
+  auto Eg = [&](int g) { return (adp && bp->weak_Eg[g]) ? nullptr : dEg + (size_t)g * N; };
+  const double* IE = (adp && bp->weak_IE) ? nullptr : bp->d_IE.get();
+  const double* EI = (adp && bp->weak_EI) ? nullptr : bp->d_EI.get();
   if (kind == MGD_PC_BLOCK_DIAG) {
     for (int a = 0; a < G + 2; ++a) {
       roles.push_back(a);
@@ -317,25 +420,46 @@ static void build_exec(block_precond* bp, std::unique_ptr<PcExec<T>>& X) {
   } else if (kind == MGD_PC_SCHUR1) {
     for (int g = 0; g < G; ++g) {
       roles.push_back(g);
-      tin.push_back({g, dgE + (size_t)g * N});
-      tout.push_back({g, dEg + (size_t)g * N});
+      tin.push_back({g, gE(g)});
+      tout.push_back({g, Eg(g)});
     }
   } else {  // SCHUR2, SCHUR2_LOWER, PCTL: groups and I after E
     const bool sum = kind == MGD_PC_SCHUR2;
     for (int g = 0; g < G; ++g) {
       roles.push_back(g);
-      tin.push_back({g, dgE + (size_t)g * N});
-      tout.push_back({g, sum ? dEg + (size_t)g * N : nullptr});
+      tin.push_back({g, gE(g)});
+      tout.push_back({g, sum ? Eg(g) : nullptr});
     }
     roles.push_back(G + 1);
-    tin.push_back({G + 1, bp->d_IE.get()});
-    tout.push_back({G + 1, sum ? bp->d_EI.get() : nullptr});
+    tin.push_back({G + 1, IE});
+    tout.push_back({G + 1, sum ? EI : nullptr});
+  }
+  // V-cycle members first, Jacobi members (option #1) after them
+  {
+    std::vector<size_t> order(roles.size());
+    for (size_t m = 0; m < order.size(); ++m) order[m] = m;
+    std::stable_partition(order.begin(), order.end(),
+                          [&](size_t m) { return !bp->jacobi[roles[m]]; });
+    std::vector<int> r2;
+    std::vector<SegIn> i2;
+    std::vector<SegOut> o2;
+    for (size_t m : order) {
+      r2.push_back(roles[m]);
+      i2.push_back(tin[m]);
+      o2.push_back(tout[m]);
+    }
+    roles.swap(r2);
+    tin.swap(i2);
+    tout.swap(o2);
   }
   Group<T>& grp = X->grp;
   grp.roles = roles;
-  grp.cycles = bp->cycles[roles[0]];
+  int n_amg = 0;
+  for (int r : roles) n_amg += bp->jacobi[r] ? 0 : 1;
+  grp.n_amg = n_amg;
+  grp.cycles = n_amg > 0 ? bp->cycles[roles[0]] : 1;
   bool uniform = true;
-  for (int r : roles) uniform = uniform && bp->cycles[r] == grp.cycles;
+  for (int m = 0; m < n_amg; ++m) uniform = uniform && bp->cycles[roles[m]] == grp.cycles;
   const size_t nm = roles.size();
   grp.in.alloc(c, nm * N);
   grp.out.alloc(c, nm * N);
@@ -343,17 +467,30 @@ static void build_exec(block_precond* bp, std::unique_ptr<PcExec<T>>& X) {
   grp.out_tab.alloc(c, nm);
   copy_h2d(c, grp.in_tab.get(), tin.data(), nm);
   copy_h2d(c, grp.out_tab.get(), tout.data(), nm);
-  if (bp->prm.batched && uniform && nm > 1) {
+  if (bp->prm.batched && uniform && n_amg > 1) {
     std::vector<const SetupHierarchy*> hs;
-    for (int r : roles) hs.push_back(&bp->hier[r]->H);
+    for (int m = 0; m < n_amg; ++m) hs.push_back(&bp->hier[roles[m]]->H);
     grp.batched = build_union<T>(c, hs, bp->prm.amg.n_pre, bp->prm.amg.n_post, bp->prm.amg.autotune,
                                 bp->prm.amg.smoother);
   } else {
-    for (int r : roles) grp.seq.push_back(union_of<T>(bp->hier[r].get()));
+    for (int m = 0; m < n_amg; ++m) grp.seq.push_back(union_of<T>(bp->hier[roles[m]].get()));
     if (!uniform) {
       // members with different cycle counts run one by one with their own count
       grp.cycles = -1;
     }
+  }
+  const int nj = (int)nm - n_amg;
+  if (nj > 0) {
+    std::vector<JacMember> jt;
+    for (size_t m = n_amg; m < nm; ++m) {
+      const Csr<double>& A = bp->hier[roles[m]]->H.levels[0].A;
+      jt.push_back({A.rp.get(), A.ci.get(), A.v.get(), bp->jac_diag[roles[m]].get()});
+      grp.jac_nnz += (double)A.nnz;
+    }
+    grp.jac_tab.alloc(c, (size_t)nj);
+    copy_h2d(c, grp.jac_tab.get(), jt.data(), (size_t)nj);
+    grp.jac_sweeps = bp->prm.jacobi_sweeps;
+    grp.jac_tmp.alloc(c, (size_t)nj * N);
   }
 }
 
@@ -381,6 +518,11 @@ static void run_group(block_precond* bp, Group<T>& grp) {
   for (size_t m = 0; m < grp.seq.size(); ++m)
     grp.seq[m]->apply(c, grp.in.get() + m * (size_t)N, grp.out.get() + m * (size_t)N,
                       bp->cycles[grp.roles[m]]);
+  const int nj = (int)grp.roles.size() - grp.n_amg;
+  if (nj > 0)
+    jacobi_run<T>(c, N, grp.jac_tab.get(), nj, grp.jac_sweeps, grp.jac_nnz,
+                  grp.in.get() + (size_t)grp.n_amg * N, grp.out.get() + (size_t)grp.n_amg * N,
+                  grp.jac_tmp.get());
 }
 
 template <typename T>
@@ -391,6 +533,15 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
   const dim3 g1(cdiv(N, 256)), b1(256);
   int ninv = 0, nmv = 0;
   auto U = [&](int role) { return union_of<T>(bp->hier[role].get()); };
+  const bool adaptive = bp->prm.adaptive != 0;
+  // one scalar inverse: V-cycles, or Jacobi iterations (option #1)
+  auto inv = [&](int role, const T* in, T* out) {
+    if (bp->jacobi[role])
+      jacobi_run<T>(c, N, X.jac_one[role].get(), 1, bp->prm.jacobi_sweeps,
+                    (double)bp->hier[role]->H.levels[0].A.nnz, in, out, X.jac_tmp1.get());
+    else
+      U(role)->apply(c, in, out, bp->cycles[role]);
+  };
   Group<T>& grp = X.grp;
   const int nm = (int)grp.roles.size();
   auto group_in = [&](const T* w) {
@@ -434,17 +585,35 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
     case MGD_PC_SCHUR2:
     case MGD_PC_SCHUR2_LOWER:
     case MGD_PC_PCTL: {
+      if (adaptive && kind == MGD_PC_SCHUR2 && bp->from_E_weak) {
+        // every row block independent of E (block lower triangular):
+        // w_a = S^_a^{-1} r_a, then w_E = A_E^{-1}(r_E - sum_a D_Ea w_a)
+        group_in(nullptr);
+        run_group(bp, grp);
+        group_out(true, X.b_in.get());
+        hipLaunchKernelGGL(k_lower_E_in<T>, g1, b1, 0, c->stream, N, r + (size_t)G * N,
+                           (const double*)nullptr, (const T*)nullptr, (const T*)X.b_in.get(),
+                           X.b_out.get());
+        MGD_CHECK_LAUNCH();
+        inv(G, X.b_out.get(), X.a_out.get());
+        hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.a_out.get(),
+                           (const T*)nullptr, z + (size_t)G * N);
+        MGD_CHECK_LAUNCH();
+        ninv = G + 2;
+        break;
+      }
       // step 1: w_E* = A_E^{-1} r_E
       const T* inE = as_input<T>(c, r + (size_t)G * N, X.a_in, N);
-      U(G)->apply(c, inE, X.a_out.get(), bp->cycles[G]);
+      inv(G, inE, X.a_out.get());
       // step 2: groups and I against r - D_.E w_E*
       group_in(X.a_out.get());
       run_group(bp, grp);
       ninv = 1 + G + 1;
-      if (kind == MGD_PC_SCHUR2) {
+      const bool e_coupled = !(adaptive && bp->into_E_weak);
+      if (kind == MGD_PC_SCHUR2 && e_coupled) {
         // step 3: w_E = w_E* - A_E^{-1}(sum_g D_Eg w_g + D_EI w_I)
         group_out(true, X.b_in.get());
-        U(G)->apply(c, X.b_in.get(), X.b_out.get(), bp->cycles[G]);
+        inv(G, X.b_in.get(), X.b_out.get());
         hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.a_out.get(),
                            (const T*)X.b_out.get(), z + (size_t)G * N);
         MGD_CHECK_LAUNCH();
@@ -455,7 +624,7 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
                            (const T*)nullptr, z + (size_t)G * N);
         MGD_CHECK_LAUNCH();
       }
-      if (kind == MGD_PC_PCTL) {
+      if (kind == MGD_PC_PCTL && e_coupled) {
         // coarse-grid correction: A_c w_c = P^T (b - A w); w += P w_c
         block_matvec(c, bp->sys, z, r, X.res.get());
         nmv = G + 2;
@@ -471,37 +640,67 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
       break;
     }
     case MGD_PC_SCHUR1: {
+      const double* dEI = (adaptive && bp->weak_EI) ? nullptr : bp->d_EI.get();
       // 1. w_I* = A_I^{-1} r_I
       const T* inI = as_input<T>(c, r + (size_t)(G + 1) * N, X.a_in, N);
-      U(G + 1)->apply(c, inI, X.a_out.get(), bp->cycles[G + 1]);
-      // 2. w_E* = C_E^{-1}(r_E - D_EI w_I*)
-      hipLaunchKernelGGL((k_single_in<T, T>), g1, b1, 0, c->stream, N, r + (size_t)G * N,
-                         (const double*)bp->d_EI.get(), (const T*)X.a_out.get(), X.b_in.get());
-      MGD_CHECK_LAUNCH();
-      U(G)->apply(c, X.b_in.get(), X.b_out.get(), bp->cycles[G]);
-      // 3. w_g = C_g^{-1}(r_g - D_gE w_E*)
-      group_in(X.b_out.get());
-      run_group(bp, grp);
-      // 4. w_E = w_E* - C_E^{-1} sum_g D_Eg w_g
-      group_out(true, X.b_in.get());
-      {
-        DBuf<T>& tmp = X.a_in;  // free after step 1 (FP32) / unused (FP64)
-        if (tmp.n < nN) tmp.alloc(c, nN);
-        U(G)->apply(c, X.b_in.get(), tmp.get(), bp->cycles[G]);
-        hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.b_out.get(),
-                           (const T*)tmp.get(), z + (size_t)G * N);
+      inv(G + 1, inI, X.a_out.get());
+      if (adaptive && bp->groups_from_E_weak) {
+        // groups independent of E: w_g = C^_g^{-1} r_g, then one C^_E inverse
+        // w_E = C^_E^{-1}((r_E - D_EI w_I*) - sum_g D_Eg w_g)
+        group_in(nullptr);
+        run_group(bp, grp);
+        group_out(true, X.b_in.get());
+        hipLaunchKernelGGL(k_lower_E_in<T>, g1, b1, 0, c->stream, N, r + (size_t)G * N, dEI,
+                           (const T*)X.a_out.get(), (const T*)X.b_in.get(), X.b_out.get());
         MGD_CHECK_LAUNCH();
+        inv(G, X.b_out.get(), X.b_in.get());
+        hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.b_in.get(),
+                           (const T*)nullptr, z + (size_t)G * N);
+        MGD_CHECK_LAUNCH();
+        ninv = 1 + G + 1;
+      } else {
+        // 2. w_E* = C^_E^{-1}(r_E - D_EI w_I*)
+        hipLaunchKernelGGL((k_single_in<T, T>), g1, b1, 0, c->stream, N, r + (size_t)G * N, dEI,
+                           (const T*)X.a_out.get(), X.b_in.get());
+        MGD_CHECK_LAUNCH();
+        inv(G, X.b_in.get(), X.b_out.get());
+        // 3. w_g = C^_g^{-1}(r_g - D_gE w_E*)
+        group_in(X.b_out.get());
+        run_group(bp, grp);
+        ninv = 1 + 1 + G;
+        if (adaptive && bp->into_E_weak_groups) {
+          group_out(false, nullptr);
+          hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.b_out.get(),
+                             (const T*)nullptr, z + (size_t)G * N);
+          MGD_CHECK_LAUNCH();
+        } else {
+          // 4. w_E = w_E* - C^_E^{-1} sum_g D_Eg w_g
+          group_out(true, X.b_in.get());
+          DBuf<T>& tmp = X.a_in;  // free after step 1 (FP32) / unused (FP64)
+          if (tmp.n < nN) tmp.alloc(c, nN);
+          inv(G, X.b_in.get(), tmp.get());
+          hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.b_out.get(),
+                             (const T*)tmp.get(), z + (size_t)G * N);
+          MGD_CHECK_LAUNCH();
+          ninv += 1;
+        }
       }
-      // 5. w_I = w_I* - A_I^{-1} D_IE w_E
-      hipLaunchKernelGGL((k_single_in<T, double>), g1, b1, 0, c->stream, N, (const double*)nullptr,
-                         (const double*)bp->d_IE.get(), (const double*)(z + (size_t)G * N),
-                         X.b_in.get());
-      MGD_CHECK_LAUNCH();
-      U(G + 1)->apply(c, X.b_in.get(), X.b_out.get(), bp->cycles[G + 1]);
-      hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.a_out.get(),
-                         (const T*)X.b_out.get(), z + (size_t)(G + 1) * N);
-      MGD_CHECK_LAUNCH();
-      ninv = G + 4;
+      if (adaptive && bp->weak_IE) {
+        hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.a_out.get(),
+                           (const T*)nullptr, z + (size_t)(G + 1) * N);
+        MGD_CHECK_LAUNCH();
+      } else {
+        // 5. w_I = w_I* - A_I^{-1} D_IE w_E
+        hipLaunchKernelGGL((k_single_in<T, double>), g1, b1, 0, c->stream, N,
+                           (const double*)nullptr, (const double*)bp->d_IE.get(),
+                           (const double*)(z + (size_t)G * N), X.b_in.get());
+        MGD_CHECK_LAUNCH();
+        inv(G + 1, X.b_in.get(), X.b_out.get());
+        hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.a_out.get(),
+                           (const T*)X.b_out.get(), z + (size_t)(G + 1) * N);
+        MGD_CHECK_LAUNCH();
+        ninv += 1;
+      }
       break;
     }
     default:
@@ -695,6 +894,89 @@ static Csr<double> monolithic(Ctx* c, const BlockSysDev& S) {
   return M;
 }
 
+// Adaptive strategy (Section 3.5), first level: Definition 1 for every
+// coupling block relative to the diagonal of its row block; a coupling is
+// neglected when more than sigma_wc N rows are weak, and the neglected ones
+// are zeroed in the preconditioner's own copy of the system (so the hats and
+// the PCTL residual see the modified matrix).
+static void adaptive_couplings(block_precond* bp) {
+  Ctx* c = bp->ctx;
+  const int G = bp->G, N = bp->N;
+  const double th = bp->prm.theta_wc, sig = bp->prm.sigma_wc;
+  DBuf<double> dg(c, (size_t)(G + 2) * N);
+  for (int a = 0; a < G + 2; ++a) diag_of(c, bp->blocks[a], dg.get() + (size_t)a * N);
+  const int nc = 2 * G + 2;
+  DBuf<int> cnt(c, (size_t)nc);
+  fill<int>(c, cnt.get(), 0, (size_t)nc);
+  const dim3 g1(cdiv(N, 256)), b1(256);
+  auto count = [&](int slot, const double* d, int row_block) {
+    hipLaunchKernelGGL(k_weak_count, g1, b1, 0, c->stream, N, d,
+                       (const double*)(dg.get() + (size_t)row_block * N), th, cnt.get() + slot);
+    MGD_CHECK_LAUNCH();
+  };
+  for (int g = 0; g < G; ++g) {
+    count(g, bp->d_gE.get() + (size_t)g * N, g);
+    count(G + g, bp->d_Eg.get() + (size_t)g * N, G);
+  }
+  count(2 * G, bp->d_EI.get(), G);
+  count(2 * G + 1, bp->d_IE.get(), G + 1);
+  std::vector<int> h((size_t)nc);
+  copy_d2h(c, h.data(), cnt.get(), (size_t)nc);
+  auto weak = [&](int k) { return (double)k > sig * (double)N; };
+  bp->cnt_gE.assign(h.begin(), h.begin() + G);
+  bp->cnt_Eg.assign(h.begin() + G, h.begin() + 2 * G);
+  bp->cnt_EI = h[2 * G];
+  bp->cnt_IE = h[2 * G + 1];
+  bp->weak_gE.assign(G, 0);
+  bp->weak_Eg.assign(G, 0);
+  bool all_gE = true, all_Eg = true;
+  for (int g = 0; g < G; ++g) {
+    bp->weak_gE[g] = weak(bp->cnt_gE[g]);
+    bp->weak_Eg[g] = weak(bp->cnt_Eg[g]);
+    if (bp->weak_gE[g]) fill<double>(c, bp->d_gE.get() + (size_t)g * N, 0.0, (size_t)N);
+    if (bp->weak_Eg[g]) fill<double>(c, bp->d_Eg.get() + (size_t)g * N, 0.0, (size_t)N);
+    all_gE = all_gE && bp->weak_gE[g];
+    all_Eg = all_Eg && bp->weak_Eg[g];
+  }
+  bp->weak_EI = weak(bp->cnt_EI);
+  bp->weak_IE = weak(bp->cnt_IE);
+  if (bp->weak_EI) fill<double>(c, bp->d_EI.get(), 0.0, (size_t)N);
+  if (bp->weak_IE) fill<double>(c, bp->d_IE.get(), 0.0, (size_t)N);
+  bp->groups_from_E_weak = all_gE;
+  bp->into_E_weak_groups = all_Eg;
+  bp->from_E_weak = all_gE && bp->weak_IE;
+  bp->into_E_weak = all_Eg && bp->weak_EI;
+  c->sync();
+}
+
+// Second level: Definition 2 on the matrix of every scalar inverse of the
+// kind (not PCTL's coarse operator); a matrix with no weakly dominant row is
+// inverted by Jacobi iterations (option #1), the others keep V-cycles.
+static void adaptive_inverses(block_precond* bp) {
+  Ctx* c = bp->ctx;
+  const int G = bp->G;
+  DBuf<int> cnt(c, (size_t)G + 2);
+  fill<int>(c, cnt.get(), 0, (size_t)G + 2);
+  for (int r = 0; r < G + 2; ++r) {
+    const Csr<double>& A = bp->hier[r]->H.levels[0].A;
+    hipLaunchKernelGGL(k_wd_count, dim3(cdiv(A.n_rows, 256)), dim3(256), 0, c->stream, A.n_rows,
+                       A.rp.get(), A.ci.get(), A.v.get(), bp->prm.theta_wd, cnt.get() + r);
+    MGD_CHECK_LAUNCH();
+  }
+  std::vector<int> h((size_t)G + 2);
+  copy_d2h(c, h.data(), cnt.get(), (size_t)G + 2);
+  for (int r = 0; r < G + 2; ++r) {
+    bp->wd_count[r] = h[r];
+    if (h[r] == 0) {
+      const Csr<double>& A = bp->hier[r]->H.levels[0].A;
+      bp->jacobi[r] = 1;
+      bp->jac_diag[r].alloc(c, (size_t)std::max(A.n_rows, 1));
+      diag_of(c, A, bp->jac_diag[r].get());
+    }
+  }
+  c->sync();
+}
+
 block_precond* block_precond_create_impl(Ctx* c, const mgd_block_system* A, const block_params* p) {
   auto t0 = std::chrono::steady_clock::now();
   auto bp = std::make_unique<block_precond>();
@@ -707,6 +989,14 @@ block_precond* block_precond_create_impl(Ctx* c, const mgd_block_system* A, cons
   MGD_REQUIRE(p->cycles_rad >= 1 && p->cycles_E >= 1 && p->cycles_I >= 1, "cycles must be >= 1");
   MGD_REQUIRE(p->amg.precision == 0 || p->amg.precision == 1, "precision must be 0 or 1");
   copy_system(bp.get(), A);
+  bp->jacobi.assign(G + 3, 0);
+  bp->wd_count.assign(G + 3, -1);
+  bp->jac_diag.resize(G + 3);
+  if (p->adaptive) {
+    MGD_REQUIRE(kind == MGD_PC_PCTL || kind == MGD_PC_SCHUR1 || kind == MGD_PC_SCHUR2,
+                "the adaptive strategy applies to PCTL, SCHUR1 and SCHUR2");
+    adaptive_couplings(bp.get());
+  }
   bp->cycles.assign(G + 3, 1);
   for (int g = 0; g < G; ++g) bp->cycles[g] = p->cycles_rad;
   bp->cycles[G] = p->cycles_E;
@@ -783,6 +1073,7 @@ block_precond* block_precond_create_impl(Ctx* c, const mgd_block_system* A, cons
           if (h) h->u64.reset();
     }
   }
+  if (p->adaptive) adaptive_inverses(bp.get());
   if (p->amg.precision == 1 && kind != MGD_PC_IDENTITY)
     build_exec<float>(bp.get(), bp->x32);
   else

@@ -607,6 +607,11 @@ void block_params_default(block_params* p) {
   p->batched = 0;
   p->use_graph = 0;
   p->transpose = 0;
+  p->adaptive = 0;
+  p->theta_wc = 1e-2;
+  p->sigma_wc = 0.5;
+  p->theta_wd = 0.9;
+  p->jacobi_sweeps = 2;
 }
 
 mgd_status block_precond_create(mgd_ctx* ctx, const mgd_block_system* A, const block_params* p,
@@ -617,6 +622,15 @@ mgd_status block_precond_create(mgd_ctx* ctx, const mgd_block_system* A, const b
     check_block_system(A);
     check_amg_params(&p->amg);
     MGD_REQUIRE(p->pctl_p_tol > 0 && p->pctl_p_maxcycles >= 1, "bad PCTL inner tolerance");
+    MGD_REQUIRE(p->adaptive == 0 || p->adaptive == 1, "adaptive must be 0 or 1");
+    if (p->adaptive) {
+      MGD_REQUIRE(p->kind == MGD_PC_PCTL || p->kind == MGD_PC_SCHUR1 || p->kind == MGD_PC_SCHUR2,
+                  "the adaptive strategy applies to PCTL, SCHUR1 and SCHUR2");
+      MGD_REQUIRE(p->theta_wc > 0 && p->theta_wc < 1 && p->sigma_wc >= 0 && p->sigma_wc <= 1 &&
+                      p->theta_wd > 0 && p->theta_wd < 1,
+                  "adaptive thresholds out of range (theta_wc, theta_wd in (0,1), sigma_wc in [0,1])");
+      MGD_REQUIRE(p->jacobi_sweeps >= 1 && p->jacobi_sweeps <= 64, "jacobi_sweeps must be in [1, 64]");
+    }
     ctx->make_current();
     for (int a = 0; a < A->G + 2; ++a) validate_csr_device(ctx, &A->blocks[a], true);
     *out = block_precond_create_impl(ctx, A, p);
@@ -649,6 +663,23 @@ mgd_status block_precond_get_info(const block_precond* M, block_precond_info* ou
     out->matvecs_per_apply = M->matvecs_last;
     for (size_t i = 0; i < M->p_cycles.size() && i < 66; ++i) out->pctl_p_cycles[i] = M->p_cycles[i];
     out->setup_ms = M->setup_ms;
+    for (int r = 0; r < 66; ++r) out->wd_count[r] = -1;
+    if (M->prm.adaptive) {
+      for (int g = 0; g < M->G && g < 64; ++g) {
+        out->wc_count_gE[g] = M->cnt_gE[g];
+        out->wc_count_Eg[g] = M->cnt_Eg[g];
+        out->weak_gE[g] = M->weak_gE[g];
+        out->weak_Eg[g] = M->weak_Eg[g];
+      }
+      out->wc_count_EI = M->cnt_EI;
+      out->wc_count_IE = M->cnt_IE;
+      out->weak_EI = M->weak_EI;
+      out->weak_IE = M->weak_IE;
+      for (size_t r = 0; r < M->wd_count.size() && r < 66; ++r) {
+        out->wd_count[r] = M->wd_count[r];
+        out->jacobi[r] = M->jacobi[r];
+      }
+    }
     return MGD_OK;
   });
 }

@@ -36,16 +36,37 @@ struct SegOut {
   const double* coef;   // accumulate coef o x into s (or nullptr)
 };
 
+// A scalar matrix inverted by Jacobi iterations (option #1 of Section 3.4):
+// its CSR arrays and its diagonal, FP64.
+struct JacMember {
+  const int* rp;
+  const int* ci;
+  const double* v;
+  const double* d;
+};
+
+// `sweeps` Jacobi iterations from zero for `nm` members at once (member-major
+// vectors of N); tmp holds nm * N values of T.
+template <typename T>
+void jacobi_run(Ctx* c, int N, const JacMember* tab, int nm, int sweeps, double nnz, const T* b,
+                T* x, T* tmp);
+
 template <typename T>
 struct Group {
-  // one V-cycle set over several hierarchies: batched union or one per member
+  // one inverse set over several scalar matrices: members [0, n_amg) run
+  // V-cycles (batched union or one hierarchy per member), the rest Jacobi
   std::unique_ptr<Union<T>> batched;
   std::vector<Union<T>*> seq;
-  std::vector<int> roles;   // hierarchy index of each member
+  std::vector<int> roles;   // hierarchy index of each member, V-cycle members first
+  int n_amg = 0;
   int cycles = 1;
   DBuf<T> in, out;          // members x N, member-major
   DBuf<SegIn> in_tab;
   DBuf<SegOut> out_tab;
+  DBuf<JacMember> jac_tab;  // members [n_amg, roles.size())
+  int jac_sweeps = 0;
+  double jac_nnz = 0;       // entries of all Jacobi members
+  DBuf<T> jac_tmp;
   void run(Ctx* c, int N);
 };
 
@@ -54,6 +75,8 @@ struct PcExec {
   Group<T> grp;                    // the batched step
   DBuf<T> a_in, a_out, b_in, b_out;  // single-hierarchy vectors
   DBuf<double> s, res;             // FP64 scratch
+  std::vector<DBuf<JacMember>> jac_one;  // per role, for single Jacobi inverses
+  DBuf<T> jac_tmp1;
 };
 
 }  // namespace mgd
@@ -72,6 +95,19 @@ struct block_precond {
   // PCTL
   mgd::DBuf<double> p;      // (G+1) N: p_1..p_G, p_I
   std::vector<int> p_cycles;
+  // adaptive strategy (Section 3.5): Definition 1 counts, neglected couplings
+  std::vector<int> cnt_gE, cnt_Eg;
+  int cnt_EI = 0, cnt_IE = 0;
+  std::vector<uint8_t> weak_gE, weak_Eg;
+  int weak_EI = 0, weak_IE = 0;
+  bool from_E_weak = false;         // every row block's coupling to E neglected (D_gE, D_IE)
+  bool into_E_weak = false;         // every coupling in E's row neglected (D_Eg, D_EI)
+  bool groups_from_E_weak = false;  // every D_gE neglected
+  bool into_E_weak_groups = false;  // every D_Eg neglected
+  // option #1 per role (Definition 2 count, -1 where not evaluated)
+  std::vector<int> wd_count;
+  std::vector<uint8_t> jacobi;
+  std::vector<mgd::DBuf<double>> jac_diag;
   std::unique_ptr<mgd::PcExec<double>> x64;
   std::unique_ptr<mgd::PcExec<float>> x32;
   // graph cache keyed by (r, z)

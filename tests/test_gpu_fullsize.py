@@ -15,6 +15,7 @@ import synth_inputs as si
 from oracle import adjoint as oadj
 from oracle import amg as oamg
 from oracle import assemble as oasm
+from oracle import precond as opc
 
 from gpu_helpers import gpu_modules, gpu_system, rel, to_dev, to_host
 
@@ -150,6 +151,31 @@ def test_g20_3d64_fp32_batched_against_fp64_plain(ctx):
     assert true_relres(osys, x32, inp.b) <= 1e-8 * (1 + 1e-6)
     assert true_relres(osys, x64, inp.b) <= 1e-8 * (1 + 1e-6)
     assert rel(x32, x64) < 1e-6
+
+
+def test_g20_3d64_adaptive_schur2(ctx):
+    """alpha-Schur2 (Section 3.5) at the benchmark size: the Definition 1 and 2
+    counts and decisions equal the oracle's (integers), and the FP32 batched
+    solve meets rtol 1e-8 against the full system."""
+    api = gpu_modules()
+    inp, osys, co, gsys = workload(ctx, "g20_3d64")
+    plan, _, _, wd = opc.adaptive_decisions(osys, "schur2", opc.BlockParams(adaptive=True))
+    M = api.BlockPreconditioner(ctx, gsys, "schur2", amg_seed=4, amg_precision=1, batched=1,
+                                use_graph=1, adaptive=1)
+    info = M.info()
+    G = inp.G
+    assert info["wc_counts"]["gE"] == [int(v) for v in plan.counts["gE"]]
+    assert info["wc_counts"]["Eg"] == [int(v) for v in plan.counts["Eg"]]
+    assert info["wc_counts"]["EI"] == int(plan.counts["EI"][0])
+    assert info["wc_counts"]["IE"] == int(plan.counts["IE"][0])
+    assert info["weak"]["gE"] == [bool(v) for v in plan.gE]
+    keys = [("g", g) for g in range(G)] + ["E", "I"]
+    assert info["wd_count"] == [wd[k] for k in keys]
+    assert info["jacobi"] == [wd[k] == 0 for k in keys]
+    b = to_dev(ctx, inp.b)
+    x, r = api.gmres(ctx, gsys, M, b, rtol=1e-8, flexible=1)
+    assert r.converged
+    assert true_relres(osys, to_host(x), inp.b) <= 1e-8 * (1 + 1e-6)
 
 
 # ---------------------------------------------------------------------------

@@ -361,6 +361,119 @@ def test_block_preconditioner_parity(ctx, kind, mode):
 
 
 # ---------------------------------------------------------------------------
+# adaptive strategy (Section 3.5; Definitions 1-2, options #1/#2)
+# ---------------------------------------------------------------------------
+ADAPTIVE_CASES = {
+    "drawn": {},                                                     # the generator's couplings
+    "from_E": dict(c_scale=(1e-6, 1.0, 1.0), log_kappa_shift=(0.0, 0.0, 6.0)),
+    "into_E": dict(log_kappa_shift=(0.0, 6.0, 0.0)),
+    "all": dict(c_scale=(1e-6, 1e-6, 1e-6)),
+    "mixed": dict(c_scale=([1e-6, 1.0, 1e-6], 1.0, 1.0)),              # groups 1 and 3 only
+    "jacobi_I": dict(log_kappa_shift=(0.0, 0.0, -8.0)),             # option #1 for the I block
+}
+
+
+def _role_key(role, G):
+    return ("g", role) if role < G else ("E" if role == G else "I")
+
+
+def assert_same_decisions(info, M_o, G):
+    """Definition 1 and 2 counts are integers: GPU and oracle must agree exactly."""
+    plan = M_o.plan
+    assert info["wc_counts"]["gE"] == [int(v) for v in plan.counts["gE"]]
+    assert info["wc_counts"]["Eg"] == [int(v) for v in plan.counts["Eg"]]
+    assert info["wc_counts"]["EI"] == int(plan.counts["EI"][0])
+    assert info["wc_counts"]["IE"] == int(plan.counts["IE"][0])
+    assert info["weak"] == {"gE": [bool(v) for v in plan.gE], "Eg": [bool(v) for v in plan.Eg],
+                            "EI": bool(plan.EI), "IE": bool(plan.IE)}
+    keys = [_role_key(r, G) for r in range(G + 2)]
+    assert info["wd_count"] == [M_o.setup_info["wd_counts"][k] for k in keys]
+    assert info["jacobi"] == [k in M_o.jacobi_roles for k in keys]
+
+
+@pytest.mark.parametrize("case", list(ADAPTIVE_CASES))
+@pytest.mark.parametrize("kind", ["pctl", "schur1", "schur2"])
+@pytest.mark.parametrize("mode", ["seq", "batched_graph", "fp32_batched_graph"])
+def test_adaptive_preconditioner_parity(ctx, kind, case, mode):
+    import torch
+    api = gpu_modules()
+    inp = si.generate(3, 2, 16, 41, **ADAPTIVE_CASES[case])
+    osys = oracle_system(inp)
+    M_o = opc.BlockPreconditioner(osys, opc.BlockParams(kind=kind, adaptive=True,
+                                                        amg=oamg.AMGParams(seed=5)))
+    co, gsys = gpu_system(ctx, inp)
+    fp32 = mode.startswith("fp32")
+    M_g = api.BlockPreconditioner(ctx, gsys, kind, amg_seed=5, adaptive=1,
+                                  batched=int(mode != "seq"), use_graph=int(mode != "seq"),
+                                  amg_precision=int(fp32))
+    G = inp.G
+    assert_same_decisions(M_g.info(), M_o, G)
+    if case == "jacobi_I":
+        assert M_o.jacobi_roles == {"I"}
+    tol = 5e-5 if fp32 else 1e-10
+    r = np.random.default_rng(4).standard_normal(osys.n)
+    rd = to_dev(ctx, r)
+    z = to_host(M_g.apply(rd))
+    c0 = M_o.counters.inverses
+    ref = M_o(r)
+    assert rel(z, ref) < tol, rel(z, ref)
+    assert M_g.info()["inverses_per_apply"] == M_o.counters.inverses - c0
+    assert M_g.info()["matvecs_per_apply"] == M_o.counters.matvecs
+    zb = torch.empty_like(rd)
+    for _ in range(3):
+        M_g.apply(rd, zb)
+        assert np.array_equal(to_host(zb), z)
+        torch.cuda.synchronize()
+    r2 = np.random.default_rng(5).standard_normal(osys.n)
+    rd.copy_(to_dev(ctx, r2))
+    M_g.apply(rd, zb)
+    assert rel(to_host(zb), M_o(r2)) < tol
+
+
+# Structural cases for solves: the kappa-shifted apply cases above are too ill
+# conditioned for GMRES(30) at 1e-8 with any of the preconditioners, so the
+# same neglect patterns come from coupling scales here (scaling c_EI makes
+# both D_EI and D_IE weak).
+GMRES_CASES = {
+    "drawn": {},
+    "from_E": dict(c_scale=(1e-6, 1.0, 1e-6)),
+    "into_E": dict(c_scale=(1.0, 1e-6, 1e-6)),
+    "mixed": ADAPTIVE_CASES["mixed"],
+    "jacobi_I": ADAPTIVE_CASES["jacobi_I"],
+}
+
+
+@pytest.mark.parametrize("case", list(GMRES_CASES))
+def test_adaptive_schur2_gmres(ctx, case):
+    """alpha-Schur2 inside FGMRES: iteration counts within one of the oracle's,
+    both solutions at rtol 1e-8 against the full (unmodified) system."""
+    api = gpu_modules()
+    inp = si.generate(3, 2, 24, 61, **GMRES_CASES[case])
+    osys = oracle_system(inp)
+    M_o = opc.BlockPreconditioner(osys, opc.BlockParams(kind="schur2", adaptive=True,
+                                                        amg=oamg.AMGParams(seed=6)))
+    xo, io = okry.gmres(osys.matvec, M_o, inp.b, rtol=1e-8)
+    co, gsys = gpu_system(ctx, inp)
+    M_g = api.BlockPreconditioner(ctx, gsys, "schur2", amg_seed=6, adaptive=1, batched=1,
+                                  use_graph=1)
+    x, res = api.gmres(ctx, gsys, M_g, to_dev(ctx, inp.b), rtol=1e-8, flexible=1)
+    assert res.converged and abs(res.iters - io.iters) <= 1, (res.iters, io.iters)
+    xh = to_host(x)
+    bn = np.linalg.norm(inp.b)
+    assert np.linalg.norm(inp.b - osys.matvec(xh)) <= 1e-8 * bn * (1 + 1e-6)
+    assert np.linalg.norm(inp.b - osys.matvec(xo)) <= 1e-8 * bn * (1 + 1e-6)
+
+
+def test_adaptive_rejects_other_kinds(ctx):
+    api = gpu_modules()
+    inp = si.generate(2, 2, 8, 3)
+    co, gsys = gpu_system(ctx, inp)
+    for kind in ("amg", "bdiag", "schur2_lower"):
+        with pytest.raises(RuntimeError):
+            api.BlockPreconditioner(ctx, gsys, kind, adaptive=1)
+
+
+# ---------------------------------------------------------------------------
 # GMRES
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ["amg", "schur2", "schur1", "pctl"])
