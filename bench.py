@@ -12,6 +12,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -20,6 +21,37 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def sources_digest() -> str:
+    """SHA-256 (first 16 hex digits) over the library sources, sorted by name,
+    each as its relative path, a NUL byte and its bytes."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2002_04958_amd", "csrc", "*.hip"))
+                   + glob.glob(os.path.join(ROOT, "paper_2002_04958_amd", "csrc", "*.hpp")))
+    for f in files:
+        h.update(os.path.relpath(f, ROOT).encode() + b"\0")
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes, calibrated), or None when there is no
+    record for it or the library sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "solve_kernels_g20_3d64.md")
+    if not os.path.exists(path):
+        return None
+    want = sources_digest()
+    for line in open(path):
+        m = re.match(r"traffic-record: kernel=(.+) bytes_per_launch=(\d+) sources=([0-9a-f]+)\s*$",
+                     line)
+        if m and m.group(1) == kernel and m.group(3) == want:
+            return int(m.group(2))
+    return None
 
 
 def log(*a):
@@ -70,6 +102,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the candidate layouts of every level once and keep the fastest "
+                         "(cached per process, or in MGD_AUTOTUNE_CACHE)")
     ap.add_argument("--counters-run", action="store_true",
                     help="short run for hardware-counter passes: a streaming calibration "
                          "kernel (torch mul reading 1 GiB and writing 1 GiB, its input pushed "
@@ -101,7 +136,8 @@ def main():
         t0 = time.perf_counter()
         M = api.BlockPreconditioner(ctx, sysg, "schur2", amg_seed=w.seed,
                                     amg_precision=1 if fp32 else 0, batched=int(batched),
-                                    use_graph=int(graph), adaptive=int(adaptive))
+                                    use_graph=int(graph), adaptive=int(adaptive),
+                                    amg_autotune=int(a.autotune))
         torch.cuda.synchronize()
         return M, time.perf_counter() - t0
 
@@ -246,7 +282,8 @@ def main():
         "alpha_schur2_fp32": alpha,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "launches": s["launches"],
+                     "traffic": recorded_traffic(dom), "traffic_unit": "bytes per launch",
+                     "launches": s["launches"],
                      "avg_launch_us": 1e3 * s["ms"] / max(1, s["launches"]),
                      "bytes_per_launch": s["bytes"] / max(1, s["launches"])},
         "kernels": {k: {"ms": v["ms"], "launches": v["launches"],
