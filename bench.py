@@ -102,6 +102,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true")
+    ap.add_argument("--no-inner", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate layouts of every level once and keep the fastest "
                          "(cached per process, or in MGD_AUTOTUNE_CACHE)")
@@ -131,13 +132,13 @@ def main():
     b = torch.as_tensor(inp.b, device=ctx.device)
     bnorm = float(torch.linalg.vector_norm(b))
 
-    def build(batched, fp32, graph, adaptive=False):
+    def build(batched, fp32, graph, adaptive=False, inner_tol=0.0):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         M = api.BlockPreconditioner(ctx, sysg, "schur2", amg_seed=w.seed,
                                     amg_precision=1 if fp32 else 0, batched=int(batched),
                                     use_graph=int(graph), adaptive=int(adaptive),
-                                    amg_autotune=int(a.autotune))
+                                    inner_tol=inner_tol, amg_autotune=int(a.autotune))
         torch.cuda.synchronize()
         return M, time.perf_counter() - t0
 
@@ -213,6 +214,24 @@ def main():
             f"jacobi roles {alpha['jacobi_roles']}")
         del Ma, xa
 
+    # the inner solves of Section 4: S^_g and S^_I to a relative tolerance 1e-2
+    inner = None
+    if not a.no_inner:
+        Mi, setup_i = build(True, True, False, inner_tol=1e-2)
+        solve(Mi)
+        torch.cuda.synchronize()
+        t0i = time.perf_counter()
+        xi, ri = solve(Mi)
+        torch.cuda.synchronize()
+        ti = time.perf_counter() - t0i
+        relres_i = float(torch.linalg.vector_norm(b - sysg.matvec(xi))) / bnorm
+        ii = Mi.info()
+        inner = {"s": ti, "iters": ri.iters, "relres": relres_i, "setup_s": setup_i,
+                 "inner_cycles_last_apply": ii["inner_cycles"]}
+        log(f"[bench] schur2 inner tol 1e-2 fp32 batched: {ti * 1e3:.1f} ms/solve, iters {ri.iters}, "
+            f"relres {relres_i:.2e}, inner cycles of the last apply {ii['inner_cycles']}")
+        del Mi, xi
+
     # plain FP64 form: sequential launches, no graph
     plain = None
     if not a.no_plain:
@@ -280,6 +299,7 @@ def main():
         "plain_fp64": plain,
         "speedup_vs_plain_fp64": (plain["s"] / (ms_step / 1e3)) if plain else None,
         "alpha_schur2_fp32": alpha,
+        "schur2_inner_tol_1e-2_fp32": inner,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": recorded_traffic(dom), "traffic_unit": "bytes per launch",

@@ -237,6 +237,16 @@ mgd_status mgd_block_system_free(mgd_ctx* ctx, mgd_block_system* s);
  * matrix has no row with sum_j a_kj < theta_wd a_kk (Definition 2) uses
  * jacobi_sweeps Jacobi iterations from zero (option #1 of Section 3.4)
  * instead of V-cycles; PCTL's interpolation weights keep option #3.
+ *
+ * inner_tol > 0 approximates the inverses that the paper's experiments solve
+ * to a relative tolerance (Section 4; option #3 of Section 3.4) by V-cycles
+ * z <- z + V(r), r = b - A z, until ||r|| < inner_tol ||b|| or
+ * inner_maxcycles cycles: the hatted matrices of SCHUR1 (C^_E, C^_g) and
+ * SCHUR2/SCHUR2_LOWER (S^_g, S^_I) and PCTL's block relaxations (A_E, A_g,
+ * A_I); the other inverses keep their fixed cycle counts.  In a batched step
+ * each member stops on its own criterion.  The preconditioner is then
+ * nonlinear (use flexible GMRES) and every apply synchronises once per inner
+ * cycle, so use_graph is ignored.
  * ------------------------------------------------------------------------- */
 enum {
   MGD_PC_AMG_MONO = 0,
@@ -262,6 +272,8 @@ typedef struct block_params {
   double sigma_wc;                        /* 0.5 */
   double theta_wd;                        /* 0.9, Definition 2 */
   int32_t jacobi_sweeps;                  /* 2, option #1 */
+  double inner_tol;                       /* 0 = fixed cycles (option #2); 1e-2 in Section 4 */
+  int32_t inner_maxcycles;                /* 100 */
 } block_params;
 void block_params_default(block_params* p);
 
@@ -286,6 +298,9 @@ typedef struct block_precond_info {
   int32_t weak_EI, weak_IE;
   int32_t wd_count[66];
   uint8_t jacobi[66];
+  /* inner_tol > 0: V-cycles each inverse role used in the last apply (-1 for
+   * roles with a fixed cycle count) */
+  int32_t inner_cycles[66];
 } block_precond_info;
 mgd_status block_precond_get_info(const block_precond* M, block_precond_info* out);
 /* Hierarchy of one scalar inverse: index g < G for group g, G for the E

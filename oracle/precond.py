@@ -52,6 +52,8 @@ class BlockParams:
     cycles_I: int = 1
     pctl_p_tol: float = 1e-2           # inner tolerance, Section 4
     pctl_p_maxcycles: int = 100
+    inner_tol: float = 0.0             # > 0: option #3 for the inverses the paper's runs solve to a tolerance
+    inner_maxcycles: int = 100
     adaptive: bool = False             # Section 3.5 strategy + options #1/#2
     theta_wc: float = 1e-2             # Definition 1
     sigma_wc: float = 0.5
@@ -219,13 +221,34 @@ class BlockPreconditioner:
                                             self.counters)
 
     # -- scalar inverse construction -----------------------------------------
+    def tolerance_roles(self):
+        """The inverses Section 4 approximates to a relative tolerance (option
+        #3): the hatted matrices of the Schur preconditioners (C^_E, C^_g for
+        Schur1; S^_g, S^_I for Schur2) and PCTL's block relaxations (A_E, A_g,
+        A_I); the others (A_I for Schur1, A_E for Schur2, PCTL's A_c) keep the
+        fixed number of V-cycles."""
+        G = self.G
+        groups = {("g", g) for g in range(G)}
+        return {"schur1": groups | {"E"}, "schur2": groups | {"I"},
+                "schur2_lower": groups | {"I"}, "pctl": groups | {"E", "I"}}.get(self.kind, set())
+
     def _amg_factory(self, M, key):
         """key: ('g', g), 'E', 'I', 'c' (PCTL coarse) or 'mono'."""
         role = "g" if isinstance(key, tuple) else key
         cyc = {"g": self.params.cycles_rad, "E": self.params.cycles_E,
                "I": self.params.cycles_I, "c": self.params.cycles_E,
                "mono": 1}[role]
-        return amg_inverse(M, self.params.amg, cyc, self.counters)
+        inv = amg_inverse(M, self.params.amg, cyc, self.counters)
+        if self.params.inner_tol > 0 and key in self.tolerance_roles():
+            H, tol, maxc = inv.hierarchy, self.params.inner_tol, self.params.inner_maxcycles
+            inv.last_cycles = 0
+
+            def fn(b, inv=inv):
+                z, k = amg.solve_to_tolerance(H, b, tol, maxc)
+                inv.last_cycles = k
+                return z
+            inv._fn = fn
+        return inv
 
     def _pctl_setup(self, fac):
         G, N = self.G, self.N

@@ -53,7 +53,8 @@ class block_params(Structure):
                 ("cycles_E", c_int32), ("cycles_I", c_int32), ("pctl_p_tol", c_double),
                 ("pctl_p_maxcycles", c_int32), ("batched", c_int32), ("use_graph", c_int32),
                 ("transpose", c_int32), ("adaptive", c_int32), ("theta_wc", c_double),
-                ("sigma_wc", c_double), ("theta_wd", c_double), ("jacobi_sweeps", c_int32)]
+                ("sigma_wc", c_double), ("theta_wd", c_double), ("jacobi_sweeps", c_int32),
+                ("inner_tol", c_double), ("inner_maxcycles", c_int32)]
 
 
 class block_precond_info(Structure):
@@ -62,7 +63,8 @@ class block_precond_info(Structure):
                 ("setup_ms", c_double), ("wc_count_gE", c_int32 * 64),
                 ("wc_count_Eg", c_int32 * 64), ("wc_count_EI", c_int32), ("wc_count_IE", c_int32),
                 ("weak_gE", c_uint8 * 64), ("weak_Eg", c_uint8 * 64), ("weak_EI", c_int32),
-                ("weak_IE", c_int32), ("wd_count", c_int32 * 66), ("jacobi", c_uint8 * 66)]
+                ("weak_IE", c_int32), ("wd_count", c_int32 * 66), ("jacobi", c_uint8 * 66),
+                ("inner_cycles", c_int32 * 66)]
 
 
 class gmres_params(Structure):

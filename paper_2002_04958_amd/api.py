@@ -378,7 +378,8 @@ class BlockPreconditioner:
                          "Eg": [bool(v) for v in i.weak_Eg[:G]],
                          "EI": bool(i.weak_EI), "IE": bool(i.weak_IE)},
                 "wd_count": list(i.wd_count[:G + 2]),
-                "jacobi": [bool(v) for v in i.jacobi[:G + 2]]}
+                "jacobi": [bool(v) for v in i.jacobi[:G + 2]],
+                "inner_cycles": list(i.inner_cycles[:G + 3])}
 
     def hierarchy(self, index: int) -> AMG:
         h = c_void_p()

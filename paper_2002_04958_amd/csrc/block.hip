@@ -162,6 +162,76 @@ __global__ void k_wd_count(int n, const int* __restrict__ rp, const int* __restr
   const unsigned long long m = __ballot(hit);
   if ((threadIdx.x & 63) == 0 && m) atomicAdd(cnt, (int)__popcll(m));
 }
+// Sum over a 256-thread workgroup; result valid in thread 0.
+__device__ __forceinline__ double member_sum256(double v, double* lds /*[4]*/) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+  __syncthreads();
+  return r;
+}
+// Option #3 pieces, member m = blockIdx.y of member-major vectors of N.
+// part[m * nb + block] = sum of x_m^2 over the block's grid-stride rows
+template <typename T>
+__global__ void __launch_bounds__(256) k_member_sq(int N, const T* __restrict__ x,
+                                                   double* __restrict__ part, int nb) {
+  __shared__ double lds[4];
+  const size_t off = (size_t)blockIdx.y * N;
+  double s = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < N; i += nb * 256) {
+    const double v = (double)x[off + i];
+    s = s + v * v;
+  }
+  s = member_sum256(s, lds);
+  if (threadIdx.x == 0) part[(size_t)blockIdx.y * nb + blockIdx.x] = s;
+}
+// r_m = b_m - A_m z_m (FP64 arithmetic) and its squared norm, active members only
+template <typename T>
+__global__ void __launch_bounds__(256) k_member_resid(int N, const JacMember* __restrict__ tab,
+                                                      const int* __restrict__ active,
+                                                      const T* __restrict__ b,
+                                                      const T* __restrict__ z, T* __restrict__ r,
+                                                      double* __restrict__ part, int nb) {
+  __shared__ double lds[4];
+  const int m = blockIdx.y;
+  if (!active[m]) {  // uniform over the workgroup
+    if (threadIdx.x == 0) part[(size_t)m * nb + blockIdx.x] = 0.0;
+    return;
+  }
+  const JacMember A = tab[m];
+  const size_t off = (size_t)m * N;
+  double s = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < N; i += nb * 256) {
+    double v = (double)b[off + i];
+    for (int e = A.rp[i]; e < A.rp[i + 1]; ++e) v = v - A.v[e] * (double)z[off + A.ci[e]];
+    r[off + i] = (T)v;
+    s = s + v * v;
+  }
+  s = member_sum256(s, lds);
+  if (threadIdx.x == 0) part[(size_t)m * nb + blockIdx.x] = s;
+}
+// sums[m] = sum_k part[m * nb + k] in a fixed order
+__global__ void __launch_bounds__(256) k_member_final(int nb, const double* __restrict__ part,
+                                                      double* __restrict__ sums) {
+  __shared__ double lds[4];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 256) s = s + part[(size_t)blockIdx.x * nb + k];
+  s = member_sum256(s, lds);
+  if (threadIdx.x == 0) sums[blockIdx.x] = s;
+}
+// z_m += t_m for active members
+template <typename T>
+__global__ void k_member_axpy(int N, const int* __restrict__ active, const T* __restrict__ t,
+                              T* __restrict__ z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N || !active[blockIdx.y]) return;
+  const size_t k = (size_t)blockIdx.y * N + i;
+  z[k] = z[k] + t[k];
+}
 // PCTL restriction of the block residual: rc = r_E + sum_g p_g o r_g + p_I o r_I
 template <typename T>
 __global__ void k_pctl_restrict(int G, int N, const double* __restrict__ p,
@@ -365,6 +435,96 @@ static int solve_to_tol(block_precond* bp, amg_hierarchy* h, const double* rhs, 
   return k;
 }
 
+// The inverses Section 4 solves to a relative tolerance: the hatted matrices
+// of the Schur preconditioners and PCTL's block relaxations.
+static bool tolerance_role(int kind, int role, int G) {
+  if (role < G) return kind == MGD_PC_SCHUR1 || kind == MGD_PC_SCHUR2 ||
+                       kind == MGD_PC_SCHUR2_LOWER || kind == MGD_PC_PCTL;
+  if (role == G) return kind == MGD_PC_SCHUR1 || kind == MGD_PC_PCTL;
+  if (role == G + 1)
+    return kind == MGD_PC_SCHUR2 || kind == MGD_PC_SCHUR2_LOWER || kind == MGD_PC_PCTL;
+  return false;
+}
+
+template <typename T>
+static std::unique_ptr<TolSolve<T>> make_tol(block_precond* bp, const std::vector<int>& roles) {
+  Ctx* c = bp->ctx;
+  const int N = bp->N, nm = (int)roles.size();
+  auto S = std::make_unique<TolSolve<T>>();
+  S->roles = roles;
+  std::vector<JacMember> tab;
+  for (int r : roles) {
+    const Csr<double>& A = bp->hier[r]->H.levels[0].A;
+    tab.push_back({A.rp.get(), A.ci.get(), A.v.get(), nullptr});
+    S->nnz += (double)A.nnz;
+  }
+  S->mats.alloc(c, (size_t)nm);
+  copy_h2d(c, S->mats.get(), tab.data(), (size_t)nm);
+  S->r.alloc(c, (size_t)nm * N);
+  S->t.alloc(c, (size_t)nm * N);
+  S->active.alloc(c, (size_t)nm);
+  S->nb = (int)std::min<long long>(cdiv(N, 256), 128);
+  S->part.alloc(c, (size_t)nm * S->nb);
+  S->sums.alloc(c, (size_t)nm);
+  return S;
+}
+
+// Option #3 over the members of S: z = 0, r = b; then V-cycles z += V(r),
+// r = b - A z, a member leaving once ||r|| < inner_tol ||b|| (members with
+// b = 0 take no cycle).  `vcycle` runs one V-cycle on all members at once.
+template <typename T, typename V>
+static void tol_run(block_precond* bp, TolSolve<T>& S, const T* b, T* z, V&& vcycle) {
+  Ctx* c = bp->ctx;
+  const int N = bp->N, nm = (int)S.roles.size();
+  const size_t nN = (size_t)nm * N;
+  const double tol = bp->prm.inner_tol;
+  const int maxc = bp->prm.inner_maxcycles;
+  const dim3 gr(S.nb, nm), g1(cdiv(N, 256), nm), b256(256);
+  hipLaunchKernelGGL(k_member_sq<T>, gr, b256, 0, c->stream, N, b, S.part.get(), S.nb);
+  hipLaunchKernelGGL(k_member_final, dim3(nm), b256, 0, c->stream, S.nb,
+                     (const double*)S.part.get(), S.sums.get());
+  MGD_CHECK_LAUNCH();
+  std::vector<double> bn2((size_t)nm), rn2((size_t)nm);
+  copy_d2h(c, bn2.data(), S.sums.get(), (size_t)nm);
+  std::vector<int> act((size_t)nm), cyc((size_t)nm, 0);
+  int n_act = 0;
+  for (int m = 0; m < nm; ++m) {
+    act[m] = bn2[m] > 0.0 ? 1 : 0;
+    n_act += act[m];
+  }
+  fill<T>(c, z, (T)0, nN);
+  cast_copy<T, T>(c, S.r.get(), b, nN, KC_VEC);
+  copy_h2d(c, S.active.get(), act.data(), (size_t)nm);
+  for (int k = 1; k <= maxc && n_act > 0; ++k) {
+    vcycle((const T*)S.r.get(), S.t.get());
+    {
+      ProfScope ps(c, KC_VEC, 12.0 * S.nnz + (double)nN * (4.0 + 4.0 * sizeof(T)),
+                   ksym(c, "k_member_resid", {type_name<T>()}));
+      hipLaunchKernelGGL(k_member_axpy<T>, g1, b256, 0, c->stream, N, (const int*)S.active.get(),
+                         (const T*)S.t.get(), z);
+      hipLaunchKernelGGL(k_member_resid<T>, gr, b256, 0, c->stream, N,
+                         (const JacMember*)S.mats.get(), (const int*)S.active.get(), b,
+                         (const T*)z, S.r.get(), S.part.get(), S.nb);
+      hipLaunchKernelGGL(k_member_final, dim3(nm), b256, 0, c->stream, S.nb,
+                         (const double*)S.part.get(), S.sums.get());
+      MGD_CHECK_LAUNCH();
+    }
+    copy_d2h(c, rn2.data(), S.sums.get(), (size_t)nm);
+    bool changed = false;
+    for (int m = 0; m < nm; ++m) {
+      if (!act[m]) continue;
+      if (std::sqrt(rn2[m]) < tol * std::sqrt(bn2[m]) || k == maxc) {
+        act[m] = 0;
+        cyc[m] = k;
+        --n_act;
+        changed = true;
+      }
+    }
+    if (changed && n_act > 0) copy_h2d(c, S.active.get(), act.data(), (size_t)nm);
+  }
+  for (int m = 0; m < nm; ++m) bp->inner_cycles[S.roles[m]] = cyc[m];
+}
+
 template <typename T>
 static void build_exec(block_precond* bp, std::unique_ptr<PcExec<T>>& X) {
   Ctx* c = bp->ctx;
@@ -380,7 +540,10 @@ static void build_exec(block_precond* bp, std::unique_ptr<PcExec<T>>& X) {
   if (kind == MGD_PC_PCTL) singles = {G, G + 2};
   if (kind == MGD_PC_SCHUR1) singles = {G, G + 1};
   X->jac_one.resize(G + 3);
+  X->tol_one.resize(G + 3);
+  const bool inner = bp->prm.inner_tol > 0;
   for (int r : singles) {
+    if (inner && bp->tol_role[r] && !bp->jacobi[r]) X->tol_one[r] = make_tol<T>(bp, {r});
     if (bp->jacobi[r]) {
       const Csr<double>& A = bp->hier[r]->H.levels[0].A;
       JacMember jm{A.rp.get(), A.ci.get(), A.v.get(), bp->jac_diag[r].get()};
@@ -479,6 +642,12 @@ static void build_exec(block_precond* bp, std::unique_ptr<PcExec<T>>& X) {
       grp.cycles = -1;
     }
   }
+  if (inner && n_amg > 0) {
+    bool all_tol = true;
+    for (int m = 0; m < n_amg; ++m) all_tol = all_tol && bp->tol_role[roles[m]];
+    MGD_REQUIRE(all_tol, "internal: a batched step mixes fixed-count and tolerance inverses");
+    grp.tol = make_tol<T>(bp, std::vector<int>(roles.begin(), roles.begin() + n_amg));
+  }
   const int nj = (int)nm - n_amg;
   if (nj > 0) {
     std::vector<JacMember> jt;
@@ -511,6 +680,24 @@ template <typename T>
 static void run_group(block_precond* bp, Group<T>& grp) {
   Ctx* c = bp->ctx;
   const int N = bp->N;
+  if (grp.tol) {
+    // option #3 on the V-cycle members (one V-cycle per inner step), then
+    // the Jacobi members
+    tol_run<T>(bp, *grp.tol, grp.in.get(), grp.out.get(), [&](const T* rin, T* tout) {
+      if (grp.batched) {
+        grp.batched->apply(c, rin, tout, 1);
+      } else {
+        for (size_t m = 0; m < grp.seq.size(); ++m)
+          grp.seq[m]->apply(c, rin + m * (size_t)N, tout + m * (size_t)N, 1);
+      }
+    });
+    const int nj = (int)grp.roles.size() - grp.n_amg;
+    if (nj > 0)
+      jacobi_run<T>(c, N, grp.jac_tab.get(), nj, grp.jac_sweeps, grp.jac_nnz,
+                    grp.in.get() + (size_t)grp.n_amg * N, grp.out.get() + (size_t)grp.n_amg * N,
+                    grp.jac_tmp.get());
+    return;
+  }
   if (grp.cycles >= 0) {
     grp.run(c, N);
     return;
@@ -536,7 +723,10 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
   const bool adaptive = bp->prm.adaptive != 0;
   // one scalar inverse: V-cycles, or Jacobi iterations (option #1)
   auto inv = [&](int role, const T* in, T* out) {
-    if (bp->jacobi[role])
+    if (X.tol_one[role])
+      tol_run<T>(bp, *X.tol_one[role], in, out,
+                 [&](const T* rin, T* tout) { U(role)->apply(c, rin, tout, 1); });
+    else if (bp->jacobi[role])
       jacobi_run<T>(c, N, X.jac_one[role].get(), 1, bp->prm.jacobi_sweeps,
                     (double)bp->hier[role]->H.levels[0].A.nnz, in, out, X.jac_tmp1.get());
     else
@@ -721,7 +911,7 @@ void block_precond_apply_impl(block_precond* bp, const double* r, double* z) {
 
 void block_precond_apply_dispatch(block_precond* bp, const double* r, double* z) {
   Ctx* c = bp->ctx;
-  if (!bp->prm.use_graph || c->profiling) {
+  if (!bp->prm.use_graph || c->profiling || bp->prm.inner_tol > 0) {
     block_precond_apply_impl(bp, r, z);
     return;
   }
@@ -991,6 +1181,10 @@ block_precond* block_precond_create_impl(Ctx* c, const mgd_block_system* A, cons
   copy_system(bp.get(), A);
   bp->jacobi.assign(G + 3, 0);
   bp->wd_count.assign(G + 3, -1);
+  bp->tol_role.assign(G + 3, 0);
+  bp->inner_cycles.assign(G + 3, -1);
+  if (p->inner_tol > 0)
+    for (int r = 0; r < G + 3; ++r) bp->tol_role[r] = tolerance_role(kind, r, G) ? 1 : 0;
   bp->jac_diag.resize(G + 3);
   if (p->adaptive) {
     MGD_REQUIRE(kind == MGD_PC_PCTL || kind == MGD_PC_SCHUR1 || kind == MGD_PC_SCHUR2,

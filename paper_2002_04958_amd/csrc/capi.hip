@@ -612,6 +612,8 @@ void block_params_default(block_params* p) {
   p->sigma_wc = 0.5;
   p->theta_wd = 0.9;
   p->jacobi_sweeps = 2;
+  p->inner_tol = 0.0;
+  p->inner_maxcycles = 100;
 }
 
 mgd_status block_precond_create(mgd_ctx* ctx, const mgd_block_system* A, const block_params* p,
@@ -623,6 +625,9 @@ mgd_status block_precond_create(mgd_ctx* ctx, const mgd_block_system* A, const b
     check_amg_params(&p->amg);
     MGD_REQUIRE(p->pctl_p_tol > 0 && p->pctl_p_maxcycles >= 1, "bad PCTL inner tolerance");
     MGD_REQUIRE(p->adaptive == 0 || p->adaptive == 1, "adaptive must be 0 or 1");
+    MGD_REQUIRE(p->inner_tol >= 0 && p->inner_tol < 1, "inner_tol must be in [0, 1)");
+    MGD_REQUIRE(p->inner_maxcycles >= 1 && p->inner_maxcycles <= 1000,
+                "inner_maxcycles must be in [1, 1000]");
     if (p->adaptive) {
       MGD_REQUIRE(p->kind == MGD_PC_PCTL || p->kind == MGD_PC_SCHUR1 || p->kind == MGD_PC_SCHUR2,
                   "the adaptive strategy applies to PCTL, SCHUR1 and SCHUR2");
@@ -664,6 +669,8 @@ mgd_status block_precond_get_info(const block_precond* M, block_precond_info* ou
     for (size_t i = 0; i < M->p_cycles.size() && i < 66; ++i) out->pctl_p_cycles[i] = M->p_cycles[i];
     out->setup_ms = M->setup_ms;
     for (int r = 0; r < 66; ++r) out->wd_count[r] = -1;
+    for (int r = 0; r < 66; ++r)
+      out->inner_cycles[r] = r < (int)M->inner_cycles.size() ? M->inner_cycles[r] : -1;
     if (M->prm.adaptive) {
       for (int g = 0; g < M->G && g < 64; ++g) {
         out->wc_count_gE[g] = M->cnt_gE[g];

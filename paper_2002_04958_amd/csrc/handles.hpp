@@ -51,6 +51,20 @@ template <typename T>
 void jacobi_run(Ctx* c, int N, const JacMember* tab, int nm, int sweeps, double nnz, const T* b,
                 T* x, T* tmp);
 
+// Option #3 for a set of scalar inverses (one batched step, or a single
+// inverse): V-cycles z <- z + V(r), r = b - A z, each member until
+// ||r|| < tol ||b|| or maxc cycles (member-major vectors of N).
+template <typename T>
+struct TolSolve {
+  std::vector<int> roles;   // inverse role of each member
+  DBuf<JacMember> mats;     // each member's level-0 matrix (FP64, natural order)
+  DBuf<T> r, t;             // residual and V-cycle output, members x N
+  DBuf<int> active;         // members still iterating
+  DBuf<double> part, sums;  // reduction partials (members x nb) and per-member sums
+  int nb = 0;
+  double nnz = 0;           // entries of all members' matrices
+};
+
 template <typename T>
 struct Group {
   // one inverse set over several scalar matrices: members [0, n_amg) run
@@ -63,6 +77,7 @@ struct Group {
   DBuf<T> in, out;          // members x N, member-major
   DBuf<SegIn> in_tab;
   DBuf<SegOut> out_tab;
+  std::unique_ptr<TolSolve<T>> tol;  // option #3 for the V-cycle members, or null
   DBuf<JacMember> jac_tab;  // members [n_amg, roles.size())
   int jac_sweeps = 0;
   double jac_nnz = 0;       // entries of all Jacobi members
@@ -77,6 +92,7 @@ struct PcExec {
   DBuf<double> s, res;             // FP64 scratch
   std::vector<DBuf<JacMember>> jac_one;  // per role, for single Jacobi inverses
   DBuf<T> jac_tmp1;
+  std::vector<std::unique_ptr<TolSolve<T>>> tol_one;  // per role, single option #3 inverses
 };
 
 }  // namespace mgd
@@ -108,6 +124,10 @@ struct block_precond {
   std::vector<int> wd_count;
   std::vector<uint8_t> jacobi;
   std::vector<mgd::DBuf<double>> jac_diag;
+  // option #3 inner solves (inner_tol > 0): roles solved to the tolerance and
+  // the V-cycles each used in the last apply (-1 for fixed-count roles)
+  std::vector<uint8_t> tol_role;
+  std::vector<int> inner_cycles;
   std::unique_ptr<mgd::PcExec<double>> x64;
   std::unique_ptr<mgd::PcExec<float>> x32;
   // graph cache keyed by (r, z)

@@ -57,6 +57,7 @@ def test_host_defaults_follow_the_paper(lib):
     assert b.kind == _lib.PC_KINDS["schur2"] and b.pctl_p_tol == 1e-2
     assert b.adaptive == 0 and b.theta_wc == 1e-2 and b.sigma_wc == 0.5
     assert b.theta_wd == 0.9 and b.jacobi_sweeps == 2
+    assert b.inner_tol == 0.0 and b.inner_maxcycles == 100
     assert lib.mgd_kernel_class_count() >= 8
     assert lib.mgd_kernel_class_name(0) == b"spmv"
     assert b"gfx950" in lib.mgd_version()
@@ -74,6 +75,8 @@ def test_struct_layouts_match_c(tmp_path):
     src += '  printf("gmres_result.relres_est %zu\\n", offsetof(gmres_result, relres_est));\n'
     src += '  printf("block_params.jacobi_sweeps %zu\\n", offsetof(block_params, jacobi_sweeps));\n'
     src += '  printf("block_precond_info.jacobi %zu\\n", offsetof(block_precond_info, jacobi));\n'
+    src += '  printf("block_params.inner_maxcycles %zu\\n", offsetof(block_params, inner_maxcycles));\n'
+    src += '  printf("block_precond_info.inner_cycles %zu\\n", offsetof(block_precond_info, inner_cycles));\n'
     src += "  return 0;\n}\n"
     c = tmp_path / "probe.c"
     c.write_text(src)
@@ -88,6 +91,8 @@ def test_struct_layouts_match_c(tmp_path):
     assert int(got["gmres_result.relres_est"]) == _lib.gmres_result.relres_est.offset
     assert int(got["block_params.jacobi_sweeps"]) == _lib.block_params.jacobi_sweeps.offset
     assert int(got["block_precond_info.jacobi"]) == _lib.block_precond_info.jacobi.offset
+    assert int(got["block_params.inner_maxcycles"]) == _lib.block_params.inner_maxcycles.offset
+    assert int(got["block_precond_info.inner_cycles"]) == _lib.block_precond_info.inner_cycles.offset
 
 
 def test_product_path_has_no_cpu_fallback():

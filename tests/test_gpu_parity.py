@@ -474,6 +474,66 @@ def test_adaptive_rejects_other_kinds(ctx):
 
 
 # ---------------------------------------------------------------------------
+# inner solves to a tolerance (option #3 for the inverses Section 4 names)
+# ---------------------------------------------------------------------------
+def _oracle_inner_cycles(M_o, G):
+    out = []
+    for r in range(G + 3):
+        key = _role_key(r, G) if r < G + 2 else "c"
+        inv = M_o.inv.get(key)
+        out.append(getattr(inv, "last_cycles", -1) if key in M_o.tolerance_roles() else -1)
+    return out
+
+
+@pytest.mark.parametrize("kind", ["pctl", "schur1", "schur2"])
+@pytest.mark.parametrize("mode", ["seq", "batched", "fp32_batched", "adaptive_jacobi_I"])
+def test_inner_tolerance_parity(ctx, kind, mode):
+    api = gpu_modules()
+    extra = ADAPTIVE_CASES["jacobi_I"] if mode == "adaptive_jacobi_I" else {}
+    inp = si.generate(3, 2, 16, 43, **extra)
+    osys = oracle_system(inp)
+    adaptive = mode.startswith("adaptive")
+    M_o = opc.BlockPreconditioner(osys, opc.BlockParams(kind=kind, inner_tol=1e-2,
+                                                        adaptive=adaptive,
+                                                        amg=oamg.AMGParams(seed=5)))
+    co, gsys = gpu_system(ctx, inp)
+    fp32 = mode.startswith("fp32")
+    M_g = api.BlockPreconditioner(ctx, gsys, kind, amg_seed=5, inner_tol=1e-2,
+                                  adaptive=int(adaptive), batched=int(mode != "seq"),
+                                  use_graph=1, amg_precision=int(fp32))
+    G = inp.G
+    for seed in (4, 5):
+        r = np.random.default_rng(seed).standard_normal(osys.n)
+        z = to_host(M_g.apply(to_dev(ctx, r)))
+        ref = M_o(r)
+        assert rel(z, ref) < (5e-5 if fp32 else 1e-10), rel(z, ref)
+        got = M_g.info()["inner_cycles"]
+        want = _oracle_inner_cycles(M_o, G)
+        if adaptive:
+            want[G + 1] = -1          # the I block uses Jacobi (option #1)
+        if fp32:
+            assert all(abs(a - b) <= 1 for a, b in zip(got, want)), (got, want)
+        else:
+            assert got == want, (got, want)
+        assert max(got) >= 2
+
+
+def test_inner_tolerance_fgmres(ctx):
+    api = gpu_modules()
+    inp = si.generate(3, 2, 24, 61)
+    osys = oracle_system(inp)
+    M_o = opc.BlockPreconditioner(osys, opc.BlockParams(kind="schur2", inner_tol=1e-2,
+                                                        amg=oamg.AMGParams(seed=6)))
+    xo, io = okry.gmres(osys.matvec, M_o, inp.b, rtol=1e-8)
+    co, gsys = gpu_system(ctx, inp)
+    M_g = api.BlockPreconditioner(ctx, gsys, "schur2", amg_seed=6, inner_tol=1e-2, batched=1)
+    x, res = api.gmres(ctx, gsys, M_g, to_dev(ctx, inp.b), rtol=1e-8, flexible=1)
+    assert res.converged and abs(res.iters - io.iters) <= 1, (res.iters, io.iters)
+    bn = np.linalg.norm(inp.b)
+    assert np.linalg.norm(inp.b - osys.matvec(to_host(x))) <= 1e-8 * bn * (1 + 1e-6)
+
+
+# ---------------------------------------------------------------------------
 # GMRES
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ["amg", "schur2", "schur1", "pctl"])
