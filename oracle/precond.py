@@ -54,6 +54,7 @@ class BlockParams:
     pctl_p_maxcycles: int = 100
     inner_tol: float = 0.0             # > 0: option #3 for the inverses the paper's runs solve to a tolerance
     inner_maxcycles: int = 100
+    option4_steps: int = 0             # > 0: option #4 for S_I (Schur2) / C_E (Schur1)
     adaptive: bool = False             # Section 3.5 strategy + options #1/#2
     theta_wc: float = 1e-2             # Definition 1
     sigma_wc: float = 0.5
@@ -205,6 +206,13 @@ class BlockPreconditioner:
             self.sys = sys
         else:
             mats = hatted(sys, self.kind)
+        if params.option4_steps > 0:
+            if self.kind not in ("schur1", "schur2"):
+                raise ValueError("option #4 applies to schur1 (C_E) and schur2 (S_I)")
+            # the iteration works on the original blocks, not on the hat
+            mats = dict(mats)
+            mats["I" if self.kind == "schur2" else "E"] = sys.blocks[
+                G + 1 if self.kind == "schur2" else G]
         self.mats = mats
         for key, M in mats.items():
             self.inv[key] = fac(M, key)
@@ -212,6 +220,10 @@ class BlockPreconditioner:
             self._pctl_setup(fac)
         if params.adaptive:
             # second level: option #1 where the matrix is strongly diagonally dominant
+            if params.option4_steps > 0:
+                key4 = "I" if self.kind == "schur2" else "E"
+                wd = dict(wd)
+                wd[key4] = adp.weak_dominance_count(mats[key4], params.theta_wd)
             self.setup_info["wd_counts"] = wd
             for key, M in mats.items():
                 if wd[key] == 0:
@@ -219,6 +231,8 @@ class BlockPreconditioner:
                     sweeps = params.jacobi_sweeps
                     self.inv[key] = Inverse(M, lambda b, M=M, k=sweeps: adp.jacobi(M, b, k),
                                             self.counters)
+        if params.option4_steps > 0:
+            self._option4_setup()
 
     # -- scalar inverse construction -----------------------------------------
     def tolerance_roles(self):
@@ -229,8 +243,11 @@ class BlockPreconditioner:
         fixed number of V-cycles."""
         G = self.G
         groups = {("g", g) for g in range(G)}
-        return {"schur1": groups | {"E"}, "schur2": groups | {"I"},
-                "schur2_lower": groups | {"I"}, "pctl": groups | {"E", "I"}}.get(self.kind, set())
+        roles = {"schur1": groups | {"E"}, "schur2": groups | {"I"},
+                 "schur2_lower": groups | {"I"}, "pctl": groups | {"E", "I"}}.get(self.kind, set())
+        if self.params.option4_steps > 0:
+            roles = roles - {"I" if self.kind == "schur2" else "E"}
+        return roles
 
     def _amg_factory(self, M, key):
         """key: ('g', g), 'E', 'I', 'c' (PCTL coarse) or 'mono'."""
@@ -239,7 +256,9 @@ class BlockPreconditioner:
                "I": self.params.cycles_I, "c": self.params.cycles_E,
                "mono": 1}[role]
         inv = amg_inverse(M, self.params.amg, cyc, self.counters)
-        if self.params.inner_tol > 0 and key in self.tolerance_roles():
+        if self.params.inner_tol > 0 and key in self.tolerance_roles() and not (
+                self.params.option4_steps > 0
+                and key == ("I" if self.kind == "schur2" else "E")):
             H, tol, maxc = inv.hierarchy, self.params.inner_tol, self.params.inner_maxcycles
             inv.last_cycles = 0
 
@@ -249,6 +268,27 @@ class BlockPreconditioner:
                 return z
             inv._fn = fn
         return inv
+
+    def _option4_setup(self):
+        """Option #4 of Section 3.4: the exact Schur complement's inverse by a
+        fixed number of steps from zero,
+            Schur2: w <- A_I^{-1}(q + D_IE A_E^{-1}(D_EI w))   (S_I)
+            Schur1: w <- A_E^{-1}(q + D_EI A_I^{-1}(D_IE w))   (C_E)
+        with the blocks' own inverses inside (the first step is A^{-1} q)."""
+        sys = self.sys
+        k = self.params.option4_steps
+        if self.kind == "schur2":
+            outer, inner, d_out, d_in, key = self.inv["I"], self.inv["E"], sys.d_IE, sys.d_EI, "I"
+        else:
+            outer, inner, d_out, d_in, key = self.inv["E"], self.inv["I"], sys.d_EI, sys.d_IE, "E"
+
+        def fn(q):
+            w = outer(q)
+            for _ in range(k - 1):
+                w = outer(q + d_out * inner(d_in * w))
+            return w
+        self.inv[key + "4"] = Inverse(outer.M, fn, Counters())
+        self.option4_key = key
 
     def _pctl_setup(self, fac):
         G, N = self.G, self.N
@@ -307,6 +347,7 @@ class BlockPreconditioner:
             W[G + 1] = W[G + 1] + self.pI * wc
         elif self.kind == "schur1":
             plan = self.plan
+            CE = inv["E4"] if "E4" in inv else inv["E"]
             wI = inv["I"](B[G + 1])
             if plan is not None and bool(np.all(plan.gE)):
                 # groups independent of E: one C^_E inverse after them
@@ -315,9 +356,9 @@ class BlockPreconditioner:
                 s = np.zeros(N)
                 for g in range(G):
                     s = s + sys.d_Eg[g] * W[g]
-                W[G] = inv["E"]((B[G] - sys.d_EI * wI) - s)
+                W[G] = CE((B[G] - sys.d_EI * wI) - s)
             else:
-                wE = inv["E"](B[G] - sys.d_EI * wI)
+                wE = CE(B[G] - sys.d_EI * wI)
                 for g in range(G):
                     W[g] = inv[("g", g)](B[g] - sys.d_gE[g] * wE)
                 if plan is not None and bool(np.all(plan.Eg)):
@@ -326,18 +367,19 @@ class BlockPreconditioner:
                     s = np.zeros(N)
                     for g in range(G):
                         s = s + sys.d_Eg[g] * W[g]
-                    W[G] = wE - inv["E"](s)
+                    W[G] = wE - CE(s)
             if plan is not None and plan.IE:
                 W[G + 1] = wI
             else:
                 W[G + 1] = wI - inv["I"](sys.d_IE * W[G])
         elif self.kind in ("schur2", "schur2_lower"):
             plan = self.plan
+            SI = inv["I4"] if "I4" in inv else inv["I"]
             if plan is not None and plan.all_from_E_weak:
                 # every row block independent of E: block lower triangular
                 for g in range(G):
                     W[g] = inv[("g", g)](B[g])
-                W[G + 1] = inv["I"](B[G + 1])
+                W[G + 1] = SI(B[G + 1])
                 s = np.zeros(N)
                 for g in range(G):
                     s = s + sys.d_Eg[g] * W[g]
@@ -347,7 +389,7 @@ class BlockPreconditioner:
             wE = inv["E"](B[G])
             for g in range(G):
                 W[g] = inv[("g", g)](B[g] - sys.d_gE[g] * wE)
-            W[G + 1] = inv["I"](B[G + 1] - sys.d_IE * wE)
+            W[G + 1] = SI(B[G + 1] - sys.d_IE * wE)
             if self.kind == "schur2" and not (plan is not None and plan.all_into_E_rows_weak):
                 s = np.zeros(N)
                 for g in range(G):
