@@ -103,6 +103,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--no-inner", action="store_true")
+    ap.add_argument("--no-option4", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate layouts of every level once and keep the fastest "
                          "(cached per process, or in MGD_AUTOTUNE_CACHE)")
@@ -132,13 +133,14 @@ def main():
     b = torch.as_tensor(inp.b, device=ctx.device)
     bnorm = float(torch.linalg.vector_norm(b))
 
-    def build(batched, fp32, graph, adaptive=False, inner_tol=0.0):
+    def build(batched, fp32, graph, adaptive=False, inner_tol=0.0, option4=0):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         M = api.BlockPreconditioner(ctx, sysg, "schur2", amg_seed=w.seed,
                                     amg_precision=1 if fp32 else 0, batched=int(batched),
                                     use_graph=int(graph), adaptive=int(adaptive),
-                                    inner_tol=inner_tol, amg_autotune=int(a.autotune))
+                                    inner_tol=inner_tol, option4_steps=option4,
+                                    amg_autotune=int(a.autotune))
         torch.cuda.synchronize()
         return M, time.perf_counter() - t0
 
@@ -213,6 +215,28 @@ def main():
             f"relres {relres_a:.2e}, neglected {alpha['neglected']}, "
             f"jacobi roles {alpha['jacobi_roles']}")
         del Ma, xa
+
+    # option #4: S_I by two fixed-point steps on A_I and A_E instead of the hat
+    opt4 = None
+    if not a.no_option4:
+        M4, setup_4 = build(True, True, True, option4=2)
+        solve(M4)
+        torch.cuda.synchronize()
+        e40, e41 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e40.record()
+        iters_4 = []
+        for _ in range(a.steps):
+            x4, r4 = solve(M4)
+            iters_4.append(r4.iters)
+        e41.record()
+        torch.cuda.synchronize()
+        ms_4 = e40.elapsed_time(e41) / a.steps
+        relres_4 = float(torch.linalg.vector_norm(b - sysg.matvec(x4))) / bnorm
+        opt4 = {"s": ms_4 / 1e3, "iters": iters_4, "relres": relres_4, "setup_s": setup_4,
+                "steps": 2}
+        log(f"[bench] schur2 option #4 (2 steps) fp32 batched: {ms_4:.1f} ms/solve, "
+            f"iters {iters_4}, relres {relres_4:.2e}")
+        del M4, x4
 
     # the inner solves of Section 4: S^_g and S^_I to a relative tolerance 1e-2
     inner = None
@@ -300,6 +324,7 @@ def main():
         "speedup_vs_plain_fp64": (plain["s"] / (ms_step / 1e3)) if plain else None,
         "alpha_schur2_fp32": alpha,
         "schur2_inner_tol_1e-2_fp32": inner,
+        "schur2_option4_fp32": opt4,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": recorded_traffic(dom), "traffic_unit": "bytes per launch",

@@ -247,6 +247,12 @@ mgd_status mgd_block_system_free(mgd_ctx* ctx, mgd_block_system* s);
  * each member stops on its own criterion.  The preconditioner is then
  * nonlinear (use flexible GMRES) and every apply synchronises once per inner
  * cycle, so use_graph is ignored.
+ *
+ * option4_steps > 0 (SCHUR2, SCHUR1; option #4 of Section 3.4) replaces the
+ * hatted S^_I^{-1} of Schur2 (C^_E^{-1} of Schur1) by that many steps from
+ * zero of w <- A_I^{-1}(q + D_IE A_E^{-1}(D_EI w))  (Schur1: E and I
+ * exchanged), with the original blocks' inverses inside; the I hierarchy of
+ * Schur2 (E hierarchy of Schur1) is then built on the original block.
  * ------------------------------------------------------------------------- */
 enum {
   MGD_PC_AMG_MONO = 0,
@@ -274,6 +280,7 @@ typedef struct block_params {
   int32_t jacobi_sweeps;                  /* 2, option #1 */
   double inner_tol;                       /* 0 = fixed cycles (option #2); 1e-2 in Section 4 */
   int32_t inner_maxcycles;                /* 100 */
+  int32_t option4_steps;                  /* 0 = hatted inverse; > 0 option #4 */
 } block_params;
 void block_params_default(block_params* p);
 

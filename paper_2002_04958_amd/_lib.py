@@ -54,7 +54,7 @@ class block_params(Structure):
                 ("pctl_p_maxcycles", c_int32), ("batched", c_int32), ("use_graph", c_int32),
                 ("transpose", c_int32), ("adaptive", c_int32), ("theta_wc", c_double),
                 ("sigma_wc", c_double), ("theta_wd", c_double), ("jacobi_sweeps", c_int32),
-                ("inner_tol", c_double), ("inner_maxcycles", c_int32)]
+                ("inner_tol", c_double), ("inner_maxcycles", c_int32), ("option4_steps", c_int32)]
 
 
 class block_precond_info(Structure):

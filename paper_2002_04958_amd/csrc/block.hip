@@ -162,6 +162,20 @@ __global__ void k_wd_count(int n, const int* __restrict__ rp, const int* __restr
   const unsigned long long m = __ballot(hit);
   if ((threadIdx.x & 63) == 0 && m) atomicAdd(cnt, (int)__popcll(m));
 }
+// out = (T)(coef o w)
+template <typename T>
+__global__ void k_coef_mul(int N, const double* __restrict__ coef, const T* __restrict__ w,
+                           T* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) out[i] = (T)(coef[i] * (double)w[i]);
+}
+// out = (T)(q + coef o t); out may alias q
+template <typename T>
+__global__ void k_add_coef(int N, const T* q, const double* __restrict__ coef,
+                           const T* __restrict__ t, T* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) out[i] = (T)((double)q[i] + coef[i] * (double)t[i]);
+}
 // Sum over a 256-thread workgroup; result valid in thread 0.
 __device__ __forceinline__ double member_sum256(double v, double* lds /*[4]*/) {
 #pragma unroll
@@ -437,7 +451,9 @@ static int solve_to_tol(block_precond* bp, amg_hierarchy* h, const double* rhs, 
 
 // The inverses Section 4 solves to a relative tolerance: the hatted matrices
 // of the Schur preconditioners and PCTL's block relaxations.
-static bool tolerance_role(int kind, int role, int G) {
+static bool tolerance_role(int kind, int role, int G, bool option4) {
+  if (option4 && ((kind == MGD_PC_SCHUR2 && role == G + 1) || (kind == MGD_PC_SCHUR1 && role == G)))
+    return false;  // option #4 iterates on the original block instead
   if (role < G) return kind == MGD_PC_SCHUR1 || kind == MGD_PC_SCHUR2 ||
                        kind == MGD_PC_SCHUR2_LOWER || kind == MGD_PC_PCTL;
   if (role == G) return kind == MGD_PC_SCHUR1 || kind == MGD_PC_PCTL;
@@ -537,6 +553,7 @@ static void build_exec(block_precond* bp, std::unique_ptr<PcExec<T>>& X) {
   std::vector<int> singles;
   if (kind == MGD_PC_AMG_MONO) singles = {0};
   if (kind == MGD_PC_SCHUR2 || kind == MGD_PC_SCHUR2_LOWER) singles = {G};
+  if (kind == MGD_PC_SCHUR2 && bp->prm.option4_steps > 0) singles = {G, G + 1};
   if (kind == MGD_PC_PCTL) singles = {G, G + 2};
   if (kind == MGD_PC_SCHUR1) singles = {G, G + 1};
   X->jac_one.resize(G + 3);
@@ -561,6 +578,12 @@ static void build_exec(block_precond* bp, std::unique_ptr<PcExec<T>>& X) {
   X->b_out.alloc(c, n1);
   X->s.alloc(c, n1);
   if (kind == MGD_PC_PCTL) X->res.alloc(c, (size_t)(G + 2) * N);
+  if (bp->prm.option4_steps > 0) {
+    X->o4_w.alloc(c, n1);
+    X->o4_s.alloc(c, n1);
+    X->o4_t.alloc(c, n1);
+    X->o4_u.alloc(c, n1);
+  }
   if (kind == MGD_PC_AMG_MONO) return;
   // group membership
   std::vector<SegIn> tin;
@@ -593,9 +616,11 @@ static void build_exec(block_precond* bp, std::unique_ptr<PcExec<T>>& X) {
       tin.push_back({g, gE(g)});
       tout.push_back({g, sum ? Eg(g) : nullptr});
     }
-    roles.push_back(G + 1);
-    tin.push_back({G + 1, IE});
-    tout.push_back({G + 1, sum ? EI : nullptr});
+    if (!(kind == MGD_PC_SCHUR2 && bp->prm.option4_steps > 0)) {  // else I by option #4
+      roles.push_back(G + 1);
+      tin.push_back({G + 1, IE});
+      tout.push_back({G + 1, sum ? EI : nullptr});
+    }
   }
   // V-cycle members first, Jacobi members (option #1) after them
   {
@@ -732,6 +757,35 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
     else
       U(role)->apply(c, in, out, bp->cycles[role]);
   };
+  // option #4 (Schur2: S_I, Schur1: C_E): w = A_o^{-1} q, then
+  // w <- A_o^{-1}(q + D_oi A_i^{-1}(D_io w)) for the remaining steps
+  const int steps4 = bp->prm.option4_steps;
+  int extra_inv = 0;
+  auto opt4 = [&](const T* q, T* w) {
+    const bool s2 = kind == MGD_PC_SCHUR2;
+    const int outer = s2 ? G + 1 : G, inner = s2 ? G : G + 1;
+    const double* d_out = s2 ? bp->d_IE.get() : bp->d_EI.get();
+    const double* d_in = s2 ? bp->d_EI.get() : bp->d_IE.get();
+    inv(outer, q, w);
+    for (int k = 1; k < steps4; ++k) {
+      hipLaunchKernelGGL(k_coef_mul<T>, g1, b1, 0, c->stream, N, d_in, (const T*)w, X.o4_s.get());
+      MGD_CHECK_LAUNCH();
+      inv(inner, X.o4_s.get(), X.o4_t.get());
+      hipLaunchKernelGGL(k_add_coef<T>, g1, b1, 0, c->stream, N, q, d_out,
+                         (const T*)X.o4_t.get(), X.o4_u.get());
+      MGD_CHECK_LAUNCH();
+      inv(outer, X.o4_u.get(), w);
+    }
+    extra_inv += 2 * steps4 - 2;
+  };
+  // the Schur complement inverse of the kind: option #4 when asked for
+  auto cinv = [&](int role, const T* in, T* out) {
+    if (steps4 > 0 && ((kind == MGD_PC_SCHUR2 && role == G + 1) ||
+                       (kind == MGD_PC_SCHUR1 && role == G)))
+      opt4(in, out);
+    else
+      inv(role, in, out);
+  };
   Group<T>& grp = X.grp;
   const int nm = (int)grp.roles.size();
   auto group_in = [&](const T* w) {
@@ -775,12 +829,32 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
     case MGD_PC_SCHUR2:
     case MGD_PC_SCHUR2_LOWER:
     case MGD_PC_PCTL: {
+      const bool i_apart = kind == MGD_PC_SCHUR2 && steps4 > 0;  // S_I by option #4
+      const double* dIE = (adaptive && bp->weak_IE) ? nullptr : bp->d_IE.get();
+      const double* dEI = (adaptive && bp->weak_EI) ? nullptr : bp->d_EI.get();
+      // w_I = S_I^{-1}(r_I - D_IE w) by option #4 (w null: r_I), into z; then
+      // sT += D_EI w_I when sT is given
+      auto i_step = [&](const T* w, T* sT) {
+        hipLaunchKernelGGL((k_single_in<T, T>), g1, b1, 0, c->stream, N, r + (size_t)(G + 1) * N,
+                           w ? dIE : (const double*)nullptr, w, X.b_out.get());
+        MGD_CHECK_LAUNCH();
+        cinv(G + 1, X.b_out.get(), X.o4_w.get());
+        hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.o4_w.get(),
+                           (const T*)nullptr, z + (size_t)(G + 1) * N);
+        MGD_CHECK_LAUNCH();
+        if (sT && dEI) {
+          hipLaunchKernelGGL(k_add_coef<T>, g1, b1, 0, c->stream, N, (const T*)sT, dEI,
+                             (const T*)X.o4_w.get(), sT);
+          MGD_CHECK_LAUNCH();
+        }
+      };
       if (adaptive && kind == MGD_PC_SCHUR2 && bp->from_E_weak) {
         // every row block independent of E (block lower triangular):
         // w_a = S^_a^{-1} r_a, then w_E = A_E^{-1}(r_E - sum_a D_Ea w_a)
         group_in(nullptr);
         run_group(bp, grp);
         group_out(true, X.b_in.get());
+        if (i_apart) i_step(nullptr, X.b_in.get());
         hipLaunchKernelGGL(k_lower_E_in<T>, g1, b1, 0, c->stream, N, r + (size_t)G * N,
                            (const double*)nullptr, (const T*)nullptr, (const T*)X.b_in.get(),
                            X.b_out.get());
@@ -789,7 +863,7 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
         hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.a_out.get(),
                            (const T*)nullptr, z + (size_t)G * N);
         MGD_CHECK_LAUNCH();
-        ninv = G + 2;
+        ninv = G + 2 + extra_inv;
         break;
       }
       // step 1: w_E* = A_E^{-1} r_E
@@ -803,6 +877,7 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
       if (kind == MGD_PC_SCHUR2 && e_coupled) {
         // step 3: w_E = w_E* - A_E^{-1}(sum_g D_Eg w_g + D_EI w_I)
         group_out(true, X.b_in.get());
+        if (i_apart) i_step(X.a_out.get(), X.b_in.get());
         inv(G, X.b_in.get(), X.b_out.get());
         hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.a_out.get(),
                            (const T*)X.b_out.get(), z + (size_t)G * N);
@@ -810,10 +885,12 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
         ninv += 1;
       } else {
         group_out(false, nullptr);
+        if (i_apart) i_step(X.a_out.get(), nullptr);
         hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.a_out.get(),
                            (const T*)nullptr, z + (size_t)G * N);
         MGD_CHECK_LAUNCH();
       }
+      ninv += extra_inv;
       if (kind == MGD_PC_PCTL && e_coupled) {
         // coarse-grid correction: A_c w_c = P^T (b - A w); w += P w_c
         block_matvec(c, bp->sys, z, r, X.res.get());
@@ -843,7 +920,7 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
         hipLaunchKernelGGL(k_lower_E_in<T>, g1, b1, 0, c->stream, N, r + (size_t)G * N, dEI,
                            (const T*)X.a_out.get(), (const T*)X.b_in.get(), X.b_out.get());
         MGD_CHECK_LAUNCH();
-        inv(G, X.b_out.get(), X.b_in.get());
+        cinv(G, X.b_out.get(), X.b_in.get());
         hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.b_in.get(),
                            (const T*)nullptr, z + (size_t)G * N);
         MGD_CHECK_LAUNCH();
@@ -853,7 +930,7 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
         hipLaunchKernelGGL((k_single_in<T, T>), g1, b1, 0, c->stream, N, r + (size_t)G * N, dEI,
                            (const T*)X.a_out.get(), X.b_in.get());
         MGD_CHECK_LAUNCH();
-        inv(G, X.b_in.get(), X.b_out.get());
+        cinv(G, X.b_in.get(), X.b_out.get());
         // 3. w_g = C^_g^{-1}(r_g - D_gE w_E*)
         group_in(X.b_out.get());
         run_group(bp, grp);
@@ -868,7 +945,7 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
           group_out(true, X.b_in.get());
           DBuf<T>& tmp = X.a_in;  // free after step 1 (FP32) / unused (FP64)
           if (tmp.n < nN) tmp.alloc(c, nN);
-          inv(G, X.b_in.get(), tmp.get());
+          cinv(G, X.b_in.get(), tmp.get());
           hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.b_out.get(),
                              (const T*)tmp.get(), z + (size_t)G * N);
           MGD_CHECK_LAUNCH();
@@ -891,6 +968,7 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
         MGD_CHECK_LAUNCH();
         ninv += 1;
       }
+      ninv += extra_inv;
       break;
     }
     default:
@@ -1184,7 +1262,8 @@ block_precond* block_precond_create_impl(Ctx* c, const mgd_block_system* A, cons
   bp->tol_role.assign(G + 3, 0);
   bp->inner_cycles.assign(G + 3, -1);
   if (p->inner_tol > 0)
-    for (int r = 0; r < G + 3; ++r) bp->tol_role[r] = tolerance_role(kind, r, G) ? 1 : 0;
+    for (int r = 0; r < G + 3; ++r)
+      bp->tol_role[r] = tolerance_role(kind, r, G, p->option4_steps > 0) ? 1 : 0;
   bp->jac_diag.resize(G + 3);
   if (p->adaptive) {
     MGD_REQUIRE(kind == MGD_PC_PCTL || kind == MGD_PC_SCHUR1 || kind == MGD_PC_SCHUR2,
@@ -1217,7 +1296,13 @@ block_precond* block_precond_create_impl(Ctx* c, const mgd_block_system* A, cons
         make_hierarchy(bp.get(), g,
                        hat(c, B[g], bp->d_gE.get() + (size_t)g * N, bp->d_Eg.get() + (size_t)g * N,
                            dCE.get()));
-      make_hierarchy(bp.get(), G, std::move(CE));
+      if (p->option4_steps > 0) {
+        Csr<double> AE;  // option #4 iterates with A_E itself (the hat only fixed C^_g)
+        csr_copy(c, B[G], AE);
+        make_hierarchy(bp.get(), G, std::move(AE));
+      } else {
+        make_hierarchy(bp.get(), G, std::move(CE));
+      }
       Csr<double> AI;
       csr_copy(c, B[G + 1], AI);
       make_hierarchy(bp.get(), G + 1, std::move(AI));
@@ -1229,7 +1314,13 @@ block_precond* block_precond_create_impl(Ctx* c, const mgd_block_system* A, cons
       Csr<double> AE;
       csr_copy(c, B[G], AE);
       make_hierarchy(bp.get(), G, std::move(AE));
-      make_hierarchy(bp.get(), G + 1, hat(c, B[G + 1], bp->d_IE.get(), bp->d_EI.get(), dE.get()));
+      if (p->option4_steps > 0) {
+        Csr<double> AI;  // option #4 iterates with A_I itself
+        csr_copy(c, B[G + 1], AI);
+        make_hierarchy(bp.get(), G + 1, std::move(AI));
+      } else {
+        make_hierarchy(bp.get(), G + 1, hat(c, B[G + 1], bp->d_IE.get(), bp->d_EI.get(), dE.get()));
+      }
     }
     if (kind == MGD_PC_PCTL) {
       // all blocks must share A_E's pattern for eq. 3.1

@@ -614,6 +614,7 @@ void block_params_default(block_params* p) {
   p->jacobi_sweeps = 2;
   p->inner_tol = 0.0;
   p->inner_maxcycles = 100;
+  p->option4_steps = 0;
 }
 
 mgd_status block_precond_create(mgd_ctx* ctx, const mgd_block_system* A, const block_params* p,
@@ -628,6 +629,10 @@ mgd_status block_precond_create(mgd_ctx* ctx, const mgd_block_system* A, const b
     MGD_REQUIRE(p->inner_tol >= 0 && p->inner_tol < 1, "inner_tol must be in [0, 1)");
     MGD_REQUIRE(p->inner_maxcycles >= 1 && p->inner_maxcycles <= 1000,
                 "inner_maxcycles must be in [1, 1000]");
+    MGD_REQUIRE(p->option4_steps >= 0 && p->option4_steps <= 100,
+                "option4_steps must be in [0, 100]");
+    MGD_REQUIRE(p->option4_steps == 0 || p->kind == MGD_PC_SCHUR1 || p->kind == MGD_PC_SCHUR2,
+                "option #4 applies to SCHUR1 (C_E) and SCHUR2 (S_I)");
     if (p->adaptive) {
       MGD_REQUIRE(p->kind == MGD_PC_PCTL || p->kind == MGD_PC_SCHUR1 || p->kind == MGD_PC_SCHUR2,
                   "the adaptive strategy applies to PCTL, SCHUR1 and SCHUR2");

@@ -93,6 +93,7 @@ struct PcExec {
   std::vector<DBuf<JacMember>> jac_one;  // per role, for single Jacobi inverses
   DBuf<T> jac_tmp1;
   std::vector<std::unique_ptr<TolSolve<T>>> tol_one;  // per role, single option #3 inverses
+  DBuf<T> o4_w, o4_s, o4_t, o4_u;  // option #4 iterate and work vectors
 };
 
 }  // namespace mgd

@@ -57,7 +57,7 @@ def test_host_defaults_follow_the_paper(lib):
     assert b.kind == _lib.PC_KINDS["schur2"] and b.pctl_p_tol == 1e-2
     assert b.adaptive == 0 and b.theta_wc == 1e-2 and b.sigma_wc == 0.5
     assert b.theta_wd == 0.9 and b.jacobi_sweeps == 2
-    assert b.inner_tol == 0.0 and b.inner_maxcycles == 100
+    assert b.inner_tol == 0.0 and b.inner_maxcycles == 100 and b.option4_steps == 0
     assert lib.mgd_kernel_class_count() >= 8
     assert lib.mgd_kernel_class_name(0) == b"spmv"
     assert b"gfx950" in lib.mgd_version()
@@ -76,6 +76,7 @@ def test_struct_layouts_match_c(tmp_path):
     src += '  printf("block_params.jacobi_sweeps %zu\\n", offsetof(block_params, jacobi_sweeps));\n'
     src += '  printf("block_precond_info.jacobi %zu\\n", offsetof(block_precond_info, jacobi));\n'
     src += '  printf("block_params.inner_maxcycles %zu\\n", offsetof(block_params, inner_maxcycles));\n'
+    src += '  printf("block_params.option4_steps %zu\\n", offsetof(block_params, option4_steps));\n'
     src += '  printf("block_precond_info.inner_cycles %zu\\n", offsetof(block_precond_info, inner_cycles));\n'
     src += "  return 0;\n}\n"
     c = tmp_path / "probe.c"
@@ -92,6 +93,7 @@ def test_struct_layouts_match_c(tmp_path):
     assert int(got["block_params.jacobi_sweeps"]) == _lib.block_params.jacobi_sweeps.offset
     assert int(got["block_precond_info.jacobi"]) == _lib.block_precond_info.jacobi.offset
     assert int(got["block_params.inner_maxcycles"]) == _lib.block_params.inner_maxcycles.offset
+    assert int(got["block_params.option4_steps"]) == _lib.block_params.option4_steps.offset
     assert int(got["block_precond_info.inner_cycles"]) == _lib.block_precond_info.inner_cycles.offset
 
 

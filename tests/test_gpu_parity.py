@@ -534,6 +534,62 @@ def test_inner_tolerance_fgmres(ctx):
 
 
 # ---------------------------------------------------------------------------
+# option #4: S_I (Schur2) / C_E (Schur1) by fixed-point steps
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", ["schur1", "schur2"])
+@pytest.mark.parametrize("mode", ["seq", "batched_graph", "fp32_batched_graph", "adaptive_from_E",
+                                  "inner_tol"])
+def test_option4_parity(ctx, kind, mode):
+    import torch
+    api = gpu_modules()
+    adaptive = mode == "adaptive_from_E"
+    inp = si.generate(3, 2, 16, 47, **(ADAPTIVE_CASES["from_E"] if adaptive else {}))
+    osys = oracle_system(inp)
+    tol = 1e-2 if mode == "inner_tol" else 0.0
+    M_o = opc.BlockPreconditioner(osys, opc.BlockParams(kind=kind, option4_steps=3,
+                                                        adaptive=adaptive, inner_tol=tol,
+                                                        amg=oamg.AMGParams(seed=5)))
+    co, gsys = gpu_system(ctx, inp)
+    fp32 = mode.startswith("fp32")
+    M_g = api.BlockPreconditioner(ctx, gsys, kind, amg_seed=5, option4_steps=3,
+                                  adaptive=int(adaptive), inner_tol=tol,
+                                  batched=int(mode != "seq"), use_graph=int("graph" in mode),
+                                  amg_precision=int(fp32))
+    if adaptive:
+        assert_same_decisions(M_g.info(), M_o, inp.G)
+    tol_z = 5e-5 if fp32 else 1e-10
+    r = np.random.default_rng(4).standard_normal(osys.n)
+    rd = to_dev(ctx, r)
+    z = to_host(M_g.apply(rd))
+    c0 = M_o.counters.inverses
+    ref = M_o(r)
+    assert rel(z, ref) < tol_z, rel(z, ref)
+    assert M_g.info()["inverses_per_apply"] == M_o.counters.inverses - c0
+    zb = torch.empty_like(rd)
+    for _ in range(2):
+        M_g.apply(rd, zb)
+        assert np.array_equal(to_host(zb), z)
+        torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("kind", ["schur1", "schur2"])
+def test_option4_fgmres(ctx, kind):
+    api = gpu_modules()
+    inp = si.generate(3, 2, 24, 61)
+    osys = oracle_system(inp)
+    M_o = opc.BlockPreconditioner(osys, opc.BlockParams(kind=kind, option4_steps=2,
+                                                        amg=oamg.AMGParams(seed=6)))
+    xo, io = okry.gmres(osys.matvec, M_o, inp.b, rtol=1e-8)
+    co, gsys = gpu_system(ctx, inp)
+    M_g = api.BlockPreconditioner(ctx, gsys, kind, amg_seed=6, option4_steps=2, batched=1,
+                                  use_graph=1)
+    x, res = api.gmres(ctx, gsys, M_g, to_dev(ctx, inp.b), rtol=1e-8, flexible=1)
+    assert res.converged and abs(res.iters - io.iters) <= 1, (res.iters, io.iters)
+    bn = np.linalg.norm(inp.b)
+    assert np.linalg.norm(inp.b - osys.matvec(to_host(x))) <= 1e-8 * bn * (1 + 1e-6)
+
+
+# ---------------------------------------------------------------------------
 # GMRES
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ["amg", "schur2", "schur1", "pctl"])
