@@ -32,17 +32,19 @@ void dot_dev(Ctx* c, RedWork& w, const double* x, const double* y, size_t n, dou
 // classical Gram-Schmidt with selective reorthogonalisation (J < 32):
 //   mdot_dev:        h[i] = V_i . w (i < J), h[J] = w . w
 //   update_mdot_dev: w -= sum h_i V_i; h2[i] = V_i . w_new, h2[J] = w_new . w_new
-//   update_norm_dev: only if h2[J] < h1[J] / 2: w -= sum h2_i V_i; nrm2[0] = w_new . w_new
-//   arnoldi_finish:  hcol[0..J-1] = h1 (+ h2 if the second pass ran), hcol[J] = the
-//                    norm, hcol[J+1] = 1 if the second pass ran; v_next = w / hcol[J]
+//   orth_finish_dev: hcol[0..J-1] = h1 (+ h2 when h2[J] < h1[J] / 2, the second
+//                    projection then applied: w -= sum h2_i V_i), hcol[J] = the
+//                    scale (the norm, by Pythagoras after the second projection),
+//                    hcol[J+1] = 1 if it ran; w /= hcol[J] in place, and
+//                    hcol[J+2] = the exact squared norm of w before the scaling
 void mdot_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* wv, size_t n,
               double* h);
 void update_mdot_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* h,
                      double* wv, size_t n, double* h2);
-void update_norm_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* h1,
-                     const double* h2, double* wv, size_t n, double* nrm2);
-void arnoldi_finish(Ctx* c, const double* h1, const double* h2, const double* nrm2, int J,
-                    double* hcol, double* v_next, const double* w, size_t n);
+void orth_finish_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* h1,
+                     const double* h2, double* hcol, double* wv, size_t n);
+// v *= a
+void scale_dev(Ctx* c, double a, double* v, size_t n);
 // x += sum_i y_i Z_i (y on device)
 void combine_dev(Ctx* c, const double* Z, size_t ldz, int K, const double* y, double* x, size_t n);
 // y = b - y (in place, residual from a matvec result)

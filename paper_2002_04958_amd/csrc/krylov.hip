@@ -54,8 +54,7 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
   DBuf<double> hd(c, 200);
   double* h1 = hd.get();
   double* h2 = hd.get() + 40;
-  double* hc = hd.get() + 80;       // [0..J]: column, then nrm2 at 120
-  double* nrm2 = hd.get() + 120;
+  double* hc = hd.get() + 80;       // [0..J+2]: column, reorth flag, exact squared norm
   double* yd = hd.get() + 130;      // y (<= 31)
   double* bn = hd.get() + 125;
   RedWork rw;
@@ -113,16 +112,27 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
       if (evo) MGD_HIP(hipEventRecord(evo->a, c->stream));
       mdot_dev(c, rw, V.get(), n, J, w, n, h1);
       update_mdot_dev(c, rw, V.get(), n, J, h1, w, n, h2);
-      update_norm_dev(c, rw, V.get(), n, J, h1, h2, w, n, nrm2);
-      arnoldi_finish(c, h1, h2, nrm2, J, hc, w, w, n);
+      orth_finish_dev(c, rw, V.get(), n, J, h1, h2, hc, w, n);
       if (evo) MGD_HIP(hipEventRecord(evo->b, c->stream));
-      MGD_HIP(hipMemcpyAsync(hbuf, hc, (J + 2) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      MGD_HIP(hipMemcpyAsync(hbuf, hc, (J + 3) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
       c->sync();
       if (evp && M) res.t_precond_ms += evp->ms();
       if (evm) res.t_matvec_ms += evm->ms();
       if (evo) res.t_orth_ms += evo->ms();
       for (int i = 0; i <= J; ++i) Hij(i, j) = hbuf[i];
-      if (hbuf[J + 1] != 0.0) res.reorths++;
+      if (hbuf[J + 1] != 0.0) {
+        res.reorths++;
+        // The new basis vector is w''/s with s = hbuf[J] from Pythagoras, and
+        // H(J, j) = s keeps the Arnoldi relation exact.  Where s is off the
+        // exact norm (a severe cancellation, or the fallback s = 1), rescale
+        // the vector to unit length and record the exact norm instead.
+        const double ex = std::sqrt(hbuf[J + 2]);
+        const double s = hbuf[J];
+        if (!(std::fabs(ex - s) <= 1e-6 * ex)) {
+          if (ex > 0.0) scale_dev(c, s / ex, w, n);
+          Hij(J, j) = ex;
+        }
+      }
       breakdown = Hij(j + 1, j) == 0.0;
       for (int i = 0; i < j; ++i) {
         const double tt = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);

@@ -202,19 +202,6 @@ __global__ void __launch_bounds__(256) k_red_final(const double* __restrict__ pa
   if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
-// k_red_final for the reorthogonalisation pass: skipped with it
-__global__ void __launch_bounds__(256) k_red_final_if(const double* __restrict__ partial, int nb,
-                                                      const double* __restrict__ h1,
-                                                      const double* __restrict__ h2, int J,
-                                                      double* __restrict__ out) {
-  __shared__ double lds[4];
-  if (!(h2[J] < 0.5 * h1[J])) return;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nb; b += 256) s += partial[b];
-  s = block_sum256(s, lds);
-  if (threadIdx.x == 0) out[0] = s;
-}
-
 __global__ void __launch_bounds__(256) k_dot(const double* __restrict__ x,
                                              const double* __restrict__ y, size_t n,
                                              double* __restrict__ partial) {
@@ -243,8 +230,8 @@ constexpr int kMaxJ = 32;
 // reorthogonalisation, Daniel-Gragg-Kaufman-Stewart criterion eta = 1/sqrt 2):
 // mode 0: h[j] = V_j . w,                            h[J] = w . w
 // mode 1: w -= sum h_in[j] V_j;  h[j] = V_j . w_new, h[J] = w_new . w_new
-// mode 2: only when h2[J] < h1[J] / 2 (the first projection lost more than
-//         half the norm): w -= sum h2[j] V_j;        h[0] = w_new . w_new
+// (the third pass, k_orth_finish, applies the second projection when needed
+// and normalises in the same sweep)
 template <int MODE, int JB>
 __global__ void __launch_bounds__(256) k_mdot(const double* __restrict__ V, size_t ldv, int J,
                                               const double* __restrict__ h_in,
@@ -252,7 +239,7 @@ __global__ void __launch_bounds__(256) k_mdot(const double* __restrict__ V, size
                                               double* __restrict__ w, size_t n,
                                               double* __restrict__ partial, int nb) {
   __shared__ double lds[4];
-  if (MODE == 2 && !(h_in[J] < 0.5 * h_first[J])) return;  // no reorthogonalisation needed
+  (void)h_first;
   double acc[JB + 1];
   double hv[JB];
 #pragma unroll
@@ -279,18 +266,11 @@ __global__ void __launch_bounds__(256) k_mdot(const double* __restrict__ V, size
       for (int j = 0; j < JB; ++j)
         if (j < J) wi -= hv[j] * vj[j];
       w[i] = wi;
-      if (MODE == 1) {
 #pragma unroll
-        for (int j = 0; j < JB; ++j)
-          if (j < J) acc[j] += vj[j] * wi;
-      }
+      for (int j = 0; j < JB; ++j)
+        if (j < J) acc[j] += vj[j] * wi;
       nacc += wi * wi;
     }
-  }
-  if (MODE == 2) {
-    double s = block_sum256(nacc, lds);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
-    return;
   }
 #pragma unroll
   for (int j = 0; j < JB; ++j) {
@@ -362,49 +342,96 @@ void update_mdot_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, con
   MGD_CHECK_LAUNCH();
 }
 
-void update_norm_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* h1,
-                     const double* h2, double* wv, size_t n, double* nrm2) {
-  MGD_REQUIRE(J >= 1 && J < kMaxJ, "mdot: J out of range");
-  w.ensure(c);
-  ProfScope ps(c, KC_ORTH, 8.0 * n * (J + 2), ksym(c, "k_mdot", {"2", std::to_string(mdot_jb(J))}));
-  int g = red_grid(n);
-  MdotArgs a{V, ldv, J, h2, h1, wv, n, w.partial.get(), g};
-  launch_mdot<2>(c, a);
-  MGD_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_red_final_if, dim3(1), dim3(256), 0, c->stream,
-                     (const double*)w.partial.get(), g, h1, h2, J, nrm2);
-  MGD_CHECK_LAUNCH();
-}
-
-// Arnoldi column: h = h1 (+ h2 when reorthogonalised), h[J] = the new norm;
-// hcol[J+1] = 1 when the second pass ran.
-__global__ void k_arnoldi_finish_h(const double* __restrict__ h1, const double* __restrict__ h2,
-                                   const double* __restrict__ nrm2, int J,
-                                   double* __restrict__ hcol) {
+// Third pass of one Arnoldi step.  k_arnoldi_col forms the Hessenberg column
+// from the two projections: reorthogonalise when h2[J] < h1[J] / 2 (the first
+// projection removed more than half of the squared norm); then the column is
+// h1 + h2, and the new norm comes from Pythagoras, ||w''||^2 = ||w'||^2 -
+// sum h2[j]^2 (the second projection's coefficients are tiny, so this loses
+// nothing), else the column is h1 with norm ||w'||.  hcol[J] is the scale used
+// (1 when the difference is not positive), hcol[J+1] = 1 when reorthogonalised.
+__global__ void k_arnoldi_col(const double* __restrict__ h1, const double* __restrict__ h2, int J,
+                              double* __restrict__ hcol) {
   const bool re = h2[J] < 0.5 * h1[J];
   const int j = threadIdx.x;
   if (j < J) hcol[j] = re ? h1[j] + h2[j] : h1[j];
   if (j == 0) {
-    hcol[J] = sqrt(re ? nrm2[0] : h2[J]);
+    double est = h2[J];
+    if (re)
+      for (int k = 0; k < J; ++k) est = est - h2[k] * h2[k];
+    hcol[J] = est > 0.0 ? sqrt(est) : 1.0;
     hcol[J + 1] = re ? 1.0 : 0.0;
   }
 }
-__global__ void k_scale_by_norm(const double* __restrict__ hcol, int J,
-                                const double* __restrict__ w, double* __restrict__ v, size_t n) {
+// v = (w' - [reorthogonalised] sum h2[j] V_j) / hcol[J] in place, and the
+// exact ||w''||^2 of the unscaled vector per block (the host compares it with
+// the scale and corrects the rare mismatch)
+template <int JB>
+__global__ void __launch_bounds__(256) k_orth_finish(const double* __restrict__ V, size_t ldv,
+                                                     int J, const double* __restrict__ h2,
+                                                     const double* __restrict__ hcol,
+                                                     double* __restrict__ w, size_t n,
+                                                     double* __restrict__ partial) {
+  __shared__ double lds[4];
+  const bool re = hcol[J + 1] != 0.0;  // uniform
   const double nr = hcol[J];
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x)
-    v[i] = nr > 0.0 ? w[i] / nr : 0.0;
+  double hv[JB];
+#pragma unroll
+  for (int j = 0; j < JB; ++j) hv[j] = (re && j < J) ? h2[j] : 0.0;
+  double nacc = 0.0;
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    double wi = w[i];
+    if (re) {
+      double vj[JB];
+#pragma unroll
+      for (int j = 0; j < JB; ++j)
+        if (j < J) vj[j] = V[j * ldv + i];
+#pragma unroll
+      for (int j = 0; j < JB; ++j)
+        if (j < J) wi -= hv[j] * vj[j];
+    }
+    nacc += wi * wi;
+    w[i] = wi / nr;
+  }
+  double s = block_sum256(nacc, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-void arnoldi_finish(Ctx* c, const double* h1, const double* h2, const double* nrm2, int J,
-                    double* hcol, double* v_next, const double* w, size_t n) {
-  hipLaunchKernelGGL(k_arnoldi_finish_h, dim3(1), dim3(64), 0, c->stream, h1, h2, nrm2, J, hcol);
+void orth_finish_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* h1,
+                     const double* h2, double* hcol, double* wv, size_t n) {
+  MGD_REQUIRE(J >= 1 && J < kMaxJ, "mdot: J out of range");
+  w.ensure(c);
+  hipLaunchKernelGGL(k_arnoldi_col, dim3(1), dim3(64), 0, c->stream, h1, h2, J, hcol);
   MGD_CHECK_LAUNCH();
-  ProfScope ps(c, KC_ORTH, 16.0 * n, ksym(c, "k_scale_by_norm", {}));
+  // algorithmic bytes of the reorthogonalised case (the usual one)
+  ProfScope ps(c, KC_ORTH, 8.0 * n * (J + 2), ksym(c, "k_orth_finish", {std::to_string(mdot_jb(J))}));
+  const int g = red_grid(n);
+#define MGD_ORTH(JB)                                                                      \
+  hipLaunchKernelGGL((k_orth_finish<JB>), dim3(g), dim3(256), 0, c->stream, V, ldv, J, h2, \
+                     (const double*)hcol, wv, n, w.partial.get())
+  if (J <= 4)
+    MGD_ORTH(4);
+  else if (J <= 8)
+    MGD_ORTH(8);
+  else if (J <= 16)
+    MGD_ORTH(16);
+  else
+    MGD_ORTH(32);
+#undef MGD_ORTH
+  MGD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_red_final, dim3(1), dim3(256), 0, c->stream, (const double*)w.partial.get(),
+                     g, hcol + J + 2);
+  MGD_CHECK_LAUNCH();
+}
+
+__global__ void k_scale_vec(double a, double* __restrict__ v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    v[i] = v[i] * a;
+}
+void scale_dev(Ctx* c, double a, double* v, size_t n) {
+  ProfScope ps(c, KC_ORTH, 16.0 * n, ksym(c, "k_scale_vec", {}));
   int g = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 8192);
-  hipLaunchKernelGGL(k_scale_by_norm, dim3(g), dim3(kBlock), 0, c->stream, (const double*)hcol, J,
-                     w, v_next, n);
+  hipLaunchKernelGGL(k_scale_vec, dim3(g), dim3(kBlock), 0, c->stream, a, v, n);
   MGD_CHECK_LAUNCH();
 }
 
