@@ -21,9 +21,9 @@ void cast_copy(Ctx* c, D* dst, const S* src, size_t n, int cls);
 
 // ---- deterministic reductions (fixed partition, fixed order) ---------------
 struct RedWork {
-  DBuf<double> partial;  // kRedBlocks * 33
+  DBuf<double> partial;  // kRedBlocks * 66
   void ensure(Ctx* c) {
-    if (!partial.p) partial.alloc(c, (size_t)kRedBlocks * 33);
+    if (!partial.p) partial.alloc(c, (size_t)kRedBlocks * 66);
   }
 };
 // out[0] = sum x_i y_i  (device scalar)
@@ -43,6 +43,19 @@ void update_mdot_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, con
                      double* wv, size_t n, double* h2);
 void orth_finish_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, const double* h1,
                      const double* h2, double* hcol, double* wv, size_t n);
+// One Arnoldi step of classical Gram-Schmidt with delayed reorthogonalisation
+// (two sweeps over the basis).  V_0..V_{F-1} are final; vj (or null) is the
+// previous step's vector, orthogonalised once and scaled, still to be
+// reorthogonalised; w = A z_j.  Writes coef (device, kDcgsCoef doubles):
+//   [0, 32) a = V_k . vj, [32, 64) h = the projection of w on the final basis
+//   (V_0..V_{F-1}, then the corrected vj when present), [64] beta, the norm
+//   of vj - sum a_k V_k by Pythagoras, [65] alpha, the norm of w - sum h_k v_k
+//   by Pythagoras (1 when not positive), [66] and [67] the exact squared norms
+//   of the corrected vj (after division by beta) and of w before its division
+//   by alpha.  vj <- (vj - sum a_k V_k) / beta in place; w <- (w - ...) / alpha.
+constexpr int kDcgsCoef = 68;
+void dcgs_step_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int F, double* vj,
+                   double* wv, size_t n, double* dots, double* coef);
 // v *= a
 void scale_dev(Ctx* c, double a, double* v, size_t n);
 // x += sum_i y_i Z_i (y on device)

@@ -64,7 +64,7 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
     evm.reset(new EvPair);
     evo.reset(new EvPair);
   }
-  double* hbuf = static_cast<double*>(c->host_stage(64 * sizeof(double)));
+  double* hbuf = static_cast<double*>(c->host_stage(128 * sizeof(double)));
 
   dot_dev(c, rw, b, b, n, bn);
   const double bnorm = std::sqrt(read1(c, bn));
@@ -87,12 +87,21 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
   }
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   auto Hij = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+  // Flexible GMRES with a preconditioner keeps the unrotated Hessenberg
+  // matrix: the delayed reorthogonalisation completes each column one step
+  // later, and the rotations are then recomputed.
+  const bool delayed = M && flex;
+  std::vector<double> Hunrot((size_t)(m + 1) * m);
+  auto Hu = [&](int i, int j) -> double& { return Hunrot[(size_t)i * m + j]; };
+  DBuf<double> dd(c, 80), dcoef(c, kDcgsCoef);
   while (res.iters < p.max_iters) {
     scale_copy(c, V0, V0, 1.0 / beta, n);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int k = 0;
     bool breakdown = false;
+    double alpha_prev = 0.0;
+    std::fill(Hunrot.begin(), Hunrot.end(), 0.0);
     for (int j = 0; j < m; ++j) {
       double* vj = V.get() + (size_t)j * n;
       double* w = V.get() + (size_t)(j + 1) * n;
@@ -109,6 +118,72 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
       block_matvec(c, S, zj, nullptr, w);
       if (evm) MGD_HIP(hipEventRecord(evm->b, c->stream));
       const int J = j + 1;
+      if (delayed) {
+        // Classical Gram-Schmidt with the reorthogonalisation of v_j delayed
+        // into this step: two sweeps over the basis.  The previous column is
+        // completed here (v_j = V a + beta v_j_new), then this column.
+        const bool prov = j >= 1;
+        const int F = prov ? j : 1;
+        if (evo) MGD_HIP(hipEventRecord(evo->a, c->stream));
+        dcgs_step_dev(c, rw, V.get(), n, F, prov ? vj : nullptr, w, n, dd.get(), dcoef.get());
+        if (evo) MGD_HIP(hipEventRecord(evo->b, c->stream));
+        MGD_HIP(hipMemcpyAsync(hbuf, dcoef.get(), kDcgsCoef * sizeof(double),
+                               hipMemcpyDeviceToHost, c->stream));
+        c->sync();
+        if (evp) res.t_precond_ms += evp->ms();
+        if (evm) res.t_matvec_ms += evm->ms();
+        if (evo) res.t_orth_ms += evo->ms();
+        double hF = prov ? hbuf[32 + F] : 0.0;
+        if (prov) {
+          res.reorths++;
+          for (int i = 0; i < j; ++i) Hu(i, j - 1) += alpha_prev * hbuf[i];
+          Hu(j, j - 1) = alpha_prev * hbuf[64];
+          // v_j_new came out of Pythagoras' beta; where its exact norm is off
+          // unit length, rescale it and the two coefficients that multiply it
+          const double nv = std::sqrt(hbuf[66]);
+          if (!(std::fabs(nv - 1.0) <= 1e-6) && nv > 0.0) {
+            scale_dev(c, 1.0 / nv, vj, n);
+            Hu(j, j - 1) *= nv;
+            hF *= nv;
+          }
+        }
+        for (int i = 0; i < F; ++i) Hu(i, j) = hbuf[32 + i];
+        if (prov) Hu(j, j) = hF;
+        double al = hbuf[65];
+        const double ex = std::sqrt(hbuf[67]);
+        if (!(std::fabs(ex - al) <= 1e-6 * ex)) {
+          if (ex > 0.0) scale_dev(c, al / ex, w, n);
+          al = ex;
+        }
+        Hu(j + 1, j) = al;
+        alpha_prev = al;
+        breakdown = al == 0.0;
+        // Givens QR of the columns so far (the last two changed this step)
+        for (int q = 0; q <= j; ++q)
+          for (int i = 0; i <= q + 1; ++i) Hij(i, q) = Hu(i, q);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        for (int q = 0; q <= j; ++q) {
+          for (int i = 0; i < q; ++i) {
+            const double tt = cs[i] * Hij(i, q) + sn[i] * Hij(i + 1, q);
+            Hij(i + 1, q) = -sn[i] * Hij(i, q) + cs[i] * Hij(i + 1, q);
+            Hij(i, q) = tt;
+          }
+          const double den = std::sqrt(Hij(q, q) * Hij(q, q) + Hij(q + 1, q) * Hij(q + 1, q));
+          if (den == 0.0) fail(MGD_EBREAKDOWN, "GMRES breakdown: singular Hessenberg matrix");
+          cs[q] = Hij(q, q) / den;
+          sn[q] = Hij(q + 1, q) / den;
+          Hij(q, q) = den;
+          Hij(q + 1, q) = 0.0;
+          g[q + 1] = -sn[q] * g[q];
+          g[q] = cs[q] * g[q];
+        }
+        res.iters++;
+        k = j + 1;
+        res.relres_est = std::fabs(g[j + 1]) / bnorm;
+        if (std::fabs(g[j + 1]) <= tol || res.iters >= p.max_iters || breakdown) break;
+        continue;
+      }
       if (evo) MGD_HIP(hipEventRecord(evo->a, c->stream));
       mdot_dev(c, rw, V.get(), n, J, w, n, h1);
       update_mdot_dev(c, rw, V.get(), n, J, h1, w, n, h2);
@@ -158,8 +233,8 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
       for (int q = i + 1; q < k; ++q) s -= Hij(i, q) * y[q];
       y[i] = s / Hij(i, i);
     }
-    std::copy(y.begin(), y.begin() + k, hbuf + 32);  // pinned staging (k <= 31)
-    MGD_HIP(hipMemcpyAsync(yd, hbuf + 32, k * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    std::copy(y.begin(), y.begin() + k, hbuf + 96);  // pinned staging (k <= 31)
+    MGD_HIP(hipMemcpyAsync(yd, hbuf + 96, k * sizeof(double), hipMemcpyHostToDevice, c->stream));
     if (!M) {
       combine_dev(c, V.get(), n, k, yd, x, n);
     } else if (flex) {

@@ -869,31 +869,40 @@ __global__ void __launch_bounds__(256) k_prolong(int r0, int r1, int nC,
   }
 }
 
-// x = A^{-1} b for every dense-solved member (FP64 arithmetic); one workgroup
-// column of 64 rows per member, eight column loads in flight per step (the sum
-// stays in ascending j)
+// x = A^{-1} b for every dense-solved member (FP64 arithmetic).  A workgroup
+// of four waves takes 64 rows of one member; wave q sums the columns of its
+// quarter in ascending order, eight column loads in flight per step, and the
+// four partial sums are added in wave order.
 template <typename T>
-__global__ void __launch_bounds__(64) k_dense(const DenseDev* __restrict__ tab,
-                                              const T* __restrict__ b, T* __restrict__ X) {
+__global__ void __launch_bounds__(256) k_dense(const DenseDev* __restrict__ tab,
+                                               const T* __restrict__ b, T* __restrict__ X) {
+  __shared__ double part[4][64];
   const DenseDev d = tab[blockIdx.y];
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  if (i >= d.n) return;
-  const double* __restrict__ col = d.inv + i;
-  const T* __restrict__ bb = b + d.off;
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const int quarter = (d.n + 3) / 4;
+  const int j0 = min(d.n, q * quarter), j1 = min(d.n, j0 + quarter);
   double s = 0.0;
-  int j = 0;
-  for (; j + 8 <= d.n; j += 8) {
-    double a[8], x[8];
+  if (i < d.n) {
+    const double* __restrict__ col = d.inv + i;
+    const T* __restrict__ bb = b + d.off;
+    int j = j0;
+    for (; j + 8 <= j1; j += 8) {
+      double a[8], x[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      a[q] = col[(size_t)(j + q) * d.n];
-      x[q] = (double)bb[j + q];
+      for (int k = 0; k < 8; ++k) {
+        a[k] = col[(size_t)(j + k) * d.n];
+        x[k] = (double)bb[j + k];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s += a[k] * x[k];
     }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) s += a[q] * x[q];
+    for (; j < j1; ++j) s += col[(size_t)j * d.n] * (double)bb[j];
   }
-  for (; j < d.n; ++j) s += col[(size_t)j * d.n] * (double)bb[j];
-  X[d.off + i] = (T)s;
+  part[q][lane] = s;
+  __syncthreads();
+  if (q == 0 && i < d.n)
+    X[d.off + i] = (T)(((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
 }
 
 template <typename T>
@@ -1182,7 +1191,7 @@ void Union<T>::vcycle(Ctx* c, T* z) {
       ProfScope ps(c, KC_COARSE_SOLVE, 8.0 * lv.dense_entries + 2.0 * ts * (lv.nX - lv.nS),
                    ksym(c, "k_dense", {type_name<T>()}));
       dim3 grid(cdiv(lv.dense_max_n, 64), (unsigned)lv.dense.size());
-      hipLaunchKernelGGL(k_dense<T>, grid, dim3(64), 0, c->stream,
+      hipLaunchKernelGGL(k_dense<T>, grid, dim3(256), 0, c->stream,
                          (const DenseDev*)lv.dense_dev.get(), (const T*)B[l].get(), X0[l].get());
       MGD_CHECK_LAUNCH();
     }
@@ -1288,7 +1297,7 @@ void Union<T>::vcycle_gs(Ctx* c, T* z) {
     if (!lv.dense.empty()) {
       ProfScope ps(c, KC_COARSE_SOLVE, 8.0 * lv.dense_entries, ksym(c, "k_dense", {type_name<T>()}));
       dim3 grid(cdiv(lv.dense_max_n, 64), (unsigned)lv.dense.size());
-      hipLaunchKernelGGL(k_dense<T>, grid, dim3(64), 0, c->stream,
+      hipLaunchKernelGGL(k_dense<T>, grid, dim3(256), 0, c->stream,
                          (const DenseDev*)lv.dense_dev.get(), (const T*)B[l].get(), X0[l].get());
       MGD_CHECK_LAUNCH();
     }

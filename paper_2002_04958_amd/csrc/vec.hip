@@ -423,6 +423,209 @@ void orth_finish_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, con
   MGD_CHECK_LAUNCH();
 }
 
+// ---------------------------------------------------------------------------
+// Delayed reorthogonalisation (two sweeps per Arnoldi step)
+// ---------------------------------------------------------------------------
+// Sweep 1: per block partial sums of a_k = V_k . vj, b_k = V_k . w (k < F),
+// b_F = vj . w, ww = w . w, vv = vj . vj; outputs [0, F) a, [F, 2F) b, 2F b_F,
+// 2F+1 ww, 2F+2 vv (the vj terms are zero without vj).
+template <int JB, bool PROV>
+__global__ void __launch_bounds__(256) k_dcgs_dots(const double* __restrict__ V, size_t ldv, int F,
+                                                   const double* __restrict__ vj,
+                                                   const double* __restrict__ w, size_t n,
+                                                   double* __restrict__ partial, int nb) {
+  __shared__ double lds[4];
+  double aa[JB], bb[JB];
+#pragma unroll
+  for (int k = 0; k < JB; ++k) aa[k] = bb[k] = 0.0;
+  double bF = 0.0, ww = 0.0, vv = 0.0;
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const double wi = w[i];
+    const double vi = PROV ? vj[i] : 0.0;
+    double vk[JB];
+#pragma unroll
+    for (int k = 0; k < JB; ++k)
+      if (k < F) vk[k] = V[k * ldv + i];
+#pragma unroll
+    for (int k = 0; k < JB; ++k) {
+      if (k < F) {
+        if (PROV) aa[k] += vk[k] * vi;
+        bb[k] += vk[k] * wi;
+      }
+    }
+    if (PROV) {
+      bF += vi * wi;
+      vv += vi * vi;
+    }
+    ww += wi * wi;
+  }
+#pragma unroll
+  for (int k = 0; k < JB; ++k) {
+    if (k < F) {  // F is uniform: every thread takes the same branches around the barriers
+      const double sa = PROV ? block_sum256(aa[k], lds) : 0.0;
+      const double sb = block_sum256(bb[k], lds);
+      if (threadIdx.x == 0) {
+        partial[(size_t)k * nb + blockIdx.x] = sa;
+        partial[(size_t)(F + k) * nb + blockIdx.x] = sb;
+      }
+    }
+  }
+  const double s1 = PROV ? block_sum256(bF, lds) : 0.0;
+  const double s2 = block_sum256(ww, lds);
+  const double s3 = PROV ? block_sum256(vv, lds) : 0.0;
+  if (threadIdx.x == 0) {
+    partial[(size_t)(2 * F) * nb + blockIdx.x] = s1;
+    partial[(size_t)(2 * F + 1) * nb + blockIdx.x] = s2;
+    partial[(size_t)(2 * F + 2) * nb + blockIdx.x] = s3;
+  }
+}
+
+// The step's coefficients from the dots (one thread).
+__global__ void k_dcgs_coef(int F, int prov, const double* __restrict__ d,
+                            double* __restrict__ coef) {
+  if (threadIdx.x != 0) return;
+  const double* a = d;
+  const double* b = d + F;
+  double beta = 1.0;
+  for (int k = 0; k < 64; ++k) coef[k] = 0.0;
+  if (prov) {
+    double s = 0.0;
+    for (int k = 0; k < F; ++k) s = s + a[k] * a[k];
+    const double b2 = d[2 * F + 2] - s;
+    beta = b2 > 0.0 ? sqrt(b2) : 1.0;
+    for (int k = 0; k < F; ++k) coef[k] = a[k];
+  }
+  double hs = 0.0;
+  for (int k = 0; k < F; ++k) {
+    coef[32 + k] = b[k];
+    hs = hs + b[k] * b[k];
+  }
+  if (prov) {
+    double t = d[2 * F];
+    for (int k = 0; k < F; ++k) t = t - a[k] * b[k];
+    const double hF = t / beta;
+    coef[32 + F] = hF;
+    hs = hs + hF * hF;
+  }
+  const double al2 = d[2 * F + 1] - hs;
+  coef[64] = beta;
+  coef[65] = al2 > 0.0 ? sqrt(al2) : 1.0;
+}
+
+// Sweep 2: vj <- (vj - sum a_k V_k) / beta; w <- (w - sum h_k V_k - h_F vj_new) / alpha,
+// with per block partial sums of |vj_new|^2 and |w before the division|^2.
+template <int JB, bool PROV>
+__global__ void __launch_bounds__(256) k_dcgs_update(const double* __restrict__ V, size_t ldv,
+                                                     int F, const double* __restrict__ coef,
+                                                     double* __restrict__ vj,
+                                                     double* __restrict__ w, size_t n,
+                                                     double* __restrict__ partial, int nb) {
+  __shared__ double lds[4];
+  double ca[JB], ch[JB];
+#pragma unroll
+  for (int k = 0; k < JB; ++k) {
+    ca[k] = (PROV && k < F) ? coef[k] : 0.0;
+    ch[k] = k < F ? coef[32 + k] : 0.0;
+  }
+  const double hF = PROV ? coef[32 + F] : 0.0;
+  const double beta = coef[64], alpha = coef[65];
+  double sv = 0.0, sw = 0.0;
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    double vk[JB];
+#pragma unroll
+    for (int k = 0; k < JB; ++k)
+      if (k < F) vk[k] = V[k * ldv + i];
+    double wi = w[i];
+    double vn = 0.0;
+    if (PROV) {
+      double vi = vj[i];
+#pragma unroll
+      for (int k = 0; k < JB; ++k)
+        if (k < F) vi -= ca[k] * vk[k];
+      vn = vi / beta;
+      vj[i] = vn;
+      sv += vn * vn;
+    }
+#pragma unroll
+    for (int k = 0; k < JB; ++k)
+      if (k < F) wi -= ch[k] * vk[k];
+    if (PROV) wi -= hF * vn;
+    sw += wi * wi;
+    w[i] = wi / alpha;
+  }
+  const double s1 = PROV ? block_sum256(sv, lds) : 0.0;
+  const double s2 = block_sum256(sw, lds);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = s1;
+    partial[(size_t)nb + blockIdx.x] = s2;
+  }
+}
+
+void dcgs_step_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int F, double* vj,
+                   double* wv, size_t n, double* dots, double* coef) {
+  MGD_REQUIRE(F >= 1 && F <= 31, "dcgs: F out of range");
+  w.ensure(c);
+  const int g = red_grid(n);
+  const bool prov = vj != nullptr;
+  const int jb = mdot_jb(F);
+  {
+    ProfScope ps(c, KC_ORTH, 8.0 * n * (F + (prov ? 2 : 1)),
+                 ksym(c, "k_dcgs_dots", {std::to_string(jb), prov ? "true" : "false"}));
+#define MGD_DOTS(JB, P)                                                                         \
+  hipLaunchKernelGGL((k_dcgs_dots<JB, P>), dim3(g), dim3(256), 0, c->stream, V, ldv, F,           \
+                     (const double*)vj, (const double*)wv, n, w.partial.get(), g)
+#define MGD_DOTS_P(JB) \
+  if (prov)            \
+    MGD_DOTS(JB, true);  \
+  else                 \
+    MGD_DOTS(JB, false)
+    if (jb == 4) {
+      MGD_DOTS_P(4);
+    } else if (jb == 8) {
+      MGD_DOTS_P(8);
+    } else if (jb == 16) {
+      MGD_DOTS_P(16);
+    } else {
+      MGD_DOTS_P(32);
+    }
+#undef MGD_DOTS_P
+#undef MGD_DOTS
+    MGD_CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(k_red_final, dim3(2 * F + 3), dim3(256), 0, c->stream,
+                     (const double*)w.partial.get(), g, dots);
+  hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(64), 0, c->stream, F, prov ? 1 : 0,
+                     (const double*)dots, coef);
+  MGD_CHECK_LAUNCH();
+  {
+    ProfScope ps(c, KC_ORTH, 8.0 * n * (F + (prov ? 4 : 2)),
+                 ksym(c, "k_dcgs_update", {std::to_string(jb), prov ? "true" : "false"}));
+#define MGD_UPD(JB, P)                                                                            \
+  hipLaunchKernelGGL((k_dcgs_update<JB, P>), dim3(g), dim3(256), 0, c->stream, V, ldv, F,           \
+                     (const double*)coef, vj, wv, n, w.partial.get(), g)
+#define MGD_UPD_P(JB) \
+  if (prov)           \
+    MGD_UPD(JB, true);  \
+  else                \
+    MGD_UPD(JB, false)
+    if (jb == 4) {
+      MGD_UPD_P(4);
+    } else if (jb == 8) {
+      MGD_UPD_P(8);
+    } else if (jb == 16) {
+      MGD_UPD_P(16);
+    } else {
+      MGD_UPD_P(32);
+    }
+#undef MGD_UPD_P
+#undef MGD_UPD
+    MGD_CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(k_red_final, dim3(2), dim3(256), 0, c->stream, (const double*)w.partial.get(),
+                     g, coef + 66);
+  MGD_CHECK_LAUNCH();
+}
+
 __global__ void k_scale_vec(double a, double* __restrict__ v, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)
