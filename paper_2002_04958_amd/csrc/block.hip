@@ -7,6 +7,7 @@
 #pragma clang fp contract(off)
 
 #include <chrono>
+#include <functional>
 
 #include "handles.hpp"
 #include "kernels.hpp"
@@ -388,6 +389,7 @@ template struct Group<float>;
 // ===========================================================================
 block_precond::~block_precond() {
   for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+  for (auto& kv : step_graphs) hipGraphExecDestroy(kv.second);
   if (aux) hipStreamDestroy(aux);
   if (ev_in) hipEventDestroy(ev_in);
   if (ev_out) hipEventDestroy(ev_out);
@@ -1044,6 +1046,65 @@ void block_precond_graph_launch(block_precond* bp, const double* r, double* z) {
     it = bp->graphs.emplace(key, ex).first;
   }
   MGD_HIP(hipGraphLaunch(it->second, c->stream));
+}
+
+// Whether a whole GMRES step with this preconditioner may run as one graph:
+// graph replay asked for, no host decisions inside the apply, no profiling.
+bool block_precond_step_graphable(const block_precond* bp) {
+  return bp->prm.use_graph && bp->prm.inner_tol <= 0 && !bp->ctx->profiling &&
+         bp->prm.kind != MGD_PC_IDENTITY;
+}
+
+// Runs `body` (launches only, everything allocated beforehand, the apply in
+// its direct form) as one graph, captured on first use for `key`, which must
+// hold every pointer and size the launches use.  On the null stream the graph
+// runs on a private stream ordered after and before the caller's work.
+void block_precond_step_launch(block_precond* bp, const std::vector<uintptr_t>& key,
+                               const std::function<void()>& body) {
+  Ctx* c = bp->ctx;
+  const hipStream_t user = c->stream;
+  if (user == nullptr) {
+    if (!bp->aux) {
+      MGD_HIP(hipStreamCreateWithFlags(&bp->aux, hipStreamNonBlocking));
+      MGD_HIP(hipEventCreateWithFlags(&bp->ev_in, hipEventDisableTiming));
+      MGD_HIP(hipEventCreateWithFlags(&bp->ev_out, hipEventDisableTiming));
+    }
+    MGD_HIP(hipEventRecord(bp->ev_in, user));
+    MGD_HIP(hipStreamWaitEvent(bp->aux, bp->ev_in, 0));
+    c->stream = bp->aux;
+  }
+  try {
+    auto it = bp->step_graphs.find(key);
+    if (it == bp->step_graphs.end()) {
+      if (bp->step_graphs.size() >= 256) {
+        for (auto& kv : bp->step_graphs) hipGraphExecDestroy(kv.second);
+        bp->step_graphs.clear();
+      }
+      hipGraph_t g = nullptr;
+      MGD_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+      try {
+        body();
+      } catch (...) {
+        hipStreamEndCapture(c->stream, &g);
+        if (g) hipGraphDestroy(g);
+        throw;
+      }
+      MGD_HIP(hipStreamEndCapture(c->stream, &g));
+      hipGraphExec_t ex = nullptr;
+      MGD_HIP(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+      MGD_HIP(hipGraphDestroy(g));
+      it = bp->step_graphs.emplace(key, ex).first;
+    }
+    MGD_HIP(hipGraphLaunch(it->second, c->stream));
+  } catch (...) {
+    c->stream = user;
+    throw;
+  }
+  if (user == nullptr) {
+    c->stream = user;
+    MGD_HIP(hipEventRecord(bp->ev_out, bp->aux));
+    MGD_HIP(hipStreamWaitEvent(user, bp->ev_out, 0));
+  }
 }
 
 static void copy_system(block_precond* bp, const mgd_block_system* A) {

@@ -137,6 +137,7 @@ void Ctx::prof_collect() {
   pending.clear();
 }
 Ctx::~Ctx() {
+  gmres_ws.reset();  // its buffers go back through this context
   if (dev_err) dfree(dev_err);
   for (auto& p : pending) {
     hipEventDestroy(p.a);

@@ -86,6 +86,9 @@ struct Ctx {
   // pinned host staging for small readbacks
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
+  // GMRES basis and scratch kept between calls of the same size (allocation
+  // stays out of the solve, and graph-replayed steps find the same buffers)
+  std::shared_ptr<void> gmres_ws;
   // profiling
   bool profiling = false;
   struct Pending {

@@ -1,8 +1,10 @@
 // Opaque handle types behind the C ABI.
 #pragma once
+#include <cstdint>
 #include <map>
 #include <memory>
 #include <utility>
+#include <vector>
 
 #include "setup.hpp"
 #include "solve.hpp"
@@ -133,6 +135,9 @@ struct block_precond {
   std::unique_ptr<mgd::PcExec<float>> x32;
   // graph cache keyed by (r, z)
   std::map<std::pair<const void*, void*>, hipGraphExec_t> graphs;
+  // whole flexible-GMRES steps (apply, matvec, Gram-Schmidt) keyed by every
+  // pointer and size their launches use
+  std::map<std::vector<uintptr_t>, hipGraphExec_t> step_graphs;
   hipStream_t aux = nullptr;  // graph stream when the context stream is the null stream
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   int inverses_last = 0, matvecs_last = 0;

@@ -9,6 +9,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <functional>
+#include <vector>
 
 #include "handles.hpp"
 #include "kernels.hpp"
@@ -34,6 +36,43 @@ struct EvPair {
   }
 };
 
+void block_precond_apply_impl(block_precond* bp, const double* r, double* z);
+bool block_precond_step_graphable(const block_precond* bp);
+void block_precond_step_launch(block_precond* bp, const std::vector<uintptr_t>& key,
+                               const std::function<void()>& body);
+
+namespace {
+// The basis, the preconditioned vectors and the scratch of one context,
+// reallocated only when the problem size or the restart length grows.
+struct GmresWork {
+  size_t n = 0;
+  int m = 0;
+  DBuf<double> V, Z, t1, t2, hd, dd, dcoef;
+  RedWork rw;
+};
+GmresWork& gmres_work(Ctx* c, size_t n, int m, bool need_z, bool need_t) {
+  auto* w = static_cast<GmresWork*>(c->gmres_ws.get());
+  if (!w || w->n != n || w->m < m) {
+    c->gmres_ws.reset();
+    auto sp = std::make_shared<GmresWork>();
+    w = sp.get();
+    c->gmres_ws = sp;
+    w->n = n;
+    w->m = m;
+    w->V.alloc(c, (size_t)(m + 1) * n);
+    w->hd.alloc(c, 200);
+    w->dd.alloc(c, 80);
+    w->dcoef.alloc(c, kDcgsCoef);
+  }
+  if (need_z && w->Z.n < (size_t)w->m * n) w->Z.alloc(c, (size_t)w->m * n);
+  if (need_t && w->t1.n < n) {
+    w->t1.alloc(c, n);
+    w->t2.alloc(c, n);
+  }
+  return *w;
+}
+}  // namespace
+
 mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const double* b, double* x,
                       const gmres_params& p, gmres_result& res) {
   res = gmres_result{};
@@ -43,21 +82,18 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
   MGD_REQUIRE(p.max_iters >= 0, "max_iters must be >= 0");
   auto t_start = std::chrono::steady_clock::now();
   const bool flex = p.flexible != 0;
-  DBuf<double> V(c, (size_t)(m + 1) * n);
-  DBuf<double> Z;
-  if (flex && M) Z.alloc(c, (size_t)m * n);
-  DBuf<double> t1, t2;
-  if (!flex && M) {
-    t1.alloc(c, n);
-    t2.alloc(c, n);
-  }
-  DBuf<double> hd(c, 200);
+  GmresWork& ws = gmres_work(c, n, m, flex && M, !flex && M);
+  DBuf<double>& V = ws.V;
+  DBuf<double>& Z = ws.Z;
+  DBuf<double>& t1 = ws.t1;
+  DBuf<double>& t2 = ws.t2;
+  DBuf<double>& hd = ws.hd;
   double* h1 = hd.get();
   double* h2 = hd.get() + 40;
   double* hc = hd.get() + 80;       // [0..J+2]: column, reorth flag, exact squared norm
   double* yd = hd.get() + 130;      // y (<= 31)
   double* bn = hd.get() + 125;
-  RedWork rw;
+  RedWork& rw = ws.rw;
   std::unique_ptr<EvPair> evp, evm, evo;
   if (p.profile) {
     evp.reset(new EvPair);
@@ -93,7 +129,21 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
   const bool delayed = M && flex;
   std::vector<double> Hunrot((size_t)(m + 1) * m);
   auto Hu = [&](int i, int j) -> double& { return Hunrot[(size_t)i * m + j]; };
-  DBuf<double> dd(c, 80), dcoef(c, kDcgsCoef);
+  DBuf<double>& dd = ws.dd;
+  DBuf<double>& dcoef = ws.dcoef;
+  // With graph replay a step runs as one graph (no per-step events then)
+  const bool step_graph = delayed && !p.profile && block_precond_step_graphable(M);
+  std::vector<uintptr_t> sys_key;
+  if (step_graph) {
+    rw.ensure(c);  // nothing may be allocated inside a capture
+    sys_key = {(uintptr_t)S.G, (uintptr_t)S.N, (uintptr_t)S.tpr, (uintptr_t)S.shared,
+               (uintptr_t)S.d_gE, (uintptr_t)S.d_Eg, (uintptr_t)S.d_EI, (uintptr_t)S.d_IE};
+    for (int a = 0; a < S.G + 2; ++a) {
+      sys_key.push_back((uintptr_t)S.blk[a].rp);
+      sys_key.push_back((uintptr_t)S.blk[a].ci);
+      sys_key.push_back((uintptr_t)S.blk[a].v);
+    }
+  }
   while (res.iters < p.max_iters) {
     scale_copy(c, V0, V0, 1.0 / beta, n);
     std::fill(g.begin(), g.end(), 0.0);
@@ -106,7 +156,24 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
       double* vj = V.get() + (size_t)j * n;
       double* w = V.get() + (size_t)(j + 1) * n;
       const double* zj = vj;
-      if (M) {
+      if (delayed && step_graph) {
+        // the whole step as one graph: z_j = M^{-1} v_j, w = A z_j, the
+        // Gram-Schmidt step
+        const bool prov = j >= 1;
+        const int F = prov ? j : 1;
+        double* zt = Z.get() + (size_t)j * n;
+        std::vector<uintptr_t> key = sys_key;
+        for (uintptr_t v : {(uintptr_t)vj, (uintptr_t)zt, (uintptr_t)w, (uintptr_t)V.get(),
+                            (uintptr_t)n, (uintptr_t)F, (uintptr_t)dd.get(),
+                            (uintptr_t)dcoef.get(), (uintptr_t)rw.partial.get()})
+          key.push_back(v);
+        block_precond_step_launch(M, key, [&] {
+          block_precond_apply_impl(M, vj, zt);
+          block_matvec(c, S, zt, nullptr, w);
+          dcgs_step_dev(c, rw, V.get(), n, F, prov ? vj : nullptr, w, n, dd.get(), dcoef.get());
+        });
+        res.precond_applies++;
+      } else if (M) {
         double* zt = flex ? Z.get() + (size_t)j * n : t1.get();
         if (evp) MGD_HIP(hipEventRecord(evp->a, c->stream));
         block_precond_apply_dispatch(M, vj, zt);
@@ -114,9 +181,11 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
         res.precond_applies++;
         zj = zt;
       }
-      if (evm) MGD_HIP(hipEventRecord(evm->a, c->stream));
-      block_matvec(c, S, zj, nullptr, w);
-      if (evm) MGD_HIP(hipEventRecord(evm->b, c->stream));
+      if (!(delayed && step_graph)) {
+        if (evm) MGD_HIP(hipEventRecord(evm->a, c->stream));
+        block_matvec(c, S, zj, nullptr, w);
+        if (evm) MGD_HIP(hipEventRecord(evm->b, c->stream));
+      }
       const int J = j + 1;
       if (delayed) {
         // Classical Gram-Schmidt with the reorthogonalisation of v_j delayed
@@ -124,15 +193,19 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
         // completed here (v_j = V a + beta v_j_new), then this column.
         const bool prov = j >= 1;
         const int F = prov ? j : 1;
-        if (evo) MGD_HIP(hipEventRecord(evo->a, c->stream));
-        dcgs_step_dev(c, rw, V.get(), n, F, prov ? vj : nullptr, w, n, dd.get(), dcoef.get());
-        if (evo) MGD_HIP(hipEventRecord(evo->b, c->stream));
+        if (!step_graph) {
+          if (evo) MGD_HIP(hipEventRecord(evo->a, c->stream));
+          dcgs_step_dev(c, rw, V.get(), n, F, prov ? vj : nullptr, w, n, dd.get(), dcoef.get());
+          if (evo) MGD_HIP(hipEventRecord(evo->b, c->stream));
+        }
         MGD_HIP(hipMemcpyAsync(hbuf, dcoef.get(), kDcgsCoef * sizeof(double),
                                hipMemcpyDeviceToHost, c->stream));
         c->sync();
-        if (evp) res.t_precond_ms += evp->ms();
-        if (evm) res.t_matvec_ms += evm->ms();
-        if (evo) res.t_orth_ms += evo->ms();
+        if (!step_graph) {
+          if (evp) res.t_precond_ms += evp->ms();
+          if (evm) res.t_matvec_ms += evm->ms();
+          if (evo) res.t_orth_ms += evo->ms();
+        }
         double hF = prov ? hbuf[32 + F] : 0.0;
         if (prov) {
           res.reorths++;

@@ -615,6 +615,30 @@ def test_gmres_parity(ctx, kind):
     assert rel(to_host(xg2), xo2) < 1e-10
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gmres_step_graph_matches_direct(ctx, precision):
+    """With graph replay every flexible-GMRES step (apply, matvec, Gram-Schmidt)
+    runs as one cached graph; three solves in a row, with eager work and
+    synchronisation between them, equal the direct launches bit for bit."""
+    import torch
+    api = gpu_modules()
+    inp = si.generate(3, 2, 24, 61)
+    co, gsys = gpu_system(ctx, inp)
+    b = to_dev(ctx, inp.b)
+    Md = api.BlockPreconditioner(ctx, gsys, "schur2", amg_seed=6, batched=1, use_graph=0,
+                                 amg_precision=precision)
+    xd, rd = api.gmres(ctx, gsys, Md, b, rtol=1e-9, flexible=1)
+    xd = to_host(xd)
+    Mg = api.BlockPreconditioner(ctx, gsys, "schur2", amg_seed=6, batched=1, use_graph=1,
+                                 amg_precision=precision)
+    for _ in range(3):
+        xg, rg = api.gmres(ctx, gsys, Mg, b, rtol=1e-9, flexible=1)
+        assert rg.iters == rd.iters and rg.converged
+        assert np.array_equal(to_host(xg), xd)
+        torch.cuda.synchronize()
+        assert float((b * 2.0).sum()) == float((b * 2.0).sum())
+
+
 def test_gmres_no_preconditioner_and_nonflexible(ctx):
     api = gpu_modules()
     inp = si.generate(1, 2, 12, 5)
