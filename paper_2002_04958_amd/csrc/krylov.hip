@@ -49,6 +49,11 @@ struct GmresWork {
   int m = 0;
   DBuf<double> V, Z, t1, t2, hd, dd, dcoef;
   RedWork rw;
+  hipEvent_t ev[2] = {nullptr, nullptr};  // readbacks of two steps in flight
+  ~GmresWork() {
+    for (auto e : ev)
+      if (e) hipEventDestroy(e);
+  }
 };
 GmresWork& gmres_work(Ctx* c, size_t n, int m, bool need_z, bool need_t) {
   auto* w = static_cast<GmresWork*>(c->gmres_ws.get());
@@ -64,6 +69,8 @@ GmresWork& gmres_work(Ctx* c, size_t n, int m, bool need_z, bool need_t) {
     w->dd.alloc(c, 80);
     w->dcoef.alloc(c, kDcgsCoef);
   }
+  if (!w->ev[0])
+    for (auto& e : w->ev) MGD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   if (need_z && w->Z.n < (size_t)w->m * n) w->Z.alloc(c, (size_t)w->m * n);
   if (need_t && w->t1.n < n) {
     w->t1.alloc(c, n);
@@ -100,7 +107,9 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
     evm.reset(new EvPair);
     evo.reset(new EvPair);
   }
-  double* hbuf = static_cast<double*>(c->host_stage(128 * sizeof(double)));
+  double* hbuf = static_cast<double*>(c->host_stage(256 * sizeof(double)));
+  // pinned slots for the coefficients of two steps in flight
+  auto slot = [&](int jj) { return hbuf + 128 * (jj & 1); };
 
   dot_dev(c, rw, b, b, n, bn);
   const double bnorm = std::sqrt(read1(c, bn));
@@ -122,6 +131,8 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
     return MGD_OK;
   }
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  double r_last = 0.0, r_prev = 0.0;  // residual estimates of the last two steps
+  int launched = -1;     // graph-replayed steps enqueued in this cycle
   auto Hij = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
   // Flexible GMRES with a preconditioner keeps the unrotated Hessenberg
   // matrix: the delayed reorthogonalisation completes each column one step
@@ -144,6 +155,30 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
       sys_key.push_back((uintptr_t)S.blk[a].v);
     }
   }
+  // Enqueue graph-replayed step jj (z = M^{-1} v_jj, w = A z, the Gram-Schmidt
+  // step) and the readback of its coefficients into pinned slot jj % 2.
+  auto launch_step = [&](int jj) {
+    double* vjj = V.get() + (size_t)jj * n;
+    double* wj = V.get() + (size_t)(jj + 1) * n;
+    double* zt = Z.get() + (size_t)jj * n;
+    const bool prov = jj >= 1;
+    const int F = prov ? jj : 1;
+    std::vector<uintptr_t> key = sys_key;
+    for (uintptr_t v : {(uintptr_t)vjj, (uintptr_t)zt, (uintptr_t)wj, (uintptr_t)V.get(),
+                        (uintptr_t)n, (uintptr_t)F, (uintptr_t)dd.get(), (uintptr_t)dcoef.get(),
+                        (uintptr_t)rw.partial.get()})
+      key.push_back(v);
+    block_precond_step_launch(M, key, [&] {
+      block_precond_apply_impl(M, vjj, zt);
+      block_matvec(c, S, zt, nullptr, wj);
+      dcgs_step_dev(c, rw, V.get(), n, F, prov ? vjj : nullptr, wj, n, dd.get(), dcoef.get());
+    });
+    MGD_HIP(hipMemcpyAsync(slot(jj), dcoef.get(), kDcgsCoef * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+    MGD_HIP(hipEventRecord(ws.ev[jj & 1], c->stream));
+    res.precond_applies++;
+    launched = jj;
+  };
   while (res.iters < p.max_iters) {
     scale_copy(c, V0, V0, 1.0 / beta, n);
     std::fill(g.begin(), g.end(), 0.0);
@@ -152,27 +187,24 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
     bool breakdown = false;
     double alpha_prev = 0.0;
     std::fill(Hunrot.begin(), Hunrot.end(), 0.0);
+    launched = -1;
+    r_last = beta;
+    r_prev = 0.0;
     for (int j = 0; j < m; ++j) {
       double* vj = V.get() + (size_t)j * n;
       double* w = V.get() + (size_t)(j + 1) * n;
       const double* zj = vj;
       if (delayed && step_graph) {
-        // the whole step as one graph: z_j = M^{-1} v_j, w = A z_j, the
-        // Gram-Schmidt step
-        const bool prov = j >= 1;
-        const int F = prov ? j : 1;
-        double* zt = Z.get() + (size_t)j * n;
-        std::vector<uintptr_t> key = sys_key;
-        for (uintptr_t v : {(uintptr_t)vj, (uintptr_t)zt, (uintptr_t)w, (uintptr_t)V.get(),
-                            (uintptr_t)n, (uintptr_t)F, (uintptr_t)dd.get(),
-                            (uintptr_t)dcoef.get(), (uintptr_t)rw.partial.get()})
-          key.push_back(v);
-        block_precond_step_launch(M, key, [&] {
-          block_precond_apply_impl(M, vj, zt);
-          block_matvec(c, S, zt, nullptr, w);
-          dcgs_step_dev(c, rw, V.get(), n, F, prov ? vj : nullptr, w, n, dd.get(), dcoef.get());
-        });
-        res.precond_applies++;
+        if (launched < j) launch_step(j);
+        // Enqueue step j+1 before waiting for this step's coefficients: it
+        // needs only v_{j+1}, which this step writes, so the GPU works on it
+        // while the host finishes column j.  Skipped at the end of a cycle,
+        // at the iteration cap, and when the recent reduction rate says this
+        // step is likely to converge.
+        // residual estimates after j and j-1 steps: forecast the next one
+        const double ratio = (j >= 2 && r_prev > 0.0) ? r_last / r_prev : 1.0;
+        const bool likely_done = j >= 1 && r_last * ratio <= tol;
+        if (j + 1 < m && res.iters + 1 < p.max_iters && !likely_done) launch_step(j + 1);
       } else if (M) {
         double* zt = flex ? Z.get() + (size_t)j * n : t1.get();
         if (evp) MGD_HIP(hipEventRecord(evp->a, c->stream));
@@ -198,36 +230,43 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
           dcgs_step_dev(c, rw, V.get(), n, F, prov ? vj : nullptr, w, n, dd.get(), dcoef.get());
           if (evo) MGD_HIP(hipEventRecord(evo->b, c->stream));
         }
-        MGD_HIP(hipMemcpyAsync(hbuf, dcoef.get(), kDcgsCoef * sizeof(double),
-                               hipMemcpyDeviceToHost, c->stream));
-        c->sync();
-        if (!step_graph) {
+        const double* hb = hbuf;
+        if (step_graph) {
+          hb = slot(j);
+          MGD_HIP(hipEventSynchronize(ws.ev[j & 1]));
+        } else {
+          MGD_HIP(hipMemcpyAsync(hbuf, dcoef.get(), kDcgsCoef * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream));
+          c->sync();
           if (evp) res.t_precond_ms += evp->ms();
           if (evm) res.t_matvec_ms += evm->ms();
           if (evo) res.t_orth_ms += evo->ms();
         }
-        double hF = prov ? hbuf[32 + F] : 0.0;
+        double hF = prov ? hb[32 + F] : 0.0;
         if (prov) {
           res.reorths++;
-          for (int i = 0; i < j; ++i) Hu(i, j - 1) += alpha_prev * hbuf[i];
-          Hu(j, j - 1) = alpha_prev * hbuf[64];
+          for (int i = 0; i < j; ++i) Hu(i, j - 1) += alpha_prev * hb[i];
+          Hu(j, j - 1) = alpha_prev * hb[64];
           // v_j_new came out of Pythagoras' beta; where its exact norm is off
           // unit length, rescale it and the two coefficients that multiply it
-          const double nv = std::sqrt(hbuf[66]);
-          if (!(std::fabs(nv - 1.0) <= 1e-6) && nv > 0.0) {
+          // (not when the next step is already under way with it: that step's
+          // dots use its actual norm, and the relation stays exact)
+          const double nv = std::sqrt(hb[66]);
+          if (!step_graph && !(std::fabs(nv - 1.0) <= 1e-6) && nv > 0.0) {
             scale_dev(c, 1.0 / nv, vj, n);
             Hu(j, j - 1) *= nv;
             hF *= nv;
           }
         }
-        for (int i = 0; i < F; ++i) Hu(i, j) = hbuf[32 + i];
+        for (int i = 0; i < F; ++i) Hu(i, j) = hb[32 + i];
         if (prov) Hu(j, j) = hF;
-        double al = hbuf[65];
-        const double ex = std::sqrt(hbuf[67]);
-        if (!(std::fabs(ex - al) <= 1e-6 * ex)) {
+        double al = hb[65];
+        const double ex = std::sqrt(hb[67]);
+        if (!step_graph && !(std::fabs(ex - al) <= 1e-6 * ex)) {
           if (ex > 0.0) scale_dev(c, al / ex, w, n);
           al = ex;
         }
+        if (step_graph && !(ex > 0.0)) al = 0.0;  // w' vanished: breakdown
         Hu(j + 1, j) = al;
         alpha_prev = al;
         breakdown = al == 0.0;
@@ -253,6 +292,8 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
         }
         res.iters++;
         k = j + 1;
+        r_prev = r_last;
+        r_last = std::fabs(g[j + 1]);
         res.relres_est = std::fabs(g[j + 1]) / bnorm;
         if (std::fabs(g[j + 1]) <= tol || res.iters >= p.max_iters || breakdown) break;
         continue;
@@ -306,8 +347,8 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
       for (int q = i + 1; q < k; ++q) s -= Hij(i, q) * y[q];
       y[i] = s / Hij(i, i);
     }
-    std::copy(y.begin(), y.begin() + k, hbuf + 96);  // pinned staging (k <= 31)
-    MGD_HIP(hipMemcpyAsync(yd, hbuf + 96, k * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    std::copy(y.begin(), y.begin() + k, hbuf + 80);  // pinned staging (k <= 31)
+    MGD_HIP(hipMemcpyAsync(yd, hbuf + 80, k * sizeof(double), hipMemcpyHostToDevice, c->stream));
     if (!M) {
       combine_dev(c, V.get(), n, k, yd, x, n);
     } else if (flex) {
