@@ -18,6 +18,11 @@ Components the paper names but does not define, and the readings taken here:
   * interpolation: classical direct + distribution with the "modified"
     treatment of strong F-F connections that share no C point (lumped into
     the diagonal) and sign-filtered distribution coefficients; no truncation.
+  * aggressive coarsening (the paper applies it on the finest level): a
+    second pass of the same coarsening over the first pass's C points, on
+    their strength graph of distance two (one path suffices), with hash keys
+    of level + 64; the long-range interpolation it needs is multipass
+    interpolation (Stueben 2001), the passes summed in canonical order.
   * smoother: CF-ordered l1-Jacobi, d_i = a_ii + sum_{j != i} |a_ij|
     (in place of hybrid Gauss-Seidel, which is sequential).
   * coarsest level: dense LU with partial pivoting when it has at most
@@ -251,6 +256,117 @@ def hmis(A: sp.csr_matrix, S: np.ndarray, seed: int, level: int, tile: int = 102
 
 
 # ----------------------------------------------------------------------------
+# aggressive coarsening (Section 3.1 applies it on the finest level)
+# ----------------------------------------------------------------------------
+AGGRESSIVE_SALT = 64       # level offset of the second pass's hash keys
+
+
+def distance2_graph(A: sp.csr_matrix, S: np.ndarray, cand: np.ndarray) -> sp.csr_matrix:
+    """Strength graph of distance two among the points of ``cand`` (boolean
+    mask), numbered by ascending fine index: j depends on i (i != j) when
+    j is in S_i, or j is in S_k for some k in S_i.  Pattern only (values 1)."""
+    n = A.shape[0]
+    rows = csr_rows(A)[S]
+    cols = A.indices[S].astype(np.int64)
+    Sm = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(n, n))
+    reach = Sm @ (sp.identity(n, format="csr") + Sm)     # paths of length 1 or 2
+    idx = np.nonzero(cand)[0]
+    R = reach[idx][:, idx].tocoo()
+    keep = R.row != R.col
+    G2 = sp.csr_matrix((np.ones(int(keep.sum())), (R.row[keep], R.col[keep])),
+                       shape=(len(idx), len(idx)))
+    G2.sum_duplicates()
+    G2.data[:] = 1.0
+    G2.sort_indices()
+    return G2
+
+
+def aggressive_split(A: sp.csr_matrix, S: np.ndarray, cf1: np.ndarray, seed: int,
+                     level: int, coarsening: str = "pmis", tile: int = 1024):
+    """Second coarsening pass over the first pass's C points on their distance-two
+    strength graph, with the same algorithm as the first pass (every edge of that
+    graph is strong) and hash keys of level ``level + AGGRESSIVE_SALT``.  The
+    points it keeps are C; every other point is F.  Returns (cf, rounds)."""
+    isC1 = cf1 == C_PT
+    G2 = distance2_graph(A, S, isC1)
+    S2 = np.ones(G2.nnz, dtype=bool)
+    if coarsening == "hmis":
+        cf2, rounds = hmis(G2, S2, seed, level + AGGRESSIVE_SALT, tile, return_rounds=True)
+    else:
+        cf2, rounds = pmis(G2, S2, seed, level + AGGRESSIVE_SALT, return_rounds=True)
+    cf = np.full(A.shape[0], F_PT, dtype=np.int8)
+    cf[np.nonzero(isC1)[0][cf2 == C_PT]] = C_PT
+    return cf, rounds
+
+
+def multipass_passes(A: sp.csr_matrix, S: np.ndarray, cf: np.ndarray) -> np.ndarray:
+    """Pass number of every point: 0 on C points; an F point has pass m when its
+    nearest C point along strong dependencies is m steps away; -1 when no chain
+    of strong dependencies reaches a C point."""
+    rows = csr_rows(A)[S]
+    cols = A.indices[S].astype(np.int64)
+    ps = np.where(cf == C_PT, 0, -1).astype(np.int64)
+    m = 0
+    while True:
+        new = np.unique(rows[(ps[rows] == -1) & (ps[cols] == m)])
+        if len(new) == 0:
+            return ps
+        m += 1
+        ps[new] = m
+
+
+def multipass_interpolation(A: sp.csr_matrix, S: np.ndarray, cf: np.ndarray) -> sp.csr_matrix:
+    """Multipass interpolation (Stueben, "An introduction to algebraic
+    multigrid", 2001: direct interpolation, then passes through the points
+    interpolated so far).  C rows: identity.  A point i of pass m >= 1 with
+    P_i = its strong dependencies of pass m - 1:
+        sN-_i = sum of its negative off-diagonal entries      (ascending column)
+        sN+_i = sum of its other off-diagonal entries          (ascending column)
+        sP_i  = sum_{j in P_i} a_ij                            (ascending j)
+        alpha_i = sN-_i / sP_i,   d_i = a_ii + sN+_i
+        w_ik = -(alpha_i * sum_{j in P_i} a_ij w_jk) / d_i     (sum over ascending j)
+    Strong entries are negative, so sP_i < 0 and every positive entry is lumped
+    into d_i.  Rows of points no chain reaches are empty."""
+    n = A.shape[0]
+    isC = cf == C_PT
+    cidx = np.cumsum(isC) - 1
+    nc = int(isC.sum())
+    rows = csr_rows(A)
+    cols = A.indices.astype(np.int64)
+    v = A.data
+    offd = cols != rows
+    neg = offd & (v < 0.0)
+    pos = offd & ~(v < 0.0)
+    starts = A.indptr[:-1].astype(np.int64)
+    lens = np.diff(A.indptr)
+    sNn = seq_segment_sum(starts, lens, np.where(neg, v, 0.0))
+    sNp = seq_segment_sum(starts, lens, np.where(pos, v, 0.0))
+    d = diagonal_of(A) + sNp
+    ps = multipass_passes(A, S, cf)
+    pr = [np.nonzero(isC)[0]]
+    pc = [cidx[isC]]
+    pv = [np.ones(nc)]
+    for m in range(1, int(ps.max()) + 1 if n else 1):
+        cur = sp.csr_matrix((np.concatenate(pv), (np.concatenate(pr), np.concatenate(pc))),
+                            shape=(n, nc))
+        cur.sort_indices()
+        sel = S & (ps[rows] == m) & (ps[cols] == m - 1)
+        sP = seq_segment_sum(starts, lens, np.where(sel, v, 0.0))
+        Am = sp.csr_matrix((v[sel], (rows[sel], cols[sel])), shape=(n, n))
+        Am.sort_indices()
+        s = spgemm_ordered(Am, cur)
+        r = csr_rows(s)
+        alpha = sNn[r] / sP[r]
+        pr.append(r)
+        pc.append(s.indices.astype(np.int64))
+        pv.append(-(alpha * s.data) / d[r])
+    P = sp.csr_matrix((np.concatenate(pv), (np.concatenate(pr), np.concatenate(pc))),
+                      shape=(n, nc))
+    P.sort_indices()
+    return P
+
+
+# ----------------------------------------------------------------------------
 # classical modified interpolation
 # ----------------------------------------------------------------------------
 def interpolation(A: sp.csr_matrix, S: np.ndarray, cf: np.ndarray) -> sp.csr_matrix:
@@ -441,6 +557,7 @@ class AMGParams:
     coarsening: str = "pmis"           # "pmis" or "hmis"
     hmis_tile: int = 1024
     smoother: str = "cf_l1_jacobi"     # or "mc_gs" (multicolour Gauss-Seidel)
+    aggressive_levels: int = 0         # finest levels coarsened aggressively (Section 3.1: 1)
 
 
 @dataclass
@@ -493,11 +610,15 @@ def setup(A: sp.csr_matrix, params: Optional[AMGParams] = None) -> Hierarchy:
             cf, rounds = hmis(A, S, p.seed, lvl, p.hmis_tile, return_rounds=True)
         else:
             cf, rounds = pmis(A, S, p.seed, lvl, return_rounds=True)
+        aggressive = lvl < p.aggressive_levels
+        if aggressive:
+            cf, rounds2 = aggressive_split(A, S, cf, p.seed, lvl, p.coarsening, p.hmis_tile)
+            rounds += rounds2
         nc = int(np.count_nonzero(cf == C_PT))
         if nc == 0 or 10 * nc > 9 * n:
             levels.append(Level(A, d))
             break
-        P = interpolation(A, S, cf)
+        P = multipass_interpolation(A, S, cf) if aggressive else interpolation(A, S, cf)
         R, Ac = galerkin(A, P)
         levels.append(Level(A, d, cf, P, R, rounds))
         A = Ac
