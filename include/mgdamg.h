@@ -129,6 +129,10 @@ typedef struct amg_params {
   int32_t smoother;       /* 0: CF-ordered l1-Jacobi; 1: multicolour Gauss-Seidel (Jones-
                              Plassmann colours, ascending going down, descending going up;
                              a stalled coarsest level is relaxed the same way) */
+  int32_t aggressive_levels; /* 0: the number of finest levels coarsened aggressively
+                                (Section 3.1 uses 1): a second pass of the same coarsening
+                                over the C points on their strength graph of distance two,
+                                with multipass interpolation; in [0, MGD_MAX_LEVELS] */
 } amg_params;
 void amg_params_default(amg_params* p);
 

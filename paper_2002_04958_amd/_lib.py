@@ -27,7 +27,7 @@ class amg_params(Structure):
                 ("max_levels", c_int32), ("coarse_max", c_int32), ("dense_max", c_int32),
                 ("n_pre", c_int32), ("n_post", c_int32), ("precision", c_int32),
                 ("autotune", c_int32), ("coarsening", c_int32), ("hmis_tile", c_int32),
-                ("smoother", c_int32)]
+                ("smoother", c_int32), ("aggressive_levels", c_int32)]
 
 
 class amg_info(Structure):

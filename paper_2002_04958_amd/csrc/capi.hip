@@ -430,6 +430,7 @@ void amg_params_default(amg_params* p) {
   p->coarsening = 0;
   p->hmis_tile = 1024;
   p->smoother = 0;
+  p->aggressive_levels = 0;
 }
 
 static void check_amg_params(const amg_params* p) {
@@ -445,6 +446,8 @@ static void check_amg_params(const amg_params* p) {
   MGD_REQUIRE(p->coarsening == 0 || (p->hmis_tile >= 1 && p->hmis_tile <= 1024),
               "hmis_tile must be in [1, 1024]");
   MGD_REQUIRE(p->smoother == 0 || p->smoother == 1, "smoother must be 0 (CF-l1-Jacobi) or 1 (MC-GS)");
+  MGD_REQUIRE(p->aggressive_levels >= 0 && p->aggressive_levels <= MGD_MAX_LEVELS,
+              "aggressive_levels must be in [0, MGD_MAX_LEVELS]");
 }
 
 mgd_status amg_setup(mgd_ctx* ctx, const mgd_csr* A, const amg_params* p, amg_hierarchy** out) {

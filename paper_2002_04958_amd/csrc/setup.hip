@@ -621,6 +621,361 @@ void spgemm(Ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>& C) 
 }
 
 // ---------------------------------------------------------------------------
+// aggressive coarsening: a second pass of the same coarsening over the first
+// pass's C points, on their strength graph of distance two (j depends on i
+// when j is in S_i or in S_k for some k in S_i), numbered by ascending fine
+// index; hash keys of level + kAggressiveSalt.  The graph is the pattern of
+// X Y minus its diagonal, X = the strong entries of the C rows and
+// Y = I + S restricted to C columns.
+// ---------------------------------------------------------------------------
+constexpr int kAggressiveSalt = 64;
+
+__global__ void k_d2x_count(int n, const int* __restrict__ rp, const uint8_t* __restrict__ S,
+                            const int8_t* __restrict__ st, const int* __restrict__ cidx,
+                            int* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || st[i] != kC) return;
+  int k = 0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) k += S[e] ? 1 : 0;
+  cnt[cidx[i]] = k;
+}
+__global__ void k_d2x_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const uint8_t* __restrict__ S, const int8_t* __restrict__ st,
+                           const int* __restrict__ cidx, const int* __restrict__ xrp,
+                           int* __restrict__ xci, double* __restrict__ xv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || st[i] != kC) return;
+  int p = xrp[cidx[i]];
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (S[e]) {
+      xci[p] = ci[e];
+      xv[p] = 1.0;
+      ++p;
+    }
+}
+__global__ void k_d2y_count(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                            const uint8_t* __restrict__ S, const int8_t* __restrict__ st,
+                            int* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int k = st[i] == kC ? 1 : 0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) k += (S[e] && st[ci[e]] == kC) ? 1 : 0;
+  cnt[i] = k;
+}
+// row i of Y: i itself when it is C, and its strong C dependencies, in
+// ascending coarse index (strength never flags the diagonal)
+__global__ void k_d2y_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const uint8_t* __restrict__ S, const int8_t* __restrict__ st,
+                           const int* __restrict__ cidx, const int* __restrict__ yrp,
+                           int* __restrict__ yci, double* __restrict__ yv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int p = yrp[i];
+  bool self = st[i] == kC;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const int j = ci[e];
+    if (self && j > i) {
+      yci[p] = cidx[i];
+      yv[p] = 1.0;
+      ++p;
+      self = false;
+    }
+    if (S[e] && st[j] == kC) {
+      yci[p] = cidx[j];
+      yv[p] = 1.0;
+      ++p;
+    }
+  }
+  if (self) {
+    yci[p] = cidx[i];
+    yv[p] = 1.0;
+  }
+}
+__global__ void k_offdiag_count(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                int* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int k = 0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) k += ci[e] != i ? 1 : 0;
+  cnt[i] = k;
+}
+__global__ void k_offdiag_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                               const int* __restrict__ orp, int* __restrict__ oci,
+                               double* __restrict__ ov) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int p = orp[i];
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (ci[e] != i) {
+      oci[p] = ci[e];
+      ov[p] = 1.0;
+      ++p;
+    }
+}
+__global__ void k_d2_combine(int n, const int8_t* __restrict__ st1, const int* __restrict__ cidx1,
+                             const int8_t* __restrict__ st2, int8_t* __restrict__ st) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  st[i] = (st1[i] == kC && st2[cidx1[i]] == kC) ? kC : kF;
+}
+
+// state: first-pass C/F splitting in, final splitting out; returns the rounds
+// of the second pass
+int aggressive_split(Ctx* c, const Csr<double>& A, const DBuf<uint8_t>& S,
+                     const DBuf<int>& cidx1, int n1, uint64_t seed, int level, int hmis_tile,
+                     DBuf<int8_t>& state) {
+  const int n = A.n_rows;
+  const int g = cdiv(n, 256);
+  Csr<double> X, Y, Z, G2;
+  {
+    DBuf<int> cnt(c, (size_t)std::max(n1, 1));
+    hipLaunchKernelGGL(k_d2x_count, dim3(g), dim3(256), 0, c->stream, n, A.rp.get(), S.get(),
+                       state.get(), cidx1.get(), cnt.get());
+    MGD_CHECK_LAUNCH();
+    X.n_rows = n1;
+    X.n_cols = n;
+    X.rp.alloc(c, (size_t)n1 + 1);
+    X.nnz = exclusive_scan_total(c, cnt.get(), X.rp.get(), n1);
+    X.ci.alloc(c, (size_t)std::max(X.nnz, 1));
+    X.v.alloc(c, (size_t)std::max(X.nnz, 1));
+    hipLaunchKernelGGL(k_d2x_fill, dim3(g), dim3(256), 0, c->stream, n, A.rp.get(), A.ci.get(),
+                       S.get(), state.get(), cidx1.get(), (const int*)X.rp.get(), X.ci.get(),
+                       X.v.get());
+    MGD_CHECK_LAUNCH();
+  }
+  {
+    DBuf<int> cnt(c, (size_t)n);
+    hipLaunchKernelGGL(k_d2y_count, dim3(g), dim3(256), 0, c->stream, n, A.rp.get(), A.ci.get(),
+                       S.get(), state.get(), cnt.get());
+    MGD_CHECK_LAUNCH();
+    Y.n_rows = n;
+    Y.n_cols = n1;
+    Y.rp.alloc(c, (size_t)n + 1);
+    Y.nnz = exclusive_scan_total(c, cnt.get(), Y.rp.get(), n);
+    Y.ci.alloc(c, (size_t)std::max(Y.nnz, 1));
+    Y.v.alloc(c, (size_t)std::max(Y.nnz, 1));
+    hipLaunchKernelGGL(k_d2y_fill, dim3(g), dim3(256), 0, c->stream, n, A.rp.get(), A.ci.get(),
+                       S.get(), state.get(), cidx1.get(), (const int*)Y.rp.get(), Y.ci.get(),
+                       Y.v.get());
+    MGD_CHECK_LAUNCH();
+  }
+  check_structure(c, X, "distance-two graph: X", false);
+  check_structure(c, Y, "distance-two graph: Y", false);
+  spgemm(c, X, Y, Z);
+  check_structure(c, Z, "distance-two graph", false);
+  {
+    const int g1 = cdiv(n1, 256);
+    DBuf<int> cnt(c, (size_t)std::max(n1, 1));
+    hipLaunchKernelGGL(k_offdiag_count, dim3(g1), dim3(256), 0, c->stream, n1, Z.rp.get(),
+                       Z.ci.get(), cnt.get());
+    MGD_CHECK_LAUNCH();
+    G2.n_rows = G2.n_cols = n1;
+    G2.rp.alloc(c, (size_t)n1 + 1);
+    G2.nnz = exclusive_scan_total(c, cnt.get(), G2.rp.get(), n1);
+    G2.ci.alloc(c, (size_t)std::max(G2.nnz, 1));
+    G2.v.alloc(c, (size_t)std::max(G2.nnz, 1));
+    hipLaunchKernelGGL(k_offdiag_fill, dim3(g1), dim3(256), 0, c->stream, n1, Z.rp.get(),
+                       Z.ci.get(), (const int*)G2.rp.get(), G2.ci.get(), G2.v.get());
+    MGD_CHECK_LAUNCH();
+  }
+  DBuf<uint8_t> S2(c, (size_t)std::max(G2.nnz, 1));
+  fill<uint8_t>(c, S2.get(), (uint8_t)1, (size_t)G2.nnz);
+  DBuf<int> stc2(c, (size_t)std::max(n1, 1));
+  fill<int>(c, stc2.get(), 0, (size_t)n1);
+  if (G2.nnz)
+    hipLaunchKernelGGL(k_count_cols, dim3(cdiv(G2.nnz, 256)), dim3(256), 0, c->stream, G2.nnz,
+                       G2.ci.get(), stc2.get());
+  MGD_CHECK_LAUNCH();
+  DBuf<int8_t> st2;
+  const int rounds = pmis(c, G2, S2, stc2, seed, level + kAggressiveSalt, st2, hmis_tile);
+  DBuf<int8_t> out(c, (size_t)n);
+  hipLaunchKernelGGL(k_d2_combine, dim3(g), dim3(256), 0, c->stream, n, state.get(), cidx1.get(),
+                     (const int8_t*)st2.get(), out.get());
+  MGD_CHECK_LAUNCH();
+  c->sync();
+  state = std::move(out);
+  return rounds;
+}
+
+// ---------------------------------------------------------------------------
+// multipass interpolation (Stueben 2001): C rows are the identity; a point of
+// pass m (its nearest C point is m strong dependencies away) interpolates
+// through its strong dependencies P_i of pass m - 1:
+//   alpha = (sum of negative off-diagonal a_ij) / (sum_{j in P_i} a_ij),
+//   d = a_ii + (sum of the other off-diagonal a_ij),
+//   w_ik = -(alpha * (0 + sum_{j in P_i, ascending} a_ij w_jk)) / d.
+// Rows are built pass by pass into a buffer per pass; off[i], len[i] locate
+// row i in its pass's buffer.  Points no chain reaches get empty rows.
+// ---------------------------------------------------------------------------
+__global__ void k_mp_init(int n, const int8_t* __restrict__ st, const int* __restrict__ cidx,
+                          int* __restrict__ pass, int* __restrict__ off, int* __restrict__ len) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool isc = st[i] == kC;
+  pass[i] = isc ? 0 : -1;
+  off[i] = isc ? cidx[i] : 0;
+  len[i] = isc ? 1 : 0;
+}
+__global__ void k_iota(int n, int* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = i;
+}
+// pass m for every unreached point with a strong dependency of pass m - 1
+// (a point set in this launch reads as m or -1, never as m - 1)
+__global__ void k_mp_assign(int n, int m, const int* __restrict__ rp, const int* __restrict__ ci,
+                            const uint8_t* __restrict__ S, int* __restrict__ pass,
+                            int* __restrict__ added) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool hit = false;
+  if (i < n && pass[i] < 0)
+    for (int e = rp[i]; e < rp[i + 1]; ++e)
+      if (S[e] && pass[ci[e]] == m - 1) {
+        hit = true;
+        break;
+      }
+  if (hit) pass[i] = m;
+  const uint64_t b = __ballot(hit);
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(added, (int)__popcll(b));
+}
+template <bool FILL>
+__global__ void k_mp_rows(int n, int m, const int* __restrict__ rp, const int* __restrict__ ci,
+                          const double* __restrict__ v, const uint8_t* __restrict__ S,
+                          const int* __restrict__ pass, const int* __restrict__ bci,
+                          const double* __restrict__ bv, int* __restrict__ off,
+                          int* __restrict__ len, int* __restrict__ head, int* __restrict__ hend,
+                          const int* __restrict__ orp, int* __restrict__ cnt_or_oci,
+                          double* __restrict__ ov, int* __restrict__ err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (pass[i] != m) {
+    if (!FILL) cnt_or_oci[i] = 0;
+    return;
+  }
+  const int e0 = rp[i], e1 = rp[i + 1];
+  double dg = 0.0, sn = 0.0, sp = 0.0, sP = 0.0;
+  for (int e = e0; e < e1; ++e) {
+    const int j = ci[e];
+    const double a = v[e];
+    if (j == i)
+      dg = a;
+    else if (a < 0.0)
+      sn = sn + a;
+    else
+      sp = sp + a;
+    if (S[e] && pass[j] == m - 1) {
+      sP = sP + a;
+      head[e] = off[j];
+      hend[e] = off[j] + len[j];
+    } else {
+      head[e] = 0;
+      hend[e] = 0;
+    }
+  }
+  const double alpha = sn / sP, d = dg + sp;
+  int out = FILL ? orp[i] : 0;
+  const int oend = FILL ? orp[i + 1] : INT_MAX;
+  for (;;) {
+    int kmin = INT_MAX;
+    for (int e = e0; e < e1; ++e)
+      if (head[e] < hend[e]) kmin = min(kmin, bci[head[e]]);
+    if (kmin == INT_MAX) break;
+    double acc = 0.0;
+    for (int e = e0; e < e1; ++e) {
+      const int h = head[e];
+      if (h < hend[e] && bci[h] == kmin) {
+        if (FILL) acc = acc + v[e] * bv[h];
+        head[e] = h + 1;
+      }
+    }
+    if (FILL) {
+      if (out >= oend) {  // more columns than the count pass gave this row
+        atomicOr(err, 1);
+        return;
+      }
+      cnt_or_oci[out] = kmin;
+      ov[out] = -(alpha * acc) / d;
+    }
+    ++out;
+  }
+  if (!FILL) {
+    cnt_or_oci[i] = out;
+  } else {
+    if (out != oend) atomicOr(err, 2);
+    off[i] = orp[i];
+    len[i] = out - orp[i];
+  }
+}
+__global__ void k_mp_copy(int n, int m, const int* __restrict__ pass, const int* __restrict__ off,
+                          const int* __restrict__ len, const int* __restrict__ bci,
+                          const double* __restrict__ bv, const int* __restrict__ prp,
+                          int* __restrict__ pci, double* __restrict__ pv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || pass[i] != m) return;
+  const int o = off[i], p = prp[i];
+  for (int q = 0; q < len[i]; ++q) {
+    pci[p + q] = bci[o + q];
+    pv[p + q] = bv[o + q];
+  }
+}
+
+void multipass_interpolation(Ctx* c, const Csr<double>& A, const DBuf<uint8_t>& S,
+                             const DBuf<int8_t>& state, const DBuf<int>& cidx, int nc,
+                             Csr<double>& P) {
+  const int n = A.n_rows;
+  const int g = cdiv(n, 256);
+  DBuf<int> pass(c, (size_t)n), off(c, (size_t)n), len(c, (size_t)n), added(c, 1);
+  hipLaunchKernelGGL(k_mp_init, dim3(g), dim3(256), 0, c->stream, n, state.get(), cidx.get(),
+                     pass.get(), off.get(), len.get());
+  MGD_CHECK_LAUNCH();
+  std::vector<DBuf<int>> bci;
+  std::vector<DBuf<double>> bv;
+  bci.emplace_back(c, (size_t)std::max(nc, 1));
+  bv.emplace_back(c, (size_t)std::max(nc, 1));
+  hipLaunchKernelGGL(k_iota, dim3(cdiv(std::max(nc, 1), 256)), dim3(256), 0, c->stream, nc,
+                     bci[0].get());
+  MGD_CHECK_LAUNCH();
+  fill<double>(c, bv[0].get(), 1.0, (size_t)nc);
+  DBuf<int> head(c, (size_t)std::max(A.nnz, 1)), hend(c, (size_t)std::max(A.nnz, 1));
+  DBuf<int> cnt(c, (size_t)n), orp(c, (size_t)n + 1);
+  for (int m = 1;; ++m) {
+    if (m > n) fail(MGD_EHIP, "multipass interpolation did not terminate");
+    fill<int>(c, added.get(), 0, 1);
+    hipLaunchKernelGGL(k_mp_assign, dim3(g), dim3(256), 0, c->stream, n, m, A.rp.get(),
+                       A.ci.get(), S.get(), pass.get(), added.get());
+    MGD_CHECK_LAUNCH();
+    if (read1(c, added.get()) == 0) break;
+    hipLaunchKernelGGL(k_mp_rows<false>, dim3(g), dim3(256), 0, c->stream, n, m, A.rp.get(),
+                       A.ci.get(), A.v.get(), S.get(), (const int*)pass.get(),
+                       (const int*)bci[m - 1].get(), (const double*)bv[m - 1].get(), off.get(),
+                       len.get(), head.get(), hend.get(), (const int*)nullptr, cnt.get(),
+                       (double*)nullptr, c->err_flag());
+    MGD_CHECK_LAUNCH();
+    const int tot = exclusive_scan_total(c, cnt.get(), orp.get(), n);
+    bci.emplace_back(c, (size_t)std::max(tot, 1));
+    bv.emplace_back(c, (size_t)std::max(tot, 1));
+    hipLaunchKernelGGL(k_mp_rows<true>, dim3(g), dim3(256), 0, c->stream, n, m, A.rp.get(),
+                       A.ci.get(), A.v.get(), S.get(), (const int*)pass.get(),
+                       (const int*)bci[m - 1].get(), (const double*)bv[m - 1].get(), off.get(),
+                       len.get(), head.get(), hend.get(), (const int*)orp.get(), bci[m].get(),
+                       bv[m].get(), c->err_flag());
+    MGD_CHECK_LAUNCH();
+    c->check_device_errors("multipass interpolation");
+  }
+  P.n_rows = n;
+  P.n_cols = nc;
+  P.rp.alloc(c, (size_t)n + 1);
+  P.nnz = exclusive_scan_total(c, len.get(), P.rp.get(), n);
+  P.ci.alloc(c, (size_t)std::max(P.nnz, 1));
+  P.v.alloc(c, (size_t)std::max(P.nnz, 1));
+  for (int m = 0; m < (int)bci.size(); ++m)
+    hipLaunchKernelGGL(k_mp_copy, dim3(g), dim3(256), 0, c->stream, n, m, (const int*)pass.get(),
+                       (const int*)off.get(), (const int*)len.get(), (const int*)bci[m].get(),
+                       (const double*)bv[m].get(), (const int*)P.rp.get(), P.ci.get(), P.v.get());
+  MGD_CHECK_LAUNCH();
+  c->sync();
+}
+
+// ---------------------------------------------------------------------------
 // l1 diagonal
 // ---------------------------------------------------------------------------
 __global__ void k_l1diag(int n, const int* __restrict__ rp, const int* __restrict__ ci,
@@ -861,13 +1216,23 @@ void amg_build(Ctx* c, Csr<double>&& A0, const amg_params& p, SetupHierarchy& H)
     strength(c, A, p.strength_theta, p.dominance_theta, S, stc);
     DBuf<int8_t> state;
     StepScope st_pmis("amg setup: pmis" + at);
-    const int rounds = pmis(c, A, S, stc, p.seed, lvl, state, p.coarsening == 1 ? p.hmis_tile : 0);
+    int rounds = pmis(c, A, S, stc, p.seed, lvl, state, p.coarsening == 1 ? p.hmis_tile : 0);
     StepScope st_cnum("amg setup: coarse numbering" + at);
     DBuf<int> isc(c, (size_t)n), cidx(c, (size_t)n + 1);
     hipLaunchKernelGGL(k_is_c, dim3(cdiv(n, 256)), dim3(256), 0, c->stream, n, state.get(),
                        isc.get());
     MGD_CHECK_LAUNCH();
-    const int nc = exclusive_scan_total(c, isc.get(), cidx.get(), n);
+    int nc = exclusive_scan_total(c, isc.get(), cidx.get(), n);
+    const bool aggressive = lvl < p.aggressive_levels;
+    if (aggressive && nc > 0) {
+      StepScope st_agg("amg setup: aggressive second pass" + at);
+      rounds += aggressive_split(c, A, S, cidx, nc, p.seed, lvl,
+                                 p.coarsening == 1 ? p.hmis_tile : 0, state);
+      hipLaunchKernelGGL(k_is_c, dim3(cdiv(n, 256)), dim3(256), 0, c->stream, n, state.get(),
+                         isc.get());
+      MGD_CHECK_LAUNCH();
+      nc = exclusive_scan_total(c, isc.get(), cidx.get(), n);
+    }
     if (nc == 0 || 10LL * nc > 9LL * n) {  // stalled coarsening: this is the coarsest level
       L.A = std::move(A);
       H.levels.push_back(std::move(L));
@@ -876,7 +1241,10 @@ void amg_build(Ctx* c, Csr<double>&& A0, const amg_params& p, SetupHierarchy& H)
     Csr<double> P, R, AP, Ac;
     {
       StepScope st("amg setup: interpolation" + at);
-      interpolation(c, A, S, state, cidx, nc, P);
+      if (aggressive)
+        multipass_interpolation(c, A, S, state, cidx, nc, P);
+      else
+        interpolation(c, A, S, state, cidx, nc, P);
       check_structure(c, P, "interpolation", false);
     }
     {

@@ -160,6 +160,7 @@ void fill(Ctx* c, T* p, T v, size_t n) {
 }
 template void fill<int>(Ctx*, int*, int, size_t);
 template void fill<int8_t>(Ctx*, int8_t*, int8_t, size_t);
+template void fill<uint8_t>(Ctx*, uint8_t*, uint8_t, size_t);
 template void fill<double>(Ctx*, double*, double, size_t);
 template void fill<float>(Ctx*, float*, float, size_t);
 

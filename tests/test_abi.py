@@ -48,7 +48,7 @@ def test_host_defaults_follow_the_paper(lib):
     p = _lib.amg_params()
     lib.amg_params_default(ctypes.byref(p))
     assert p.strength_theta == 0.25 and p.coarse_max == 100 and p.n_pre == 1 and p.n_post == 1
-    assert p.dominance_theta == 0.9 and p.max_levels == 25
+    assert p.dominance_theta == 0.9 and p.max_levels == 25 and p.aggressive_levels == 0
     g = _lib.gmres_params()
     lib.gmres_params_default(ctypes.byref(g))
     assert g.restart == 30 and g.rtol == 1e-8 and g.max_iters == 1000
@@ -78,6 +78,7 @@ def test_struct_layouts_match_c(tmp_path):
     src += '  printf("block_params.inner_maxcycles %zu\\n", offsetof(block_params, inner_maxcycles));\n'
     src += '  printf("block_params.option4_steps %zu\\n", offsetof(block_params, option4_steps));\n'
     src += '  printf("block_precond_info.inner_cycles %zu\\n", offsetof(block_precond_info, inner_cycles));\n'
+    src += '  printf("amg_params.aggressive_levels %zu\\n", offsetof(amg_params, aggressive_levels));\n'
     src += "  return 0;\n}\n"
     c = tmp_path / "probe.c"
     c.write_text(src)
@@ -95,6 +96,7 @@ def test_struct_layouts_match_c(tmp_path):
     assert int(got["block_params.inner_maxcycles"]) == _lib.block_params.inner_maxcycles.offset
     assert int(got["block_params.option4_steps"]) == _lib.block_params.option4_steps.offset
     assert int(got["block_precond_info.inner_cycles"]) == _lib.block_precond_info.inner_cycles.offset
+    assert int(got["amg_params.aggressive_levels"]) == _lib.amg_params.aggressive_levels.offset
 
 
 def test_product_path_has_no_cpu_fallback():

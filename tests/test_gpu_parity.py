@@ -196,6 +196,34 @@ def test_amg_setup_hmis_bit_exact(ctx, which, tile):
     assert rel(to_host(g.apply(to_dev(ctx, b))), oamg.vcycle(H, b)) < 1e-12
 
 
+@pytest.mark.parametrize("which,coarsening,levels", [("block_g0_3d10", 0, 1),
+                                                     ("mono_g2_2d16_nonsym", 0, 1),
+                                                     ("block_E_g2_2d16", 1, 1),
+                                                     ("mono_g1_2d64", 0, 2)])
+def test_amg_setup_aggressive_bit_exact(ctx, which, coarsening, levels):
+    """Aggressive coarsening (a second pass over the C points on their
+    distance-two strength graph, multipass interpolation) on the finest
+    `levels` levels: the hierarchy equals the oracle's bit for bit, and one
+    V-cycle agrees to 1e-12."""
+    api = gpu_modules()
+    if which == "block_E_g2_2d16":
+        A = oracle_system(si.generate_workload("g2_2d16")).blocks[2]
+    elif which == "block_g0_3d10":
+        A = oracle_system(si.generate(1, 3, 10, 31)).blocks[0]
+    elif which == "mono_g1_2d64":
+        A = oracle_system(si.generate_workload("g1_2d64")).monolithic()
+    else:
+        A = oracle_system(si.generate(2, 2, 16, 32, nonsym=True)).monolithic()
+    H = oamg.setup(A, oamg.AMGParams(seed=5, coarsening=("hmis" if coarsening else "pmis"),
+                                     hmis_tile=128, aggressive_levels=levels))
+    g = api.AMG(ctx, A.indptr, A.indices, A.data, seed=5, coarsening=coarsening, hmis_tile=128,
+                aggressive_levels=levels)
+    _compare_hierarchies(g, H, exact_values=True)
+    assert H.levels[1].A.shape[0] * 4 < A.shape[0]
+    b = np.random.default_rng(6).uniform(size=A.shape[0])
+    assert rel(to_host(g.apply(to_dev(ctx, b))), oamg.vcycle(H, b)) < 1e-12
+
+
 def test_amg_levelwise_on_gpu_levels(ctx):
     """Binding test: the oracle's strength, PMIS and interpolation applied to
     each GPU level matrix give the GPU's C/F splitting and P bit for bit."""
@@ -612,6 +640,30 @@ def test_gmres_parity(ctx, kind):
     xo2, _ = okry.gmres(A.__matmul__, M_o, inp.b, rtol=0.0, max_iters=io.iters)
     xg2, r2 = api.gmres(ctx, gsys, M_g, b, rtol=0.0, max_iters=io.iters)
     assert r2.status == -4 and r2.iters == io.iters
+    assert rel(to_host(xg2), xo2) < 1e-10
+
+
+@pytest.mark.parametrize("kind", ["amg", "schur2"])
+def test_gmres_aggressive_parity(ctx, kind):
+    """Inner AMG with aggressive coarsening on the finest level: the same
+    iteration count as the oracle and the same iterate after it."""
+    api = gpu_modules()
+    inp = si.generate_workload("g1_2d64")
+    osys = oracle_system(inp)
+    A = osys.monolithic()
+    M_o = opc.BlockPreconditioner(osys, opc.BlockParams(
+        kind=kind, amg=oamg.AMGParams(seed=1, aggressive_levels=1)))
+    xo, io = okry.gmres(A.__matmul__, M_o, inp.b, rtol=1e-8)
+    co, gsys = gpu_system(ctx, inp)
+    M_g = api.BlockPreconditioner(ctx, gsys, kind, amg_seed=1, amg_aggressive_levels=1)
+    b = to_dev(ctx, inp.b)
+    xg, rg = api.gmres(ctx, gsys, M_g, b, rtol=1e-8)
+    assert rg.converged and io.converged
+    assert abs(rg.iters - io.iters) <= 1, (rg.iters, io.iters)
+    assert np.linalg.norm(inp.b - A @ to_host(xg)) <= 1e-8 * np.linalg.norm(inp.b)
+    xo2, _ = okry.gmres(A.__matmul__, M_o, inp.b, rtol=0.0, max_iters=io.iters)
+    xg2, r2 = api.gmres(ctx, gsys, M_g, b, rtol=0.0, max_iters=io.iters)
+    assert r2.iters == io.iters
     assert rel(to_host(xg2), xo2) < 1e-10
 
 
