@@ -623,21 +623,49 @@ struct GatherCOnly {  // first F half-sweep: F values are still zero
   int nC;
 };
 
+// position of row `row` in its slice (o: its first element, w: the slice
+// width) and, for SELL16, the slice's two column bases
+template <int FMT>
+__device__ __forceinline__ void sell_slice(const int* __restrict__ rp, int row, int& o, int& w,
+                                           int& cb, int& fb) {
+  if (FMT == kFmtSELL16) {
+    const int s3 = 3 * (row >> 6);
+    o = rp[s3] + (row & 63);
+    w = (rp[s3 + 3] - rp[s3]) >> 6;
+    cb = rp[s3 + 1];
+    fb = rp[s3 + 2];
+  } else {
+    o = rp[row >> 6] + (row & 63);
+    w = (rp[(row >> 6) + 1] - rp[row >> 6]) >> 6;
+    cb = fb = 0;
+  }
+}
+__device__ __forceinline__ int sell16_decode(unsigned u, int cb, int fb) {
+  return (u & 0x8000u) ? fb + (int)(u & 0x7fffu) : cb + (int)u;
+}
+// column of element idx of a sliced layout
+template <int FMT>
+__device__ __forceinline__ int sell_col(const int* __restrict__ ci, int idx, int cb, int fb) {
+  if (FMT == kFmtSELL16)
+    return sell16_decode(reinterpret_cast<const uint16_t*>(ci)[idx], cb, fb);
+  return ci[idx];
+}
+
 // sum over row `row` of a_rj g(j), entries in stored order; SELL uses one
 // lane per row, CSR `TPR` lanes of a wavefront per row (butterfly combine)
 template <int FMT, int TPR, typename T, typename G>
 __device__ __forceinline__ T mrow(const int* __restrict__ rp, const int* __restrict__ ci,
                                   const T* __restrict__ v, const G& g, int row, int lane) {
   T s = 0;
-  if (FMT == kFmtSELL) {
-    const int o = rp[row >> 6] + (row & 63);
-    const int w = (rp[(row >> 6) + 1] - rp[row >> 6]) >> 6;
+  if (FMT == kFmtSELL || FMT == kFmtSELL16) {
+    int o, w, cb, fb;
+    sell_slice<FMT>(rp, row, o, w, cb, fb);
     int e = 0;
     for (; e + 4 <= w; e += 4) {  // four entries' loads in flight (sum order unchanged)
       int j[4];
       T a[4], x[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) j[q] = ci[o + 64 * (e + q)];
+      for (int q = 0; q < 4; ++q) j[q] = sell_col<FMT>(ci, o + 64 * (e + q), cb, fb);
 #pragma unroll
       for (int q = 0; q < 4; ++q) a[q] = v[o + 64 * (e + q)];
 #pragma unroll
@@ -645,7 +673,7 @@ __device__ __forceinline__ T mrow(const int* __restrict__ rp, const int* __restr
 #pragma unroll
       for (int q = 0; q < 4; ++q) s += a[q] * x[q];
     }
-    for (; e < w; ++e) s += v[o + 64 * e] * g(ci[o + 64 * e]);
+    for (; e < w; ++e) s += v[o + 64 * e] * g(sell_col<FMT>(ci, o + 64 * e, cb, fb));
   } else {
     const int e1 = rp[row + 1];
     int e = rp[row] + lane;
@@ -677,15 +705,15 @@ __device__ __forceinline__ T mrow_c(const int* __restrict__ rp, const int* __res
                                     int row, int lane) {
   T s = 0;
   if (nC == 0) return s;
-  if (FMT == kFmtSELL) {
-    const int o = rp[row >> 6] + (row & 63);
-    const int w = (rp[(row >> 6) + 1] - rp[row >> 6]) >> 6;
+  if (FMT == kFmtSELL || FMT == kFmtSELL16) {
+    int o, w, cb, fb;
+    sell_slice<FMT>(rp, row, o, w, cb, fb);
     int e = 0;
     for (; e + 4 <= w; e += 4) {
       int j[4];
       T a[4], x[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) j[q] = ci[o + 64 * (e + q)];
+      for (int q = 0; q < 4; ++q) j[q] = sell_col<FMT>(ci, o + 64 * (e + q), cb, fb);
 #pragma unroll
       for (int q = 0; q < 4; ++q) a[q] = j[q] < nC ? v[o + 64 * (e + q)] : (T)0;
 #pragma unroll
@@ -694,7 +722,7 @@ __device__ __forceinline__ T mrow_c(const int* __restrict__ rp, const int* __res
       for (int q = 0; q < 4; ++q) s += a[q] * x[q];
     }
     for (; e < w; ++e) {
-      const int j = ci[o + 64 * e];
+      const int j = sell_col<FMT>(ci, o + 64 * e, cb, fb);
       if (j < nC) s += v[o + 64 * e] * xc[j];
     }
   } else {
@@ -927,6 +955,10 @@ static void with_layout(int fmt, int tpr, F&& f) {
     f.template go<kFmtSELL, 1>();
     return;
   }
+  if (fmt == kFmtSELL16) {
+    f.template go<kFmtSELL16, 1>();
+    return;
+  }
   switch (tpr) {
     case 1: f.template go<kFmtCSR, 1>(); break;
     case 2: f.template go<kFmtCSR, 2>(); break;
@@ -949,7 +981,7 @@ static std::string kname(const Ctx* c, const char* base, const LMat<T>& m,
                          std::initializer_list<std::string> extra = {}) {
   if (!c->profiling) return std::string();
   std::vector<std::string> a{type_name<T>(), std::to_string(m.fmt),
-                             std::to_string(m.fmt == kFmtSELL ? 1 : tpr_of(m.tpr))};
+                             std::to_string(m.fmt != kFmtCSR ? 1 : tpr_of(m.tpr))};
   for (const auto& e : extra) a.push_back(e);
   std::string s(base);
   const char* sep = "<";
@@ -1108,8 +1140,8 @@ struct ProlongL {
 // algorithmic bytes per launch: every matrix entry (value + column), every
 // per-row vector element read or written, and the gathered iterate once
 template <typename T>
-static double mat_bytes(long long nnz) {
-  return (double)nnz * (sizeof(T) + 4);
+static double mat_bytes(const LMat<T>& m, long long nnz) {
+  return (double)nnz * (sizeof(T) + (m.fmt == kFmtSELL16 ? 2 : 4));
 }
 static inline int cls_of(int l, int cls0) { return l == 0 ? cls0 : KC_VCYCLE_COARSE; }
 
@@ -1139,7 +1171,7 @@ void Union<T>::vcycle(Ctx* c, T* z) {
       for (int s = 0; s < n_pre; ++s) {
         if (s > 0) {  // C half of a later sweep
           ProfScope ps(c, cls_of(l, KC_SMOOTH_L0),
-                       mat_bytes<T>(lv.nnz_C) + (double)lv.nC * 4 * ts + lv.nS * ts,
+                       mat_bytes(lv.A, lv.nnz_C) + (double)lv.nC * 4 * ts + lv.nS * ts,
                        kname(c, "k_half", lv.A));
           with_layout(lv.A.fmt, lv.A.tpr,
                       HalfL<T>{c, lv.A, 0, lv.nC, lv.dinv.get(), B[l].get(),
@@ -1150,14 +1182,14 @@ void Union<T>::vcycle(Ctx* c, T* z) {
         if (nF > 0) {
           if (s == 0) {
             ProfScope ps(c, cls_of(l, KC_SMOOTH_L0),
-                         mat_bytes<T>(lv.nnz_F) + (double)nF * 3 * ts + lv.nC * ts,
+                         mat_bytes(lv.A, lv.nnz_F) + (double)nF * 3 * ts + lv.nC * ts,
                          kname(c, "k_fhalf0", lv.A));
             with_layout(lv.A.fmt, lv.A.tpr,
                         FHalf0L<T>{c, lv.A, lv.nC, lv.nS, lv.nC, lv.dinv.get(), B[l].get(),
                                    Xb(l, cc[l]), Xb(l, 1 - cf[l])});
           } else {
             ProfScope ps(c, cls_of(l, KC_SMOOTH_L0),
-                         mat_bytes<T>(lv.nnz_F) + (double)nF * 4 * ts + lv.nS * ts,
+                         mat_bytes(lv.A, lv.nnz_F) + (double)nF * 4 * ts + lv.nS * ts,
                          kname(c, "k_half", lv.A));
             with_layout(lv.A.fmt, lv.A.tpr,
                         HalfL<T>{c, lv.A, lv.nC, lv.nS, lv.dinv.get(), B[l].get(),
@@ -1171,7 +1203,7 @@ void Union<T>::vcycle(Ctx* c, T* z) {
       if (lv.nX_next > 0) {
         {
           ProfScope ps(c, cls_of(l, KC_RESID_L0),
-                       mat_bytes<T>(lv.A.nnz) + (double)lv.nS * 3 * ts,
+                       mat_bytes(lv.A, lv.A.nnz) + (double)lv.nS * 3 * ts,
                        kname(c, "k_resid", lv.A));
           with_layout(lv.A.fmt, lv.A.tpr,
                       ResidL<T>{c, lv.A, lv.nS, B[l].get(),
@@ -1179,7 +1211,7 @@ void Union<T>::vcycle(Ctx* c, T* z) {
         }
         const ULevel<T>& nx = L[l + 1];
         ProfScope ps(c, cls_of(l, KC_TRANSFER_L0),
-                     mat_bytes<T>(lv.Wt.nnz) + (double)lv.nX_next * (4 + ts) +
+                     mat_bytes(lv.Wt, lv.Wt.nnz) + (double)lv.nX_next * (4 + ts) +
                          (double)nx.nC * 2 * ts + lv.nS * ts,
                      kname(c, "k_restrict", lv.Wt, {n_pre > 0 ? "true" : "false"}));
         with_layout(lv.Wt.fmt, lv.Wt.tpr,
@@ -1203,7 +1235,7 @@ void Union<T>::vcycle(Ctx* c, T* z) {
     if (lv.nS > 0 && lv.nX_next > 0) {
       const ULevel<T>& nx = L[l + 1];
       ProfScope ps(c, cls_of(l, KC_TRANSFER_L0),
-                   mat_bytes<T>(lv.W.nnz) + (double)lv.nC * 4 + lv.nS * 2.0 * ts +
+                   mat_bytes(lv.W, lv.W.nnz) + (double)lv.nC * 4 + lv.nS * 2.0 * ts +
                        (double)lv.nX_next * ts,
                    kname(c, "k_prolong", lv.W));
       with_layout(lv.W.fmt, lv.W.tpr,
@@ -1217,7 +1249,7 @@ void Union<T>::vcycle(Ctx* c, T* z) {
       for (int s = 0; s < n_post; ++s) {
         if (nF > 0) {
           ProfScope ps(c, cls_of(l, KC_SMOOTH_L0),
-                       mat_bytes<T>(lv.nnz_F) + (double)nF * 4 * ts + lv.nS * ts,
+                       mat_bytes(lv.A, lv.nnz_F) + (double)nF * 4 * ts + lv.nS * ts,
                        kname(c, "k_half", lv.A));
           with_layout(lv.A.fmt, lv.A.tpr,
                       HalfL<T>{c, lv.A, lv.nC, lv.nS, lv.dinv.get(), B[l].get(),
@@ -1227,7 +1259,7 @@ void Union<T>::vcycle(Ctx* c, T* z) {
         }
         if (last_out && s == n_post - 1) {  // final C half writes the natural result
           ProfScope ps(c, KC_SMOOTH_L0,
-                       mat_bytes<T>(lv.nnz_C) + (double)lv.nC * 3 * ts + lv.nS * ts +
+                       mat_bytes(lv.A, lv.nnz_C) + (double)lv.nC * 3 * ts + lv.nS * ts +
                            (double)lv.nX * (4 + ts),
                        kname(c, "k_half_out", lv.A));
           with_layout(lv.A.fmt, lv.A.tpr,
@@ -1237,7 +1269,7 @@ void Union<T>::vcycle(Ctx* c, T* z) {
           return;
         }
         ProfScope ps(c, cls_of(l, KC_SMOOTH_L0),
-                     mat_bytes<T>(lv.nnz_C) + (double)lv.nC * 4 * ts + lv.nS * ts,
+                     mat_bytes(lv.A, lv.nnz_C) + (double)lv.nC * 4 * ts + lv.nS * ts,
                      kname(c, "k_half", lv.A));
         with_layout(lv.A.fmt, lv.A.tpr,
                     HalfL<T>{c, lv.A, 0, lv.nC, lv.dinv.get(), B[l].get(),
@@ -1347,7 +1379,7 @@ void Union<T>::apply(Ctx* c, const T* bvec, T* z, int cycles) {
   for (int k = 1; k < cycles; ++k) {
     {
       ProfScope ps(c, KC_RESID_L0,
-                   mat_bytes<T>(l0.A.nnz) + (double)l0.nX * (8 + 3.0 * sizeof(T)),
+                   mat_bytes(l0.A, l0.A.nnz) + (double)l0.nX * (8 + 3.0 * sizeof(T)),
                    kname(c, "k_entry_resid", l0.A, {pre ? "true" : "false"}));
       with_layout(l0.A.fmt, l0.A.tpr,
                   EntryResidL<T>{c, l0.A, l0.nX, l0.nS, l0.nC, l0.perm.get(), l0.dinv.get(), bvec,
@@ -1372,13 +1404,13 @@ double Union<T>::bytes_per_vcycle() const {
     const auto& lv = L[l];
     const double nF = lv.nS - lv.nC;
     if (lv.nS > 0) {
-      s += mat_bytes<T>(lv.nnz_F) * (n_pre + n_post) + mat_bytes<T>(lv.nnz_C) * (n_pre + n_post - 1);
+      s += mat_bytes(lv.A, lv.nnz_F) * (n_pre + n_post) + mat_bytes(lv.A, lv.nnz_C) * (n_pre + n_post - 1);
       s += (nF * 4 * ts + lv.nS * ts) * (n_pre + n_post) +
            (lv.nC * 4 * ts + lv.nS * ts) * (n_pre + n_post - 1);
       if (lv.nX_next > 0) {
-        s += mat_bytes<T>(lv.A.nnz) + lv.nS * 3 * ts;
-        s += mat_bytes<T>(lv.Wt.nnz) + lv.nX_next * (4 + ts) + lv.nS * ts;
-        s += mat_bytes<T>(lv.W.nnz) + lv.nC * 4.0 + lv.nS * 2.0 * ts + lv.nX_next * ts;
+        s += mat_bytes(lv.A, lv.A.nnz) + lv.nS * 3 * ts;
+        s += mat_bytes(lv.Wt, lv.Wt.nnz) + lv.nX_next * (4 + ts) + lv.nS * ts;
+        s += mat_bytes(lv.W, lv.W.nnz) + lv.nC * 4.0 + lv.nS * 2.0 * ts + lv.nX_next * ts;
       }
     }
     s += 8.0 * lv.dense_entries;
@@ -1477,11 +1509,77 @@ __global__ void k_sell_fill(int rows, const int* __restrict__ rp, const int* __r
   }
 }
 
+// SELL16 bases of slice s from the real entries of its rows (CSR M): the
+// smallest column below `split` and the smallest at or above it (0 without
+// one); ok is cleared when a side spans 2^15 columns or more
+__global__ void k_sell16_bases(int rows, const int* __restrict__ rp, const int* __restrict__ ci,
+                               int split, const int* __restrict__ off, int* __restrict__ rp3,
+                               int* __restrict__ ok) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ns = (rows + 63) / 64;
+  if (s >= ns) return;
+  int cmin = INT_MAX, cmax = -1, fmin = INT_MAX, fmax = -1;
+  const int r1 = min(rows, 64 * s + 64);
+  for (int r = 64 * s; r < r1; ++r)
+    for (int e = rp[r]; e < rp[r + 1]; ++e) {
+      const int j = ci[e];
+      if (j < split) {
+        cmin = min(cmin, j);
+        cmax = max(cmax, j);
+      } else {
+        fmin = min(fmin, j);
+        fmax = max(fmax, j);
+      }
+    }
+  if ((cmax >= 0 && cmax - cmin > 0x7fff) || (fmax >= 0 && fmax - fmin > 0x7fff)) atomicAnd(ok, 0);
+  rp3[3 * s] = off[s];
+  rp3[3 * s + 1] = cmax >= 0 ? cmin : 0;
+  rp3[3 * s + 2] = fmax >= 0 ? fmin : 0;
+  if (s == ns - 1) rp3[3 * ns] = off[ns];
+}
+// codes of row r: column - C base below the split, (column - F base) | 2^15
+// at or above it; padding elements get code 0 (the C base, weight zero)
+__global__ void k_sell16_encode(int rows, const int* __restrict__ rp, const int* __restrict__ ci,
+                                int split, const int* __restrict__ rp3,
+                                uint16_t* __restrict__ c16) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int s3 = 3 * (r >> 6);
+  const int o = rp3[s3] + (r & 63), w = (rp3[s3 + 3] - rp3[s3]) >> 6;
+  const int cb = rp3[s3 + 1], fb = rp3[s3 + 2];
+  const int e0 = rp[r], len = rp[r + 1] - e0;
+  for (int q = 0; q < w; ++q) {
+    unsigned code = 0;
+    if (q < len) {
+      const int j = ci[e0 + q];
+      code = j < split ? (unsigned)(j - cb) : (0x8000u | (unsigned)(j - fb));
+    }
+    c16[o + 64 * q] = (uint16_t)code;
+  }
+}
+// every real element decodes to its CSR column, every padding element to a
+// column inside [0, ncols)
+__global__ void k_sell16_check(int rows, int ncols, const int* __restrict__ rp,
+                               const int* __restrict__ ci, const int* __restrict__ rp3,
+                               const uint16_t* __restrict__ c16, int* __restrict__ err) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int s3 = 3 * (r >> 6);
+  const int o = rp3[s3] + (r & 63), w = (rp3[s3 + 3] - rp3[s3]) >> 6;
+  const int cb = rp3[s3 + 1], fb = rp3[s3 + 2];
+  const int e0 = rp[r], len = rp[r + 1] - e0;
+  for (int q = 0; q < w; ++q) {
+    const int j = sell16_decode(c16[o + 64 * q], cb, fb);
+    if (q < len ? j != ci[e0 + q] : (j < 0 || j >= ncols)) atomicOr(err, 4);
+  }
+}
+
 // CSR (FP64 values) -> layout `fmt` with values in T; `self_pad` pads SELL rows
-// with their own index as column (square stored-order matrices), else column 0
+// with their own index as column (square stored-order matrices), else column 0.
+// A SELL result becomes SELL16 when split16 >= 0 and every slice fits.
 template <typename T>
 static void to_layout(Ctx* c, const Csr<double>& M, int fmt, int tpr, bool self_pad,
-                      LMat<T>& out) {
+                      LMat<T>& out, int split16 = -1) {
   out.rows = M.n_rows;
   out.nnz = M.nnz;
   out.fmt = fmt;
@@ -1513,6 +1611,28 @@ static void to_layout(Ctx* c, const Csr<double>& M, int fmt, int tpr, bool self_
                      out.ci.get(), out.v.get());
   MGD_CHECK_LAUNCH();
   c->sync();
+  if (split16 < 0 || M.nnz == 0) return;
+  DBuf<int> rp3(c, 3 * (size_t)ns + 1), ok(c, 1);
+  fill<int>(c, ok.get(), 1, 1);
+  hipLaunchKernelGGL(k_sell16_bases, dim3(cdiv(ns, 256)), dim3(256), 0, c->stream, M.n_rows,
+                     (const int*)M.rp.get(), (const int*)M.ci.get(), split16,
+                     (const int*)out.rp.get(), rp3.get(), ok.get());
+  MGD_CHECK_LAUNCH();
+  if (!read1(c, ok.get())) return;  // some slice spans too many columns: stay SELL
+  DBuf<int> c16(c, (size_t)std::max(1LL, (out.stored + 1) / 2));
+  hipLaunchKernelGGL(k_sell16_encode, dim3(cdiv(M.n_rows, 256)), dim3(256), 0, c->stream,
+                     M.n_rows, (const int*)M.rp.get(), (const int*)M.ci.get(), split16,
+                     (const int*)rp3.get(), reinterpret_cast<uint16_t*>(c16.get()));
+  MGD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_sell16_check, dim3(cdiv(M.n_rows, 256)), dim3(256), 0, c->stream,
+                     M.n_rows, M.n_cols, (const int*)M.rp.get(), (const int*)M.ci.get(),
+                     (const int*)rp3.get(), reinterpret_cast<const uint16_t*>(c16.get()),
+                     c->err_flag());
+  MGD_CHECK_LAUNCH();
+  c->check_device_errors("16-bit sliced layout");
+  out.rp = std::move(rp3);
+  out.ci = std::move(c16);
+  out.fmt = kFmtSELL16;
 }
 // padded size of the SELL layout of M (host-side estimate through the device widths)
 static long long sell_stored(Ctx* c, const Csr<double>& M) {
@@ -1530,6 +1650,17 @@ static void tune_layout(Ctx* c, ULevel<T>& lv, const Csr<double>& A, int autotun
 
 constexpr long long kFillLanes = 1 << 17;  // lanes that keep all compute units busy
 constexpr int kSellMinRows = 1 << 17;
+// Test overrides: MGD_SELL_MIN_ROWS lowers the row count from which sliced
+// layouts are considered (so that small systems exercise them), MGD_SELL16=0
+// keeps sliced layouts at 32-bit columns.
+static long long sell_min_rows() {
+  const char* e = std::getenv("MGD_SELL_MIN_ROWS");
+  return e && *e ? std::max(1LL, std::atoll(e)) : (long long)kSellMinRows;
+}
+static bool sell16_enabled() {
+  const char* e = std::getenv("MGD_SELL16");
+  return !(e && e[0] == '0');
+}
 // lanes per row so that a small matrix still spreads over the device
 static int small_level_tpr(long long rows, double avg) {
   int t = 1;
@@ -1539,10 +1670,10 @@ static int small_level_tpr(long long rows, double avg) {
 // interpolation / restriction layout: SELL for large matrices with little
 // padding, otherwise CSR with enough lanes per row
 template <typename T>
-static void layout_transfer(Ctx* c, const Csr<double>& M, LMat<T>& out) {
+static void layout_transfer(Ctx* c, const Csr<double>& M, LMat<T>& out, int split16) {
   const double avg = M.n_rows ? (double)M.nnz / M.n_rows : 1.0;
-  if (M.nnz > 0 && M.n_rows >= kSellMinRows && sell_stored(c, M) <= (long long)(1.5 * M.nnz))
-    to_layout<T>(c, M, kFmtSELL, 1, false, out);
+  if (M.nnz > 0 && M.n_rows >= sell_min_rows() && sell_stored(c, M) <= (long long)(1.5 * M.nnz))
+    to_layout<T>(c, M, kFmtSELL, 1, false, out, sell16_enabled() ? split16 : -1);
   else
     to_layout<T>(c, M, kFmtCSR, std::max(small_level_tpr(M.n_rows, avg), default_tpr(avg)), false,
                  out);
@@ -1674,8 +1805,10 @@ static void finalize_levels(Ctx* c, std::vector<BuildLevel<T>>& bl, Union<T>& U,
                             "stored-order interpolation");
       check_index_structure(c, Wt2.n_rows, b.nS - b.nC, Wt2.nnz, Wt2.rp.get(), Wt2.ci.get(),
                             "stored-order restriction");
-      layout_transfer<T>(c, b.W, lv.W);
-      layout_transfer<T>(c, Wt2, lv.Wt);
+      // W gathers from three regions of the next level: 32-bit columns;
+      // W^T's columns are F indices, one region
+      layout_transfer<T>(c, b.W, lv.W, -1);
+      layout_transfer<T>(c, Wt2, lv.Wt, 0);
     }
     c->check_device_errors("stored-order level");
     tune_layout<T>(c, lv, b.A, autotune, sizeof(T) == 4);
@@ -1717,7 +1850,7 @@ static void tune_layout(Ctx* c, ULevel<T>& lv, const Csr<double>& A, int autotun
   const long long st = sell_stored(c, A);
   auto apply = [&](int code) {
     if (code == kTuneSell)
-      to_layout<T>(c, A, kFmtSELL, 1, true, lv.A);
+      to_layout<T>(c, A, kFmtSELL, 1, true, lv.A, sell16_enabled() ? lv.nC : -1);
     else
       to_layout<T>(c, A, kFmtCSR, code, true, lv.A);
   };
@@ -1728,7 +1861,7 @@ static void tune_layout(Ctx* c, ULevel<T>& lv, const Csr<double>& A, int autotun
   }
   // enough lanes to occupy the device on small levels (a lane per row serialises
   // long rows), SELL when the level is large and its padding small
-  const int dflt = (lv.nS >= kSellMinRows && st <= (long long)(1.3 * A.nnz))
+  const int dflt = (lv.nS >= sell_min_rows() && st <= (long long)(1.3 * A.nnz))
                        ? kTuneSell
                        : std::max(small_level_tpr(lv.nS, avg), default_tpr(avg));
   if (!autotune) {

@@ -32,17 +32,24 @@ struct DenseDev {
 //         slice's longest row as its width (entry e of row 64 s + t at
 //         off[s] + 64 e + t; padding entries are zero with the row's own
 //         column), so one lane per row reads consecutive addresses;
+//   SELL16: SELL with 16-bit column offsets (below);
 //   CSR:  row pointers, and `tpr` lanes of a wavefront per row.
 template <typename T>
 struct LMat {
-  int rows = 0, fmt = 0, tpr = 1;  // fmt: 0 CSR, 1 SELL
+  int rows = 0, fmt = 0, tpr = 1;  // fmt: 0 CSR, 1 SELL, 2 SELL16
   long long nnz = 0;               // entries (without padding)
   long long stored = 0;            // stored entries (with padding)
-  DBuf<int> rp;                    // CSR: rows + 1 row pointers; SELL: slices + 1 offsets
-  DBuf<int> ci;
+  DBuf<int> rp;                    // CSR: rows + 1 row pointers; SELL: slices + 1 offsets;
+                                   // SELL16: 3 slices + 1 (offset, two column bases)
+  DBuf<int> ci;                    // SELL16: 16-bit codes, two per element
   DBuf<T> v;
 };
-enum { kFmtCSR = 0, kFmtSELL = 1 };
+// SELL16: SELL whose columns are 16-bit offsets from two bases per slice,
+// one for the columns below a split (the C-block of a level matrix) and one
+// for the rest (bit 15 set); slice s keeps its entry offset and the two bases
+// at rp[3s], rp[3s+1], rp[3s+2] (rp[3 * slices] = stored entries).  Used
+// when every slice's columns on each side of the split span less than 2^15.
+enum { kFmtCSR = 0, kFmtSELL = 1, kFmtSELL16 = 2 };
 
 // One level of a union in extended stored order: [0, nC) the C-block, [nC, nS)
 // the F-block (rows smoothed, F points and relaxed coarsest rows), [nS, nX)

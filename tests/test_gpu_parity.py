@@ -295,6 +295,31 @@ def test_vcycle_parity(ctx, cycles, precision):
     assert rel(z, ref) < (1e-12 if precision == 0 else 2e-5)
 
 
+@pytest.mark.parametrize("sell16", ["1", "0"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sliced_layouts_forced_small(ctx, monkeypatch, sell16, precision):
+    """Sliced-ELL level layouts, with 32-bit columns or with 16-bit offsets from
+    two column bases per 64-row slice, forced on every level of small systems:
+    two V-cycles and a batched Schur2 apply agree with the oracle."""
+    monkeypatch.setenv("MGD_SELL_MIN_ROWS", "64")
+    monkeypatch.setenv("MGD_SELL16", sell16)
+    api = gpu_modules()
+    tol = 1e-12 if precision == 0 else 2e-5
+    A = oracle_system(si.generate_workload("g1_2d64")).monolithic()
+    H = oamg.setup(A, oamg.AMGParams(seed=1))
+    g = api.AMG(ctx, A.indptr, A.indices, A.data, seed=1, precision=precision)
+    b = np.random.default_rng(2).uniform(size=A.shape[0])
+    assert rel(to_host(g.apply(to_dev(ctx, b), cycles=2)), oamg.apply_cycles(H, b, 2)) < tol
+    inp = si.generate(3, 2, 24, 41)
+    osys = oracle_system(inp)
+    M_o = opc.BlockPreconditioner(osys, opc.BlockParams(kind="schur2", amg=oamg.AMGParams(seed=5)))
+    co, gsys = gpu_system(ctx, inp)
+    M_g = api.BlockPreconditioner(ctx, gsys, "schur2", amg_seed=5, batched=1,
+                                  amg_precision=precision)
+    r = np.random.default_rng(4).standard_normal(osys.n)
+    assert rel(to_host(M_g.apply(to_dev(ctx, r))), M_o(r)) < (1e-10 if precision == 0 else 5e-5)
+
+
 def test_vcycle_n_pre_n_post(ctx):
     api = gpu_modules()
     A = oracle_system(si.generate(1, 2, 20, 9)).blocks[0]
