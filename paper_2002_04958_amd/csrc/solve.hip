@@ -623,19 +623,22 @@ struct GatherCOnly {  // first F half-sweep: F values are still zero
   int nC;
 };
 
-// position of row `row` in its slice (o: its first element, w: the slice
-// width) and, for SELL16, the slice's two column bases
+// position of row `row` in its slice: o its first value, oc its first column
+// code, w the slice width; for SELL16 the slice's two column bases (fb < 0:
+// the slice keeps 32-bit columns, oc then counts 32-bit words)
 template <int FMT>
-__device__ __forceinline__ void sell_slice(const int* __restrict__ rp, int row, int& o, int& w,
-                                           int& cb, int& fb) {
+__device__ __forceinline__ void sell_slice(const int* __restrict__ rp, int row, int& o, int& oc,
+                                           int& w, int& cb, int& fb) {
   if (FMT == kFmtSELL16) {
-    const int s3 = 3 * (row >> 6);
-    o = rp[s3] + (row & 63);
-    w = (rp[s3 + 3] - rp[s3]) >> 6;
-    cb = rp[s3 + 1];
-    fb = rp[s3 + 2];
+    const int s4 = 4 * (row >> 6);
+    o = rp[s4] + (row & 63);
+    w = (rp[s4 + 4] - rp[s4]) >> 6;
+    cb = rp[s4 + 2];
+    fb = rp[s4 + 3];
+    oc = (fb < 0 ? rp[s4 + 1] >> 1 : rp[s4 + 1]) + (row & 63);
   } else {
     o = rp[row >> 6] + (row & 63);
+    oc = o;
     w = (rp[(row >> 6) + 1] - rp[row >> 6]) >> 6;
     cb = fb = 0;
   }
@@ -643,12 +646,57 @@ __device__ __forceinline__ void sell_slice(const int* __restrict__ rp, int row, 
 __device__ __forceinline__ int sell16_decode(unsigned u, int cb, int fb) {
   return (u & 0x8000u) ? fb + (int)(u & 0x7fffu) : cb + (int)u;
 }
-// column of element idx of a sliced layout
-template <int FMT>
+// column of code idx of a sliced layout: a 16-bit code (NARROW) or a 32-bit column
+template <bool NARROW>
 __device__ __forceinline__ int sell_col(const int* __restrict__ ci, int idx, int cb, int fb) {
-  if (FMT == kFmtSELL16)
-    return sell16_decode(reinterpret_cast<const uint16_t*>(ci)[idx], cb, fb);
+  if (NARROW) return sell16_decode(reinterpret_cast<const uint16_t*>(ci)[idx], cb, fb);
   return ci[idx];
+}
+// sum of a_rj g(j) over one sliced row (values from o, column codes from oc)
+template <bool NARROW, typename T, typename G>
+__device__ __forceinline__ T sell_row(const int* __restrict__ ci, const T* __restrict__ v,
+                                      const G& g, int o, int oc, int w, int cb, int fb) {
+  T s = 0;
+  int e = 0;
+  for (; e + 4 <= w; e += 4) {  // four entries' loads in flight (sum order unchanged)
+    int j[4];
+    T a[4], x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) j[q] = sell_col<NARROW>(ci, oc + 64 * (e + q), cb, fb);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = v[o + 64 * (e + q)];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[q] = g(j[q]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s += a[q] * x[q];
+  }
+  for (; e < w; ++e) s += v[o + 64 * e] * g(sell_col<NARROW>(ci, oc + 64 * e, cb, fb));
+  return s;
+}
+// the same over the C columns only (j < nC), F columns weighted zero
+template <bool NARROW, typename T>
+__device__ __forceinline__ T sell_row_c(const int* __restrict__ ci, const T* __restrict__ v,
+                                        const T* __restrict__ xc, int nC, int o, int oc, int w,
+                                        int cb, int fb) {
+  T s = 0;
+  int e = 0;
+  for (; e + 4 <= w; e += 4) {
+    int j[4];
+    T a[4], x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) j[q] = sell_col<NARROW>(ci, oc + 64 * (e + q), cb, fb);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = j[q] < nC ? v[o + 64 * (e + q)] : (T)0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[q] = xc[j[q] < nC ? j[q] : 0];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s += a[q] * x[q];
+  }
+  for (; e < w; ++e) {
+    const int j = sell_col<NARROW>(ci, oc + 64 * e, cb, fb);
+    if (j < nC) s += v[o + 64 * e] * xc[j];
+  }
+  return s;
 }
 
 // sum over row `row` of a_rj g(j), entries in stored order; SELL uses one
@@ -658,22 +706,14 @@ __device__ __forceinline__ T mrow(const int* __restrict__ rp, const int* __restr
                                   const T* __restrict__ v, const G& g, int row, int lane) {
   T s = 0;
   if (FMT == kFmtSELL || FMT == kFmtSELL16) {
-    int o, w, cb, fb;
-    sell_slice<FMT>(rp, row, o, w, cb, fb);
-    int e = 0;
-    for (; e + 4 <= w; e += 4) {  // four entries' loads in flight (sum order unchanged)
-      int j[4];
-      T a[4], x[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) j[q] = sell_col<FMT>(ci, o + 64 * (e + q), cb, fb);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) a[q] = v[o + 64 * (e + q)];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) x[q] = g(j[q]);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) s += a[q] * x[q];
-    }
-    for (; e < w; ++e) s += v[o + 64 * e] * g(sell_col<FMT>(ci, o + 64 * e, cb, fb));
+    int o, oc, w, cb, fb;
+    sell_slice<FMT>(rp, row, o, oc, w, cb, fb);
+    // a slice is 16-bit or 32-bit as a whole: lanes diverge only in the waves
+    // that straddle two slices
+    if (FMT == kFmtSELL16 && fb >= 0)
+      s = sell_row<true>(ci, v, g, o, oc, w, cb, fb);
+    else
+      s = sell_row<false>(ci, v, g, o, oc, w, cb, fb);
   } else {
     const int e1 = rp[row + 1];
     int e = rp[row] + lane;
@@ -706,25 +746,12 @@ __device__ __forceinline__ T mrow_c(const int* __restrict__ rp, const int* __res
   T s = 0;
   if (nC == 0) return s;
   if (FMT == kFmtSELL || FMT == kFmtSELL16) {
-    int o, w, cb, fb;
-    sell_slice<FMT>(rp, row, o, w, cb, fb);
-    int e = 0;
-    for (; e + 4 <= w; e += 4) {
-      int j[4];
-      T a[4], x[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) j[q] = sell_col<FMT>(ci, o + 64 * (e + q), cb, fb);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) a[q] = j[q] < nC ? v[o + 64 * (e + q)] : (T)0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) x[q] = xc[j[q] < nC ? j[q] : 0];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) s += a[q] * x[q];
-    }
-    for (; e < w; ++e) {
-      const int j = sell_col<FMT>(ci, o + 64 * e, cb, fb);
-      if (j < nC) s += v[o + 64 * e] * xc[j];
-    }
+    int o, oc, w, cb, fb;
+    sell_slice<FMT>(rp, row, o, oc, w, cb, fb);
+    if (FMT == kFmtSELL16 && fb >= 0)
+      s = sell_row_c<true>(ci, v, xc, nC, o, oc, w, cb, fb);
+    else
+      s = sell_row_c<false>(ci, v, xc, nC, o, oc, w, cb, fb);
   } else {
     const int e1 = rp[row + 1];
     for (int e = rp[row] + lane; e < e1; e += TPR) {
@@ -1509,12 +1536,22 @@ __global__ void k_sell_fill(int rows, const int* __restrict__ rp, const int* __r
   }
 }
 
+// Test override: MGD_SELL16_SPAN lowers the column span a slice side may have
+// in the 16-bit layout (so that small systems get 32-bit slices too).
+static int sell16_span() {
+  const char* e = std::getenv("MGD_SELL16_SPAN");
+  const int d = 0x7fff;
+  return e && *e ? std::min(d, std::max(0, std::atoi(e))) : d;
+}
+
 // SELL16 bases of slice s from the real entries of its rows (CSR M): the
 // smallest column below `split` and the smallest at or above it (0 without
-// one); ok is cleared when a side spans 2^15 columns or more
+// one); a side spanning more than `span` (<= 2^15 - 1) columns makes the
+// slice keep 32-bit columns (F base -1).  units[s]: the slice's code size in
+// 16-bit units.
 __global__ void k_sell16_bases(int rows, const int* __restrict__ rp, const int* __restrict__ ci,
-                               int split, const int* __restrict__ off, int* __restrict__ rp3,
-                               int* __restrict__ ok) {
+                               int split, int span, const int* __restrict__ off,
+                               int* __restrict__ rp4, int* __restrict__ units) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   const int ns = (rows + 63) / 64;
   if (s >= ns) return;
@@ -1531,45 +1568,56 @@ __global__ void k_sell16_bases(int rows, const int* __restrict__ rp, const int* 
         fmax = max(fmax, j);
       }
     }
-  if ((cmax >= 0 && cmax - cmin > 0x7fff) || (fmax >= 0 && fmax - fmin > 0x7fff)) atomicAnd(ok, 0);
-  rp3[3 * s] = off[s];
-  rp3[3 * s + 1] = cmax >= 0 ? cmin : 0;
-  rp3[3 * s + 2] = fmax >= 0 ? fmin : 0;
-  if (s == ns - 1) rp3[3 * ns] = off[ns];
+  const bool wide = (cmax >= 0 && cmax - cmin > span) || (fmax >= 0 && fmax - fmin > span);
+  rp4[4 * s] = off[s];
+  rp4[4 * s + 2] = cmax >= 0 ? cmin : 0;
+  rp4[4 * s + 3] = wide ? -1 : (fmax >= 0 ? fmin : 0);
+  units[s] = (off[s + 1] - off[s]) * (wide ? 2 : 1);
+  if (s == ns - 1) rp4[4 * ns] = off[ns];
+}
+__global__ void k_sell16_coff(int ns, const int* __restrict__ coff, int* __restrict__ rp4) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s <= ns) rp4[4 * s + 1] = coff[s];
 }
 // codes of row r: column - C base below the split, (column - F base) | 2^15
-// at or above it; padding elements get code 0 (the C base, weight zero)
+// at or above it, or the column itself in a 32-bit slice; padding elements
+// get code 0 (the C base, or column 0, with weight zero)
 __global__ void k_sell16_encode(int rows, const int* __restrict__ rp, const int* __restrict__ ci,
-                                int split, const int* __restrict__ rp3,
-                                uint16_t* __restrict__ c16) {
+                                int split, const int* __restrict__ rp4, uint16_t* __restrict__ c16) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= rows) return;
-  const int s3 = 3 * (r >> 6);
-  const int o = rp3[s3] + (r & 63), w = (rp3[s3 + 3] - rp3[s3]) >> 6;
-  const int cb = rp3[s3 + 1], fb = rp3[s3 + 2];
+  const int s4 = 4 * (r >> 6);
+  const int w = (rp4[s4 + 4] - rp4[s4]) >> 6;
+  const int cb = rp4[s4 + 2], fb = rp4[s4 + 3];
   const int e0 = rp[r], len = rp[r + 1] - e0;
+  if (fb < 0) {
+    int* c32 = reinterpret_cast<int*>(c16) + (rp4[s4 + 1] >> 1) + (r & 63);
+    for (int q = 0; q < w; ++q) c32[64 * q] = q < len ? ci[e0 + q] : 0;
+    return;
+  }
+  const int oc = rp4[s4 + 1] + (r & 63);
   for (int q = 0; q < w; ++q) {
     unsigned code = 0;
     if (q < len) {
       const int j = ci[e0 + q];
       code = j < split ? (unsigned)(j - cb) : (0x8000u | (unsigned)(j - fb));
     }
-    c16[o + 64 * q] = (uint16_t)code;
+    c16[oc + 64 * q] = (uint16_t)code;
   }
 }
 // every real element decodes to its CSR column, every padding element to a
 // column inside [0, ncols)
 __global__ void k_sell16_check(int rows, int ncols, const int* __restrict__ rp,
-                               const int* __restrict__ ci, const int* __restrict__ rp3,
-                               const uint16_t* __restrict__ c16, int* __restrict__ err) {
+                               const int* __restrict__ ci, const int* __restrict__ rp4,
+                               const int* __restrict__ codes, int* __restrict__ err) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= rows) return;
-  const int s3 = 3 * (r >> 6);
-  const int o = rp3[s3] + (r & 63), w = (rp3[s3 + 3] - rp3[s3]) >> 6;
-  const int cb = rp3[s3 + 1], fb = rp3[s3 + 2];
+  int o, oc, w, cb, fb;
+  sell_slice<kFmtSELL16>(rp4, r, o, oc, w, cb, fb);
   const int e0 = rp[r], len = rp[r + 1] - e0;
   for (int q = 0; q < w; ++q) {
-    const int j = sell16_decode(c16[o + 64 * q], cb, fb);
+    const int j = fb >= 0 ? sell_col<true>(codes, oc + 64 * q, cb, fb)
+                          : sell_col<false>(codes, oc + 64 * q, cb, fb);
     if (q < len ? j != ci[e0 + q] : (j < 0 || j >= ncols)) atomicOr(err, 4);
   }
 }
@@ -1612,26 +1660,27 @@ static void to_layout(Ctx* c, const Csr<double>& M, int fmt, int tpr, bool self_
   MGD_CHECK_LAUNCH();
   c->sync();
   if (split16 < 0 || M.nnz == 0) return;
-  DBuf<int> rp3(c, 3 * (size_t)ns + 1), ok(c, 1);
-  fill<int>(c, ok.get(), 1, 1);
+  DBuf<int> rp4(c, 4 * (size_t)ns + 2), units(c, (size_t)ns), coff(c, (size_t)ns + 1);
   hipLaunchKernelGGL(k_sell16_bases, dim3(cdiv(ns, 256)), dim3(256), 0, c->stream, M.n_rows,
-                     (const int*)M.rp.get(), (const int*)M.ci.get(), split16,
-                     (const int*)out.rp.get(), rp3.get(), ok.get());
+                     (const int*)M.rp.get(), (const int*)M.ci.get(), split16, sell16_span(),
+                     (const int*)out.rp.get(), rp4.get(), units.get());
   MGD_CHECK_LAUNCH();
-  if (!read1(c, ok.get())) return;  // some slice spans too many columns: stay SELL
-  DBuf<int> c16(c, (size_t)std::max(1LL, (out.stored + 1) / 2));
+  const long long total = exclusive_scan_total(c, units.get(), coff.get(), ns);
+  hipLaunchKernelGGL(k_sell16_coff, dim3(cdiv(ns + 1, 256)), dim3(256), 0, c->stream, ns,
+                     (const int*)coff.get(), rp4.get());
+  MGD_CHECK_LAUNCH();
+  DBuf<int> codes(c, (size_t)std::max(1LL, (total + 1) / 2));
   hipLaunchKernelGGL(k_sell16_encode, dim3(cdiv(M.n_rows, 256)), dim3(256), 0, c->stream,
                      M.n_rows, (const int*)M.rp.get(), (const int*)M.ci.get(), split16,
-                     (const int*)rp3.get(), reinterpret_cast<uint16_t*>(c16.get()));
+                     (const int*)rp4.get(), reinterpret_cast<uint16_t*>(codes.get()));
   MGD_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_sell16_check, dim3(cdiv(M.n_rows, 256)), dim3(256), 0, c->stream,
                      M.n_rows, M.n_cols, (const int*)M.rp.get(), (const int*)M.ci.get(),
-                     (const int*)rp3.get(), reinterpret_cast<const uint16_t*>(c16.get()),
-                     c->err_flag());
+                     (const int*)rp4.get(), (const int*)codes.get(), c->err_flag());
   MGD_CHECK_LAUNCH();
   c->check_device_errors("16-bit sliced layout");
-  out.rp = std::move(rp3);
-  out.ci = std::move(c16);
+  out.rp = std::move(rp4);
+  out.ci = std::move(codes);
   out.fmt = kFmtSELL16;
 }
 // padded size of the SELL layout of M (host-side estimate through the device widths)

@@ -40,15 +40,18 @@ struct LMat {
   long long nnz = 0;               // entries (without padding)
   long long stored = 0;            // stored entries (with padding)
   DBuf<int> rp;                    // CSR: rows + 1 row pointers; SELL: slices + 1 offsets;
-                                   // SELL16: 3 slices + 1 (offset, two column bases)
+                                   // SELL16: 4 slices + 2 (offsets, two column bases)
   DBuf<int> ci;                    // SELL16: 16-bit codes, two per element
   DBuf<T> v;
 };
 // SELL16: SELL whose columns are 16-bit offsets from two bases per slice,
 // one for the columns below a split (the C-block of a level matrix) and one
-// for the rest (bit 15 set); slice s keeps its entry offset and the two bases
-// at rp[3s], rp[3s+1], rp[3s+2] (rp[3 * slices] = stored entries).  Used
-// when every slice's columns on each side of the split span less than 2^15.
+// for the rest (bit 15 set).  A slice whose columns on either side of the
+// split span 2^15 or more (the slice across the C/F boundary of a union)
+// keeps 32-bit columns.  Slice s keeps at rp[4s .. 4s+3] the offset of its
+// values, the offset of its column codes in 16-bit units (even), the C base
+// and the F base (-1: 32-bit columns); rp[4 * slices] and rp[4 * slices + 1]
+// hold the totals.
 enum { kFmtCSR = 0, kFmtSELL = 1, kFmtSELL16 = 2 };
 
 // One level of a union in extended stored order: [0, nC) the C-block, [nC, nS)

@@ -295,14 +295,18 @@ def test_vcycle_parity(ctx, cycles, precision):
     assert rel(z, ref) < (1e-12 if precision == 0 else 2e-5)
 
 
-@pytest.mark.parametrize("sell16", ["1", "0"])
+@pytest.mark.parametrize("sell16,span", [("1", "32767"), ("1", "40"), ("1", "0"),
+                                         ("0", "32767")])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_sliced_layouts_forced_small(ctx, monkeypatch, sell16, precision):
+def test_sliced_layouts_forced_small(ctx, monkeypatch, sell16, span, precision):
     """Sliced-ELL level layouts, with 32-bit columns or with 16-bit offsets from
-    two column bases per 64-row slice, forced on every level of small systems:
-    two V-cycles and a batched Schur2 apply agree with the oracle."""
+    two column bases per 64-row slice (slices whose columns span more than
+    `span` on a side keep 32-bit columns: none, some, all), forced on every
+    level of small systems: two V-cycles and a batched Schur2 apply agree with
+    the oracle."""
     monkeypatch.setenv("MGD_SELL_MIN_ROWS", "64")
     monkeypatch.setenv("MGD_SELL16", sell16)
+    monkeypatch.setenv("MGD_SELL16_SPAN", span)
     api = gpu_modules()
     tol = 1e-12 if precision == 0 else 2e-5
     A = oracle_system(si.generate_workload("g1_2d64")).monolithic()
