@@ -115,8 +115,8 @@ def main():
                          "--steps solves; no timing lines")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is designed but "
-                                   "not implemented (see DESIGN.md)", "n_gpus": a.gpus}))
+        print(json.dumps({"error": "the library runs on one GPU; sharding across GPUs is designed "
+                                   "but not implemented", "n_gpus": a.gpus}))
         sys.exit(2)
 
     import numpy as np
