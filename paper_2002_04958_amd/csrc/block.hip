@@ -393,6 +393,9 @@ block_precond::~block_precond() {
   if (aux) hipStreamDestroy(aux);
   if (ev_in) hipEventDestroy(ev_in);
   if (ev_out) hipEventDestroy(ev_out);
+  if (ovl_stream) hipStreamDestroy(ovl_stream);
+  if (ovl_fork) hipEventDestroy(ovl_fork);
+  if (ovl_join) hipEventDestroy(ovl_join);
 }
 
 static void make_hierarchy(block_precond* bp, int role, Csr<double>&& M) {
@@ -880,10 +883,21 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
         // step 3: w_E = w_E* - A_E^{-1}(sum_g D_Eg w_g + D_EI w_I)
         group_out(true, X.b_in.get());
         if (i_apart) i_step(X.a_out.get(), X.b_in.get());
+        const bool fork = bp->ovl_S != nullptr;
+        if (fork) {  // the part of A z that needs no z_E runs beside the E solve
+          MGD_HIP(hipEventRecord(bp->ovl_fork, c->stream));
+          MGD_HIP(hipStreamWaitEvent(bp->ovl_stream, bp->ovl_fork, 0));
+          block_matvec_split(c, *bp->ovl_S, z, bp->ovl_y, bp->ovl_stream);
+          MGD_HIP(hipEventRecord(bp->ovl_join, bp->ovl_stream));
+        }
         inv(G, X.b_in.get(), X.b_out.get());
         hipLaunchKernelGGL(k_sub_out<T>, g1, b1, 0, c->stream, N, (const T*)X.a_out.get(),
                            (const T*)X.b_out.get(), z + (size_t)G * N);
         MGD_CHECK_LAUNCH();
+        if (fork) {
+          MGD_HIP(hipStreamWaitEvent(c->stream, bp->ovl_join, 0));
+          bp->ovl_forked = true;
+        }
         ninv += 1;
       } else {
         group_out(false, nullptr);
@@ -1046,6 +1060,36 @@ void block_precond_graph_launch(block_precond* bp, const double* r, double* z) {
     it = bp->graphs.emplace(key, ex).first;
   }
   MGD_HIP(hipGraphLaunch(it->second, c->stream));
+}
+
+// z = M^{-1} r, then y = A z for the system S.  With Schur2 and the shared
+// block pattern, the part of A z that does not read z_E runs on a second
+// stream beside the last E solve (launches only: usable under capture).
+void block_precond_apply_matvec(block_precond* bp, const double* r, double* z,
+                                const BlockSysDev& S, double* y) {
+  Ctx* c = bp->ctx;
+  const bool split = S.shared && !c->profiling && bp->prm.kind == MGD_PC_SCHUR2 &&
+                     S.G == bp->G && S.N == bp->N;
+  if (split && !bp->ovl_stream) {
+    MGD_HIP(hipStreamCreateWithFlags(&bp->ovl_stream, hipStreamNonBlocking));
+    MGD_HIP(hipEventCreateWithFlags(&bp->ovl_fork, hipEventDisableTiming));
+    MGD_HIP(hipEventCreateWithFlags(&bp->ovl_join, hipEventDisableTiming));
+  }
+  bp->ovl_S = split ? &S : nullptr;
+  bp->ovl_y = y;
+  bp->ovl_forked = false;
+  try {
+    block_precond_apply_impl(bp, r, z);
+  } catch (...) {
+    bp->ovl_S = nullptr;
+    throw;
+  }
+  bp->ovl_S = nullptr;
+  if (bp->ovl_forked)
+    block_matvec_finish(c, S, z, y);
+  else
+    block_matvec(c, S, z, nullptr, y);
+  bp->ovl_forked = false;
 }
 
 // Whether a whole GMRES step with this preconditioner may run as one graph:

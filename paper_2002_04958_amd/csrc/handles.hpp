@@ -138,6 +138,12 @@ struct block_precond {
   // whole flexible-GMRES steps (apply, matvec, Gram-Schmidt) keyed by every
   // pointer and size their launches use
   std::map<std::vector<uintptr_t>, hipGraphExec_t> step_graphs;
+  // GMRES steps with Schur2: the block matvec of z overlaps the last E solve
+  hipStream_t ovl_stream = nullptr;
+  hipEvent_t ovl_fork = nullptr, ovl_join = nullptr;
+  const mgd::BlockSysDev* ovl_S = nullptr;  // set for one apply: split matvec of z into ovl_y
+  double* ovl_y = nullptr;
+  bool ovl_forked = false;
   hipStream_t aux = nullptr;  // graph stream when the context stream is the null stream
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   int inverses_last = 0, matvecs_last = 0;

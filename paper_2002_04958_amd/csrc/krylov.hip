@@ -37,6 +37,8 @@ struct EvPair {
 };
 
 void block_precond_apply_impl(block_precond* bp, const double* r, double* z);
+void block_precond_apply_matvec(block_precond* bp, const double* r, double* z,
+                                const BlockSysDev& S, double* y);
 bool block_precond_step_graphable(const block_precond* bp);
 void block_precond_step_launch(block_precond* bp, const std::vector<uintptr_t>& key,
                                const std::function<void()>& body);
@@ -169,8 +171,7 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
                         (uintptr_t)rw.partial.get()})
       key.push_back(v);
     block_precond_step_launch(M, key, [&] {
-      block_precond_apply_impl(M, vjj, zt);
-      block_matvec(c, S, zt, nullptr, wj);
+      block_precond_apply_matvec(M, vjj, zt, S, wj);
       dcgs_step_dev(c, rw, V.get(), n, F, prov ? vjj : nullptr, wj, n, dd.get(), dcoef.get());
     });
     MGD_HIP(hipMemcpyAsync(slot(jj), dcoef.get(), kDcgsCoef * sizeof(double),

@@ -96,7 +96,12 @@ struct BlockMatvecLaunch {
 // is accumulated while the thread passes block g, where x_g[i] was just
 // gathered.
 // ---------------------------------------------------------------------------
-template <int R, bool RESID>
+//
+// SPLIT: the part that does not read x_E, for overlap with the work that
+// produces x_E: y_g = A_g x_g, y_I = A_I x_I and y_E = sum_g d_Eg[g] o x_g
+// (the E block's values are not read); k_block_matvec_finish adds the rest
+// in the order of the whole kernel, so that the result is the same.
+template <int R, bool RESID, bool SPLIT>
 __global__ void __launch_bounds__(R) k_block_matvec_shared(BlockSysDev S,
                                                            const double* __restrict__ x,
                                                            const double* __restrict__ b,
@@ -121,11 +126,15 @@ __global__ void __launch_bounds__(R) k_block_matvec_shared(BlockSysDev S,
   const bool one_chunk = end - beg <= CAP;
   if (one_chunk)
     for (int k = t; k < end - beg; k += R) s_ci[k] = ci[beg + k];
-  const double xE = active ? x[(size_t)G * N + i] : 0.0;
+  const double xE = (active && !SPLIT) ? x[(size_t)G * N + i] : 0.0;
   double sE = 0.0;
   for (int a = 0; a < nb; ++a) {
     const double* __restrict__ xa = x + (size_t)a * N;
     double s = 0.0;
+    if (SPLIT && a == G) {  // uniform over the workgroup
+      if (active) y[(size_t)G * N + i] = sE;
+      continue;
+    }
     for (int cb = beg; cb < end; cb += CAP) {
       const int cl = min(CAP, end - cb);
       const double* __restrict__ v = S.blk[a].v + cb;
@@ -149,17 +158,44 @@ __global__ void __launch_bounds__(R) k_block_matvec_shared(BlockSysDev S,
     }
     if (!active) continue;
     if (a < G) {
-      s += S.d_gE[(size_t)a * N + i] * xE;
+      if (!SPLIT) s += S.d_gE[(size_t)a * N + i] * xE;
       sE += S.d_Eg[(size_t)a * N + i] * xa[i];
     } else if (a == G) {
       s += sE;
       s += S.d_EI[i] * x[(size_t)(G + 1) * N + i];
-    } else {
+    } else if (!SPLIT) {
       s += S.d_IE[i] * xE;
     }
     const size_t ro = (size_t)a * N + i;
     y[ro] = RESID ? b[ro] - s : s;
   }
+}
+
+// the rest of a SPLIT block matvec, once x_E is known: the E row's stencil
+// sum, then + sum_g d_Eg[g] o x_g (held in y_E) + d_EI o x_I; y_g += d_gE o x_E;
+// y_I += d_IE o x_E
+__global__ void __launch_bounds__(256) k_block_matvec_finish(BlockSysDev S,
+                                                             const double* __restrict__ x,
+                                                             double* __restrict__ y) {
+  const int G = S.G, N = S.N;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double* __restrict__ xEv = x + (size_t)G * N;
+  const double xE = xEv[i];
+  const int* __restrict__ rp = S.blk[0].rp;
+  const int* __restrict__ ci = S.blk[0].ci;
+  const double* __restrict__ v = S.blk[G].v;
+  double s = 0.0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) s += v[k] * xEv[ci[k]];
+  s += y[(size_t)G * N + i];
+  s += S.d_EI[i] * x[(size_t)(G + 1) * N + i];
+  y[(size_t)G * N + i] = s;
+  for (int g = 0; g < G; ++g) {
+    const size_t r = (size_t)g * N + i;
+    y[r] = y[r] + S.d_gE[r] * xE;
+  }
+  const size_t r = (size_t)(G + 1) * N + i;
+  y[r] = y[r] + S.d_IE[i] * xE;
 }
 
 constexpr int kSharedRows = 512;
@@ -181,16 +217,32 @@ void block_matvec(Ctx* c, const BlockSysDev& S, const double* x, const double* b
                  ksym(c, "k_block_matvec_shared", {std::to_string(R), b ? "true" : "false"}));
     const dim3 grid(cdiv(S.N, R));
     if (b)
-      hipLaunchKernelGGL((k_block_matvec_shared<R, true>), grid, dim3(R), 0, c->stream, S, x, b, y);
+      hipLaunchKernelGGL((k_block_matvec_shared<R, true, false>), grid, dim3(R), 0, c->stream, S, x,
+                         b, y);
     else
-      hipLaunchKernelGGL((k_block_matvec_shared<R, false>), grid, dim3(R), 0, c->stream, S, x, b,
-                         y);
+      hipLaunchKernelGGL((k_block_matvec_shared<R, false, false>), grid, dim3(R), 0, c->stream, S,
+                         x, b, y);
     MGD_CHECK_LAUNCH();
     return;
   }
   ProfScope ps(c, KC_BLOCK_MATVEC, block_matvec_bytes(S, b != nullptr),
                ksym(c, "k_block_matvec", {std::to_string(tpr_of(S.tpr)), b ? "true" : "false"}));
   dispatch_tpr<BlockMatvecLaunch>(S.tpr, c, S, x, b, y);
+}
+
+void block_matvec_split(Ctx* c, const BlockSysDev& S, const double* x, double* y,
+                        hipStream_t stream) {
+  MGD_REQUIRE(S.shared, "split block matvec needs the shared pattern");
+  constexpr int R = kSharedRows;
+  hipLaunchKernelGGL((k_block_matvec_shared<R, false, true>), dim3(cdiv(S.N, R)), dim3(R), 0,
+                     stream, S, x, (const double*)nullptr, y);
+  MGD_CHECK_LAUNCH();
+}
+
+void block_matvec_finish(Ctx* c, const BlockSysDev& S, const double* x, double* y) {
+  hipLaunchKernelGGL(k_block_matvec_finish, dim3(cdiv(S.N, 256)), dim3(256), 0, c->stream, S, x,
+                     y);
+  MGD_CHECK_LAUNCH();
 }
 
 }  // namespace mgd

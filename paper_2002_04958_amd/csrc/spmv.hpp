@@ -30,5 +30,11 @@ void check_block_system(const mgd_block_system* A);
 // y = A x, or y = b - A x when b != nullptr.
 void block_matvec(Ctx* c, const BlockSysDev& S, const double* x, const double* b, double* y);
 double block_matvec_bytes(const BlockSysDev& S, bool resid);
+// y = A x in two parts (shared pattern only): the part that does not read x_E,
+// on `stream`, and, on the context stream once x_E is known, the rest; the
+// result equals block_matvec's bit for bit.
+void block_matvec_split(Ctx* c, const BlockSysDev& S, const double* x, double* y,
+                        hipStream_t stream);
+void block_matvec_finish(Ctx* c, const BlockSysDev& S, const double* x, double* y);
 
 }  // namespace mgd

@@ -110,14 +110,16 @@ def test_g20_3d64_assembly_bit_exact(ctx):
     assert_assembly_equal(gsys, osys)
 
 
-def test_g20_3d64_E_block_hierarchy_and_vcycle(ctx):
+@pytest.mark.parametrize("aggressive", [0, 1])
+def test_g20_3d64_E_block_hierarchy_and_vcycle(ctx, aggressive):
     """The whole AMG hierarchy of A_E (262,144 rows) equals the oracle's bit for
-    bit, and one FP64 V-cycle agrees to 1e-12."""
+    bit, also with aggressive coarsening and multipass interpolation on the
+    finest level, and one FP64 V-cycle agrees to 1e-12."""
     api = gpu_modules()
     inp, osys, co, gsys = workload(ctx, "g20_3d64")
     A = osys.blocks[inp.G]
-    H = oamg.setup(A, oamg.AMGParams(seed=4))
-    g = api.AMG(ctx, A.indptr, A.indices, A.data, seed=4)
+    H = oamg.setup(A, oamg.AMGParams(seed=4, aggressive_levels=aggressive))
+    g = api.AMG(ctx, A.indptr, A.indices, A.data, seed=4, aggressive_levels=aggressive)
     info = g.info()
     assert info["levels"] == len(H.levels)
     for l, L in enumerate(H.levels):
