@@ -7,6 +7,7 @@
 #pragma clang fp contract(off)
 
 #include <chrono>
+#include <cstdlib>
 #include <functional>
 
 #include "handles.hpp"
@@ -1068,8 +1069,10 @@ void block_precond_graph_launch(block_precond* bp, const double* r, double* z) {
 void block_precond_apply_matvec(block_precond* bp, const double* r, double* z,
                                 const BlockSysDev& S, double* y) {
   Ctx* c = bp->ctx;
+  // MGD_STEP_OVERLAP=0 keeps the one-kernel matvec after the apply (for comparisons)
+  const char* ov = std::getenv("MGD_STEP_OVERLAP");
   const bool split = S.shared && !c->profiling && bp->prm.kind == MGD_PC_SCHUR2 &&
-                     S.G == bp->G && S.N == bp->N;
+                     S.G == bp->G && S.N == bp->N && !(ov && ov[0] == '0');
   if (split && !bp->ovl_stream) {
     MGD_HIP(hipStreamCreateWithFlags(&bp->ovl_stream, hipStreamNonBlocking));
     MGD_HIP(hipEventCreateWithFlags(&bp->ovl_fork, hipEventDisableTiming));
