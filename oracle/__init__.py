@@ -13,6 +13,8 @@ Modules
   assemble  block system of eq. 2.2 from per-cell coefficients
   amg       classical AMG: strength, PMIS, modified classical interpolation,
             Galerkin coarse operators, CF-l1-Jacobi V(1,1) cycle
+  interp.c  the modified classical interpolation as a plain loop over rows
+            (built by ``cext`` with gcc, loaded with ctypes)
   precond   monolithic AMG, block-diagonal, PCTL (Sec. 3.2), Schur1/Schur2
             (Sec. 3.3) with the diagonal approximations of Sec. 3.4
   krylov    restarted right-preconditioned (flexible) GMRES(m)

@@ -183,6 +183,69 @@ def test_interpolation_hand_fixture():
     np.testing.assert_allclose(P, exp, rtol=1e-15, atol=0)
 
 
+def test_interpolation_sign_filter_hand_fixture():
+    """Positive off-diagonal entries in the rows of strong F neighbours: the
+    sign filter of the distribution coefficients moves a whole F-F coupling to
+    one C point and lumps another into the diagonal."""
+    g = _load("interp_positive_5pt.json")
+    A = _csr_from_rows(g["rows"], g["vals"])
+    S = amg.strength(A, 0.25, 0.9)
+    strong = {i: sorted(int(j) for j in A.indices[A.indptr[i]:A.indptr[i + 1]][
+        S[A.indptr[i]:A.indptr[i + 1]]]) for i in range(5)}
+    assert strong[0] == [1, 2, 3, 4] and strong[2] == [0, 1] and strong[4] == [0]
+    cf = np.array(g["cf"], dtype=np.int8)
+    P = amg.interpolation(A, S, cf).toarray()
+    exp = np.zeros((5, 2))
+    for i, j, num, den in g["P_entries"]:
+        exp[i, j] = num / den
+    assert np.array_equal(P, exp)
+    # the values an unfiltered distribution would give are not these
+    for j, num, den in g["no_filter_row0"]:
+        assert P[0, j] != num / den
+    Pv = amg.interpolation_vectorised(A, S, cf).toarray()
+    assert np.array_equal(Pv, exp)
+
+
+def _mixed_sign_matrix(n, seed, density=0.12, frac_pos=0.2):
+    """Random nonsymmetric matrix with a positive diagonal and off-diagonal
+    entries of both signs (about frac_pos of them positive)."""
+    rng = np.random.default_rng(seed)
+    M = sp.random(n, n, density=density, random_state=rng, format="csr")
+    mag = rng.uniform(0.05, 1.0, size=M.nnz)
+    pos = rng.uniform(size=M.nnz) < frac_pos
+    M.data[:] = np.where(pos, mag * 0.5, -mag)
+    M = sp.csr_matrix(M)
+    M.setdiag(0.0)
+    M.eliminate_zeros()
+    d = np.asarray(abs(M).sum(axis=1)).ravel() * rng.uniform(0.6, 1.2, size=n) + 0.1
+    A = sp.csr_matrix(M + sp.diags(d))
+    A.sort_indices()
+    return A
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_interpolation_loop_matches_vectorised_form(seed):
+    """The per-row loop and the array formulation of the same formula agree
+    bit for bit, on every level of a hierarchy of a matrix with off-diagonal
+    entries of both signs (where the sign filter is active)."""
+    A = _mixed_sign_matrix(400, seed)
+    filt = 0
+    for lvl in range(4):
+        S = amg.strength(A, 0.25, 0.9)
+        cf = amg.pmis(A, S, seed, lvl)
+        if not np.any(cf == 1) or np.all(cf == 1):
+            break
+        P = amg.interpolation(A, S, cf)
+        Pv = amg.interpolation_vectorised(A, S, cf)
+        assert np.array_equal(P.indptr, Pv.indptr) and np.array_equal(P.indices, Pv.indices)
+        assert np.array_equal(P.data.view(np.int64), Pv.data.view(np.int64))
+        rows = amg.csr_rows(A)
+        d = amg.diagonal_of(A)
+        filt += int(np.count_nonzero((A.indices != rows) & (np.sign(A.data) == np.sign(d[rows]))))
+        _, A = amg.galerkin(A, P)
+    assert filt > 0
+
+
 def test_interpolation_1d_alternating_is_half():
     n = 9
     A = sp.csr_matrix(sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1]))
