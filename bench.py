@@ -3,9 +3,14 @@ AMG V-cycles inside FP64 FGMRES vs the plain FP64 form.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload g20_3d64]
 
-One step is one complete preconditioned GMRES(30) solve to rtol 1e-8 of the
-synthetic system (preconditioner built beforehand; setup is timed and
-reported separately).  Prints ONE JSON line.
+One step is one complete preconditioned FGMRES(30) solve to rtol 1e-8 of the
+synthetic 20-group 3D 64^3 system (Schur2 of Section 3.3 with the Section 3.4
+diagonal approximations; the preconditioner is built beforehand and its setup
+is timed and reported separately).  Prints ONE JSON line: the headline, the
+forms that split the FP32/FP64 ratio, the other workloads (2D 1024^2 G=1 with
+five preconditioners, 2D 256^2 G=20 block-diagonal batched against
+sequential, 2D 512^2 G=20 forward and adjoint), the roofline of the kernel
+with the largest time and the oracle timed on the host.
 """
 from __future__ import annotations
 
@@ -39,9 +44,10 @@ def sources_digest() -> str:
 
 
 def recorded_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE passes, calibrated), or None when there is no
-    record for it or the library sources changed since the counters were taken."""
+    """HBM bytes per launch of `kernel` (symbol, with its level tag) from the
+    committed counter summary (FETCH_SIZE and WRITE_SIZE passes, calibrated),
+    or None when there is no record for it or the library sources changed since
+    the counters were taken."""
     path = os.path.join(ROOT, "profiles", "solve_kernels_g20_3d64.md")
     if not os.path.exists(path):
         return None
@@ -58,11 +64,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(name: str, budget_s: float = 20.0):
-    """The oracle (numpy/scipy FP64) on a bounded sample: the same generator,
-    group count and preconditioner on a smaller mesh, scaled linearly in the
-    number of unknowns to the full workload."""
-    import numpy as np
+def host_cpu() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(name: str):
+    """The oracle (numpy/scipy FP64, single-threaded: BLAS limited to one
+    thread, scipy.sparse is serial) on the full workload: Schur2 setup, then
+    FGMRES(30) to rtol 1e-8 from zero.  Returns (record, oracle solution)."""
+    from threadpoolctl import threadpool_limits
 
     import synth_inputs as si
     from oracle import amg as oamg
@@ -71,26 +88,73 @@ def cpu_baseline(name: str, budget_s: float = 20.0):
     from oracle import precond as opc
 
     w = si.WORKLOADS[name]
-    n_sample = {3: 28, 2: 192}[w.dim]
-    inp = si.generate(w.G, w.dim, n_sample, w.seed)
-    t0 = time.perf_counter()
-    sysm = oasm.assemble(inp)
-    M = opc.BlockPreconditioner(sysm, opc.BlockParams(kind="schur2", amg=oamg.AMGParams(seed=w.seed)))
-    t1 = time.perf_counter()
-    A = sysm.monolithic()
-    x, info = okry.gmres(sysm.matvec, M, inp.b, rtol=1e-8)
-    t2 = time.perf_counter()
-    scale = w.n_unknowns / sysm.n
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except Exception:
-        cores = os.cpu_count() or 1
-    return {
-        "value": (t2 - t1) * scale, "unit": "s", "cores": cores, "kind": "oracle",
-        "sample": (f"G={w.G} {w.dim}D {n_sample}^{w.dim} ({sysm.n} unknowns): setup {t1 - t0:.2f}s, "
-                   f"solve {t2 - t1:.2f}s in {info.iters} iterations; solve time scaled x{scale:.0f} "
-                   "by unknowns"),
+    inp = si.generate_workload(name)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        sysm = oasm.assemble(inp)
+        M = opc.BlockPreconditioner(sysm, opc.BlockParams(kind="schur2",
+                                                          amg=oamg.AMGParams(seed=w.seed)))
+        t1 = time.perf_counter()
+        log(f"[bench] oracle setup {t1 - t0:.1f} s; FGMRES(30) to 1e-8 ...")
+        x, info = okry.gmres(sysm.matvec, M, inp.b, rtol=1e-8, flexible=True)
+        t2 = time.perf_counter()
+    log(f"[bench] oracle solve {t2 - t1:.1f} s, {info.iters} iterations")
+    rec = {
+        "value": t2 - t1, "unit": "s", "cores": 1, "kind": "oracle",
+        "sample": (f"the full workload (G={w.G} {w.dim}D {w.n}^{w.dim}, {w.n_unknowns} unknowns): "
+                   f"oracle Schur2 setup {t1 - t0:.1f} s (not in value), FGMRES(30) to rtol 1e-8 "
+                   f"in {info.iters} iterations {t2 - t1:.1f} s; one thread"),
+        "setup_s": t1 - t0, "iters": info.iters, "relres_true": info.relres_true,
+        "host_cpu": host_cpu(), "host_cpus_available": len(os.sched_getaffinity(0)),
     }
+    return rec, x
+
+
+def error_against(x, ref, G):
+    """max_i |x_i - ref_i| / max_{seg(i)} |ref| over the block segments, and
+    the relative 2-norm difference."""
+    import numpy as np
+    X = np.asarray(x).reshape(G + 2, -1)
+    R = np.asarray(ref).reshape(G + 2, -1)
+    seg = np.abs(R).max(axis=1, keepdims=True)
+    return {"max_abs_over_segment_max": float((np.abs(X - R) / seg).max()),
+            "rel_2norm": float(np.linalg.norm(X - R) / np.linalg.norm(R))}
+
+
+def error_against_sample(x, name, G):
+    """The same measure at the stored sample positions of the oracle's solution
+    (written by tests/golden/make_fullsize.py)."""
+    import numpy as np
+    jpath = os.path.join(ROOT, "tests", "golden", f"fullsize_{name}.json")
+    npath = os.path.join(ROOT, "tests", "golden", f"fullsize_{name}.npz")
+    if not (os.path.exists(jpath) and os.path.exists(npath)):
+        return None
+    meta = json.load(open(jpath))
+    case = meta["cases"]["schur2"]
+    with np.load(npath) as z:
+        pos, ref = z["pos"], z["schur2/x"]
+    N = np.asarray(x).size // (G + 2)
+    seg = np.asarray(case["x_norminf"])[pos // N]
+    return {"max_abs_over_segment_max": float((np.abs(np.asarray(x)[pos] - ref) / seg).max()),
+            "positions": int(len(pos)), "oracle_iters": case["gmres"]["iters"]}
+
+
+def copy_ceiling(torch, device, reps=10):
+    """Streaming copy of 1 GiB into another 1 GiB on the device (torch's copy
+    kernel), timed with events: (GB/s counting bytes read + written)."""
+    src = torch.ones(256 << 20, dtype=torch.float32, device=device)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * (1 << 30) / (ms * 1e-3) / 1e9
 
 
 def main():
@@ -98,13 +162,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--form-steps", type=int, default=3,
+                    help="solves timed for each of the other forms and workloads")
     ap.add_argument("--workload", default="g20_3d64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-adaptive", action="store_true")
-    ap.add_argument("--no-inner", action="store_true")
-    ap.add_argument("--no-option4", action="store_true")
-    ap.add_argument("--no-aggressive", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the adaptive, option #4, aggressive and inner-tolerance variants")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the 2D 1024^2, 2D 256^2 and 2D 512^2 workloads")
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate layouts of every level once and keep the fastest "
                          "(cached per process, or in MGD_AUTOTUNE_CACHE)")
@@ -134,22 +200,33 @@ def main():
     b = torch.as_tensor(inp.b, device=ctx.device)
     bnorm = float(torch.linalg.vector_norm(b))
 
-    def build(batched, fp32, graph, adaptive=False, inner_tol=0.0, option4=0, aggressive=0):
+    def build(sysx, kind, seed, fp32, batched, graph, **kw):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        M = api.BlockPreconditioner(ctx, sysg, "schur2", amg_seed=w.seed,
+        M = api.BlockPreconditioner(ctx, sysx, kind, amg_seed=seed,
                                     amg_precision=1 if fp32 else 0, batched=int(batched),
-                                    use_graph=int(graph), adaptive=int(adaptive),
-                                    inner_tol=inner_tol, option4_steps=option4,
-                                    amg_aggressive_levels=aggressive,
-                                    amg_autotune=int(a.autotune))
+                                    use_graph=int(graph), amg_autotune=int(a.autotune), **kw)
         torch.cuda.synchronize()
         return M, time.perf_counter() - t0
 
-    def solve(M):
-        x = torch.zeros_like(b)
-        x, r = api.gmres(ctx, sysg, M, b, x, rtol=1e-8, flexible=1)
-        return x, r
+    def solve(sysx, M, rhs):
+        x = torch.zeros_like(rhs)
+        return api.gmres(ctx, sysx, M, rhs, x, rtol=1e-8, flexible=1)
+
+    def timed(sysx, M, rhs, steps, warmup=1):
+        """Mean event-timed ms per solve over `steps` solves after `warmup`."""
+        for _ in range(warmup):
+            solve(sysx, M, rhs)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        iters = []
+        for _ in range(steps):
+            x, r = solve(sysx, M, rhs)
+            iters.append(r.iters)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps, iters, x, r
 
     if a.counters_run:
         src = torch.ones(256 << 20, dtype=torch.float32, device=ctx.device)
@@ -158,174 +235,164 @@ def main():
         torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst, flush
-        M32, _ = build(True, True, True)
+        M32, _ = build(sysg, "schur2", w.seed, True, True, True)
         for _ in range(max(1, a.steps)):
-            x, r = solve(M32)
+            x, r = solve(sysg, M32, b)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "counters", "workload": w.name, "iters": r.iters,
                           "calibration_bytes": {"read": 1 << 30, "written": 1 << 30}}))
         return
 
     # headline form: FP32 hierarchies, batched V-cycles, graph replay
-    M32, setup32 = build(True, True, True)
+    M32, setup32 = build(sysg, "schur2", w.seed, True, True, True)
     log(f"[bench] fp32 batched setup {setup32:.2f}s")
     for idx, label in ((0, "group 1"), (w.G, "E"), (w.G + 1, "I")):
         hi = M32.hierarchy(idx).info()
         log(f"[bench] hierarchy {label}: rows per level {hi['n']}, nnz {hi['nnz']}")
-    for _ in range(a.warmup):
-        solve(M32)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    t0 = time.perf_counter()
-    iters = []
-    for _ in range(a.steps):
-        x, r = solve(M32)
-        iters.append(r.iters)
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = e0.elapsed_time(e1) / a.steps
-    relres = float(torch.linalg.vector_norm(b - sysg.matvec(x))) / bnorm
+    ms_step, iters, x32, r32 = timed(sysg, M32, b, a.steps, a.warmup)
+    relres = float(torch.linalg.vector_norm(b - sysg.matvec(x32))) / bnorm
+    x32h = x32.cpu().numpy()
     log(f"[bench] fp32 batched: {ms_step:.1f} ms/solve, iters {iters}, relres {relres:.2e}")
 
-    # the adaptive variant of the same preconditioner (alpha-Schur2, Section 3.5)
-    alpha = None
-    if not a.no_adaptive:
-        Ma, setup_a = build(True, True, True, adaptive=True)
-        ia = Ma.info()
-        solve(Ma)
-        torch.cuda.synchronize()
-        ea0, ea1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ea0.record()
-        iters_a = []
-        for _ in range(a.steps):
-            xa, ra = solve(Ma)
-            iters_a.append(ra.iters)
-        ea1.record()
-        torch.cuda.synchronize()
-        ms_a = ea0.elapsed_time(ea1) / a.steps
-        relres_a = float(torch.linalg.vector_norm(b - sysg.matvec(xa))) / bnorm
-        weak = ia["weak"]
-        alpha = {"s": ms_a / 1e3, "iters": iters_a, "relres": relres_a, "setup_s": setup_a,
-                 "neglected": {"gE": [g for g, v in enumerate(weak["gE"]) if v],
-                               "Eg": [g for g, v in enumerate(weak["Eg"]) if v],
-                               "EI": weak["EI"], "IE": weak["IE"]},
-                 "jacobi_roles": [r for r, v in enumerate(ia["jacobi"]) if v],
-                 "inverses_per_apply": ia["inverses_per_apply"]}
-        log(f"[bench] alpha-schur2 fp32 batched: {ms_a:.1f} ms/solve, iters {iters_a}, "
-            f"relres {relres_a:.2e}, neglected {alpha['neglected']}, "
-            f"jacobi roles {alpha['jacobi_roles']}")
-        del Ma, xa
+    # the forms that split the FP32-batched / FP64-plain ratio
+    forms = {}
+    if not a.no_forms:
+        for key, fp32, batched, graph in (("fp64_plain", False, False, False),
+                                          ("fp64_batched_graph", False, True, True),
+                                          ("fp32_sequential", True, False, False)):
+            M, su = build(sysg, "schur2", w.seed, fp32, batched, graph)
+            ms, it, xf, rf = timed(sysg, M, b, a.form_steps)
+            rr = float(torch.linalg.vector_norm(b - sysg.matvec(xf))) / bnorm
+            forms[key] = {"ms": ms, "iters": it, "setup_s": su, "relres_true": rr}
+            if key == "fp64_plain":
+                x64h = xf.cpu().numpy()
+            log(f"[bench] {key}: {ms:.1f} ms/solve, iters {it}, setup {su:.2f}s")
+            del M, xf
+        forms["fp32_batched_graph"] = {"ms": ms_step, "iters": iters, "setup_s": setup32,
+                                       "relres_true": relres}
+        p = forms["fp64_plain"]["ms"]
+        forms["ratios_vs_fp64_plain"] = {k: p / v["ms"] for k, v in forms.items()
+                                         if isinstance(v, dict) and "ms" in v}
 
-    # option #4: S_I by two fixed-point steps on A_I and A_E instead of the hat
-    opt4 = None
-    if not a.no_option4:
-        M4, setup_4 = build(True, True, True, option4=2)
-        solve(M4)
-        torch.cuda.synchronize()
-        e40, e41 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e40.record()
-        iters_4 = []
-        for _ in range(a.steps):
-            x4, r4 = solve(M4)
-            iters_4.append(r4.iters)
-        e41.record()
-        torch.cuda.synchronize()
-        ms_4 = e40.elapsed_time(e41) / a.steps
-        relres_4 = float(torch.linalg.vector_norm(b - sysg.matvec(x4))) / bnorm
-        opt4 = {"s": ms_4 / 1e3, "iters": iters_4, "relres": relres_4, "setup_s": setup_4,
-                "steps": 2}
-        log(f"[bench] schur2 option #4 (2 steps) fp32 batched: {ms_4:.1f} ms/solve, "
-            f"iters {iters_4}, relres {relres_4:.2e}")
-        del M4, x4
-
-    # aggressive coarsening with multipass interpolation on the finest level of every inverse
-    aggr = None
-    if not a.no_aggressive:
-        Mg_, setup_g = build(True, True, True, aggressive=1)
-        solve(Mg_)
-        torch.cuda.synchronize()
-        eg0, eg1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        eg0.record()
-        iters_g = []
-        for _ in range(a.steps):
-            xg_, rg_ = solve(Mg_)
-            iters_g.append(rg_.iters)
-        eg1.record()
-        torch.cuda.synchronize()
-        ms_g = eg0.elapsed_time(eg1) / a.steps
-        relres_g = float(torch.linalg.vector_norm(b - sysg.matvec(xg_))) / bnorm
-        hg = Mg_.hierarchy(0).info()
-        aggr = {"s": ms_g / 1e3, "iters": iters_g, "relres": relres_g, "setup_s": setup_g,
-                "group0_levels": hg["n"], "group0_operator_complexity": hg["operator_complexity"]}
-        log(f"[bench] schur2 aggressive finest level fp32 batched: {ms_g:.1f} ms/solve, "
-            f"iters {iters_g}, relres {relres_g:.2e}, setup {setup_g:.3f} s, "
-            f"group-0 levels {hg['n']}")
-        del Mg_, xg_
-
-    # the inner solves of Section 4: S^_g and S^_I to a relative tolerance 1e-2
-    inner = None
-    if not a.no_inner:
-        Mi, setup_i = build(True, True, False, inner_tol=1e-2)
-        solve(Mi)
-        torch.cuda.synchronize()
-        t0i = time.perf_counter()
-        xi, ri = solve(Mi)
-        torch.cuda.synchronize()
-        ti = time.perf_counter() - t0i
-        relres_i = float(torch.linalg.vector_norm(b - sysg.matvec(xi))) / bnorm
-        ii = Mi.info()
-        inner = {"s": ti, "iters": ri.iters, "relres": relres_i, "setup_s": setup_i,
-                 "inner_cycles_last_apply": ii["inner_cycles"]}
-        log(f"[bench] schur2 inner tol 1e-2 fp32 batched: {ti * 1e3:.1f} ms/solve, iters {ri.iters}, "
-            f"relres {relres_i:.2e}, inner cycles of the last apply {ii['inner_cycles']}")
-        del Mi, xi
-
-    # plain FP64 form: sequential launches, no graph
-    plain = None
-    if not a.no_plain:
-        M64, setup64 = build(False, False, False)
-        solve(M64)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        x64, r64 = solve(M64)
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - t0
-        err32 = float(torch.linalg.vector_norm(x - x64)) / float(torch.linalg.vector_norm(x64))
-        plain = {"s": t64, "iters": r64.iters, "setup_s": setup64,
-                 "relres": r64.relres_true, "fp32_vs_fp64_rel_err": err32}
-        log(f"[bench] fp64 plain: {t64 * 1e3:.1f} ms/solve, iters {r64.iters}")
-        del M64
+    # the adaptive, option #4, aggressive and inner-tolerance variants (Sections 3.4, 3.5)
+    variants = {}
+    if not a.no_variants:
+        for key, kw, graph in (("alpha_schur2", dict(adaptive=1), True),
+                               ("option4_2steps", dict(option4_steps=2), True),
+                               ("aggressive_finest", dict(amg_aggressive_levels=1), True),
+                               ("inner_tol_1e-2", dict(inner_tol=1e-2), False)):
+            M, su = build(sysg, "schur2", w.seed, True, True, graph, **kw)
+            steps = 1 if key.startswith("inner") else a.form_steps
+            ms, it, xv, rv = timed(sysg, M, b, steps)
+            rr = float(torch.linalg.vector_norm(b - sysg.matvec(xv))) / bnorm
+            rec = {"ms": ms, "iters": it, "setup_s": su, "relres_true": rr}
+            inf = M.info()
+            if key == "alpha_schur2":
+                weak = inf["weak"]
+                rec["neglected"] = {"gE": [g for g, v in enumerate(weak["gE"]) if v],
+                                    "Eg": [g for g, v in enumerate(weak["Eg"]) if v],
+                                    "EI": weak["EI"], "IE": weak["IE"]}
+                rec["jacobi_roles"] = [r for r, v in enumerate(inf["jacobi"]) if v]
+            if key == "aggressive_finest":
+                hg = M.hierarchy(0).info()
+                rec["group0_levels"] = hg["n"]
+            if key.startswith("inner"):
+                rec["inner_cycles_last_apply"] = inf["inner_cycles"]
+            variants[key] = rec
+            log(f"[bench] {key}: {ms:.1f} ms/solve, iters {it}, relres {rr:.2e}")
+            del M, xv
 
     # per-kernel timing pass: HIP events on the context stream around every
-    # launch of one solve (no graph), algorithmic bytes from the hierarchy
+    # launch of one FP32 batched solve (direct launches, no graph)
+    M32d, _ = build(sysg, "schur2", w.seed, True, True, False)
+    solve(sysg, M32d, b)
     ctx.reset_kernel_stats()
     ctx.set_profiling(True)
-    solve(M32)
+    solve(sysg, M32d, b)
     ctx.set_profiling(False)
     stats = ctx.kernel_stats()
-    tagged = ctx.kernel_symbol_stats()  # "symbol@L<level>/<members>"
-    syms = {}
-    for k, v in tagged.items():
-        agg = syms.setdefault(k.split("@")[0], {"launches": 0, "ms": 0.0, "bytes": 0.0})
-        for f in agg:
-            agg[f] += v[f]
-    dom = max(syms, key=lambda k: syms[k]["ms"])
-    s = syms[dom]
-    achieved = (s["bytes"] / 1e9) / (s["ms"] / 1e3) if s["ms"] > 0 else 0.0
+    tagged = ctx.kernel_symbol_stats()  # "symbol@L<level>/<members>" for V-cycle kernels
+    del M32d
+    dom = max((k for k in tagged if tagged[k]["bytes"] > 0), key=lambda k: tagged[k]["ms"])
+    s = tagged[dom]
+    avg_us = 1e3 * s["ms"] / s["launches"]
+    bpl = s["bytes"] / s["launches"]
+    bpl_csr = s["bytes_csr"] / s["launches"]
+    copy_gbs = copy_ceiling(torch, ctx.device)
+    achieved = bpl_csr / (avg_us * 1e-6) / 1e9
+    achieved_stored = bpl / (avg_us * 1e-6) / 1e9
     log("[bench] kernel classes: " + ", ".join(
         f"{k}={v['ms']:.1f}ms/{v['launches']}" for k, v in stats.items() if v["launches"]))
     log("[bench] kernels: " + ", ".join(
-        f"{k}={v['ms']:.1f}ms/{v['launches']}" for k, v in sorted(syms.items(), key=lambda kv: -kv[1]["ms"])))
-    log("[bench] by level: " + ", ".join(
-        f"{k}={v['ms']:.1f}ms/{v['launches']}({(v['bytes'] / 1e9) / (v['ms'] / 1e3) if v['ms'] else 0:.0f}GB/s)"
+        f"{k}={v['ms']:.2f}ms/{v['launches']}({v['bytes_csr'] / v['ms'] / 1e6 if v['ms'] else 0:.0f}GB/s)"
         for k, v in sorted(tagged.items(), key=lambda kv: -kv[1]["ms"])[:40]))
+    log(f"[bench] dominant {dom}: {avg_us:.2f} us/launch, {achieved:.0f} GB/s (CSR model), "
+        f"{achieved_stored:.0f} GB/s (stored layout); copy {copy_gbs:.0f} GB/s")
+
+    # the other workloads: 2D 1024^2 G=1, 2D 256^2 G=20, 2D 512^2 G=20 (FP64 unless stated)
+    workloads = {}
+    if not a.no_workloads:
+        del M32
+        for wname, cases in (("g1_2d1024", [("amg", False, False), ("pctl", False, False),
+                                            ("schur2_lower", False, False), ("schur1", False, False),
+                                            ("schur2", False, False)]),
+                             ("g20_2d256", [("bdiag", False, False), ("bdiag", True, True)]),
+                             ("g20_2d512", [("schur2", True, True)])):
+            ww = si.WORKLOADS[wname]
+            winp = si.generate_workload(wname)
+            wco = api.Coeffs.from_inputs(ctx, winp)
+            wsys = api.BlockSystem.assemble(ctx, wco)
+            wb = torch.as_tensor(winp.b, device=ctx.device)
+            wn = float(torch.linalg.vector_norm(wb))
+            out = {}
+            for kind, batched, graph in cases:
+                fp32 = wname == "g20_2d512"
+                M, su = build(wsys, kind, ww.seed, fp32, batched, graph)
+                ms, it, xw, rw = timed(wsys, M, wb, a.form_steps)
+                rr = float(torch.linalg.vector_norm(wb - wsys.matvec(xw))) / wn
+                key = kind + ("_batched_graph" if batched else "_sequential") + \
+                    ("_fp32" if fp32 else "_fp64")
+                out[key] = {"ms": ms, "iters": it, "setup_s": su, "relres_true": rr}
+                log(f"[bench] {wname} {key}: {ms:.1f} ms/solve, iters {it}, setup {su:.2f}s")
+                if wname == "g20_2d512":
+                    # adjoint: A^T lambda = x - x_target with Schur2 built on A^T
+                    g = xw - torch.as_tensor(winp.x_target, device=ctx.device)
+                    MT, sut = build(wsys, kind, ww.seed, fp32, batched, graph, transpose=1)
+                    api.adjoint(ctx, wco, wsys, MT, xw, g, rtol=1e-8, flexible=1)
+                    torch.cuda.synchronize()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(a.form_steps):
+                        lam, dk, dc, ra = api.adjoint(ctx, wco, wsys, MT, xw, g, rtol=1e-8,
+                                                      flexible=1)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    msa = e0.elapsed_time(e1) / a.form_steps
+                    out["adjoint_" + key] = {"ms": msa, "iters": ra.iters, "setup_s": sut,
+                                             "relres_est": ra.relres_est,
+                                             "includes": "adjoint FGMRES and the gradients"}
+                    log(f"[bench] {wname} adjoint: {msa:.1f} ms, iters {ra.iters}")
+                    del MT
+                del M, xw
+            if wname == "g20_2d256":
+                out["batched_speedup"] = (out["bdiag_sequential_fp64"]["ms"]
+                                          / out["bdiag_batched_graph_fp64"]["ms"])
+            workloads[wname] = out
+            del wsys, wco
 
     cpu = None
+    err_oracle = None
     if not a.no_cpu_baseline:
-        log("[bench] oracle CPU baseline (bounded sample)...")
-        cpu = cpu_baseline(w.name)
+        log("[bench] oracle CPU baseline on the full workload ...")
+        cpu, x_or = cpu_baseline(w.name)
+        err_oracle = {"fp32_batched": error_against(x32h, x_or, w.G)}
+        if forms:
+            err_oracle["fp64_plain"] = error_against(x64h, x_or, w.G)
+        err_oracle["against"] = f"oracle FGMRES(30) solution to 1e-8 ({cpu['iters']} iterations)"
+    else:
+        e = error_against_sample(x32h, w.name, w.G)
+        if e is not None:
+            err_oracle = {"fp32_batched": e, "against": "stored oracle solution at sample positions"}
 
     out = {
         "metric": "time to rtol 1e-8 (s) & SpMV HBM GB/s, G=20; FP32-AMG batched vs FP64 plain",
@@ -346,24 +413,27 @@ def main():
         "iters": iters,
         "relres_true": relres,
         "setup_s": setup32,
-        "plain_fp64": plain,
-        "speedup_vs_plain_fp64": (plain["s"] / (ms_step / 1e3)) if plain else None,
-        "alpha_schur2_fp32": alpha,
-        "schur2_inner_tol_1e-2_fp32": inner,
-        "schur2_option4_fp32": opt4,
-        "schur2_aggressive_fp32": aggr,
+        "forms": forms or None,
+        "speedup_vs_plain_fp64": (forms["fp64_plain"]["ms"] / ms_step) if forms else None,
+        "error_vs_oracle": err_oracle,
+        "variants": variants or None,
+        "workloads": workloads or None,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": recorded_traffic(dom), "traffic_unit": "bytes per launch",
-                     "launches": s["launches"],
-                     "avg_launch_us": 1e3 * s["ms"] / max(1, s["launches"]),
-                     "bytes_per_launch": s["bytes"] / max(1, s["launches"])},
+                     "bytes_model": "plain CSR: value + 4-byte column per entry, 4-byte row "
+                                    "pointer per row, vectors once",
+                     "bytes_per_launch": bpl_csr,
+                     "bytes_per_launch_stored": bpl,
+                     "achieved_stored": achieved_stored,
+                     "frac_stored": achieved_stored / HBM_PEAK_GBS,
+                     "copy_ceiling": copy_gbs,
+                     "frac_of_copy": achieved / copy_gbs,
+                     "launches": s["launches"], "avg_launch_us": avg_us},
         "kernels": {k: {"ms": v["ms"], "launches": v["launches"],
-                        "GB/s": (v["bytes"] / 1e9) / (v["ms"] / 1e3) if v["ms"] else 0.0}
-                    for k, v in syms.items()},
-        "kernels_by_level": {k: {"ms": v["ms"], "launches": v["launches"],
-                                 "GB/s": (v["bytes"] / 1e9) / (v["ms"] / 1e3) if v["ms"] else 0.0}
-                             for k, v in tagged.items()},
+                        "GB/s": (v["bytes_csr"] / 1e9) / (v["ms"] / 1e3) if v["ms"] else 0.0,
+                        "GB/s_stored": (v["bytes"] / 1e9) / (v["ms"] / 1e3) if v["ms"] else 0.0}
+                    for k, v in tagged.items()},
         "kernel_classes": {k: {"ms": v["ms"], "launches": v["launches"],
                                "GB/s": (v["bytes"] / 1e9) / (v["ms"] / 1e3) if v["ms"] else 0.0}
                            for k, v in stats.items() if v["launches"]},

@@ -82,11 +82,17 @@ mgd_status mgd_ctx_kernel_stats(mgd_ctx* ctx, int cls, int64_t* launches, double
 /* The same statistics per kernel symbol, for the launches that a profiling
  * scope times alone (the V-cycle kernels, SpMV and the block matvec).  Names
  * are the kernel's name with its template arguments as a demangler prints
- * them, e.g. "k_half<float, 1>".  mgd_ctx_kernel_symbol_count synchronises;
- * name receives at most name_cap-1 characters and a terminating zero. */
+ * them, e.g. "k_half<float, 1>", followed for V-cycle kernels by
+ * "@L<level>/<hierarchies in the union>".  total_bytes counts the matrix in
+ * its stored layout (e.g. 16-bit column offsets); total_bytes_csr prices the
+ * same launches as plain CSR (value and 4-byte column per entry, 4-byte row
+ * pointer per row swept; block matvec: the pattern once per block), vectors
+ * alike.  mgd_ctx_kernel_symbol_count synchronises; name receives at most
+ * name_cap-1 characters and a terminating zero; any output may be NULL. */
 mgd_status mgd_ctx_kernel_symbol_count(mgd_ctx* ctx, int* count);
 mgd_status mgd_ctx_kernel_symbol_stats(mgd_ctx* ctx, int index, char* name, int name_cap,
-                                       int64_t* launches, double* total_ms, double* total_bytes);
+                                       int64_t* launches, double* total_ms, double* total_bytes,
+                                       double* total_bytes_csr);
 
 /* ---------------------------------------------------------------------------
  * Sparse matrices (CSR).  Columns sorted ascending within each row; every
@@ -223,7 +229,7 @@ mgd_status mgd_block_system_free(mgd_ctx* ctx, mgd_block_system* s);
  *   SCHUR2_LOWER Schur2 steps 1-2: the elimination factor of eq. 3.3
  *   IDENTITY     z = r
  * Each scalar inverse is a fixed number of V-cycles (option #2 of Section
- * 3.5): cycles_rad for group blocks, cycles_E for E blocks (and A_c),
+ * 3.4): cycles_rad for group blocks, cycles_E for E blocks (and A_c),
  * cycles_I for I blocks.  batched = 1 applies the independent V-cycles of a
  * step (the group blocks, plus I where the step has it) as one set of
  * launches over all hierarchies; use_graph = 1 replays the whole apply from

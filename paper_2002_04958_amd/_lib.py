@@ -103,7 +103,7 @@ SIGNATURES = [
     ("mgd_ctx_kernel_symbol_count", c_int32, [c_void_p, POINTER(c_int)]),
     ("mgd_ctx_kernel_symbol_stats", c_int32, [c_void_p, c_int, ctypes.c_char_p, c_int,
                                               POINTER(c_int64), POINTER(c_double),
-                                              POINTER(c_double)]),
+                                              POINTER(c_double), POINTER(c_double)]),
     ("mgd_csr_spmv", c_int32, [c_void_p, POINTER(mgd_csr), c_void_p, c_void_p]),
     ("amg_params_default", None, [POINTER(amg_params)]),
     ("amg_setup", c_int32, [c_void_p, POINTER(mgd_csr), POINTER(amg_params), POINTER(c_void_p)]),

@@ -36,18 +36,46 @@ def _dev_i32(x, device) -> torch.Tensor:
     return t.to(device=device, dtype=torch.int32).contiguous()
 
 
+def _torch_allocator(device: int):
+    """mgd_allocator callbacks that take the library's device memory from
+    torch's caching allocator on the context stream (memory the library frees
+    returns to torch's pool, ordered on that stream)."""
+    def alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, int(stream or 0))
+        except Exception:
+            return None          # the library reports MGD_ENOMEM
+
+    def free(ptr, stream, user):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass                 # interpreter shutdown: the process frees it
+
+    cbs = (L.ALLOC_FN(alloc), L.FREE_FN(free))
+    return cbs, L.mgd_allocator(cbs[0], cbs[1], None)
+
+
 class Context:
     """Device, stream and library context.  The stream defaults to torch's
-    current stream on the device, so library work and torch work are ordered."""
+    current stream on the device, so library work and torch work are ordered.
+    allocator="torch" (default) hands the library torch's caching allocator
+    for all device memory it owns; "hip" leaves it on hipMalloc/hipFree."""
 
-    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None):
+    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None,
+                 allocator: str = "torch"):
         self.lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device is visible")
+        if allocator not in ("torch", "hip"):
+            raise ValueError("allocator must be 'torch' or 'hip'")
         self.device = torch.device("cuda", device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._alloc_cbs, alloc = (_torch_allocator(device) if allocator == "torch"
+                                  else (None, None))
         h = c_void_p()
-        L.check(self.lib.mgd_ctx_create(device, c_void_p(self.stream.cuda_stream), None, byref(h)))
+        L.check(self.lib.mgd_ctx_create(device, c_void_p(self.stream.cuda_stream),
+                                        byref(alloc) if alloc is not None else None, byref(h)))
         self.h = h
 
     def synchronize(self):
@@ -81,16 +109,18 @@ class Context:
         return out
 
     def kernel_symbol_stats(self) -> dict:
-        """Per-kernel-symbol launches, total ms and algorithmic bytes."""
+        """Per-kernel-symbol launches, total ms and algorithmic bytes (stored
+        layout, and the same launches priced as plain CSR)."""
         cnt = ctypes.c_int()
         L.check(self.lib.mgd_ctx_kernel_symbol_count(self.h, byref(cnt)))
         out = {}
         buf = ctypes.create_string_buffer(256)
         for i in range(cnt.value):
-            n, ms, by = c_int64(), c_double(), c_double()
+            n, ms, by, bc = c_int64(), c_double(), c_double(), c_double()
             L.check(self.lib.mgd_ctx_kernel_symbol_stats(self.h, i, buf, 256, byref(n), byref(ms),
-                                                         byref(by)))
-            out[buf.value.decode()] = {"launches": n.value, "ms": ms.value, "bytes": by.value}
+                                                         byref(by), byref(bc)))
+            out[buf.value.decode()] = {"launches": n.value, "ms": ms.value, "bytes": by.value,
+                                       "bytes_csr": bc.value}
         return out
 
     def empty(self, n, dtype=torch.float64):

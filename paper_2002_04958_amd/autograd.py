@@ -65,12 +65,15 @@ class MGDSolve(torch.autograd.Function):
             raise RuntimeError(f"forward GMRES did not converge: {res}")
         fctx.state = (ctx, coeffs, system, kind, opts, rtol, G, N,
                       (kappa.shape, c_gE.shape, c_Eg.shape, c_EI.shape, b.shape))
-        fctx.save_for_backward(x)
+        # the assembled system and coeffs view the caller's coefficient
+        # tensors: saving them lets autograd's version check reject an
+        # in-place change between forward and backward
+        fctx.save_for_backward(x, kappa, c_gE, c_Eg, c_EI)
         return x
 
     @staticmethod
     def backward(fctx, grad_x):
-        (x,) = fctx.saved_tensors
+        x = fctx.saved_tensors[0]
         ctx, coeffs, system, kind, opts, rtol, G, N, shapes = fctx.state
         MT = api.BlockPreconditioner(ctx, system, kind, transpose=1, **opts)
         g = grad_x.detach().to(torch.float64).contiguous()

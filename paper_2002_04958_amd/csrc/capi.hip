@@ -105,10 +105,10 @@ void Ctx::prof_begin(int cls, hipEvent_t* a) {
   *a = take_event();
   MGD_HIP(hipEventRecord(*a, stream));
 }
-void Ctx::prof_end(int cls, hipEvent_t a, double bytes_, std::string kernel) {
+void Ctx::prof_end(int cls, hipEvent_t a, double bytes_, double bytes_csr_, std::string kernel) {
   hipEvent_t b = take_event();
   MGD_HIP(hipEventRecord(b, stream));
-  pending.push_back({cls, a, b, bytes_, std::move(kernel)});
+  pending.push_back({cls, a, b, bytes_, bytes_csr_, std::move(kernel)});
   if (pending.size() > 4096) prof_collect();
 }
 void Ctx::prof_collect() {
@@ -130,6 +130,7 @@ void Ctx::prof_collect() {
       it->second.launches += 1;
       it->second.ms += ms_;
       it->second.bytes += p.bytes;
+      it->second.bytes_csr += p.bytes_csr;
     }
     event_pool.push_back(p.a);
     event_pool.push_back(p.b);
@@ -383,7 +384,8 @@ mgd_status mgd_ctx_kernel_symbol_count(mgd_ctx* ctx, int* count) {
   });
 }
 mgd_status mgd_ctx_kernel_symbol_stats(mgd_ctx* ctx, int index, char* name, int name_cap,
-                                       int64_t* launches, double* total_ms, double* total_bytes) {
+                                       int64_t* launches, double* total_ms, double* total_bytes,
+                                       double* total_bytes_csr) {
   return guard([&] {
     StepScope step_("mgd_ctx_kernel_symbol_stats");
     MGD_REQUIRE(ctx, "ctx is NULL");
@@ -397,6 +399,7 @@ mgd_status mgd_ctx_kernel_symbol_stats(mgd_ctx* ctx, int index, char* name, int 
     if (launches) *launches = kv.second.launches;
     if (total_ms) *total_ms = kv.second.ms;
     if (total_bytes) *total_bytes = kv.second.bytes;
+    if (total_bytes_csr) *total_bytes_csr = kv.second.bytes_csr;
     return MGD_OK;
   });
 }

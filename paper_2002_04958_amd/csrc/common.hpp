@@ -94,12 +94,13 @@ struct Ctx {
   struct Pending {
     int cls;
     hipEvent_t a, b;
-    double bytes;
+    double bytes;        // algorithmic bytes in the stored layout
+    double bytes_csr;    // the same launch priced as plain CSR with 32-bit indices
     std::string kernel;  // symbol of the single kernel timed, or empty
   };
   struct KernelStat {
     int64_t launches = 0;
-    double ms = 0, bytes = 0;
+    double ms = 0, bytes = 0, bytes_csr = 0;
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> event_pool;
@@ -119,7 +120,7 @@ struct Ctx {
   // profiling hooks
   hipEvent_t take_event();
   void prof_begin(int cls, hipEvent_t* a);
-  void prof_end(int cls, hipEvent_t a, double bytes, std::string kernel);
+  void prof_end(int cls, hipEvent_t a, double bytes, double bytes_csr, std::string kernel);
   void prof_collect();  // synchronises
   ~Ctx();
 };
@@ -127,18 +128,23 @@ struct Ctx {
 // RAII scope: events around one launch (or a short fixed sequence) when
 // profiling is on.  `kernel` names the kernel symbol when the scope holds
 // exactly one launch, so per-kernel averages can be compared with a trace.
+// bytes: algorithmic bytes of the launch in its stored layout; bytes_csr: the
+// same launch priced as plain CSR (value and 4-byte column per entry, 4-byte
+// row pointer per row swept), which equals bytes where no matrix is read
 struct ProfScope {
   Ctx* c;
   int cls;
-  double bytes;
+  double bytes, bytes_csr;
   std::string kernel;
   hipEvent_t a = nullptr;
-  ProfScope(Ctx* c_, int cls_, double bytes_, std::string kernel_ = std::string())
-      : c(c_), cls(cls_), bytes(bytes_), kernel(std::move(kernel_)) {
+  ProfScope(Ctx* c_, int cls_, double bytes_, std::string kernel_ = std::string(),
+            double bytes_csr_ = -1.0)
+      : c(c_), cls(cls_), bytes(bytes_), bytes_csr(bytes_csr_ < 0 ? bytes_ : bytes_csr_),
+        kernel(std::move(kernel_)) {
     if (c->profiling) c->prof_begin(cls, &a);
   }
   ~ProfScope() {
-    if (c->profiling && a) c->prof_end(cls, a, bytes, std::move(kernel));
+    if (c->profiling && a) c->prof_end(cls, a, bytes, bytes_csr, std::move(kernel));
   }
 };
 

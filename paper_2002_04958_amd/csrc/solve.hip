@@ -1170,6 +1170,15 @@ template <typename T>
 static double mat_bytes(const LMat<T>& m, long long nnz) {
   return (double)nnz * (sizeof(T) + (m.fmt == kFmtSELL16 ? 2 : 4));
 }
+// profiling scope of a launch that reads `nnz` entries of m over `rows` rows
+// plus vec_bytes of vectors: stored-layout bytes, and the same launch priced
+// as plain CSR (value and 4-byte column per entry, 4-byte row pointer per row)
+template <typename T>
+static ProfScope prof_level(Ctx* c, int cls, const LMat<T>& m, long long nnz, long long rows,
+                            double vec_bytes, std::string name) {
+  return ProfScope(c, cls, mat_bytes(m, nnz) + vec_bytes, std::move(name),
+                   (double)nnz * (sizeof(T) + 4) + 4.0 * (double)rows + vec_bytes);
+}
 static inline int cls_of(int l, int cls0) { return l == 0 ? cls0 : KC_VCYCLE_COARSE; }
 
 template <typename T>
@@ -1197,9 +1206,8 @@ void Union<T>::vcycle(Ctx* c, T* z) {
     if (lv.nS > 0) {
       for (int s = 0; s < n_pre; ++s) {
         if (s > 0) {  // C half of a later sweep
-          ProfScope ps(c, cls_of(l, KC_SMOOTH_L0),
-                       mat_bytes(lv.A, lv.nnz_C) + (double)lv.nC * 4 * ts + lv.nS * ts,
-                       kname(c, "k_half", lv.A));
+          ProfScope ps = prof_level(c, cls_of(l, KC_SMOOTH_L0), lv.A, lv.nnz_C, lv.nC,
+                                    (double)lv.nC * 4 * ts + lv.nS * ts, kname(c, "k_half", lv.A));
           with_layout(lv.A.fmt, lv.A.tpr,
                       HalfL<T>{c, lv.A, 0, lv.nC, lv.dinv.get(), B[l].get(),
                                gather_cf<T>(Xb(l, cc[l]), Xb(l, cf[l]), lv.nC), Xb(l, cc[l]),
@@ -1208,16 +1216,14 @@ void Union<T>::vcycle(Ctx* c, T* z) {
         }
         if (nF > 0) {
           if (s == 0) {
-            ProfScope ps(c, cls_of(l, KC_SMOOTH_L0),
-                         mat_bytes(lv.A, lv.nnz_F) + (double)nF * 3 * ts + lv.nC * ts,
-                         kname(c, "k_fhalf0", lv.A));
+            ProfScope ps = prof_level(c, cls_of(l, KC_SMOOTH_L0), lv.A, lv.nnz_F, nF,
+                                      (double)nF * 3 * ts + lv.nC * ts, kname(c, "k_fhalf0", lv.A));
             with_layout(lv.A.fmt, lv.A.tpr,
                         FHalf0L<T>{c, lv.A, lv.nC, lv.nS, lv.nC, lv.dinv.get(), B[l].get(),
                                    Xb(l, cc[l]), Xb(l, 1 - cf[l])});
           } else {
-            ProfScope ps(c, cls_of(l, KC_SMOOTH_L0),
-                         mat_bytes(lv.A, lv.nnz_F) + (double)nF * 4 * ts + lv.nS * ts,
-                         kname(c, "k_half", lv.A));
+            ProfScope ps = prof_level(c, cls_of(l, KC_SMOOTH_L0), lv.A, lv.nnz_F, nF,
+                                      (double)nF * 4 * ts + lv.nS * ts, kname(c, "k_half", lv.A));
             with_layout(lv.A.fmt, lv.A.tpr,
                         HalfL<T>{c, lv.A, lv.nC, lv.nS, lv.dinv.get(), B[l].get(),
                                  gather_cf<T>(Xb(l, cc[l]), Xb(l, cf[l]), lv.nC), Xb(l, cf[l]),
@@ -1229,18 +1235,17 @@ void Union<T>::vcycle(Ctx* c, T* z) {
       if (n_pre == 0 && nF > 0) fill<T>(c, Xb(l, cf[l]) + lv.nC, (T)0, (size_t)nF);
       if (lv.nX_next > 0) {
         {
-          ProfScope ps(c, cls_of(l, KC_RESID_L0),
-                       mat_bytes(lv.A, lv.A.nnz) + (double)lv.nS * 3 * ts,
-                       kname(c, "k_resid", lv.A));
+          ProfScope ps = prof_level(c, cls_of(l, KC_RESID_L0), lv.A, lv.A.nnz, lv.nS,
+                                    (double)lv.nS * 3 * ts, kname(c, "k_resid", lv.A));
           with_layout(lv.A.fmt, lv.A.tpr,
                       ResidL<T>{c, lv.A, lv.nS, B[l].get(),
                                 gather_cf<T>(Xb(l, cc[l]), Xb(l, cf[l]), lv.nC), R[l].get()});
         }
         const ULevel<T>& nx = L[l + 1];
-        ProfScope ps(c, cls_of(l, KC_TRANSFER_L0),
-                     mat_bytes(lv.Wt, lv.Wt.nnz) + (double)lv.nX_next * (4 + ts) +
-                         (double)nx.nC * 2 * ts + lv.nS * ts,
-                     kname(c, "k_restrict", lv.Wt, {n_pre > 0 ? "true" : "false"}));
+        ProfScope ps = prof_level(c, cls_of(l, KC_TRANSFER_L0), lv.Wt, lv.Wt.nnz, lv.Wt.rows,
+                                  (double)lv.nX_next * (4 + ts) + (double)nx.nC * 2 * ts +
+                                      lv.nS * ts,
+                                  kname(c, "k_restrict", lv.Wt, {n_pre > 0 ? "true" : "false"}));
         with_layout(lv.Wt.fmt, lv.Wt.tpr,
                     RestrictL<T>{c, lv.Wt, lv.nX_next, lv.nC, nx.nC, lv.cpos.get(), R[l].get(),
                                  nx.dinv.get(), B[l + 1].get(), Xb(l + 1, 0), n_pre > 0});
@@ -1261,10 +1266,9 @@ void Union<T>::vcycle(Ctx* c, T* z) {
     const int nF = lv.nS - lv.nC;
     if (lv.nS > 0 && lv.nX_next > 0) {
       const ULevel<T>& nx = L[l + 1];
-      ProfScope ps(c, cls_of(l, KC_TRANSFER_L0),
-                   mat_bytes(lv.W, lv.W.nnz) + (double)lv.nC * 4 + lv.nS * 2.0 * ts +
-                       (double)lv.nX_next * ts,
-                   kname(c, "k_prolong", lv.W));
+      ProfScope ps = prof_level(c, cls_of(l, KC_TRANSFER_L0), lv.W, lv.W.nnz, lv.W.rows,
+                                (double)lv.nC * 4 + lv.nS * 2.0 * ts + (double)lv.nX_next * ts,
+                                kname(c, "k_prolong", lv.W));
       with_layout(lv.W.fmt, lv.W.tpr,
                   ProlongL<T>{c, lv.W, lv.nS, lv.nC, lv.cmap.get(),
                               gather_cfd<T>(Xb(l + 1, cc[l + 1]), Xb(l + 1, cf[l + 1]),
@@ -1275,9 +1279,8 @@ void Union<T>::vcycle(Ctx* c, T* z) {
     if (lv.nS > 0) {
       for (int s = 0; s < n_post; ++s) {
         if (nF > 0) {
-          ProfScope ps(c, cls_of(l, KC_SMOOTH_L0),
-                       mat_bytes(lv.A, lv.nnz_F) + (double)nF * 4 * ts + lv.nS * ts,
-                       kname(c, "k_half", lv.A));
+          ProfScope ps = prof_level(c, cls_of(l, KC_SMOOTH_L0), lv.A, lv.nnz_F, nF,
+                                    (double)nF * 4 * ts + lv.nS * ts, kname(c, "k_half", lv.A));
           with_layout(lv.A.fmt, lv.A.tpr,
                       HalfL<T>{c, lv.A, lv.nC, lv.nS, lv.dinv.get(), B[l].get(),
                                gather_cf<T>(Xb(l, cc[l]), Xb(l, cf[l]), lv.nC), Xb(l, cf[l]),
@@ -1285,19 +1288,17 @@ void Union<T>::vcycle(Ctx* c, T* z) {
           cf[l] = 1 - cf[l];
         }
         if (last_out && s == n_post - 1) {  // final C half writes the natural result
-          ProfScope ps(c, KC_SMOOTH_L0,
-                       mat_bytes(lv.A, lv.nnz_C) + (double)lv.nC * 3 * ts + lv.nS * ts +
-                           (double)lv.nX * (4 + ts),
-                       kname(c, "k_half_out", lv.A));
+          ProfScope ps = prof_level(c, KC_SMOOTH_L0, lv.A, lv.nnz_C, lv.nC,
+                                    (double)lv.nC * 3 * ts + lv.nS * ts + (double)lv.nX * (4 + ts),
+                                    kname(c, "k_half_out", lv.A));
           with_layout(lv.A.fmt, lv.A.tpr,
                       HalfOutL<T>{c, lv.A, lv.nX, lv.nC, lv.nS, lv.dinv.get(), B[l].get(),
                                   gather_cf<T>(Xb(l, cc[l]), Xb(l, cf[l]), lv.nC), X0[l].get(),
                                   lv.perm.get(), z});
           return;
         }
-        ProfScope ps(c, cls_of(l, KC_SMOOTH_L0),
-                     mat_bytes(lv.A, lv.nnz_C) + (double)lv.nC * 4 * ts + lv.nS * ts,
-                     kname(c, "k_half", lv.A));
+        ProfScope ps = prof_level(c, cls_of(l, KC_SMOOTH_L0), lv.A, lv.nnz_C, lv.nC,
+                                  (double)lv.nC * 4 * ts + lv.nS * ts, kname(c, "k_half", lv.A));
         with_layout(lv.A.fmt, lv.A.tpr,
                     HalfL<T>{c, lv.A, 0, lv.nC, lv.dinv.get(), B[l].get(),
                              gather_cf<T>(Xb(l, cc[l]), Xb(l, cf[l]), lv.nC), Xb(l, cc[l]),
@@ -1405,9 +1406,9 @@ void Union<T>::apply(Ctx* c, const T* bvec, T* z, int cycles) {
     vcycle(c, z);
   for (int k = 1; k < cycles; ++k) {
     {
-      ProfScope ps(c, KC_RESID_L0,
-                   mat_bytes(l0.A, l0.A.nnz) + (double)l0.nX * (8 + 3.0 * sizeof(T)),
-                   kname(c, "k_entry_resid", l0.A, {pre ? "true" : "false"}));
+      ProfScope ps = prof_level(c, KC_RESID_L0, l0.A, l0.A.nnz, l0.nS,
+                                (double)l0.nX * (8 + 3.0 * sizeof(T)),
+                                kname(c, "k_entry_resid", l0.A, {pre ? "true" : "false"}));
       with_layout(l0.A.fmt, l0.A.tpr,
                   EntryResidL<T>{c, l0.A, l0.nX, l0.nS, l0.nC, l0.perm.get(), l0.dinv.get(), bvec,
                                  z, B[0].get(), X0[0].get(), pre});

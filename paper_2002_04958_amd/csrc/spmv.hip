@@ -200,21 +200,23 @@ __global__ void __launch_bounds__(256) k_block_matvec_finish(BlockSysDev S,
 
 constexpr int kSharedRows = 512;
 
-double block_matvec_bytes(const BlockSysDev& S, bool resid) {
+// values, pattern (once when shared, or per block with csr = true: the plain
+// CSR pricing of every block), x, couplings, y (and b)
+double block_matvec_bytes(const BlockSysDev& S, bool resid, bool csr) {
   const double n = (double)(S.G + 2) * S.N;
   double nnz = 0;
   for (int a = 0; a < S.G + 2; ++a) nnz += S.nnz[a];
-  // values, pattern (once when shared), x, couplings, y (and b)
-  const double pattern = S.shared ? 4.0 * S.nnz[0] + 4.0 * (S.N + 1)
-                                  : 4.0 * nnz + 4.0 * n;
+  const double pattern = (S.shared && !csr) ? 4.0 * S.nnz[0] + 4.0 * (S.N + 1)
+                                            : 4.0 * nnz + 4.0 * n;
   return 8.0 * nnz + pattern + 8.0 * (2.0 * S.G + 2.0) * S.N + 8.0 * n * (resid ? 3 : 2);
 }
 
 void block_matvec(Ctx* c, const BlockSysDev& S, const double* x, const double* b, double* y) {
   if (S.shared) {
     constexpr int R = kSharedRows;
-    ProfScope ps(c, KC_BLOCK_MATVEC, block_matvec_bytes(S, b != nullptr),
-                 ksym(c, "k_block_matvec_shared", {std::to_string(R), b ? "true" : "false"}));
+    ProfScope ps(c, KC_BLOCK_MATVEC, block_matvec_bytes(S, b != nullptr, false),
+                 ksym(c, "k_block_matvec_shared", {std::to_string(R), b ? "true" : "false"}),
+                 block_matvec_bytes(S, b != nullptr, true));
     const dim3 grid(cdiv(S.N, R));
     if (b)
       hipLaunchKernelGGL((k_block_matvec_shared<R, true, false>), grid, dim3(R), 0, c->stream, S, x,
@@ -225,7 +227,7 @@ void block_matvec(Ctx* c, const BlockSysDev& S, const double* x, const double* b
     MGD_CHECK_LAUNCH();
     return;
   }
-  ProfScope ps(c, KC_BLOCK_MATVEC, block_matvec_bytes(S, b != nullptr),
+  ProfScope ps(c, KC_BLOCK_MATVEC, block_matvec_bytes(S, b != nullptr, false),
                ksym(c, "k_block_matvec", {std::to_string(tpr_of(S.tpr)), b ? "true" : "false"}));
   dispatch_tpr<BlockMatvecLaunch>(S.tpr, c, S, x, b, y);
 }

@@ -29,7 +29,7 @@ BlockSysDev make_block_sys_dev(const mgd_block_system* A);
 void check_block_system(const mgd_block_system* A);
 // y = A x, or y = b - A x when b != nullptr.
 void block_matvec(Ctx* c, const BlockSysDev& S, const double* x, const double* b, double* y);
-double block_matvec_bytes(const BlockSysDev& S, bool resid);
+double block_matvec_bytes(const BlockSysDev& S, bool resid, bool csr);
 // y = A x in two parts (shared pattern only): the part that does not read x_E,
 // on `stream`, and, on the context stream once x_E is known, the rest; the
 // result equals block_matvec's bit for bit.

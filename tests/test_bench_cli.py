@@ -37,3 +37,13 @@ def test_traffic_record_needs_the_current_digest(tmp_path, monkeypatch):
     assert bench.recorded_traffic("k_half<float, 2, 1>") == 123
     assert bench.recorded_traffic("k_resid<float, 2, 1>") is None   # stale record
     assert bench.recorded_traffic("k_fhalf0<float, 2, 1>") is None  # no record
+
+
+def test_error_against_is_per_segment():
+    import numpy as np
+    ref = np.concatenate([np.full(4, 10.0), np.full(4, 1e-3), np.full(4, 2.0)])
+    x = ref.copy()
+    x[5] += 1e-9          # segment 1: max 1e-3, so 1e-6 of its scale
+    e = bench.error_against(x, ref, 1)
+    assert abs(e["max_abs_over_segment_max"] - 1e-6) < 1e-12
+    assert 0 < e["rel_2norm"] < 1e-9
