@@ -6,7 +6,9 @@ every entry point raises LibraryMissing.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import weakref
 from ctypes import byref, c_double, c_int64, c_void_p
 from dataclasses import dataclass
 from typing import Optional, Sequence
@@ -56,6 +58,20 @@ def _torch_allocator(device: int):
     return cbs, L.mgd_allocator(cbs[0], cbs[1], None)
 
 
+_LIVE_CONTEXTS = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all_contexts():
+    """Release every handle and context while the interpreter and torch are
+    still whole (finalizers at shutdown run in no defined order)."""
+    for c in list(_LIVE_CONTEXTS):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
 class Context:
     """Device, stream and library context.  The stream defaults to torch's
     current stream on the device, so library work and torch work are ordered.
@@ -77,14 +93,29 @@ class Context:
         L.check(self.lib.mgd_ctx_create(device, c_void_p(self.stream.cuda_stream),
                                         byref(alloc) if alloc is not None else None, byref(h)))
         self.h = h
+        self._children = weakref.WeakSet()
+        _LIVE_CONTEXTS.add(self)
+
+    def _adopt(self, obj):
+        """Handles made on this context are closed before it (preconditioners,
+        then hierarchies, then systems), whatever order their finalizers run in."""
+        self._children.add(obj)
 
     def synchronize(self):
         L.check(self.lib.mgd_ctx_synchronize(self.h))
 
     def close(self):
         if getattr(self, "h", None):
+            order = {"BlockPreconditioner": 0, "AMG": 1, "BlockSystem": 2}
+            for ch in sorted(list(getattr(self, "_children", ())),
+                             key=lambda o: order.get(type(o).__name__, 3)):
+                ch.close()
             self.lib.mgd_ctx_destroy(self.h)
             self.h = None
+
+    @property
+    def alive(self) -> bool:
+        return bool(getattr(self, "h", None))
 
     def __del__(self):
         try:
@@ -169,6 +200,7 @@ class BlockSystem:
         self.s = L.mgd_block_system()
         self._owned = False
         self._keep = []
+        ctx._adopt(self)
 
     @staticmethod
     def assemble(ctx: Context, coeffs: Coeffs) -> "BlockSystem":
@@ -235,9 +267,9 @@ class BlockSystem:
         return y
 
     def close(self):
-        if self._owned and self.s.blocks:
+        if self._owned and self.s.blocks and self.ctx.alive:
             self.ctx.lib.mgd_block_system_free(self.ctx.h, byref(self.s))
-            self._owned = False
+        self._owned = False
 
     def __del__(self):
         try:
@@ -310,6 +342,7 @@ class AMG:
         L.check(ctx.lib.amg_setup(ctx.h, byref(A), byref(self.params), byref(h)))
         self.h = h
         self._owned = True
+        ctx._adopt(self)
 
     def apply(self, r: torch.Tensor, z: Optional[torch.Tensor] = None, cycles: int = 1):
         z = torch.empty_like(r) if z is None else z
@@ -348,9 +381,9 @@ class AMG:
         return out
 
     def close(self):
-        if self._owned and self.h:
+        if self._owned and self.h and self.ctx.alive:
             self.ctx.lib.amg_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
@@ -386,6 +419,7 @@ class BlockPreconditioner:
         L.check(ctx.lib.block_precond_create(ctx.h, byref(system.s), byref(self.params), byref(h)))
         self.h = h
         self.G, self.N = system.G, system.N
+        ctx._adopt(self)
 
     def apply(self, r: torch.Tensor, z: Optional[torch.Tensor] = None) -> torch.Tensor:
         z = torch.empty_like(r) if z is None else z
@@ -417,9 +451,9 @@ class BlockPreconditioner:
         return AMG(self.ctx, None, None, None, _handle=h, _owner=self)
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and self.ctx.alive:
             self.ctx.lib.block_precond_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:

@@ -1071,7 +1071,7 @@ void block_precond_apply_matvec(block_precond* bp, const double* r, double* z,
   Ctx* c = bp->ctx;
   // MGD_STEP_OVERLAP=0 keeps the one-kernel matvec after the apply (for comparisons)
   const char* ov = std::getenv("MGD_STEP_OVERLAP");
-  const bool split = S.shared && !c->profiling && bp->prm.kind == MGD_PC_SCHUR2 &&
+  const bool split = S.shared && bp->prm.kind == MGD_PC_SCHUR2 &&
                      S.G == bp->G && S.N == bp->N && !(ov && ov[0] == '0');
   if (split && !bp->ovl_stream) {
     MGD_HIP(hipStreamCreateWithFlags(&bp->ovl_stream, hipStreamNonBlocking));

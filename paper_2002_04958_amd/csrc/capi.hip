@@ -29,6 +29,9 @@ thread_local std::string g_last_error;
 
 template <typename F>
 mgd_status guard(F&& f) {
+  // an error left in the runtime's per-thread state by another caller's HIP
+  // call must not be reported by this call's launch checks
+  (void)hipGetLastError();
   try {
     return f();
   } catch (const Error& e) {
@@ -100,14 +103,15 @@ hipEvent_t Ctx::take_event() {
   MGD_HIP(hipEventCreate(&e));
   return e;
 }
-void Ctx::prof_begin(int cls, hipEvent_t* a) {
+void Ctx::prof_begin(int cls, hipEvent_t* a, hipStream_t s) {
   (void)cls;
   *a = take_event();
-  MGD_HIP(hipEventRecord(*a, stream));
+  MGD_HIP(hipEventRecord(*a, s));
 }
-void Ctx::prof_end(int cls, hipEvent_t a, double bytes_, double bytes_csr_, std::string kernel) {
+void Ctx::prof_end(int cls, hipEvent_t a, double bytes_, double bytes_csr_, std::string kernel,
+                   hipStream_t s) {
   hipEvent_t b = take_event();
-  MGD_HIP(hipEventRecord(b, stream));
+  MGD_HIP(hipEventRecord(b, s));
   pending.push_back({cls, a, b, bytes_, bytes_csr_, std::move(kernel)});
   if (pending.size() > 4096) prof_collect();
 }

@@ -119,8 +119,9 @@ struct Ctx {
   void check_device_errors(const char* where);  // synchronises; throws when set
   // profiling hooks
   hipEvent_t take_event();
-  void prof_begin(int cls, hipEvent_t* a);
-  void prof_end(int cls, hipEvent_t a, double bytes, double bytes_csr, std::string kernel);
+  void prof_begin(int cls, hipEvent_t* a, hipStream_t s);
+  void prof_end(int cls, hipEvent_t a, double bytes, double bytes_csr, std::string kernel,
+                hipStream_t s);
   void prof_collect();  // synchronises
   ~Ctx();
 };
@@ -130,21 +131,24 @@ struct Ctx {
 // exactly one launch, so per-kernel averages can be compared with a trace.
 // bytes: algorithmic bytes of the launch in its stored layout; bytes_csr: the
 // same launch priced as plain CSR (value and 4-byte column per entry, 4-byte
-// row pointer per row swept), which equals bytes where no matrix is read
+// row pointer per row swept), which equals bytes where no matrix is read.
+// The events go on `stream` (default: the context stream), the stream the
+// timed launch runs on.
 struct ProfScope {
   Ctx* c;
   int cls;
   double bytes, bytes_csr;
   std::string kernel;
+  hipStream_t s;
   hipEvent_t a = nullptr;
   ProfScope(Ctx* c_, int cls_, double bytes_, std::string kernel_ = std::string(),
-            double bytes_csr_ = -1.0)
+            double bytes_csr_ = -1.0, hipStream_t stream = nullptr)
       : c(c_), cls(cls_), bytes(bytes_), bytes_csr(bytes_csr_ < 0 ? bytes_ : bytes_csr_),
-        kernel(std::move(kernel_)) {
-    if (c->profiling) c->prof_begin(cls, &a);
+        kernel(std::move(kernel_)), s(stream ? stream : c_->stream) {
+    if (c->profiling) c->prof_begin(cls, &a, s);
   }
   ~ProfScope() {
-    if (c->profiling && a) c->prof_end(cls, a, bytes, bytes_csr, std::move(kernel));
+    if (c->profiling && a) c->prof_end(cls, a, bytes, bytes_csr, std::move(kernel), s);
   }
 };
 

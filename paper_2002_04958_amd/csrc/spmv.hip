@@ -232,16 +232,37 @@ void block_matvec(Ctx* c, const BlockSysDev& S, const double* x, const double* b
   dispatch_tpr<BlockMatvecLaunch>(S.tpr, c, S, x, b, y);
 }
 
+// the split kernel: values of every block but E, the pattern once (per block
+// in the CSR pricing), x without x_E, d_Eg, y written
+static void split_bytes(const BlockSysDev& S, double& stored, double& csr) {
+  const double N = S.N, G = S.G;
+  double nnz = 0;
+  for (int a = 0; a < S.G + 2; ++a)
+    if (a != S.G) nnz += S.nnz[a];
+  const double vec = 8.0 * (G + 1) * N + 8.0 * G * N + 8.0 * (G + 2) * N;
+  stored = 8.0 * nnz + 4.0 * S.nnz[0] + 4.0 * (N + 1) + vec;
+  csr = 12.0 * nnz + 4.0 * (G + 1) * (N + 1) + vec;
+}
+
 void block_matvec_split(Ctx* c, const BlockSysDev& S, const double* x, double* y,
                         hipStream_t stream) {
   MGD_REQUIRE(S.shared, "split block matvec needs the shared pattern");
   constexpr int R = kSharedRows;
+  double bs = 0, bc = 0;
+  if (c->profiling) split_bytes(S, bs, bc);
+  ProfScope ps(c, KC_BLOCK_MATVEC, bs,
+               ksym(c, "k_block_matvec_shared", {std::to_string(R), "false", "true"}), bc, stream);
   hipLaunchKernelGGL((k_block_matvec_shared<R, false, true>), dim3(cdiv(S.N, R)), dim3(R), 0,
                      stream, S, x, (const double*)nullptr, y);
   MGD_CHECK_LAUNCH();
 }
 
 void block_matvec_finish(Ctx* c, const BlockSysDev& S, const double* x, double* y) {
+  // A_E (values, pattern), x_E, x_I, d_EI, d_IE, d_gE, y read and written
+  const double N = S.N, G = S.G;
+  const double b = 12.0 * S.nnz[S.G] + 4.0 * (N + 1) + 8.0 * 4 * N + 8.0 * G * N +
+                   16.0 * (G + 2) * N;
+  ProfScope ps(c, KC_BLOCK_MATVEC, b, ksym(c, "k_block_matvec_finish", {}));
   hipLaunchKernelGGL(k_block_matvec_finish, dim3(cdiv(S.N, 256)), dim3(256), 0, c->stream, S, x,
                      y);
   MGD_CHECK_LAUNCH();
