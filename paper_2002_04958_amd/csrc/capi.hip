@@ -750,7 +750,9 @@ mgd_status gmres_solve(mgd_ctx* ctx, const mgd_block_system* A, block_precond* M
     MGD_REQUIRE(!M || (M->G == A->G && M->N == A->N), "preconditioner built for another shape");
     MGD_REQUIRE(p->rtol >= 0, "rtol must be >= 0");
     ctx->make_current();
-    return gmres_impl(ctx, make_block_sys_dev(A), M, b, x, *p, *out);
+    const mgd_status st = gmres_impl(ctx, make_block_sys_dev(A), M, b, x, *p, *out);
+    ctx->check_device_errors("gmres_solve (V-cycle tail barrier)");
+    return st;
   });
 }
 
@@ -791,6 +793,7 @@ mgd_status adjoint_solve(mgd_ctx* ctx, const mgd_coeffs* c, const mgd_block_syst
     if (st != MGD_OK && st != MGD_ENOTCONV) return st;
     adjoint_gradients_impl(ctx, c, x, lambda, dL_dkappa, dL_dc);
     ctx->sync();
+    ctx->check_device_errors("adjoint_solve (V-cycle tail barrier)");
     if (st == MGD_ENOTCONV) g_last_error = "adjoint GMRES reached max_iters";
     return st;
   });

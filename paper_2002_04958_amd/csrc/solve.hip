@@ -576,6 +576,7 @@ std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHiera
     if (ncoarse == 0) break;
   }
   finalize_levels(c, built, *U, autotune);
+  U->build_tail(c);
   c->sync();
   return U;
 }
@@ -967,6 +968,155 @@ __global__ void k_axpy_t(int n, const T* __restrict__ x, T* __restrict__ y) {
 }
 
 // ---------------------------------------------------------------------------
+// persistent tail: every level from a threshold down (and back up) in one
+// launch.  Each phase does what the per-level kernel of the same name does,
+// with the same arithmetic, over a grid-stride loop; phases are separated by
+// a grid-wide barrier.  The grid is sized so that all its workgroups are
+// resident at once; a barrier wait that exceeds its spin bound reports
+// through the error flag and lets the workgroup go on, so the kernel always
+// ends.  The last workgroup to finish resets the counters for the next launch.
+// Pointers to vectors that earlier phases write are read without __restrict__,
+// so every such load goes through the memory system after the barrier's fence.
+// ---------------------------------------------------------------------------
+constexpr int kTailThreads = 256;
+constexpr unsigned kTailSpinLimit = 1u << 17;  // about 0.1 s of polling
+constexpr int kTailSyncStride = 32;  // counters 128 bytes apart
+constexpr int kErrTailBarrier = 64;
+
+__device__ __forceinline__ void tail_barrier(unsigned* arrive, unsigned target, int* err) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned spins = 0;
+    while (__hip_atomic_load(arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      // once any wait has timed out, later waits of the launch end at once
+      if (++spins > kTailSpinLimit ||
+          (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTailBarrier)) {
+        atomicOr(err, kErrTailBarrier);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+template <int FMT, int TPR, typename T>
+__device__ __forceinline__ void tail_rows(const TailOp<T>& op) {
+  const long long n = (long long)(op.r1 - op.r0) * TPR;
+  const long long stride = (long long)gridDim.x * kTailThreads;
+  for (long long t = blockIdx.x * (long long)kTailThreads + threadIdx.x; t < n; t += stride) {
+    // a group of TPR lanes shares a row: the whole group is in or out of range
+    const int lane = (int)(t % TPR);
+    const int k = op.r0 + (int)(t / TPR);
+    if (op.kind == kTopFHalf0) {
+      const T s = mrow_c<FMT, TPR>(op.rp, op.ci, op.v, op.xc, op.nC, k, lane);
+      if (lane == 0) op.out[k] = (T)0 + (op.B[k] - s) * op.dinv[k];
+    } else if (op.kind == kTopHalf) {
+      const T s = mrow<FMT, TPR>(op.rp, op.ci, op.v, GatherCF<T>{op.xc, op.f_minus_c, op.nC}, k,
+                                 lane);
+      if (lane == 0) op.out[k] = op.xold[k] + (op.B[k] - s) * op.dinv[k];
+    } else if (op.kind == kTopResid) {
+      const T s = mrow<FMT, TPR>(op.rp, op.ci, op.v, GatherCF<T>{op.xc, op.f_minus_c, op.nC}, k,
+                                 lane);
+      if (lane == 0) op.out[k] = op.B[k] - s;
+    } else if (op.kind == kTopRestrict) {
+      const T s = mrow<FMT, TPR>(op.rp, op.ci, op.v, Gather1<T>{op.B + op.nC}, k, lane);
+      if (lane == 0) {
+        const T bb = op.B[op.map[k]] + s;
+        op.out[k] = bb;
+        if (k < op.nCn) op.out2[k] = op.pre ? bb * op.dinv[k] : (T)0;
+      }
+    } else {  // kTopProlong
+      const GatherCFD<T> E{op.xc, (ptrdiff_t)op.f_minus_c, (ptrdiff_t)op.d_minus_c, op.nC, op.nS};
+      if (k < op.nCn) {
+        if (lane == 0) op.out2[k] += E(op.map[k]);
+      } else {
+        const T s = mrow<FMT, TPR>(op.rp, op.ci, op.v, E, k - op.nCn, lane);
+        if (lane == 0) op.out[k] += s;
+      }
+    }
+  }
+}
+
+// k_dense over virtual workgroups (member, 64-row chunk)
+template <typename T>
+__device__ __forceinline__ void tail_dense(const TailOp<T>& op) {
+  __shared__ double part[4][64];
+  const int nvb = op.ndense * op.dchunks;
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+    const DenseDev d = op.dense[vb / op.dchunks];
+    const int i = (vb % op.dchunks) * 64 + lane;
+    const int quarter = (d.n + 3) / 4;
+    const int j0 = min(d.n, q * quarter), j1 = min(d.n, j0 + quarter);
+    double sum = 0.0;
+    if (i < d.n) {
+      const double* __restrict__ col = d.inv + i;
+      const T* bb = op.B + d.off;
+      int j = j0;
+      for (; j + 8 <= j1; j += 8) {
+        double a[8], x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          a[k] = col[(size_t)(j + k) * d.n];
+          x[k] = (double)bb[j + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sum += a[k] * x[k];
+      }
+      for (; j < j1; ++j) sum += col[(size_t)j * d.n] * (double)bb[j];
+    }
+    part[q][lane] = sum;
+    __syncthreads();
+    if (q == 0 && i < d.n)
+      op.out[d.off + i] = (T)(((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void tail_phase(const TailOp<T>& op) {
+  if (op.kind == kTopDense) {
+    tail_dense(op);
+    return;
+  }
+  if (op.fmt == kFmtSELL) return tail_rows<kFmtSELL, 1>(op);
+  if (op.fmt == kFmtSELL16) return tail_rows<kFmtSELL16, 1>(op);
+  switch (op.tpr) {
+    case 1: tail_rows<kFmtCSR, 1>(op); break;
+    case 2: tail_rows<kFmtCSR, 2>(op); break;
+    case 4: tail_rows<kFmtCSR, 4>(op); break;
+    case 8: tail_rows<kFmtCSR, 8>(op); break;
+    case 16: tail_rows<kFmtCSR, 16>(op); break;
+    case 32: tail_rows<kFmtCSR, 32>(op); break;
+    default: tail_rows<kFmtCSR, 64>(op); break;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kTailThreads) k_tail(const TailOp<T>* __restrict__ ops, int nops,
+                                                       unsigned* sync, int* err) {
+  for (int p = 0; p < nops; ++p) {
+    if (p > 0) tail_barrier(sync, (unsigned)p * gridDim.x, err);
+    const TailOp<T> op = ops[p];
+    tail_phase(op);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // every workgroup has passed every barrier once it counts itself out here;
+    // only the counters are touched (atomically), so no data fence is needed
+    const unsigned k =
+        __hip_atomic_fetch_add(sync + kTailSyncStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (k == gridDim.x - 1) {
+      __hip_atomic_store(sync, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(sync + kTailSyncStride, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers: one row per lane (SELL) or TPR lanes per row (CSR)
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -1198,7 +1348,8 @@ void Union<T>::vcycle(Ctx* c, T* z) {
   std::vector<int> cc(nl, 0), cf(nl, 0);
   auto Xb = [&](int l, int which) -> T* { return which ? X1[l].get() : X0[l].get(); };
   t_prof_members = members;
-  for (int l = 0; l < nl; ++l) {
+  const int lt = tail_from >= 0 ? tail_from : nl;
+  for (int l = 0; l < lt; ++l) {
     t_prof_level = l;
     ULevel<T>& lv = L[l];
     const int nF = lv.nS - lv.nC;
@@ -1260,7 +1411,17 @@ void Union<T>::vcycle(Ctx* c, T* z) {
       MGD_CHECK_LAUNCH();
     }
   }
-  for (int l = nl - 1; l >= 0; --l) {
+  if (lt < nl) {  // levels lt .. nl-1, down and up, in one launch
+    t_prof_level = lt;
+    ProfScope ps(c, KC_VCYCLE_COARSE, tail_bytes, ksym(c, "k_tail", {type_name<T>()}) + level_tag(),
+                 tail_bytes_csr);
+    hipLaunchKernelGGL(k_tail<T>, dim3(tail_blocks), dim3(kTailThreads), 0, c->stream,
+                       (const TailOp<T>*)tail_ops.get(), tail_nops, tail_sync.get(), c->err_flag());
+    MGD_CHECK_LAUNCH();
+    cc[lt] = tail_cc;
+    cf[lt] = tail_cf;
+  }
+  for (int l = lt - 1; l >= 0; --l) {
     t_prof_level = l;
     ULevel<T>& lv = L[l];
     const int nF = lv.nS - lv.nC;
@@ -1313,6 +1474,181 @@ void Union<T>::vcycle(Ctx* c, T* z) {
       MGD_CHECK_LAUNCH();
     }
   }
+}
+
+// Levels from which the persistent tail takes over: the first level from
+// which every level has at most MGD_TAIL_ROWS extended rows (default
+// kTailRows = 0: off, the per-level launches measure faster on gfx950, where
+// the barrier's device-scope release and acquire write back and invalidate
+// the L2 of the workgroup's chiplet at every phase).  Workgroups:
+// MGD_TAIL_BLOCKS (default kTailBlocks), capped by what the device holds
+// resident at once.
+constexpr int kTailRows = 0;
+constexpr int kTailBlocks = 256;
+static long long env_ll(const char* name, long long dflt) {
+  const char* e = std::getenv(name);
+  return e && *e ? std::atoll(e) : dflt;
+}
+
+// The phase table of vcycle() for levels >= tail_from, recorded with the same
+// buffer choices (the two iterate buffers of every level start at X0 in each
+// cycle, so the table is the same for every cycle).
+template <typename T>
+void Union<T>::build_tail(Ctx* c) {
+  tail_from = -1;
+  const int nl = (int)L.size();
+  const long long rows = env_ll("MGD_TAIL_ROWS", kTailRows);
+  if (gs || n_pre < 1 || rows <= 0 || nl < 2) return;
+  int lt = nl;
+  while (lt > 1 && L[lt - 1].nX <= rows) --lt;
+  if (lt >= nl) return;
+  std::vector<int> cc(nl, 0), cf(nl, 0);
+  auto Xb = [&](int l, int which) -> T* { return which ? X1[l].get() : X0[l].get(); };
+  std::vector<TailOp<T>> ops;
+  double bytes = 0, bytes_csr = 0;
+  const size_t ts = sizeof(T);
+  auto mat_op = [&](int kind, const LMat<T>& m, int r0, int r1, long long nnz, double vec) {
+    TailOp<T> o{};
+    o.kind = kind;
+    o.fmt = m.fmt;
+    o.tpr = m.fmt == kFmtCSR ? tpr_of(m.tpr) : 1;
+    o.r0 = r0;
+    o.r1 = r1;
+    o.rp = m.rp.get();
+    o.ci = m.ci.get();
+    o.v = m.v.get();
+    bytes += mat_bytes(m, nnz) + vec;
+    bytes_csr += (double)nnz * (ts + 4) + 4.0 * (r1 - r0) + vec;
+    return o;
+  };
+  auto gather = [&](TailOp<T>& o, int l) {
+    o.xc = Xb(l, cc[l]);
+    o.f_minus_c = Xb(l, cf[l]) - Xb(l, cc[l]);
+    o.nC = L[l].nC;
+  };
+  for (int l = lt; l < nl; ++l) {  // down: the same steps as vcycle()
+    ULevel<T>& lv = L[l];
+    const int nF = lv.nS - lv.nC;
+    if (lv.nS > 0) {
+      for (int s = 0; s < n_pre; ++s) {
+        if (s > 0) {
+          if (lv.nC > 0) {
+            TailOp<T> o = mat_op(kTopHalf, lv.A, 0, lv.nC, lv.nnz_C, (double)lv.nC * 4 * ts + lv.nS * ts);
+            gather(o, l);
+            o.dinv = lv.dinv.get();
+            o.B = B[l].get();
+            o.xold = Xb(l, cc[l]);
+            o.out = Xb(l, 1 - cc[l]);
+            ops.push_back(o);
+          }
+          cc[l] = 1 - cc[l];
+        }
+        if (nF > 0) {
+          TailOp<T> o = mat_op(s == 0 ? kTopFHalf0 : kTopHalf, lv.A, lv.nC, lv.nS, lv.nnz_F,
+                               (double)nF * (s == 0 ? 3 : 4) * ts + (s == 0 ? lv.nC : lv.nS) * ts);
+          gather(o, l);
+          o.dinv = lv.dinv.get();
+          o.B = B[l].get();
+          o.xold = Xb(l, cf[l]);
+          o.out = Xb(l, 1 - cf[l]);
+          ops.push_back(o);
+          cf[l] = 1 - cf[l];
+        }
+      }
+      if (lv.nX_next > 0) {
+        TailOp<T> o = mat_op(kTopResid, lv.A, 0, lv.nS, lv.A.nnz, (double)lv.nS * 3 * ts);
+        gather(o, l);
+        o.B = B[l].get();
+        o.out = R[l].get();
+        ops.push_back(o);
+        const ULevel<T>& nx = L[l + 1];
+        TailOp<T> q = mat_op(kTopRestrict, lv.Wt, 0, lv.nX_next, lv.Wt.nnz,
+                             (double)lv.nX_next * (4 + ts) + (double)nx.nC * 2 * ts + lv.nS * ts);
+        q.nC = lv.nC;
+        q.nCn = nx.nC;
+        q.pre = 1;
+        q.map = lv.cpos.get();
+        q.B = R[l].get();
+        q.dinv = nx.dinv.get();
+        q.out = B[l + 1].get();
+        q.out2 = X0[l + 1].get();
+        ops.push_back(q);
+      }
+    }
+    if (!lv.dense.empty()) {
+      TailOp<T> o{};
+      o.kind = kTopDense;
+      o.dense = (const DenseDev*)lv.dense_dev.get();
+      o.ndense = (int)lv.dense.size();
+      o.dchunks = cdiv(lv.dense_max_n, 64);
+      o.B = B[l].get();
+      o.out = X0[l].get();
+      bytes += 8.0 * lv.dense_entries + 2.0 * ts * (lv.nX - lv.nS);
+      bytes_csr += 8.0 * lv.dense_entries + 2.0 * ts * (lv.nX - lv.nS);
+      ops.push_back(o);
+    }
+  }
+  for (int l = nl - 1; l >= lt; --l) {  // up
+    ULevel<T>& lv = L[l];
+    const int nF = lv.nS - lv.nC;
+    if (lv.nS > 0 && lv.nX_next > 0) {
+      const ULevel<T>& nx = L[l + 1];
+      TailOp<T> o = mat_op(kTopProlong, lv.W, 0, lv.nS, lv.W.nnz,
+                           (double)lv.nC * 4 + lv.nS * 2.0 * ts + (double)lv.nX_next * ts);
+      o.xc = Xb(l + 1, cc[l + 1]);
+      o.f_minus_c = Xb(l + 1, cf[l + 1]) - Xb(l + 1, cc[l + 1]);
+      o.d_minus_c = X0[l + 1].get() - Xb(l + 1, cc[l + 1]);
+      o.nC = nx.nC;
+      o.nS = nx.nS;
+      o.nCn = lv.nC;
+      o.map = lv.cmap.get();
+      o.out2 = Xb(l, cc[l]);
+      o.out = Xb(l, cf[l]);
+      ops.push_back(o);
+    }
+    if (lv.nS > 0) {
+      for (int s = 0; s < n_post; ++s) {
+        if (nF > 0) {
+          TailOp<T> o = mat_op(kTopHalf, lv.A, lv.nC, lv.nS, lv.nnz_F, (double)nF * 4 * ts + lv.nS * ts);
+          gather(o, l);
+          o.dinv = lv.dinv.get();
+          o.B = B[l].get();
+          o.xold = Xb(l, cf[l]);
+          o.out = Xb(l, 1 - cf[l]);
+          ops.push_back(o);
+          cf[l] = 1 - cf[l];
+        }
+        if (lv.nC > 0) {
+          TailOp<T> o = mat_op(kTopHalf, lv.A, 0, lv.nC, lv.nnz_C, (double)lv.nC * 4 * ts + lv.nS * ts);
+          gather(o, l);
+          o.dinv = lv.dinv.get();
+          o.B = B[l].get();
+          o.xold = Xb(l, cc[l]);
+          o.out = Xb(l, 1 - cc[l]);
+          ops.push_back(o);
+        }
+        cc[l] = 1 - cc[l];
+      }
+    }
+  }
+  if (ops.empty()) return;
+  // workgroups resident at once on the whole device
+  int dev = 0, cus = 0, per_cu = 0;
+  MGD_HIP(hipGetDevice(&dev));
+  MGD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  MGD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tail<T>, kTailThreads, 0));
+  const long long want = env_ll("MGD_TAIL_BLOCKS", kTailBlocks);
+  tail_blocks = (int)std::max(1LL, std::min(want, (long long)cus * std::max(per_cu, 1)));
+  tail_ops.alloc(c, ops.size());
+  copy_h2d(c, tail_ops.get(), ops.data(), ops.size());
+  tail_sync.alloc(c, 2 * kTailSyncStride);
+  fill<unsigned>(c, tail_sync.get(), 0u, 2 * kTailSyncStride);
+  tail_nops = (int)ops.size();
+  tail_cc = cc[lt];
+  tail_cf = cf[lt];
+  tail_bytes = bytes;
+  tail_bytes_csr = bytes_csr;
+  tail_from = lt;
 }
 
 template <typename T>

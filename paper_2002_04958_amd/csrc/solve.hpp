@@ -81,6 +81,33 @@ struct ULevel {
   long long dense_entries = 0;
 };
 
+// One phase of the persistent tail: the small levels of a V-cycle run in one
+// launch, phase after phase, separated by a grid-wide barrier.  Each phase is
+// one of the per-level launches below with the same arguments.
+enum : int { kTopFHalf0 = 0, kTopHalf = 1, kTopResid = 2, kTopRestrict = 3, kTopProlong = 4,
+             kTopDense = 5 };
+template <typename T>
+struct TailOp {
+  int kind, fmt, tpr;
+  int r0, r1;                 // rows of the phase
+  int nC, nS;                 // C-block (and stored rows) of the gathered level
+  int nCn, pre;               // restrict: next level's C-block, first-sweep C values;
+                              // prolong: this level's C-block
+  long long f_minus_c, d_minus_c;
+  const int* rp;              // matrix (A, W^T or W): read only
+  const int* ci;
+  const T* v;
+  const T* dinv;              // 1 / d of the rows (restrict: of the next level)
+  const T* B;                 // right-hand side (restrict: the residual)
+  const T* xc;                // gathered vector, buffer of its C region
+  const T* xold;              // half-sweep: previous values of the rows
+  T* out;                     // rows written
+  T* out2;                    // restrict: next level's C values; prolong: C region
+  const int* map;             // restrict: cpos; prolong: cmap
+  const DenseDev* dense;      // dense solves: members, 64-row chunks per member
+  int ndense, dchunks;
+};
+
 template <typename T>
 struct Union {
   std::vector<ULevel<T>> L;
@@ -92,6 +119,15 @@ struct Union {
   int n_pre = 1, n_post = 1;
   int members = 0;
   bool gs = false;  // multicolour Gauss-Seidel instead of CF-l1-Jacobi
+
+  // persistent tail: levels >= tail_from run as one launch of tail_blocks
+  // workgroups over the phase table tail_ops (tail_from < 0: no tail)
+  int tail_from = -1, tail_nops = 0, tail_blocks = 0;
+  int tail_cc = 0, tail_cf = 0;  // iterate buffers of level tail_from after the tail
+  double tail_bytes = 0, tail_bytes_csr = 0;
+  DBuf<TailOp<T>> tail_ops;
+  DBuf<unsigned> tail_sync;  // barrier counters (reset by the last workgroup out)
+  void build_tail(Ctx* c);
 
   // z = k V-cycles on b (zero initial guess); b, z natural level-0 vectors.
   void apply(Ctx* c, const T* b, T* z, int cycles);

@@ -159,6 +159,7 @@ void fill(Ctx* c, T* p, T v, size_t n) {
   MGD_CHECK_LAUNCH();
 }
 template void fill<int>(Ctx*, int*, int, size_t);
+template void fill<unsigned>(Ctx*, unsigned*, unsigned, size_t);
 template void fill<int8_t>(Ctx*, int8_t*, int8_t, size_t);
 template void fill<uint8_t>(Ctx*, uint8_t*, uint8_t, size_t);
 template void fill<double>(Ctx*, double*, double, size_t);

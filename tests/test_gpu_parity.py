@@ -953,3 +953,48 @@ def test_context_memory_comes_from_torch_allocator(ctx):
     Mh.close()
     hsys.close()
     hctx.close()
+
+
+# ---------------------------------------------------------------------------
+# persistent tail of the batched V-cycle
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("blocks", ["3", "256"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_persistent_tail_matches_level_launches(ctx, monkeypatch, precision, blocks):
+    """The levels below MGD_TAIL_ROWS run as one persistent launch whose
+    phases are separated by a grid-wide barrier.  It computes what the
+    per-level launches compute, bit for bit: V-cycles of a monolithic
+    hierarchy, and a batched, graph-replayed Schur2 apply and FGMRES solve
+    (three workgroups make every phase loop over its rows several times)."""
+    import torch
+    api = gpu_modules()
+    A = oracle_system(si.generate_workload("g1_2d64")).monolithic()
+    inp = si.generate(3, 2, 24, 41)
+    co, gsys = gpu_system(ctx, inp)
+    b = np.random.default_rng(2).uniform(size=A.shape[0])
+    r = to_dev(ctx, np.random.default_rng(4).standard_normal(gsys.n))
+    out = {}
+    for mode in ("levels", "tail"):
+        monkeypatch.setenv("MGD_TAIL_ROWS", "0" if mode == "levels" else "65536")
+        monkeypatch.setenv("MGD_TAIL_BLOCKS", blocks)
+        g = api.AMG(ctx, A.indptr, A.indices, A.data, seed=1, precision=precision)
+        M = api.BlockPreconditioner(ctx, gsys, "schur2", amg_seed=5, batched=1, use_graph=1,
+                                    amg_precision=precision)
+        ctx.reset_kernel_stats()
+        ctx.set_profiling(True)
+        v1 = to_host(g.apply(to_dev(ctx, b)))
+        ctx.set_profiling(False)
+        tails = [k for k in ctx.kernel_symbol_stats() if k.startswith("k_tail")]
+        assert bool(tails) == (mode == "tail"), tails
+        v3 = to_host(g.apply(to_dev(ctx, b), cycles=3))
+        z = [to_host(M.apply(r)) for _ in range(2)]      # graph replays
+        torch.cuda.synchronize()
+        x, res = api.gmres(ctx, gsys, M, to_dev(ctx, inp.b), rtol=1e-9, flexible=1)
+        out[mode] = (v1, v3, z, to_host(x), res.iters)
+        g.close()
+        M.close()
+    (a1, a3, az, ax, ai), (b1, b3, bz, bx, bi) = out["levels"], out["tail"]
+    assert np.array_equal(a1, b1) and np.array_equal(a3, b3)
+    assert np.array_equal(az[0], bz[0]) and np.array_equal(az[1], bz[1])
+    assert np.array_equal(az[0], az[1])
+    assert ai == bi and np.array_equal(ax, bx)
