@@ -1123,7 +1123,7 @@ template <typename T>
 struct MatArgs {
   const LMat<T>* m;
 };
-static inline dim3 rows_grid(int rows, int tpr) { return dim3(cdiv((long long)rows * tpr, 256)); }
+static inline dim3 rows_grid(int rows, int tpr, int bs) { return dim3(cdiv((long long)rows * tpr, bs)); }
 
 // Calls F.template go<FMT, TPR>() for the matrix's layout.
 template <typename F>
@@ -1182,7 +1182,7 @@ struct HalfL {
   template <int FMT, int TPR>
   void go() const {
     if (r1 <= r0) return;
-    hipLaunchKernelGGL((k_half<T, FMT, TPR>), rows_grid(r1 - r0, TPR), dim3(256), 0, c->stream,
+    hipLaunchKernelGGL((k_half<T, FMT, TPR>), rows_grid(r1 - r0, TPR, A.bs), dim3(A.bs), 0, c->stream,
                        r0, r1, A.rp.get(), A.ci.get(), A.v.get(), dinv, B, X, Xold, Xout);
     MGD_CHECK_LAUNCH();
   }
@@ -1197,7 +1197,7 @@ struct FHalf0L {
   template <int FMT, int TPR>
   void go() const {
     if (r1 <= r0) return;
-    hipLaunchKernelGGL((k_fhalf0<T, FMT, TPR>), rows_grid(r1 - r0, TPR), dim3(256), 0, c->stream,
+    hipLaunchKernelGGL((k_fhalf0<T, FMT, TPR>), rows_grid(r1 - r0, TPR, A.bs), dim3(A.bs), 0, c->stream,
                        r0, r1, nC, A.rp.get(), A.ci.get(), A.v.get(), dinv, B, XC, Xout);
     MGD_CHECK_LAUNCH();
   }
@@ -1215,7 +1215,7 @@ struct HalfOutL {
   template <int FMT, int TPR>
   void go() const {
     if (nX <= 0) return;
-    hipLaunchKernelGGL((k_half_out<T, FMT, TPR>), rows_grid(nX, TPR), dim3(256), 0, c->stream, 0,
+    hipLaunchKernelGGL((k_half_out<T, FMT, TPR>), rows_grid(nX, TPR, A.bs), dim3(A.bs), 0, c->stream, 0,
                        nX, nC, nS, A.rp.get(), A.ci.get(), A.v.get(), dinv, B, X, XD, perm, z);
     MGD_CHECK_LAUNCH();
   }
@@ -1230,7 +1230,7 @@ struct GsL {
   template <int FMT, int TPR>
   void go() const {
     if (n1 + n2 <= 0) return;
-    hipLaunchKernelGGL((k_gs<T, FMT, TPR>), rows_grid(n1 + n2, TPR), dim3(256), 0, c->stream, r0,
+    hipLaunchKernelGGL((k_gs<T, FMT, TPR>), rows_grid(n1 + n2, TPR, A.bs), dim3(A.bs), 0, c->stream, r0,
                        n1, r2, n2, A.rp.get(), A.ci.get(), A.v.get(), dg, B, X);
     MGD_CHECK_LAUNCH();
   }
@@ -1246,7 +1246,7 @@ struct ResidL {
   template <int FMT, int TPR>
   void go() const {
     if (nS <= 0) return;
-    hipLaunchKernelGGL((k_resid<T, FMT, TPR>), rows_grid(nS, TPR), dim3(256), 0, c->stream, 0, nS,
+    hipLaunchKernelGGL((k_resid<T, FMT, TPR>), rows_grid(nS, TPR, A.bs), dim3(A.bs), 0, c->stream, 0, nS,
                        A.rp.get(), A.ci.get(), A.v.get(), B, X, R);
     MGD_CHECK_LAUNCH();
   }
@@ -1264,11 +1264,11 @@ struct EntryResidL {
   void go() const {
     if (nX <= 0) return;
     if (pre)
-      hipLaunchKernelGGL((k_entry_resid<T, FMT, TPR, true>), rows_grid(nX, TPR), dim3(256), 0,
+      hipLaunchKernelGGL((k_entry_resid<T, FMT, TPR, true>), rows_grid(nX, TPR, A.bs), dim3(A.bs), 0,
                          c->stream, 0, nX, nS, nC, A.rp.get(), A.ci.get(), A.v.get(), perm, dinv,
                          b, z, B, XC);
     else
-      hipLaunchKernelGGL((k_entry_resid<T, FMT, TPR, false>), rows_grid(nX, TPR), dim3(256), 0,
+      hipLaunchKernelGGL((k_entry_resid<T, FMT, TPR, false>), rows_grid(nX, TPR, A.bs), dim3(A.bs), 0,
                          c->stream, 0, nX, nS, nC, A.rp.get(), A.ci.get(), A.v.get(), perm, dinv,
                          b, z, B, XC);
     MGD_CHECK_LAUNCH();
@@ -1287,11 +1287,11 @@ struct RestrictL {
   void go() const {
     if (nXn <= 0) return;
     if (pre)
-      hipLaunchKernelGGL((k_restrict<T, FMT, TPR, true>), rows_grid(nXn, TPR), dim3(256), 0,
+      hipLaunchKernelGGL((k_restrict<T, FMT, TPR, true>), rows_grid(nXn, TPR, Wt.bs), dim3(Wt.bs), 0,
                          c->stream, 0, nXn, nC, nCn, Wt.rp.get(), Wt.ci.get(), Wt.v.get(), cpos, R,
                          dinv_n, Bn, XCn);
     else
-      hipLaunchKernelGGL((k_restrict<T, FMT, TPR, false>), rows_grid(nXn, TPR), dim3(256), 0,
+      hipLaunchKernelGGL((k_restrict<T, FMT, TPR, false>), rows_grid(nXn, TPR, Wt.bs), dim3(Wt.bs), 0,
                          c->stream, 0, nXn, nC, nCn, Wt.rp.get(), Wt.ci.get(), Wt.v.get(), cpos, R,
                          dinv_n, Bn, XCn);
     MGD_CHECK_LAUNCH();
@@ -1308,7 +1308,7 @@ struct ProlongL {
   template <int FMT, int TPR>
   void go() const {
     if (nS <= 0) return;
-    hipLaunchKernelGGL((k_prolong<T, FMT, TPR>), rows_grid(nS, TPR), dim3(256), 0, c->stream, 0,
+    hipLaunchKernelGGL((k_prolong<T, FMT, TPR>), rows_grid(nS, TPR, W.bs), dim3(W.bs), 0, c->stream, 0,
                        nS, nC, W.rp.get(), W.ci.get(), W.v.get(), cmap, E, XC, XF);
     MGD_CHECK_LAUNCH();
   }
@@ -2216,10 +2216,15 @@ static void finalize_levels(Ctx* c, std::vector<BuildLevel<T>>& bl, Union<T>& U,
 }
 
 // Layout of a level matrix: the tuned choice cached per (rows, nnz, longest
-// row) key (1000 = SELL, t = CSR with t lanes per row); without a cached
-// choice and with autotuning off, SELL when padding stays within 30%, else
-// CSR with a lane count from the mean row length.
+// row) key as code + (threads per workgroup / 64) * kTuneBsUnit, code 1000 =
+// SELL, t = CSR with t lanes per row (a value below kTuneBsUnit keeps 256
+// threads); without a cached choice and with autotuning off, SELL when
+// padding stays within 30%, else CSR with a lane count from the mean row
+// length, on 256-thread workgroups.  Autotuning times the residual kernel for
+// every layout with 64, 128 and 256 threads per workgroup (rows per workgroup
+// = threads / lanes per row; 64-row slices for SELL) and keeps the fastest.
 constexpr int kTuneSell = 1000;
+constexpr int kTuneBsUnit = 100000;
 template <typename T>
 static void tune_layout(Ctx* c, ULevel<T>& lv, const Csr<double>& A, int autotune, bool fp32) {
   if (lv.nS == 0) {
@@ -2234,11 +2239,13 @@ static void tune_layout(Ctx* c, ULevel<T>& lv, const Csr<double>& A, int autotun
   const int maxrow = read1(c, mr.get());
   const double avg = (double)A.nnz / lv.nS;
   const long long st = sell_stored(c, A);
-  auto apply = [&](int code) {
+  auto apply = [&](int value) {
+    const int code = value % kTuneBsUnit, units = value / kTuneBsUnit;
     if (code == kTuneSell)
       to_layout<T>(c, A, kFmtSELL, 1, true, lv.A, sell16_enabled() ? lv.nC : -1);
     else
       to_layout<T>(c, A, kFmtCSR, code, true, lv.A);
+    lv.A.bs = units ? 64 * units : 256;
   };
   const int cached = autotune_lookup(lv.nS, A.nnz, maxrow, fp32);
   if (cached > 0) {
@@ -2255,9 +2262,12 @@ static void tune_layout(Ctx* c, ULevel<T>& lv, const Csr<double>& A, int autotun
     return;
   }
   std::vector<int> cands;
-  if (st <= 2 * A.nnz) cands.push_back(kTuneSell);
+  std::vector<int> layouts;
+  if (st <= 2 * A.nnz) layouts.push_back(kTuneSell);
   for (int t : {1, 2, 4, 8, 16, 32})
-    if (t == 1 || t <= 2 * std::max(avg, 1.0)) cands.push_back(t);
+    if (t == 1 || t <= 2 * std::max(avg, 1.0)) layouts.push_back(t);
+  for (int code : layouts)
+    for (int bs : {64, 128, 256}) cands.push_back(code + (bs / 64) * kTuneBsUnit);
   DBuf<T> x(c, (size_t)std::max(lv.nX, 1)), bb(c, (size_t)lv.nS), r(c, (size_t)lv.nS);
   fill<T>(c, x.get(), (T)1, (size_t)std::max(lv.nX, 1));
   fill<T>(c, bb.get(), (T)1, (size_t)lv.nS);

@@ -37,6 +37,7 @@ struct DenseDev {
 template <typename T>
 struct LMat {
   int rows = 0, fmt = 0, tpr = 1;  // fmt: 0 CSR, 1 SELL, 2 SELL16
+  int bs = 256;                    // threads per workgroup of the kernels reading it
   long long nnz = 0;               // entries (without padding)
   long long stored = 0;            // stored entries (with padding)
   DBuf<int> rp;                    // CSR: rows + 1 row pointers; SELL: slices + 1 offsets;

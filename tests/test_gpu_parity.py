@@ -998,3 +998,58 @@ def test_persistent_tail_matches_level_launches(ctx, monkeypatch, precision, blo
     assert np.array_equal(az[0], bz[0]) and np.array_equal(az[1], bz[1])
     assert np.array_equal(az[0], az[1])
     assert ai == bi and np.array_equal(ax, bx)
+
+
+# ---------------------------------------------------------------------------
+# level-layout autotuning
+# ---------------------------------------------------------------------------
+_AUTOTUNE_CHILD = r"""
+import sys, numpy as np, torch
+sys.path.insert(0, sys.argv[1])
+import synth_inputs as si
+from oracle import assemble as oasm
+from paper_2002_04958_amd import api
+inp = si.generate(2, 2, 22, 77)
+A = oasm.assemble(inp).monolithic()
+ctx = api.Context(0)
+g = api.AMG(ctx, A.indptr, A.indices, A.data, seed=3, precision=int(sys.argv[3]), autotune=0)
+b = np.random.default_rng(5).uniform(size=A.shape[0])
+z = g.apply(torch.as_tensor(b, device=ctx.device), cycles=2).cpu().numpy()
+np.save(sys.argv[2], z)
+"""
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_autotune_layouts_and_cache(ctx, monkeypatch, tmp_path, precision):
+    """autotune = 1 times every level matrix's layouts (SELL, CSR with 1-32
+    lanes per row) with 64, 128 and 256 threads per workgroup and keeps the
+    fastest: the tuned V-cycles agree with the oracle, the choices are written
+    to MGD_AUTOTUNE_CACHE, and a fresh process that reads the file (autotune
+    off) builds the same layouts, so its result equals this one bit for bit."""
+    import json
+    import os
+    import subprocess
+    import sys
+    api = gpu_modules()
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("MGD_AUTOTUNE_CACHE", str(cache))
+    inp = si.generate(2, 2, 22, 77)
+    A = oracle_system(inp).monolithic()
+    H = oamg.setup(A, oamg.AMGParams(seed=3))
+    g = api.AMG(ctx, A.indptr, A.indices, A.data, seed=3, precision=precision, autotune=1)
+    b = np.random.default_rng(5).uniform(size=A.shape[0])
+    z = to_host(g.apply(to_dev(ctx, b), cycles=2))
+    assert_elementwise(z, oamg.apply_cycles(H, b, 2), 1e-12 if precision == 0 else 5e-5,
+                       floor=(FP32_FLOOR if precision else 1e-3), what="autotuned V-cycles")
+    tuned = json.loads(cache.read_text())
+    mine = {k: v for k, v in tuned.items() if k.startswith("f32:" if precision else "f64:")}
+    assert len(mine) >= g.info()["levels"] - 1, tuned
+    for v in mine.values():
+        code, units = v % 100000, v // 100000
+        assert units in (1, 2, 4) and (code == 1000 or code in (1, 2, 4, 8, 16, 32)), v
+    out = tmp_path / "child.npy"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, "-c", _AUTOTUNE_CHILD, root, str(out), str(precision)],
+                       capture_output=True, text=True, timeout=240, env=dict(os.environ))
+    assert p.returncode == 0, p.stderr[-2000:]
+    assert np.array_equal(np.load(out), z)
