@@ -360,6 +360,26 @@ typedef struct gmres_result {
 mgd_status gmres_solve(mgd_ctx* ctx, const mgd_block_system* A, block_precond* M,
                        const double* b, double* x, const gmres_params* p, gmres_result* out);
 
+/* gmres_solve for callers that cannot allocate device memory (work under
+ * HIP graph capture around the call, serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, iteration and result as gmres_solve, with
+ * no device allocation, no pinned host allocation and no graph instantiation.
+ * The Krylov basis V ((m+1) n doubles), the preconditioned vectors Z (m n,
+ * flexible with a preconditioner) or two n-vectors (non-flexible), the
+ * Hessenberg scratch and the reduction partials (about 0.5 MiB) live in a
+ * static device array of 64 MiB per device, held until the process ends;
+ * n = (G+2) N, m = restart.  Sizes that do not fit return MGD_EINVAL before
+ * any launch (with m = 30 and a flexible preconditioned solve, up to about
+ * 137,000 unknowns); profile = 1 returns MGD_EINVAL.  Preconditioner applies
+ * run as direct launches (a use_graph preconditioner is not replayed here)
+ * and the whole solve stays on the context stream.  Every call on one device
+ * shares that device's array and leaves its contents behind: calls that
+ * overlap on one device race, so run them on one stream or one at a time.
+ * M must have been created (its own memory allocated) beforehand. */
+mgd_status gmres_solve_noalloc(mgd_ctx* ctx, const mgd_block_system* A, block_precond* M,
+                               const double* b, double* x, const gmres_params* p,
+                               gmres_result* out);
+
 /* ---------------------------------------------------------------------------
  * Adjoint.  With A x = b and g = dL/dx: solve A^T lambda = g by GMRES with
  * M_T (a preconditioner created with transpose = 1 on A), then

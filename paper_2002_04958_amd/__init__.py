@@ -9,7 +9,8 @@ import importlib
 from ._lib import LibraryMissing, MgdError, load as load_library  # noqa: F401
 
 _API_NAMES = {"Context", "Coeffs", "BlockSystem", "AMG", "BlockPreconditioner", "GmresResult",
-              "gmres", "adjoint", "adjoint_gradients", "csr_spmv", "PC_KINDS", "MGDSolve"}
+              "gmres", "gmres_noalloc", "adjoint", "adjoint_gradients", "csr_spmv", "PC_KINDS",
+              "MGDSolve"}
 
 
 def __getattr__(name):

@@ -105,6 +105,8 @@ SIGNATURES = [
                                               POINTER(c_int64), POINTER(c_double),
                                               POINTER(c_double), POINTER(c_double)]),
     ("mgd_csr_spmv", c_int32, [c_void_p, POINTER(mgd_csr), c_void_p, c_void_p]),
+    ("gmres_solve_noalloc", c_int32, [c_void_p, POINTER(mgd_block_system), c_void_p, c_void_p,
+                                      c_void_p, POINTER(gmres_params), POINTER(gmres_result)]),
     ("amg_params_default", None, [POINTER(amg_params)]),
     ("amg_setup", c_int32, [c_void_p, POINTER(mgd_csr), POINTER(amg_params), POINTER(c_void_p)]),
     ("amg_apply", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int]),

@@ -19,7 +19,7 @@ import torch
 from . import _lib as L
 
 __all__ = ["Context", "Coeffs", "BlockSystem", "AMG", "BlockPreconditioner", "GmresResult",
-           "gmres", "adjoint", "adjoint_gradients", "csr_spmv", "PC_KINDS"]
+           "gmres", "gmres_noalloc", "adjoint", "adjoint_gradients", "csr_spmv", "PC_KINDS"]
 
 PC_KINDS = L.PC_KINDS
 
@@ -503,6 +503,20 @@ def gmres(ctx: Context, system: BlockSystem, M: Optional[BlockPreconditioner], b
     r = L.gmres_result()
     st = ctx.lib.gmres_solve(ctx.h, byref(system.s), M.h if M is not None else None, _p(b), _p(x),
                              byref(p), byref(r))
+    L.check(st, allow=(-4,))
+    return x, _result(st, r)
+
+
+def gmres_noalloc(ctx: Context, system: BlockSystem, M: Optional[BlockPreconditioner],
+                  b: torch.Tensor, x: Optional[torch.Tensor] = None, **kw):
+    """gmres_solve_noalloc: the same solve with no device allocation (the
+    workspace is the library's static per-device array).  x must be given or
+    is allocated here, outside the call.  Returns (x, GmresResult)."""
+    x = torch.zeros_like(b) if x is None else x
+    p = gmres_params(**kw)
+    r = L.gmres_result()
+    st = ctx.lib.gmres_solve_noalloc(ctx.h, byref(system.s), M.h if M is not None else None,
+                                     _p(b), _p(x), byref(p), byref(r))
     L.check(st, allow=(-4,))
     return x, _result(st, r)
 

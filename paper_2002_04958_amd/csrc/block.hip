@@ -1006,7 +1006,7 @@ void block_precond_apply_impl(block_precond* bp, const double* r, double* z) {
 
 void block_precond_apply_dispatch(block_precond* bp, const double* r, double* z) {
   Ctx* c = bp->ctx;
-  if (!bp->prm.use_graph || c->profiling || bp->prm.inner_tol > 0) {
+  if (!bp->prm.use_graph || c->profiling || c->no_alloc || bp->prm.inner_tol > 0) {
     block_precond_apply_impl(bp, r, z);
     return;
   }
@@ -1071,7 +1071,7 @@ void block_precond_apply_matvec(block_precond* bp, const double* r, double* z,
   Ctx* c = bp->ctx;
   // MGD_STEP_OVERLAP=0 keeps the one-kernel matvec after the apply (for comparisons)
   const char* ov = std::getenv("MGD_STEP_OVERLAP");
-  const bool split = S.shared && bp->prm.kind == MGD_PC_SCHUR2 &&
+  const bool split = S.shared && !c->no_alloc && bp->prm.kind == MGD_PC_SCHUR2 &&
                      S.G == bp->G && S.N == bp->N && !(ov && ov[0] == '0');
   if (split && !bp->ovl_stream) {
     MGD_HIP(hipStreamCreateWithFlags(&bp->ovl_stream, hipStreamNonBlocking));
@@ -1099,6 +1099,7 @@ void block_precond_apply_matvec(block_precond* bp, const double* r, double* z,
 // graph replay asked for, no host decisions inside the apply, no profiling.
 bool block_precond_step_graphable(const block_precond* bp) {
   return bp->prm.use_graph && bp->prm.inner_tol <= 0 && !bp->ctx->profiling &&
+         !bp->ctx->no_alloc &&
          bp->prm.kind != MGD_PC_IDENTITY;
 }
 

@@ -64,6 +64,9 @@ const char* kernel_class_name(int c) {
 
 void* Ctx::dmalloc(size_t bytes) {
   void* p = nullptr;
+  if (no_alloc)
+    fail(MGD_EINVAL, "a device allocation of " + std::to_string(bytes) +
+                         " bytes was requested inside a no-allocation call");
   if (has_alloc) {
     p = alloc.alloc(bytes, (void*)stream, alloc.user);
     if (!p) fail(MGD_ENOMEM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes");
@@ -84,6 +87,12 @@ void Ctx::dfree(void* p) {
     (void)hipFree(p);
 }
 void* Ctx::host_stage(size_t bytes) {
+  if (no_alloc && bytes > pinned_bytes) {
+    // pageable static staging: no pinned allocation inside a no-allocation call
+    alignas(256) static thread_local double stage[1024];
+    MGD_REQUIRE(bytes <= sizeof(stage), "readback too large for a no-allocation call");
+    return stage;
+  }
   if (bytes > pinned_bytes) {
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
@@ -752,6 +761,30 @@ mgd_status gmres_solve(mgd_ctx* ctx, const mgd_block_system* A, block_precond* M
     ctx->make_current();
     const mgd_status st = gmres_impl(ctx, make_block_sys_dev(A), M, b, x, *p, *out);
     ctx->check_device_errors("gmres_solve (V-cycle tail barrier)");
+    return st;
+  });
+}
+
+mgd_status gmres_solve_noalloc(mgd_ctx* ctx, const mgd_block_system* A, block_precond* M,
+                               const double* b, double* x, const gmres_params* p,
+                               gmres_result* out) {
+  return guard([&] {
+    StepScope step_("gmres_solve_noalloc");
+    MGD_REQUIRE(ctx && p && out, "ctx, params or result is NULL");
+    check_block_system(A);
+    MGD_REQUIRE(b && x && (const void*)b != (const void*)x, "b, x must be distinct and non-NULL");
+    MGD_REQUIRE(!M || M->ctx == ctx, "preconditioner belongs to another context");
+    MGD_REQUIRE(!M || (M->G == A->G && M->N == A->N), "preconditioner built for another shape");
+    MGD_REQUIRE(p->rtol >= 0, "rtol must be >= 0");
+    MGD_REQUIRE(!p->profile, "per-phase profiling is not available in a no-allocation call");
+    ctx->make_current();
+    struct NoAlloc {  // restores the context's mode on every exit
+      Ctx* c;
+      explicit NoAlloc(Ctx* c_) : c(c_) { c->no_alloc = true; }
+      ~NoAlloc() { c->no_alloc = false; }
+    } na(ctx);
+    const mgd_status st = gmres_impl(ctx, make_block_sys_dev(A), M, b, x, *p, *out);
+    ctx->check_device_errors("gmres_solve_noalloc (V-cycle tail barrier)");
     return st;
   });
 }

@@ -91,6 +91,10 @@ struct Ctx {
   std::shared_ptr<void> gmres_ws;
   // profiling
   bool profiling = false;
+  // set for the duration of a no-allocation call: any device allocation is an
+  // error, small readbacks stage through static host memory, and the solve
+  // runs as direct launches (no graph instantiation, no second stream)
+  bool no_alloc = false;
   struct Pending {
     int cls;
     hipEvent_t a, b;

@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <functional>
+#include <mutex>
 #include <vector>
 
 #include "handles.hpp"
@@ -42,6 +43,12 @@ void block_precond_apply_matvec(block_precond* bp, const double* r, double* z,
 bool block_precond_step_graphable(const block_precond* bp);
 void block_precond_step_launch(block_precond* bp, const std::vector<uintptr_t>& key,
                                const std::function<void()>& body);
+
+// Workspace of gmres_solve_noalloc: a static device array, one copy per
+// device, shared by every such call on that device (the contents of the last
+// call stay; the solve writes every buffer before it reads it).
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace {
 // The basis, the preconditioned vectors and the scratch of one context,
@@ -80,6 +87,80 @@ GmresWork& gmres_work(Ctx* c, size_t n, int m, bool need_z, bool need_t) {
   }
   return *w;
 }
+
+// ---------------------------------------------------------------------------
+// workspace of the no-allocation entry point (the array `scratch` below)
+// ---------------------------------------------------------------------------
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's array (the host symbol is only a
+// stand-in): looked up once per device, with that device current.
+void* scratch_address(Ctx* c) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  MGD_REQUIRE(c->device >= 0 && c->device < kMaxDevices, "device ordinal out of range");
+  if (!g_scratch_ptr[c->device]) {
+    void* p = nullptr;
+    MGD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    MGD_REQUIRE(p != nullptr, "no device address for the scratch array");
+    g_scratch_ptr[c->device] = p;
+  }
+  return g_scratch_ptr[c->device];
+}
+
+// Buffers of one solve laid out in the array, 256-byte aligned, in doubles.
+struct ScratchLayout {
+  size_t V = 0, Z = 0, t1 = 0, t2 = 0, hd = 0, dd = 0, dcoef = 0, part = 0, total = 0;
+};
+ScratchLayout scratch_layout(size_t n, int m, bool need_z, bool need_t) {
+  ScratchLayout L;
+  size_t at = 0;
+  auto take = [&](size_t count) {
+    const size_t o = at;
+    at += (count + 31) / 32 * 32;  // 256 bytes
+    return o;
+  };
+  L.V = take((size_t)(m + 1) * n);
+  if (need_z) L.Z = take((size_t)m * n);
+  if (need_t) {
+    L.t1 = take(n);
+    L.t2 = take(n);
+  }
+  L.hd = take(200);
+  L.dd = take(80);
+  L.dcoef = take(kDcgsCoef);
+  L.part = take((size_t)kRedBlocks * 66);
+  L.total = at * sizeof(double);
+  return L;
+}
+
+// non-owning views of the array (a view has no context, so nothing frees it)
+template <typename T>
+void view(DBuf<T>& b, double* base, size_t off, size_t count) {
+  b.ctx = nullptr;
+  b.p = reinterpret_cast<T*>(base + off);
+  b.n = count;
+}
+void scratch_work(Ctx* c, GmresWork& w, size_t n, int m, bool need_z, bool need_t) {
+  const ScratchLayout L = scratch_layout(n, m, need_z, need_t);
+  MGD_REQUIRE(L.total <= kNoAllocBytes, "the no-allocation workspace holds " +
+                                            std::to_string(kNoAllocBytes) + " bytes; this solve needs " +
+                                            std::to_string(L.total));
+  double* base = static_cast<double*>(scratch_address(c));
+  w.n = n;
+  w.m = m;
+  view(w.V, base, L.V, (size_t)(m + 1) * n);
+  if (need_z) view(w.Z, base, L.Z, (size_t)m * n);
+  if (need_t) {
+    view(w.t1, base, L.t1, n);
+    view(w.t2, base, L.t2, n);
+  }
+  view(w.hd, base, L.hd, 200);
+  view(w.dd, base, L.dd, 80);
+  view(w.dcoef, base, L.dcoef, kDcgsCoef);
+  view(w.rw.partial, base, L.part, (size_t)kRedBlocks * 66);
+}
 }  // namespace
 
 mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const double* b, double* x,
@@ -91,7 +172,9 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
   MGD_REQUIRE(p.max_iters >= 0, "max_iters must be >= 0");
   auto t_start = std::chrono::steady_clock::now();
   const bool flex = p.flexible != 0;
-  GmresWork& ws = gmres_work(c, n, m, flex && M, !flex && M);
+  GmresWork local;  // views of the static array in a no-allocation call
+  if (c->no_alloc) scratch_work(c, local, n, m, flex && M, !flex && M);
+  GmresWork& ws = c->no_alloc ? local : gmres_work(c, n, m, flex && M, !flex && M);
   DBuf<double>& V = ws.V;
   DBuf<double>& Z = ws.Z;
   DBuf<double>& t1 = ws.t1;
