@@ -318,6 +318,9 @@ mgd_status mgd_ctx_create(int device, void* hip_stream, const mgd_allocator* all
       c->has_alloc = true;
     }
     c->make_current();
+    // MGD_XCD_ROWS=1: level kernels take contiguous row shares per chiplet
+    const char* xr = std::getenv("MGD_XCD_ROWS");
+    set_xcd_rows(xr && xr[0] == '1' ? 1 : 0);
     *out = c.release();
     return MGD_OK;
   });

@@ -292,12 +292,15 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
       } else if (M) {
         double* zt = flex ? Z.get() + (size_t)j * n : t1.get();
         if (evp) MGD_HIP(hipEventRecord(evp->a, c->stream));
-        block_precond_apply_dispatch(M, vj, zt);
+        if (delayed && !p.profile)  // the launches a graph-replayed step runs
+          block_precond_apply_matvec(M, vj, zt, S, w);
+        else
+          block_precond_apply_dispatch(M, vj, zt);
         if (evp) MGD_HIP(hipEventRecord(evp->b, c->stream));
         res.precond_applies++;
         zj = zt;
       }
-      if (!(delayed && step_graph)) {
+      if (!(delayed && (step_graph || !p.profile))) {
         if (evm) MGD_HIP(hipEventRecord(evm->a, c->stream));
         block_matvec(c, S, zj, nullptr, w);
         if (evm) MGD_HIP(hipEventRecord(evm->b, c->stream));

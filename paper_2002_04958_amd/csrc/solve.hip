@@ -767,10 +767,25 @@ __device__ __forceinline__ T mrow_c(const int* __restrict__ rp, const int* __res
   return s;
 }
 
-#define MGD_ROWS_TPR                                             \
-  const long t_ = blockIdx.x * (long)blockDim.x + threadIdx.x;   \
-  const int lane = (int)(t_ % TPR);                              \
-  const int k = r0 + (int)(t_ / TPR);                            \
+// Row ranges per workgroup.  Workgroups are dispatched to the device's
+// chiplets (XCDs, each with its own L2) in turn; with c_xcd_rows set,
+// workgroup b takes the rows of workgroup xcd_block(b), so that each chiplet
+// works on one contiguous share of the rows and finds the iterate values its
+// rows gather (mostly near its own rows) in its own L2.
+__constant__ int c_xcd_rows = 0;
+constexpr int kXcds = 8;
+__device__ __forceinline__ long xcd_block(long b, long nb) {
+  const long q = nb / kXcds, r = nb % kXcds, x = b % kXcds;
+  return x * q + (x < r ? x : r) + b / kXcds;
+}
+void set_xcd_rows(int on) {
+  MGD_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_xcd_rows), &on, sizeof(int)));
+}
+#define MGD_ROWS_TPR                                                              \
+  const long b_ = c_xcd_rows ? xcd_block(blockIdx.x, gridDim.x) : (long)blockIdx.x; \
+  const long t_ = b_ * blockDim.x + threadIdx.x;                                  \
+  const int lane = (int)(t_ % TPR);                                               \
+  const int k = r0 + (int)(t_ / TPR);                                             \
   if (k >= r1) return;
 
 // level-0 entry: B[k] = b[perm[k]]; C values of the first sweep X_C = B_C / d_C

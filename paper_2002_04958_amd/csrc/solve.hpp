@@ -149,6 +149,9 @@ std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHiera
 // Tuned row-group widths, keyed by (rows, nnz, max row length); persisted to
 // the JSON file named by MGD_AUTOTUNE_CACHE when set.
 int autotune_lookup(long long rows, long long nnz, int maxrow, bool fp32);
+// Level kernels' row ranges per workgroup: contiguous shares per chiplet (1)
+// or in dispatch order (0) for every device kernel launched afterwards.
+void set_xcd_rows(int on);
 void autotune_store(long long rows, long long nnz, int maxrow, bool fp32, int tpr);
 
 }  // namespace mgd
