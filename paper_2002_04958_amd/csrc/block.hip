@@ -397,6 +397,8 @@ block_precond::~block_precond() {
   if (ovl_stream) hipStreamDestroy(ovl_stream);
   if (ovl_fork) hipEventDestroy(ovl_fork);
   if (ovl_join) hipEventDestroy(ovl_join);
+  if (fs_fork) hipEventDestroy(fs_fork);
+  if (fs_join) hipEventDestroy(fs_join);
 }
 
 static void make_hierarchy(block_precond* bp, int role, Csr<double>&& M) {
@@ -872,9 +874,12 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
         ninv = G + 2 + extra_inv;
         break;
       }
-      // step 1: w_E* = A_E^{-1} r_E
-      const T* inE = as_input<T>(c, r + (size_t)G * N, X.a_in, N);
-      inv(G, inE, X.a_out.get());
+      // step 1: w_E* = A_E^{-1} r_E (or already in X.a_out: first_stage 2)
+      if (bp->first_stage != 2) {
+        const T* inE = as_input<T>(c, r + (size_t)G * N, X.a_in, N);
+        inv(G, inE, X.a_out.get());
+        if (bp->first_stage == 1) return;
+      }
       // step 2: groups and I against r - D_.E w_E*
       group_in(X.a_out.get());
       run_group(bp, grp);
@@ -1063,36 +1068,80 @@ void block_precond_graph_launch(block_precond* bp, const double* r, double* z) {
   MGD_HIP(hipGraphLaunch(it->second, c->stream));
 }
 
+bool block_precond_has_first_stage(const block_precond* bp);
+
 // z = M^{-1} r, then y = A z for the system S.  With Schur2 and the shared
 // block pattern, the part of A z that does not read z_E runs on a second
 // stream beside the last E solve (launches only: usable under capture).
+// first_done: w_E* for r was computed by block_precond_first_stage(bp, r).
 void block_precond_apply_matvec(block_precond* bp, const double* r, double* z,
-                                const BlockSysDev& S, double* y) {
+                                const BlockSysDev& S, double* y, bool first_done) {
   Ctx* c = bp->ctx;
+  MGD_REQUIRE(!first_done || block_precond_has_first_stage(bp),
+              "apply: no first stage to skip for this preconditioner");
   // MGD_STEP_OVERLAP=0 keeps the one-kernel matvec after the apply (for comparisons)
   const char* ov = std::getenv("MGD_STEP_OVERLAP");
   const bool split = S.shared && !c->no_alloc && bp->prm.kind == MGD_PC_SCHUR2 &&
                      S.G == bp->G && S.N == bp->N && !(ov && ov[0] == '0');
-  if (split && !bp->ovl_stream) {
-    MGD_HIP(hipStreamCreateWithFlags(&bp->ovl_stream, hipStreamNonBlocking));
-    MGD_HIP(hipEventCreateWithFlags(&bp->ovl_fork, hipEventDisableTiming));
-    MGD_HIP(hipEventCreateWithFlags(&bp->ovl_join, hipEventDisableTiming));
+  if (split) {
+    if (!bp->ovl_stream) MGD_HIP(hipStreamCreateWithFlags(&bp->ovl_stream, hipStreamNonBlocking));
+    if (!bp->ovl_fork) MGD_HIP(hipEventCreateWithFlags(&bp->ovl_fork, hipEventDisableTiming));
+    if (!bp->ovl_join) MGD_HIP(hipEventCreateWithFlags(&bp->ovl_join, hipEventDisableTiming));
   }
   bp->ovl_S = split ? &S : nullptr;
   bp->ovl_y = y;
   bp->ovl_forked = false;
+  bp->first_stage = first_done ? 2 : 0;
   try {
     block_precond_apply_impl(bp, r, z);
   } catch (...) {
     bp->ovl_S = nullptr;
+    bp->first_stage = 0;
     throw;
   }
   bp->ovl_S = nullptr;
+  bp->first_stage = 0;
   if (bp->ovl_forked)
     block_matvec_finish(c, S, z, y);
   else
     block_matvec(c, S, z, nullptr, y);
   bp->ovl_forked = false;
+}
+
+// Whether the apply starts with w_E* = A_E^{-1} r_E, a solve that reads r_E
+// only (Schur2, its lower form and PCTL, unless every block's coupling to E
+// was neglected; inner solves excluded, they decide on the host).
+bool block_precond_has_first_stage(const block_precond* bp) {
+  const int k = bp->prm.kind;
+  if (k != MGD_PC_SCHUR2 && k != MGD_PC_SCHUR2_LOWER && k != MGD_PC_PCTL) return false;
+  if (bp->prm.adaptive && k == MGD_PC_SCHUR2 && bp->from_E_weak) return false;
+  return bp->prm.inner_tol <= 0;
+}
+
+// w_E* = A_E^{-1} r_E for the apply to r that follows with first_done
+// (launches only; the buffer it fills is the apply's own, so nothing else
+// may apply this preconditioner in between).
+void block_precond_first_stage(block_precond* bp, const double* r) {
+  MGD_REQUIRE(block_precond_has_first_stage(bp), "apply: no first stage for this preconditioner");
+  bp->first_stage = 1;
+  try {
+    block_precond_apply_impl(bp, r, nullptr);
+  } catch (...) {
+    bp->first_stage = 0;
+    throw;
+  }
+  bp->first_stage = 0;
+}
+
+// Stream and events that order the rest of a Gram-Schmidt update beside the
+// first stage of the next apply (created on first use, outside any capture).
+void block_precond_side(block_precond* bp, hipStream_t* s, hipEvent_t* fork, hipEvent_t* join) {
+  if (!bp->ovl_stream) MGD_HIP(hipStreamCreateWithFlags(&bp->ovl_stream, hipStreamNonBlocking));
+  if (!bp->fs_fork) MGD_HIP(hipEventCreateWithFlags(&bp->fs_fork, hipEventDisableTiming));
+  if (!bp->fs_join) MGD_HIP(hipEventCreateWithFlags(&bp->fs_join, hipEventDisableTiming));
+  *s = bp->ovl_stream;
+  *fork = bp->fs_fork;
+  *join = bp->fs_join;
 }
 
 // Whether a whole GMRES step with this preconditioner may run as one graph:

@@ -144,6 +144,12 @@ struct block_precond {
   const mgd::BlockSysDev* ovl_S = nullptr;  // set for one apply: split matvec of z into ovl_y
   double* ovl_y = nullptr;
   bool ovl_forked = false;
+  // GMRES steps whose apply starts with w_E* = A_E^{-1} r_E: that solve for
+  // the next basis vector runs at the end of a step, beside the rest of its
+  // Gram-Schmidt update (fs_fork/fs_join order the update on ovl_stream).
+  // first_stage: 0 whole apply, 1 only that solve, 2 the apply without it
+  hipEvent_t fs_fork = nullptr, fs_join = nullptr;
+  int first_stage = 0;
   hipStream_t aux = nullptr;  // graph stream when the context stream is the null stream
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   int inverses_last = 0, matvecs_last = 0;

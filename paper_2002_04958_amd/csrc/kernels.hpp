@@ -1,5 +1,7 @@
 // Launchers shared between translation units.  All enqueue on ctx->stream.
 #pragma once
+#include <functional>
+
 #include "common.hpp"
 
 namespace mgd {
@@ -54,8 +56,19 @@ void orth_finish_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int J, con
 //   of the corrected vj (after division by beta) and of w before its division
 //   by alpha.  vj <- (vj - sum a_k V_k) / beta in place; w <- (w - ...) / alpha.
 constexpr int kDcgsCoef = 68;
+// With `split`, the update sweep runs first over entries [lo, hi), then over
+// the rest on the `side` stream while `beside` enqueues other work on
+// ctx->stream; both are joined before [66] and [67] are summed.  The vectors
+// are the same as without it; [66] and [67] are summed in another order.
+struct DcgsSplit {
+  size_t lo = 0, hi = 0;
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  std::function<void()> beside;
+};
 void dcgs_step_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int F, double* vj,
-                   double* wv, size_t n, double* dots, double* coef);
+                   double* wv, size_t n, double* dots, double* coef,
+                   const DcgsSplit* split = nullptr);
 // v *= a
 void scale_dev(Ctx* c, double a, double* v, size_t n);
 // x += sum_i y_i Z_i (y on device)

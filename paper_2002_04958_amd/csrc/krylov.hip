@@ -39,7 +39,10 @@ struct EvPair {
 
 void block_precond_apply_impl(block_precond* bp, const double* r, double* z);
 void block_precond_apply_matvec(block_precond* bp, const double* r, double* z,
-                                const BlockSysDev& S, double* y);
+                                const BlockSysDev& S, double* y, bool first_done = false);
+bool block_precond_has_first_stage(const block_precond* bp);
+void block_precond_first_stage(block_precond* bp, const double* r);
+void block_precond_side(block_precond* bp, hipStream_t* s, hipEvent_t* fork, hipEvent_t* join);
 bool block_precond_step_graphable(const block_precond* bp);
 void block_precond_step_launch(block_precond* bp, const std::vector<uintptr_t>& key,
                                const std::function<void()>& body);
@@ -230,6 +233,16 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
   // With graph replay a step runs as one graph (no per-step events then)
   const bool step_graph = delayed && !p.profile && block_precond_step_graphable(M);
   std::vector<uintptr_t> sys_key;
+  // Where the apply starts with w_E* = A_E^{-1} r_E, each step graph ends by
+  // computing it for the next basis vector beside the rest of its update
+  // sweep (the E segment of the sweep first), and the next step skips it.
+  const bool early_E = step_graph && block_precond_has_first_stage(M);
+  DcgsSplit split;
+  if (early_E) {
+    block_precond_side(M, &split.side, &split.fork, &split.join);
+    split.lo = (size_t)S.G * S.N;
+    split.hi = split.lo + S.N;
+  }
   if (step_graph) {
     rw.ensure(c);  // nothing may be allocated inside a capture
     sys_key = {(uintptr_t)S.G, (uintptr_t)S.N, (uintptr_t)S.tpr, (uintptr_t)S.shared,
@@ -248,14 +261,20 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
     double* zt = Z.get() + (size_t)jj * n;
     const bool prov = jj >= 1;
     const int F = prov ? jj : 1;
+    // step jj-1 of this cycle computed w_E* for v_jj; step m-1 skips it for v_m
+    const bool done = early_E && jj >= 1;
+    const bool next = early_E && jj + 1 < m;
     std::vector<uintptr_t> key = sys_key;
     for (uintptr_t v : {(uintptr_t)vjj, (uintptr_t)zt, (uintptr_t)wj, (uintptr_t)V.get(),
                         (uintptr_t)n, (uintptr_t)F, (uintptr_t)dd.get(), (uintptr_t)dcoef.get(),
-                        (uintptr_t)rw.partial.get()})
+                        (uintptr_t)rw.partial.get(), (uintptr_t)done, (uintptr_t)next})
       key.push_back(v);
     block_precond_step_launch(M, key, [&] {
-      block_precond_apply_matvec(M, vjj, zt, S, wj);
-      dcgs_step_dev(c, rw, V.get(), n, F, prov ? vjj : nullptr, wj, n, dd.get(), dcoef.get());
+      block_precond_apply_matvec(M, vjj, zt, S, wj, done);
+      if (next) split.beside = [&] { block_precond_first_stage(M, wj); };
+      dcgs_step_dev(c, rw, V.get(), n, F, prov ? vjj : nullptr, wj, n, dd.get(), dcoef.get(),
+                    next ? &split : nullptr);
+      split.beside = nullptr;
     });
     MGD_HIP(hipMemcpyAsync(slot(jj), dcoef.get(), kDcgsCoef * sizeof(double),
                            hipMemcpyDeviceToHost, c->stream));

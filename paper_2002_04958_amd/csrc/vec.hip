@@ -192,6 +192,16 @@ static int red_grid(size_t n) {
   return (int)std::max<size_t>(1, std::min<size_t>(g, kRedBlocks));
 }
 
+// Index of element i's slot in the t-th grid stride counted from the END of the
+// vector: a sweep that follows a forward sweep over the same vectors starts on
+// the data that sweep read last, which the device's last-level cache (256 MB)
+// still holds.
+__device__ __forceinline__ size_t rev_stride_index(size_t t, size_t n) {
+  const size_t stride = (size_t)gridDim.x * 256;
+  const size_t last = (n - 1) / stride;
+  return (last - t) * stride + blockIdx.x * (size_t)256 + threadIdx.x;
+}
+
 // Final stage: out[j] = sum_b partial[j*nb + b] for b ascending over a fixed
 // tree: thread t sums b = t, t+256, ...; then the workgroup tree.
 __global__ void __launch_bounds__(256) k_red_final(const double* __restrict__ partial, int nb,
@@ -251,7 +261,12 @@ __global__ void __launch_bounds__(256) k_mdot(const double* __restrict__ V, size
   }
   acc[JB] = 0.0;
   double nacc = 0.0;
-  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+  // mode 0 sweeps forward, mode 1 (which follows it) backward
+  const size_t nt = n ? (n - 1) / ((size_t)gridDim.x * 256) + 1 : 0;
+  for (size_t t = 0; t < nt; ++t) {
+    const size_t i = MODE == 0 ? t * (size_t)gridDim.x * 256 + blockIdx.x * (size_t)256 + threadIdx.x
+                               : rev_stride_index(t, n);
+    if (i >= n) continue;
     double wi = w[i];
     // all loads of the basis column first, so they are in flight together
     double vj[JB];
@@ -515,13 +530,18 @@ __global__ void k_dcgs_coef(int F, int prov, const double* __restrict__ d,
 }
 
 // Sweep 2: vj <- (vj - sum a_k V_k) / beta; w <- (w - sum h_k V_k - h_F vj_new) / alpha,
-// with per block partial sums of |vj_new|^2 and |w before the division|^2.
+// with per block partial sums of |vj_new|^2 and |w before the division|^2
+// (written at partial[poff + block] and partial[nb + poff + block]).  The
+// sweep covers m entries: the k-th is entry base + k, plus gap from k = lo on
+// (a range with one hole).
 template <int JB, bool PROV>
 __global__ void __launch_bounds__(256) k_dcgs_update(const double* __restrict__ V, size_t ldv,
                                                      int F, const double* __restrict__ coef,
                                                      double* __restrict__ vj,
-                                                     double* __restrict__ w, size_t n,
-                                                     double* __restrict__ partial, int nb) {
+                                                     double* __restrict__ w, size_t m,
+                                                     size_t base, size_t lo, size_t gap,
+                                                     double* __restrict__ partial, int nb,
+                                                     int poff) {
   __shared__ double lds[4];
   double ca[JB], ch[JB];
 #pragma unroll
@@ -532,7 +552,12 @@ __global__ void __launch_bounds__(256) k_dcgs_update(const double* __restrict__ 
   const double hF = PROV ? coef[32 + F] : 0.0;
   const double beta = coef[64], alpha = coef[65];
   double sv = 0.0, sw = 0.0;
-  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+  // backward: the dots sweep before it ran forward over the same vectors
+  const size_t nt = m ? (m - 1) / ((size_t)gridDim.x * 256) + 1 : 0;
+  for (size_t t = 0; t < nt; ++t) {
+    const size_t k = rev_stride_index(t, m);
+    if (k >= m) continue;
+    const size_t i = base + k + (k >= lo ? gap : 0);
     double vk[JB];
 #pragma unroll
     for (int k = 0; k < JB; ++k)
@@ -558,13 +583,13 @@ __global__ void __launch_bounds__(256) k_dcgs_update(const double* __restrict__ 
   const double s1 = PROV ? block_sum256(sv, lds) : 0.0;
   const double s2 = block_sum256(sw, lds);
   if (threadIdx.x == 0) {
-    partial[blockIdx.x] = s1;
-    partial[(size_t)nb + blockIdx.x] = s2;
+    partial[(size_t)poff + blockIdx.x] = s1;
+    partial[(size_t)nb + poff + blockIdx.x] = s2;
   }
 }
 
 void dcgs_step_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int F, double* vj,
-                   double* wv, size_t n, double* dots, double* coef) {
+                   double* wv, size_t n, double* dots, double* coef, const DcgsSplit* split) {
   MGD_REQUIRE(F >= 1 && F <= 31, "dcgs: F out of range");
   w.ensure(c);
   const int g = red_grid(n);
@@ -599,12 +624,14 @@ void dcgs_step_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int F, doubl
   hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(64), 0, c->stream, F, prov ? 1 : 0,
                      (const double*)dots, coef);
   MGD_CHECK_LAUNCH();
-  {
-    ProfScope ps(c, KC_ORTH, 8.0 * n * (F + (prov ? 4 : 2)),
-                 ksym(c, "k_dcgs_update", {std::to_string(jb), prov ? "true" : "false"}));
-#define MGD_UPD(JB, P)                                                                            \
-  hipLaunchKernelGGL((k_dcgs_update<JB, P>), dim3(g), dim3(256), 0, c->stream, V, ldv, F,           \
-                     (const double*)coef, vj, wv, n, w.partial.get(), g)
+  // one update sweep over m entries (see k_dcgs_update), partials at poff
+  auto update = [&](size_t m, size_t base, size_t lo, size_t gap, int gu, int nb, int poff,
+                    hipStream_t s) {
+    ProfScope ps(c, KC_ORTH, 8.0 * m * (F + (prov ? 4 : 2)),
+                 ksym(c, "k_dcgs_update", {std::to_string(jb), prov ? "true" : "false"}), -1, s);
+#define MGD_UPD(JB, P)                                                                        \
+  hipLaunchKernelGGL((k_dcgs_update<JB, P>), dim3(gu), dim3(256), 0, s, V, ldv, F,              \
+                     (const double*)coef, vj, wv, m, base, lo, gap, w.partial.get(), nb, poff)
 #define MGD_UPD_P(JB) \
   if (prov)           \
     MGD_UPD(JB, true);  \
@@ -622,9 +649,28 @@ void dcgs_step_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int F, doubl
 #undef MGD_UPD_P
 #undef MGD_UPD
     MGD_CHECK_LAUNCH();
+  };
+  int nb = g;
+  if (!split) {
+    update(n, 0, n, 0, g, g, 0, c->stream);
+  } else {
+    MGD_REQUIRE(split->lo < split->hi && split->hi <= n && split->side && split->fork &&
+                    split->join,
+                "dcgs: bad split");
+    const size_t mh = split->hi - split->lo, mr = n - mh;
+    const int gh = red_grid(mh), gr = mr ? red_grid(mr) : 0;
+    nb = gh + gr;
+    MGD_REQUIRE(2 * (size_t)nb <= (size_t)kRedBlocks * 66, "dcgs: too many partials");
+    update(mh, split->lo, mh, 0, gh, nb, 0, c->stream);
+    MGD_HIP(hipEventRecord(split->fork, c->stream));
+    MGD_HIP(hipStreamWaitEvent(split->side, split->fork, 0));
+    if (mr) update(mr, 0, split->lo, mh, gr, nb, gh, split->side);
+    MGD_HIP(hipEventRecord(split->join, split->side));
+    if (split->beside) split->beside();
+    MGD_HIP(hipStreamWaitEvent(c->stream, split->join, 0));
   }
   hipLaunchKernelGGL(k_red_final, dim3(2), dim3(256), 0, c->stream, (const double*)w.partial.get(),
-                     g, coef + 66);
+                     nb, coef + 66);
   MGD_CHECK_LAUNCH();
 }
 

@@ -754,24 +754,28 @@ def test_gmres_aggressive_parity(ctx, kind):
                        segments=inp.G + 2, what=f"aggressive {kind} same-iteration solution")
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_gmres_step_graph_matches_direct(ctx, precision):
+@pytest.mark.parametrize("kind,precision,restart", [
+    ("schur2", 0, 30), ("schur2", 1, 30), ("schur2", 1, 4), ("schur2_lower", 1, 5),
+    ("pctl", 0, 4), ("schur1", 1, 30)])
+def test_gmres_step_graph_matches_direct(ctx, kind, precision, restart):
     """With graph replay every flexible-GMRES step (apply, matvec, Gram-Schmidt)
-    runs as one cached graph; three solves in a row, with eager work and
-    synchronisation between them, equal the direct launches bit for bit."""
+    runs as one cached graph, and where the apply starts with the E solve that
+    solve for the next basis vector ends the step before it (the first step of
+    each restart cycle does its own); three solves in a row, with eager work
+    and synchronisation between them, equal the direct launches bit for bit."""
     import torch
     api = gpu_modules()
     inp = si.generate(3, 2, 24, 61)
     co, gsys = gpu_system(ctx, inp)
     b = to_dev(ctx, inp.b)
-    Md = api.BlockPreconditioner(ctx, gsys, "schur2", amg_seed=6, batched=1, use_graph=0,
+    Md = api.BlockPreconditioner(ctx, gsys, kind, amg_seed=6, batched=1, use_graph=0,
                                  amg_precision=precision)
-    xd, rd = api.gmres(ctx, gsys, Md, b, rtol=1e-9, flexible=1)
+    xd, rd = api.gmres(ctx, gsys, Md, b, rtol=1e-9, flexible=1, restart=restart)
     xd = to_host(xd)
-    Mg = api.BlockPreconditioner(ctx, gsys, "schur2", amg_seed=6, batched=1, use_graph=1,
+    Mg = api.BlockPreconditioner(ctx, gsys, kind, amg_seed=6, batched=1, use_graph=1,
                                  amg_precision=precision)
     for _ in range(3):
-        xg, rg = api.gmres(ctx, gsys, Mg, b, rtol=1e-9, flexible=1)
+        xg, rg = api.gmres(ctx, gsys, Mg, b, rtol=1e-9, flexible=1, restart=restart)
         assert rg.iters == rd.iters and rg.converged
         assert np.array_equal(to_host(xg), xd)
         torch.cuda.synchronize()
