@@ -12,7 +12,24 @@ __device__ __forceinline__ AT row_dot(const int* __restrict__ rp, const int* __r
                                       int lane) {
   AT s = 0;
   const int e1 = rp[row + 1];
-  for (int e = rp[row] + lane; e < e1; e += TPR) s += (AT)v[e] * (AT)x[ci[e]];
+  // eight of the lane's entries at a time, their gathers in flight together
+  // (loads past the row's end masked off); the lane's sum stays in entry order
+  for (int e = rp[row] + lane; e < e1; e += 8 * TPR) {
+    int j[8];
+    AT a[8], xv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (e + q * TPR < e1) {
+        j[q] = ci[e + q * TPR];
+        a[q] = (AT)v[e + q * TPR];
+      }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (e + q * TPR < e1) xv[q] = (AT)x[j[q]];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (e + q * TPR < e1) s += a[q] * xv[q];
+  }
   if (TPR > 1) {
 #pragma unroll
     for (int off = TPR / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, TPR);

@@ -700,13 +700,83 @@ __device__ __forceinline__ T sell_row_c(const int* __restrict__ ci, const T* __r
   return s;
 }
 
+// The same sums for a wave whose 64 lanes are the 64 rows of one slice (the
+// launch is aligned to slices): the slice header is read once into scalar
+// registers, and the entries go in groups of eight with every column code and
+// value of a group in flight together, then every gather of the group.  The
+// entries past the row width in the last group load the last entry again and
+// are not added, so the sum, its order and its rounding are those above.
+template <bool NARROW, typename T, typename G>
+__device__ __forceinline__ T sell_row8(const int* __restrict__ ci, const T* __restrict__ v,
+                                       const G& g, int o, int oc, int w, int cb, int fb) {
+  T s = 0;
+  for (int e = 0; e < w; e += 8) {
+    int j[8];
+    T a[8], x[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int eq = min(e + q, w - 1);
+      j[q] = sell_col<NARROW>(ci, oc + 64 * eq, cb, fb);
+      a[q] = v[o + 64 * eq];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) x[q] = g(j[q]);
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (e + q < w) s += a[q] * x[q];
+  }
+  return s;
+}
+// C columns only: an F column's product is zero (adding a zero product leaves
+// the sum as it is: a sum that starts at +0 is never -0)
+template <bool NARROW, typename T>
+__device__ __forceinline__ T sell_row8_c(const int* __restrict__ ci, const T* __restrict__ v,
+                                         const T* __restrict__ xc, int nC, int o, int oc, int w,
+                                         int cb, int fb) {
+  T s = 0;
+  for (int e = 0; e < w; e += 8) {
+    int j[8];
+    T a[8], x[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int eq = min(e + q, w - 1);
+      j[q] = sell_col<NARROW>(ci, oc + 64 * eq, cb, fb);
+      a[q] = v[o + 64 * eq];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) x[q] = xc[j[q] < nC ? j[q] : 0];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (e + q < w && j[q] < nC) s += a[q] * x[q];
+  }
+  return s;
+}
+// slice header of the wave's slice (uniform), then the lane's row in it
+template <int FMT>
+__device__ __forceinline__ void sell_slice_wave(const int* __restrict__ rp, int row, int& o,
+                                                int& oc, int& w, int& cb, int& fb) {
+  const int r64 = __builtin_amdgcn_readfirstlane(row & ~63);
+  sell_slice<FMT>(rp, r64, o, oc, w, cb, fb);
+  o += row & 63;
+  oc += row & 63;
+}
+
 // sum over row `row` of a_rj g(j), entries in stored order; SELL uses one
-// lane per row, CSR `TPR` lanes of a wavefront per row (butterfly combine)
-template <int FMT, int TPR, typename T, typename G>
+// lane per row, CSR `TPR` lanes of a wavefront per row (butterfly combine).
+// WAVE: sliced rows of a launch aligned to slices (every lane of a wave in the
+// same slice)
+template <int FMT, int TPR, bool WAVE = false, typename T, typename G>
 __device__ __forceinline__ T mrow(const int* __restrict__ rp, const int* __restrict__ ci,
                                   const T* __restrict__ v, const G& g, int row, int lane) {
   T s = 0;
-  if (FMT == kFmtSELL || FMT == kFmtSELL16) {
+  if ((FMT == kFmtSELL || FMT == kFmtSELL16) && WAVE) {
+    int o, oc, w, cb, fb;
+    sell_slice_wave<FMT>(rp, row, o, oc, w, cb, fb);
+    if (FMT == kFmtSELL16 && fb >= 0)
+      s = sell_row8<true>(ci, v, g, o, oc, w, cb, fb);
+    else
+      s = sell_row8<false>(ci, v, g, o, oc, w, cb, fb);
+  } else if (FMT == kFmtSELL || FMT == kFmtSELL16) {
     int o, oc, w, cb, fb;
     sell_slice<FMT>(rp, row, o, oc, w, cb, fb);
     // a slice is 16-bit or 32-bit as a whole: lanes diverge only in the waves
@@ -716,21 +786,26 @@ __device__ __forceinline__ T mrow(const int* __restrict__ rp, const int* __restr
     else
       s = sell_row<false>(ci, v, g, o, oc, w, cb, fb);
   } else {
+    // eight of the lane's entries at a time, every column, value and gather
+    // of the batch in flight together (loads past the row's end masked off),
+    // the lane's sum in entry order
     const int e1 = rp[row + 1];
-    int e = rp[row] + lane;
-    for (; e + 3 * TPR < e1; e += 4 * TPR) {
-      int j[4];
-      T a[4], x[4];
+    for (int e = rp[row] + lane; e < e1; e += 8 * TPR) {
+      int j[8];
+      T a[8], x[8];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) j[q] = ci[e + q * TPR];
+      for (int q = 0; q < 8; ++q)
+        if (e + q * TPR < e1) {
+          j[q] = ci[e + q * TPR];
+          a[q] = v[e + q * TPR];
+        }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) a[q] = v[e + q * TPR];
+      for (int q = 0; q < 8; ++q)
+        if (e + q * TPR < e1) x[q] = g(j[q]);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) x[q] = g(j[q]);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) s += a[q] * x[q];
+      for (int q = 0; q < 8; ++q)
+        if (e + q * TPR < e1) s += a[q] * x[q];
     }
-    for (; e < e1; e += TPR) s += v[e] * g(ci[e]);
     if (TPR > 1) {
 #pragma unroll
       for (int off = TPR / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, TPR);
@@ -740,13 +815,20 @@ __device__ __forceinline__ T mrow(const int* __restrict__ rp, const int* __restr
 }
 // the same, with only C columns (the F part of the iterate is zero): F columns
 // read the first C value with weight zero, so every lane issues the same loads
-template <int FMT, int TPR, typename T>
+template <int FMT, int TPR, bool WAVE = false, typename T>
 __device__ __forceinline__ T mrow_c(const int* __restrict__ rp, const int* __restrict__ ci,
                                     const T* __restrict__ v, const T* __restrict__ xc, int nC,
                                     int row, int lane) {
   T s = 0;
   if (nC == 0) return s;
-  if (FMT == kFmtSELL || FMT == kFmtSELL16) {
+  if ((FMT == kFmtSELL || FMT == kFmtSELL16) && WAVE) {
+    int o, oc, w, cb, fb;
+    sell_slice_wave<FMT>(rp, row, o, oc, w, cb, fb);
+    if (FMT == kFmtSELL16 && fb >= 0)
+      s = sell_row8_c<true>(ci, v, xc, nC, o, oc, w, cb, fb);
+    else
+      s = sell_row8_c<false>(ci, v, xc, nC, o, oc, w, cb, fb);
+  } else if (FMT == kFmtSELL || FMT == kFmtSELL16) {
     int o, oc, w, cb, fb;
     sell_slice<FMT>(rp, row, o, oc, w, cb, fb);
     if (FMT == kFmtSELL16 && fb >= 0)
@@ -755,9 +837,21 @@ __device__ __forceinline__ T mrow_c(const int* __restrict__ rp, const int* __res
       s = sell_row_c<false>(ci, v, xc, nC, o, oc, w, cb, fb);
   } else {
     const int e1 = rp[row + 1];
-    for (int e = rp[row] + lane; e < e1; e += TPR) {
-      const int j = ci[e];
-      if (j < nC) s += v[e] * xc[j];
+    for (int e = rp[row] + lane; e < e1; e += 8 * TPR) {  // batches as in mrow
+      int j[8];
+      T a[8], x[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (e + q * TPR < e1) {
+          j[q] = ci[e + q * TPR];
+          a[q] = v[e + q * TPR];
+        }
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (e + q * TPR < e1 && j[q] < nC) x[q] = xc[j[q]];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (e + q * TPR < e1 && j[q] < nC) s += a[q] * x[q];
     }
     if (TPR > 1) {
 #pragma unroll
@@ -773,6 +867,12 @@ __device__ __forceinline__ T mrow_c(const int* __restrict__ rp, const int* __res
 // works on one contiguous share of the rows and finds the iterate values its
 // rows gather (mostly near its own rows) in its own L2.
 __constant__ int c_xcd_rows = 0;
+template <int FMT>
+constexpr bool kSliced = FMT == kFmtSELL || FMT == kFmtSELL16;
+template <int FMT>
+__host__ __device__ __forceinline__ int launch_start(int r0) {
+  return kSliced<FMT> ? (r0 & ~63) : r0;
+}
 constexpr int kXcds = 8;
 __device__ __forceinline__ long xcd_block(long b, long nb) {
   const long q = nb / kXcds, r = nb % kXcds, x = b % kXcds;
@@ -781,12 +881,14 @@ __device__ __forceinline__ long xcd_block(long b, long nb) {
 void set_xcd_rows(int on) {
   MGD_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_xcd_rows), &on, sizeof(int)));
 }
+// Sliced layouts (one lane per row) start at r0 rounded down to a 64-row
+// slice, so that every wave works on one slice (kSliced, launch_start).
 #define MGD_ROWS_TPR                                                              \
   const long b_ = c_xcd_rows ? xcd_block(blockIdx.x, gridDim.x) : (long)blockIdx.x; \
   const long t_ = b_ * blockDim.x + threadIdx.x;                                  \
   const int lane = (int)(t_ % TPR);                                               \
-  const int k = r0 + (int)(t_ / TPR);                                             \
-  if (k >= r1) return;
+  const int k = launch_start<FMT>(r0) + (int)(t_ / TPR);                          \
+  if (k >= r1 || k < r0) return;
 
 // level-0 entry: B[k] = b[perm[k]]; C values of the first sweep X_C = B_C / d_C
 template <typename T, bool PRE>
@@ -814,9 +916,10 @@ __global__ void __launch_bounds__(256) k_entry_resid(int r0, int r1, int nS, int
     if (lane == 0) B[k] = (T)0;
     return;
   }
-  const T s = mrow<FMT, TPR>(rp, ci, v, GatherPerm<T>{z, perm}, k, lane);
+  const T bk = b[perm[k]];
+  const T s = mrow<FMT, TPR, true>(rp, ci, v, GatherPerm<T>{z, perm}, k, lane);
   if (lane == 0) {
-    const T bb = b[perm[k]] - s;
+    const T bb = bk - s;
     B[k] = bb;
     if (k < nC) XC[k] = PRE ? bb * dinv[k] : (T)0;
   }
@@ -831,8 +934,9 @@ __global__ void __launch_bounds__(256) k_fhalf0(int r0, int r1, int nC, const in
                                                 const T* __restrict__ B, const T* __restrict__ XC,
                                                 T* __restrict__ Xout) {
   MGD_ROWS_TPR
-  const T s = mrow_c<FMT, TPR>(rp, ci, v, XC, nC, k, lane);
-  if (lane == 0) Xout[k] = (T)0 + (B[k] - s) * dinv[k];
+  const T bk = B[k], dk = dinv[k];
+  const T s = mrow_c<FMT, TPR, true>(rp, ci, v, XC, nC, k, lane);
+  if (lane == 0) Xout[k] = (T)0 + (bk - s) * dk;
 }
 
 // half-sweep on rows [r0, r1): Xout = Xold + (B - A X) / d
@@ -843,8 +947,9 @@ __global__ void __launch_bounds__(256) k_half(int r0, int r1, const int* __restr
                                               GatherCF<T> X, const T* __restrict__ Xold,
                                               T* __restrict__ Xout) {
   MGD_ROWS_TPR
-  const T s = mrow<FMT, TPR>(rp, ci, v, X, k, lane);
-  if (lane == 0) Xout[k] = Xold[k] + (B[k] - s) * dinv[k];
+  const T xk = Xold[k], bk = B[k], dk = dinv[k];
+  const T s = mrow<FMT, TPR, true>(rp, ci, v, X, k, lane);
+  if (lane == 0) Xout[k] = xk + (bk - s) * dk;
 }
 
 // level-0 final C half-sweep fused with the output: z[perm[k]] = new X_C on
@@ -860,8 +965,10 @@ __global__ void __launch_bounds__(256) k_half_out(int r0, int r1, int nC, int nS
                                                   const int* __restrict__ perm, T* __restrict__ z) {
   MGD_ROWS_TPR
   if (k < nC) {
-    const T s = mrow<FMT, TPR>(rp, ci, v, X, k, lane);
-    if (lane == 0) z[perm[k]] = X.base[k] + (B[k] - s) * dinv[k];
+    const T xk = X.base[k], bk = B[k], dk = dinv[k];
+    const int pk = perm[k];
+    const T s = mrow<FMT, TPR, true>(rp, ci, v, X, k, lane);
+    if (lane == 0) z[pk] = xk + (bk - s) * dk;
   } else if (lane == 0) {
     if (k < nS)
       z[perm[k]] = X.base[k + X.f_minus_c];
@@ -899,8 +1006,9 @@ __global__ void __launch_bounds__(256) k_resid(int r0, int r1, const int* __rest
                                                const T* __restrict__ v, const T* __restrict__ B,
                                                GatherCF<T> X, T* __restrict__ R) {
   MGD_ROWS_TPR
-  const T s = mrow<FMT, TPR>(rp, ci, v, X, k, lane);
-  if (lane == 0) R[k] = B[k] - s;
+  const T bk = B[k];
+  const T s = mrow<FMT, TPR, true>(rp, ci, v, X, k, lane);
+  if (lane == 0) R[k] = bk - s;
 }
 
 // restriction into level l+1 (rows in its extended order):
@@ -915,9 +1023,10 @@ __global__ void __launch_bounds__(256) k_restrict(int r0, int r1, int nC, int nC
                                                   const T* __restrict__ dinv_n,
                                                   T* __restrict__ Bn, T* __restrict__ XCn) {
   MGD_ROWS_TPR
-  const T s = mrow<FMT, TPR>(rp, ci, v, Gather1<T>{R + nC}, k, lane);
+  const T rc = R[cpos[k]];
+  const T s = mrow<FMT, TPR, true>(rp, ci, v, Gather1<T>{R + nC}, k, lane);
   if (lane == 0) {
-    const T bb = R[cpos[k]] + s;
+    const T bb = rc + s;
     Bn[k] = bb;
     if (k < nCn) XCn[k] = PRE ? bb * dinv_n[k] : (T)0;
   }
@@ -935,8 +1044,9 @@ __global__ void __launch_bounds__(256) k_prolong(int r0, int r1, int nC,
   if (k < nC) {
     if (lane == 0) XC[k] += E(cmap[k]);
   } else {
+    const T xk = XF[k];
     const T s = mrow<FMT, TPR>(rp, ci, v, E, k - nC, lane);
-    if (lane == 0) XF[k] += s;
+    if (lane == 0) XF[k] = xk + s;
   }
 }
 
@@ -1197,7 +1307,8 @@ struct HalfL {
   template <int FMT, int TPR>
   void go() const {
     if (r1 <= r0) return;
-    hipLaunchKernelGGL((k_half<T, FMT, TPR>), rows_grid(r1 - r0, TPR, A.bs), dim3(A.bs), 0, c->stream,
+    hipLaunchKernelGGL((k_half<T, FMT, TPR>), rows_grid(r1 - launch_start<FMT>(r0), TPR, A.bs),
+                       dim3(A.bs), 0, c->stream,
                        r0, r1, A.rp.get(), A.ci.get(), A.v.get(), dinv, B, X, Xold, Xout);
     MGD_CHECK_LAUNCH();
   }
@@ -1212,7 +1323,8 @@ struct FHalf0L {
   template <int FMT, int TPR>
   void go() const {
     if (r1 <= r0) return;
-    hipLaunchKernelGGL((k_fhalf0<T, FMT, TPR>), rows_grid(r1 - r0, TPR, A.bs), dim3(A.bs), 0, c->stream,
+    hipLaunchKernelGGL((k_fhalf0<T, FMT, TPR>), rows_grid(r1 - launch_start<FMT>(r0), TPR, A.bs),
+                       dim3(A.bs), 0, c->stream,
                        r0, r1, nC, A.rp.get(), A.ci.get(), A.v.get(), dinv, B, XC, Xout);
     MGD_CHECK_LAUNCH();
   }

@@ -140,10 +140,7 @@ __global__ void __launch_bounds__(R) k_block_matvec_shared(BlockSysDev S,
       const double* __restrict__ v = S.blk[a].v + cb;
       double r[PT];
 #pragma unroll
-      for (int j = 0; j < PT; ++j) {
-        const int k = t + j * R;
-        r[j] = k < cl ? v[k] : 0.0;
-      }
+      for (int j = 0; j < PT; ++j) r[j] = v[min(t + j * R, cl - 1)];  // cl >= 1 here
       __syncthreads();  // every thread is done with the previous chunk
       if (!one_chunk)
         for (int k = t; k < cl; k += R) s_ci[k] = ci[cb + k];
@@ -154,7 +151,23 @@ __global__ void __launch_bounds__(R) k_block_matvec_shared(BlockSysDev S,
       }
       __syncthreads();
       const int kb = max(rb, cb), ke = min(re, cb + cl);
-      for (int k = kb; k < ke; ++k) s += s_v[k - cb] * xa[s_ci[k - cb]];
+      // eight entries at a time: their gathers in flight together (the sum in
+      // entry order; entries past the row's end repeat its last and are not added)
+      for (int k0 = kb; k0 < ke; k0 += 8) {
+        int jj[8];
+        double av[8], xv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int kq = min(k0 + q, ke - 1) - cb;
+          jj[q] = s_ci[kq];
+          av[q] = s_v[kq];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xv[q] = xa[jj[q]];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (k0 + q < ke) s += av[q] * xv[q];
+      }
     }
     if (!active) continue;
     if (a < G) {
@@ -186,7 +199,22 @@ __global__ void __launch_bounds__(256) k_block_matvec_finish(BlockSysDev S,
   const int* __restrict__ ci = S.blk[0].ci;
   const double* __restrict__ v = S.blk[G].v;
   double s = 0.0;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) s += v[k] * xEv[ci[k]];
+  const int kb = rp[i], ke = rp[i + 1];
+  for (int k0 = kb; k0 < ke; k0 += 8) {  // as in k_block_matvec_shared
+    int jj[8];
+    double av[8], xv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int kq = min(k0 + q, ke - 1);
+      jj[q] = ci[kq];
+      av[q] = v[kq];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xv[q] = xEv[jj[q]];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (k0 + q < ke) s += av[q] * xv[q];
+  }
   s += y[(size_t)G * N + i];
   s += S.d_EI[i] * x[(size_t)(G + 1) * N + i];
   y[(size_t)G * N + i] = s;
