@@ -428,7 +428,8 @@ def main():
                      "achieved_stored": achieved_stored,
                      "frac_stored": achieved_stored / HBM_PEAK_GBS,
                      "copy_ceiling": copy_gbs,
-                     "frac_of_copy": achieved / copy_gbs,
+                     # the bytes the launch moves as stored, against a device copy's rate
+                     "frac_of_copy": achieved_stored / copy_gbs,
                      "launches": s["launches"], "avg_launch_us": avg_us},
         "kernels": {k: {"ms": v["ms"], "launches": v["launches"],
                         "GB/s": (v["bytes_csr"] / 1e9) / (v["ms"] / 1e3) if v["ms"] else 0.0,
