@@ -171,9 +171,10 @@ def main():
                     help="skip the adaptive, option #4, aggressive and inner-tolerance variants")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the 2D 1024^2, 2D 256^2 and 2D 512^2 workloads")
-    ap.add_argument("--autotune", action="store_true",
-                    help="time the candidate layouts of every level once and keep the fastest "
-                         "(cached per process, or in MGD_AUTOTUNE_CACHE)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the default layout rules instead of timing the candidate layouts "
+                         "of every level at setup (the tuned choice is cached per process, or "
+                         "in MGD_AUTOTUNE_CACHE)")
     ap.add_argument("--counters-run", action="store_true",
                     help="short run for hardware-counter passes: a streaming calibration "
                          "kernel (torch mul reading 1 GiB and writing 1 GiB, its input pushed "
@@ -413,6 +414,7 @@ def main():
         "iters": iters,
         "relres_true": relres,
         "setup_s": setup32,
+        "layouts": "autotuned at setup" if a.autotune else "default rules",
         "forms": forms or None,
         "speedup_vs_plain_fp64": (forms["fp64_plain"]["ms"] / ms_step) if forms else None,
         "error_vs_oracle": err_oracle,
