@@ -802,6 +802,16 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
                        (const SegIn*)grp.in_tab.get(), r, w, grp.in.get());
     MGD_CHECK_LAUNCH();
   };
+  // group_in, then the group's inverses; a batched group of V-cycle members
+  // with one cycle each forms its inputs in the union's entry kernel instead
+  auto group_solve = [&](const T* w) {
+    if (!grp.tol && grp.cycles == 1 && grp.batched && grp.n_amg == nm) {
+      grp.batched->apply_seg(c, N, (const SegIn*)grp.in_tab.get(), r, w, grp.out.get());
+      return;
+    }
+    group_in(w);
+    run_group(bp, grp);
+  };
   auto group_out = [&](bool sum, T* sT) {
     ProfScope ps(c, KC_VEC, (double)nm * N * (sizeof(T) + 8 + (sum ? 8 : 0)));
     if (sum)
@@ -829,8 +839,7 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
       break;
     }
     case MGD_PC_BLOCK_DIAG:
-      group_in(nullptr);
-      run_group(bp, grp);
+      group_solve(nullptr);
       group_out(false, nullptr);
       ninv = G + 2;
       break;
@@ -859,8 +868,7 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
       if (adaptive && kind == MGD_PC_SCHUR2 && bp->from_E_weak) {
         // every row block independent of E (block lower triangular):
         // w_a = S^_a^{-1} r_a, then w_E = A_E^{-1}(r_E - sum_a D_Ea w_a)
-        group_in(nullptr);
-        run_group(bp, grp);
+        group_solve(nullptr);
         group_out(true, X.b_in.get());
         if (i_apart) i_step(nullptr, X.b_in.get());
         hipLaunchKernelGGL(k_lower_E_in<T>, g1, b1, 0, c->stream, N, r + (size_t)G * N,
@@ -881,8 +889,7 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
         if (bp->first_stage == 1) return;
       }
       // step 2: groups and I against r - D_.E w_E*
-      group_in(X.a_out.get());
-      run_group(bp, grp);
+      group_solve(X.a_out.get());
       ninv = 1 + G + 1;
       const bool e_coupled = !(adaptive && bp->into_E_weak);
       if (kind == MGD_PC_SCHUR2 && e_coupled) {
@@ -936,8 +943,7 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
       if (adaptive && bp->groups_from_E_weak) {
         // groups independent of E: w_g = C^_g^{-1} r_g, then one C^_E inverse
         // w_E = C^_E^{-1}((r_E - D_EI w_I*) - sum_g D_Eg w_g)
-        group_in(nullptr);
-        run_group(bp, grp);
+        group_solve(nullptr);
         group_out(true, X.b_in.get());
         hipLaunchKernelGGL(k_lower_E_in<T>, g1, b1, 0, c->stream, N, r + (size_t)G * N, dEI,
                            (const T*)X.a_out.get(), (const T*)X.b_in.get(), X.b_out.get());
@@ -954,8 +960,7 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
         MGD_CHECK_LAUNCH();
         cinv(G, X.b_in.get(), X.b_out.get());
         // 3. w_g = C^_g^{-1}(r_g - D_gE w_E*)
-        group_in(X.b_out.get());
-        run_group(bp, grp);
+        group_solve(X.b_out.get());
         ninv = 1 + 1 + G;
         if (adaptive && bp->into_E_weak_groups) {
           group_out(false, nullptr);

@@ -29,10 +29,6 @@ struct amg_hierarchy {
 namespace mgd {
 
 // Glue descriptors for a group of independent scalar solves.
-struct SegIn {
-  int seg;              // source segment of the Krylov vector (0..G+1)
-  const double* coef;   // subtract coef o w (or nullptr)
-};
 struct SegOut {
   int seg;              // destination segment of the result
   const double* coef;   // accumulate coef o x into s (or nullptr)

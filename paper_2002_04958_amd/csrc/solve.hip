@@ -900,6 +900,24 @@ __global__ void k_entry(int nX, int nC, const int* __restrict__ perm, const T* _
   B[k] = bb;
   if (k < nC) XC[k] = PRE ? bb * dinv[k] : (T)0;
 }
+// the same with the members' right-hand sides formed here from a block vector:
+// member m = p / N of natural row p takes (T)(r[seg_m N + i] - coef_m[i] w[i])
+template <typename T, bool PRE>
+__global__ void k_entry_seg(int nX, int nC, int N, const int* __restrict__ perm,
+                            const T* __restrict__ dinv, const SegIn* __restrict__ tab,
+                            const double* __restrict__ r, const T* __restrict__ w,
+                            T* __restrict__ B, T* __restrict__ XC) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nX) return;
+  const int p = perm[k];
+  const int m = p / N, i = p - m * N;
+  const SegIn d = tab[m];
+  double v = r[(size_t)d.seg * N + i];
+  if (d.coef) v = v - d.coef[i] * (double)w[i];
+  const T bb = (T)v;
+  B[k] = bb;
+  if (k < nC) XC[k] = PRE ? bb * dinv[k] : (T)0;
+}
 // later cycles: B = (b - A z) in stored order (dense rows: 0), X_C as above
 template <typename T, int FMT, int TPR, bool PRE>
 __global__ void __launch_bounds__(256) k_entry_resid(int r0, int r1, int nS, int nC,
@@ -1844,6 +1862,33 @@ void Union<T>::vcycle_gs(Ctx* c, T* z) {
                      gather_cfd<T>(X0[0].get(), X0[0].get(), X0[0].get(), l0.nC, l0.nS),
                      (const int*)l0.perm.get(), z);
   MGD_CHECK_LAUNCH();
+}
+
+template <typename T>
+void Union<T>::apply_seg(Ctx* c, int N, const SegIn* tab, const double* r, const T* w, T* z) {
+  ULevel<T>& l0 = L[0];
+  MGD_REQUIRE(N > 0 && (long long)N * members == l0.nX, "apply_seg: rows do not match the union");
+  const bool pre = n_pre > 0 && !gs;
+  {
+    // perm, r and the coefficients (FP64), w, d^-1 on C rows, B and X_C written
+    ProfScope ps(c, KC_TRANSFER_L0,
+                 (double)l0.nX * (4 + 16 + 2.0 * sizeof(T)) + l0.nC * 2.0 * sizeof(T),
+                 ksym(c, "k_entry_seg", {type_name<T>(), pre ? "true" : "false"}));
+    if (pre)
+      hipLaunchKernelGGL((k_entry_seg<T, true>), dim3(cdiv(l0.nX, 256)), dim3(256), 0, c->stream,
+                         l0.nX, l0.nC, N, (const int*)l0.perm.get(), (const T*)l0.dinv.get(), tab,
+                         r, w, B[0].get(), X0[0].get());
+    else
+      hipLaunchKernelGGL((k_entry_seg<T, false>), dim3(cdiv(l0.nX, 256)), dim3(256), 0, c->stream,
+                         l0.nX, l0.nC, N, (const int*)l0.perm.get(), (const T*)l0.dinv.get(), tab,
+                         r, w, B[0].get(), X0[0].get());
+    MGD_CHECK_LAUNCH();
+  }
+  if (gs)
+    vcycle_gs(c, z);
+  else
+    vcycle(c, z);
+  t_prof_level = -1;
 }
 
 template <typename T>

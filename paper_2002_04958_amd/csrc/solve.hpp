@@ -21,6 +21,13 @@
 
 namespace mgd {
 
+// one member's input of a batched apply, read from a block vector of
+// (G+2) segments of N rows
+struct SegIn {
+  int seg;              // source segment of the Krylov vector (0..G+1)
+  const double* coef;   // subtract coef o w (or nullptr)
+};
+
 struct DenseDev {
   int off;  // first row of the member in the level's extended stored order
   int n;
@@ -132,6 +139,10 @@ struct Union {
 
   // z = k V-cycles on b (zero initial guess); b, z natural level-0 vectors.
   void apply(Ctx* c, const T* b, T* z, int cycles);
+  // One cycle with the members' right-hand sides formed in the entry kernel:
+  // member m's is (T)(r[tab[m].seg] - tab[m].coef o w) over N rows, the same
+  // arithmetic as forming them into a vector first and calling apply.
+  void apply_seg(Ctx* c, int N, const SegIn* tab, const double* r, const T* w, T* z);
   double bytes_per_vcycle() const;
 
  private:
