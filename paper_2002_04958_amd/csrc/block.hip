@@ -592,6 +592,11 @@ static void build_exec(block_precond* bp, std::unique_ptr<PcExec<T>>& X) {
     X->o4_t.alloc(c, n1);
     X->o4_u.alloc(c, n1);
   }
+  {
+    const SegIn st[2] = {{G, nullptr}, {G + 1, nullptr}};
+    X->seg_tab.alloc(c, 2);
+    copy_h2d(c, X->seg_tab.get(), st, 2);
+  }
   if (kind == MGD_PC_AMG_MONO) return;
   // group membership
   std::vector<SegIn> tin;
@@ -786,6 +791,17 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
     }
     extra_inv += 2 * steps4 - 2;
   };
+  // out = inverse of role applied to segment seg (E or I) of r; in FP32 a
+  // plain single V-cycle takes the segment in its entry kernel (the cast and
+  // the cycle's arithmetic unchanged)
+  auto inv_seg = [&](int role, int seg, T* out) {
+    if (std::is_same<T, float>::value && !X.tol_one[role] && !bp->jacobi[role] &&
+        bp->cycles[role] == 1) {
+      U(role)->apply_seg(c, N, X.seg_tab.get() + (seg - G), r, nullptr, out);
+      return;
+    }
+    inv(role, as_input<T>(c, r + (size_t)seg * N, X.a_in, N), out);
+  };
   // the Schur complement inverse of the kind: option #4 when asked for
   auto cinv = [&](int role, const T* in, T* out) {
     if (steps4 > 0 && ((kind == MGD_PC_SCHUR2 && role == G + 1) ||
@@ -884,8 +900,7 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
       }
       // step 1: w_E* = A_E^{-1} r_E (or already in X.a_out: first_stage 2)
       if (bp->first_stage != 2) {
-        const T* inE = as_input<T>(c, r + (size_t)G * N, X.a_in, N);
-        inv(G, inE, X.a_out.get());
+        inv_seg(G, G, X.a_out.get());
         if (bp->first_stage == 1) return;
       }
       // step 2: groups and I against r - D_.E w_E*
@@ -938,8 +953,7 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
     case MGD_PC_SCHUR1: {
       const double* dEI = (adaptive && bp->weak_EI) ? nullptr : bp->d_EI.get();
       // 1. w_I* = A_I^{-1} r_I
-      const T* inI = as_input<T>(c, r + (size_t)(G + 1) * N, X.a_in, N);
-      inv(G + 1, inI, X.a_out.get());
+      inv_seg(G + 1, G + 1, X.a_out.get());
       if (adaptive && bp->groups_from_E_weak) {
         // groups independent of E: w_g = C^_g^{-1} r_g, then one C^_E inverse
         // w_E = C^_E^{-1}((r_E - D_EI w_I*) - sum_g D_Eg w_g)

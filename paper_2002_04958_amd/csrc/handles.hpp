@@ -92,6 +92,7 @@ struct PcExec {
   DBuf<T> jac_tmp1;
   std::vector<std::unique_ptr<TolSolve<T>>> tol_one;  // per role, single option #3 inverses
   DBuf<T> o4_w, o4_s, o4_t, o4_u;  // option #4 iterate and work vectors
+  DBuf<SegIn> seg_tab;             // {E, no coupling}, {I, no coupling}: single inputs
 };
 
 }  // namespace mgd
