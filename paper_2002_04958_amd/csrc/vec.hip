@@ -592,9 +592,11 @@ void dcgs_step_dev(Ctx* c, RedWork& w, const double* V, size_t ldv, int F, doubl
                    double* wv, size_t n, double* dots, double* coef, const DcgsSplit* split) {
   MGD_REQUIRE(F >= 1 && F <= 31, "dcgs: F out of range");
   w.ensure(c);
-  const int g = red_grid(n);
   const bool prov = vj != nullptr;
   const int jb = mdot_jb(F);
+  // with 32-vector register arrays two workgroups fit a compute unit: one
+  // round of resident workgroups
+  const int g = jb == 32 ? std::min(red_grid(n), kRedBlocks / 2) : red_grid(n);
   {
     ProfScope ps(c, KC_ORTH, 8.0 * n * (F + (prov ? 2 : 1)),
                  ksym(c, "k_dcgs_dots", {std::to_string(jb), prov ? "true" : "false"}));
