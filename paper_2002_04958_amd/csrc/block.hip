@@ -81,11 +81,25 @@ __global__ void k_group_out(int N, int nm, const SegOut* __restrict__ tab, const
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   double s = 0.0;
-  for (int m = 0; m < nm; ++m) {
-    const SegOut d = tab[m];
-    const double x = (double)out[(size_t)m * N + i];
-    z[(size_t)d.seg * N + i] = x;
-    if (SUM && d.coef) s = s + d.coef[i] * x;
+  // four members at a time: their loads in flight together, the sum in member order
+  for (int m0 = 0; m0 < nm; m0 += 4) {
+    double x[4], cf[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (m0 + q < nm) {
+        const SegOut d = tab[m0 + q];
+        x[q] = (double)out[(size_t)(m0 + q) * N + i];
+        cf[q] = (SUM && d.coef) ? d.coef[i] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (m0 + q < nm) {
+        const SegOut d = tab[m0 + q];
+        z[(size_t)d.seg * N + i] = x[q];
+        if (SUM && d.coef) s = s + cf[q] * x[q];
+      }
+    }
   }
   if (SUM) sT[i] = (T)s;
 }
