@@ -329,6 +329,14 @@ def main():
         for k, v in sorted(tagged.items(), key=lambda kv: -kv[1]["ms"])[:40]))
     log(f"[bench] dominant {dom}: {avg_us:.2f} us/launch, {achieved:.0f} GB/s (CSR model), "
         f"{achieved_stored:.0f} GB/s (stored layout); copy {copy_gbs:.0f} GB/s")
+    # the whole solve: every launch's algorithmic bytes (the same 38-step solve,
+    # event-timed above) over the graph-replayed time of one solve
+    # (the class totals include the few launches profiled without a symbol:
+    # vector work, whose bytes are the same under both pricings)
+    solve_bytes = sum(v["bytes"] for v in stats.values())
+    solve_bytes_csr = (sum(v["bytes_csr"] for v in tagged.values()) + solve_bytes -
+                       sum(v["bytes"] for v in tagged.values()))
+    solve_gbs = solve_bytes / (ms_step * 1e-3) / 1e9
 
     # the other workloads: 2D 1024^2 G=1, 2D 256^2 G=20, 2D 512^2 G=20 (FP64 unless stated)
     workloads = {}
@@ -433,6 +441,10 @@ def main():
                      # the bytes the launch moves as stored, against a device copy's rate
                      "frac_of_copy": achieved_stored / copy_gbs,
                      "launches": s["launches"], "avg_launch_us": avg_us},
+        "solve_bandwidth": {"bytes_stored": solve_bytes, "bytes_csr": solve_bytes_csr,
+                            "GB/s_stored": solve_gbs, "frac_of_peak": solve_gbs / HBM_PEAK_GBS,
+                            "frac_of_copy": solve_gbs / copy_gbs,
+                            "time_at_copy_rate_ms": solve_bytes / (copy_gbs * 1e9) * 1e3},
         "kernels": {k: {"ms": v["ms"], "launches": v["launches"],
                         "GB/s": (v["bytes_csr"] / 1e9) / (v["ms"] / 1e3) if v["ms"] else 0.0,
                         "GB/s_stored": (v["bytes"] / 1e9) / (v["ms"] / 1e3) if v["ms"] else 0.0}
