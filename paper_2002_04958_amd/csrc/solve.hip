@@ -125,6 +125,14 @@ __global__ void k_iota(int n, int first, int* __restrict__ out) {
   if (i < n) out[i] = first + i;
 }
 // inverse of a permutation given as perm[k] (k < n), with a range check
+template <typename T>
+__global__ void k_dinv_nat(int n, int nC, const int* __restrict__ iperm,
+                           const T* __restrict__ dinv, T* __restrict__ dn) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int k = iperm[p];
+  dn[p] = k < nC ? dinv[k] : (T)0;
+}
 __global__ void k_invert(int n, const int* __restrict__ perm, int* __restrict__ inv,
                          int* __restrict__ err) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -576,6 +584,23 @@ std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHiera
     if (ncoarse == 0) break;
   }
   finalize_levels(c, built, *U, autotune);
+  {
+    // level 0 seen from the natural side, for entry kernels that read their
+    // inputs in natural order: the inverse permutation and d^-1 of C rows
+    ULevel<T>& l0 = U->L[0];
+    const int nX = l0.nX, g = cdiv(std::max(nX, 1), 256);
+    l0.iperm.alloc(c, (size_t)std::max(nX, 1));
+    l0.dinv_nat.alloc(c, (size_t)std::max(nX, 1));
+    if (nX > 0) {
+      hipLaunchKernelGGL(k_invert, dim3(g), dim3(256), 0, c->stream, nX,
+                         (const int*)l0.perm.get(), l0.iperm.get(), c->err_flag());
+      MGD_CHECK_LAUNCH();
+      hipLaunchKernelGGL(k_dinv_nat<T>, dim3(g), dim3(256), 0, c->stream, nX, l0.nC,
+                         (const int*)l0.iperm.get(), (const T*)l0.dinv.get(), l0.dinv_nat.get());
+      MGD_CHECK_LAUNCH();
+    }
+    c->check_device_errors("natural-order map of level 0");
+  }
   U->build_tail(c);
   c->sync();
   return U;
@@ -900,23 +925,24 @@ __global__ void k_entry(int nX, int nC, const int* __restrict__ perm, const T* _
   B[k] = bb;
   if (k < nC) XC[k] = PRE ? bb * dinv[k] : (T)0;
 }
-// the same with the members' right-hand sides formed here from a block vector:
-// member m = p / N of natural row p takes (T)(r[seg_m N + i] - coef_m[i] w[i])
+// level-0 entry with the members' right-hand sides formed here from a block
+// vector, read in natural order (member m = blockIdx.y, row i, coalesced):
+// (T)(r[seg_m N + i] - coef_m[i] w[i]) written at its stored position iperm[.]
 template <typename T, bool PRE>
-__global__ void k_entry_seg(int nX, int nC, int N, const int* __restrict__ perm,
-                            const T* __restrict__ dinv, const SegIn* __restrict__ tab,
+__global__ void k_entry_nat(int N, int nC, const int* __restrict__ iperm,
+                            const T* __restrict__ dinv_nat, const SegIn* __restrict__ tab,
                             const double* __restrict__ r, const T* __restrict__ w,
                             T* __restrict__ B, T* __restrict__ XC) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nX) return;
-  const int p = perm[k];
-  const int m = p / N, i = p - m * N;
-  const SegIn d = tab[m];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const SegIn d = tab[blockIdx.y];
+  const size_t p = (size_t)blockIdx.y * N + i;
   double v = r[(size_t)d.seg * N + i];
   if (d.coef) v = v - d.coef[i] * (double)w[i];
   const T bb = (T)v;
+  const int k = iperm[p];
   B[k] = bb;
-  if (k < nC) XC[k] = PRE ? bb * dinv[k] : (T)0;
+  if (k < nC) XC[k] = PRE ? bb * dinv_nat[p] : (T)0;
 }
 // later cycles: B = (b - A z) in stored order (dense rows: 0), X_C as above
 template <typename T, int FMT, int TPR, bool PRE>
@@ -1870,18 +1896,19 @@ void Union<T>::apply_seg(Ctx* c, int N, const SegIn* tab, const double* r, const
   MGD_REQUIRE(N > 0 && (long long)N * members == l0.nX, "apply_seg: rows do not match the union");
   const bool pre = n_pre > 0 && !gs;
   {
-    // perm, r and the coefficients (FP64), w, d^-1 on C rows, B and X_C written
+    // iperm, r and the coefficients (FP64), w, d^-1 on C rows, B and X_C written
     ProfScope ps(c, KC_TRANSFER_L0,
                  (double)l0.nX * (4 + 16 + 2.0 * sizeof(T)) + l0.nC * 2.0 * sizeof(T),
-                 ksym(c, "k_entry_seg", {type_name<T>(), pre ? "true" : "false"}));
+                 ksym(c, "k_entry_nat", {type_name<T>(), pre ? "true" : "false"}));
+    const dim3 grid(cdiv(N, 256), members);
     if (pre)
-      hipLaunchKernelGGL((k_entry_seg<T, true>), dim3(cdiv(l0.nX, 256)), dim3(256), 0, c->stream,
-                         l0.nX, l0.nC, N, (const int*)l0.perm.get(), (const T*)l0.dinv.get(), tab,
-                         r, w, B[0].get(), X0[0].get());
+      hipLaunchKernelGGL((k_entry_nat<T, true>), grid, dim3(256), 0, c->stream, N, l0.nC,
+                         (const int*)l0.iperm.get(), (const T*)l0.dinv_nat.get(), tab, r, w,
+                         B[0].get(), X0[0].get());
     else
-      hipLaunchKernelGGL((k_entry_seg<T, false>), dim3(cdiv(l0.nX, 256)), dim3(256), 0, c->stream,
-                         l0.nX, l0.nC, N, (const int*)l0.perm.get(), (const T*)l0.dinv.get(), tab,
-                         r, w, B[0].get(), X0[0].get());
+      hipLaunchKernelGGL((k_entry_nat<T, false>), grid, dim3(256), 0, c->stream, N, l0.nC,
+                         (const int*)l0.iperm.get(), (const T*)l0.dinv_nat.get(), tab, r, w,
+                         B[0].get(), X0[0].get());
     MGD_CHECK_LAUNCH();
   }
   if (gs)

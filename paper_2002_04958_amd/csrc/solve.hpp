@@ -77,6 +77,8 @@ struct ULevel {
   LMat<T> A;          // nS rows, stored-order columns
   DBuf<T> dinv;       // 1 / l1 diagonal, stored rows
   DBuf<int> perm;     // extended stored order -> natural union numbering (nX)
+  DBuf<int> iperm;    // level 0: natural union numbering -> extended stored order
+  DBuf<T> dinv_nat;   // level 0: dinv at the natural position of each C row, else 0
   LMat<T> W;          // F rows of P (nS - nC rows), columns in level l+1 extended order
   LMat<T> Wt;         // W transposed, rows in level l+1 extended order, columns F index
   DBuf<int> cmap;     // C row I -> its level l+1 extended index (nC)
