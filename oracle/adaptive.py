@@ -17,7 +17,7 @@ needed:
 
 Readings (where the paper leaves the details open):
   * Each coupling block of eq. 2.2 (D_gE, D_Eg for every g, D_EI, D_IE) is
-    judged on its own; the neglected ones are set to zero and the chosen
+    evaluated on its own; the neglected ones are set to zero and the chosen
     preconditioner (PCTL, Schur1, Schur2) is formed from the modified matrix,
     hats included (a hat update whose product involves a neglected coupling
     leaves the block unchanged).
