@@ -205,18 +205,20 @@ def test_g20_3d64_schur2_fp64_batched_graph_against_oracle(ctx):
     fp64_solve_checks(ctx, "g20_3d64", "schur2", 4, batched=True, graph=True)
 
 
-def test_g20_3d64_schur2_fp32_batched_against_oracle(ctx):
+@pytest.mark.parametrize("autotune", [0, 1])
+def test_g20_3d64_schur2_fp32_batched_against_oracle(ctx, autotune):
     """The benchmark's form (FP32 hierarchies, batched, graph-replayed, FP64
-    FGMRES): the hierarchies are the oracle's (the setup is FP64), the
-    iteration count is within +-2 of the oracle's, the true FP64 residual meets
-    1e-8, and the solution agrees with the oracle's to 1e-6 of each block
-    segment's largest entry."""
+    FGMRES; with autotune = 1 the level layouts it times at setup, as the
+    benchmark builds them): the hierarchies are the oracle's (the setup is
+    FP64), the iteration count is within +-2 of the oracle's, the true FP64
+    residual meets 1e-8, and the solution agrees with the oracle's to 1e-6 of
+    each block segment's largest entry."""
     api = gpu_modules()
     inp, osys, co, gsys = workload(ctx, "g20_3d64")
     meta, arrays = golden("g20_3d64")
     case = meta["cases"]["schur2"]
     M = api.BlockPreconditioner(ctx, gsys, "schur2", amg_seed=4, amg_precision=1, batched=1,
-                                use_graph=1)
+                                use_graph=1, amg_autotune=autotune)
     assert_precond_hierarchies(M, case, inp.G)
     x, r = api.gmres(ctx, gsys, M, to_dev(ctx, inp.b), rtol=1e-8, flexible=1)
     assert r.converged and abs(r.iters - case["gmres"]["iters"]) <= 2, r.iters
