@@ -962,6 +962,82 @@ def test_context_memory_comes_from_torch_allocator(ctx):
 # ---------------------------------------------------------------------------
 # persistent tail of the batched V-cycle
 # ---------------------------------------------------------------------------
+def _fp32_solve_outputs(api, c, A, gsys, inp, b, r):
+    """V-cycles of a sliced FP32 hierarchy, two graph replays of a batched
+    Schur2 apply and an FGMRES solve, on context c."""
+    import torch
+    g = api.AMG(c, A.indptr, A.indices, A.data, seed=1, precision=1)
+    M = api.BlockPreconditioner(c, gsys, "schur2", amg_seed=5, batched=1, use_graph=1,
+                                amg_precision=1)
+    v3 = to_host(g.apply(to_dev(c, b), cycles=3))
+    z = [to_host(M.apply(r)) for _ in range(2)]
+    torch.cuda.synchronize()
+    x, res = api.gmres(c, gsys, M, to_dev(c, inp.b), rtol=1e-9, flexible=1)
+    out = (v3, z, to_host(x), res.iters)
+    g.close()
+    M.close()
+    return out
+
+
+def test_chiplet_row_shares_leave_results_unchanged(monkeypatch):
+    """MGD_XCD_ROWS=1 (set when a context is created) hands each chiplet a
+    contiguous share of the rows of every level kernel: only the workgroup
+    that handles a row changes, so V-cycles, applies and the solve are the
+    same bit for bit (sliced layouts forced on a small system)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    api = gpu_modules()
+    monkeypatch.setenv("MGD_SELL_MIN_ROWS", "256")
+    A = oracle_system(si.generate_workload("g1_2d64")).monolithic()
+    inp = si.generate(3, 2, 24, 41)
+    b = np.random.default_rng(2).uniform(size=A.shape[0])
+    out = {}
+    try:
+        for mode in ("0", "1"):
+            monkeypatch.setenv("MGD_XCD_ROWS", mode)
+            c = api.Context(0)
+            co, gsys = gpu_system(c, inp)
+            r = to_dev(c, np.random.default_rng(4).standard_normal(gsys.n))
+            out[mode] = _fp32_solve_outputs(api, c, A, gsys, inp, b, r)
+            gsys.close()
+            c.close()
+    finally:
+        monkeypatch.delenv("MGD_XCD_ROWS", raising=False)
+        api.Context(0).close()  # the device constant back to the default
+    (a3, az, ax, ai), (b3, bz, bx, bi) = out["0"], out["1"]
+    assert np.array_equal(a3, b3)
+    assert np.array_equal(az[0], bz[0]) and np.array_equal(az[1], bz[1])
+    assert ai == bi and np.array_equal(ax, bx)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_step_overlap_switch_leaves_solve_unchanged(ctx, monkeypatch, precision):
+    """A Schur2 GMRES step splits its block matvec so that the part without
+    z_E runs beside the last E solve, and a finishing kernel adds the rest in
+    the order of the one-kernel matvec: with MGD_STEP_OVERLAP=0 (one kernel
+    after the apply) the solve is the same bit for bit, with graph replay
+    and without."""
+    api = gpu_modules()
+    inp = si.generate(3, 2, 24, 61)
+    co, gsys = gpu_system(ctx, inp)
+    b = to_dev(ctx, inp.b)
+    out = {}
+    for ov in ("1", "0"):
+        monkeypatch.setenv("MGD_STEP_OVERLAP", ov)
+        for graph in (0, 1):
+            M = api.BlockPreconditioner(ctx, gsys, "schur2", amg_seed=6, batched=1,
+                                        use_graph=graph, amg_precision=precision)
+            x, r = api.gmres(ctx, gsys, M, b, rtol=1e-9, flexible=1)
+            assert r.converged
+            out[(ov, graph)] = (to_host(x), r.iters)
+            M.close()
+    ref = out[("1", 1)]
+    for k, v in out.items():
+        assert v[1] == ref[1] and np.array_equal(v[0], ref[0]), k
+
+
+# ---------------------------------------------------------------------------
 @pytest.mark.parametrize("blocks", ["3", "256"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_persistent_tail_matches_level_launches(ctx, monkeypatch, precision, blocks):
