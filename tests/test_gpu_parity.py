@@ -1099,6 +1099,49 @@ np.save(sys.argv[2], z)
 """
 
 
+_DEBUG_UNION_CHILD = r"""
+import sys, numpy as np, torch
+sys.path.insert(0, sys.argv[1])
+import synth_inputs as si
+from paper_2002_04958_amd import api
+inp = si.generate(3, 2, 24, 41)
+ctx = api.Context(0)
+co = api.Coeffs.from_inputs(ctx, inp)
+sysg = api.BlockSystem.assemble(ctx, co)
+M = api.BlockPreconditioner(ctx, sysg, "schur2", amg_seed=5, batched=1, use_graph=0,
+                            amg_precision=1)
+r = torch.as_tensor(np.random.default_rng(4).standard_normal(sysg.n), device=ctx.device)
+np.save(sys.argv[2], M.apply(r).cpu().numpy())
+"""
+
+
+def test_debug_union_verification_passes(ctx, monkeypatch, tmp_path):
+    """MGD_DEBUG_UNION=1 (read once per process) verifies every level of every
+    union on the host while it is built: the stored-row map is a permutation
+    and every copied row equals its source row.  A child process builds a
+    batched FP32 Schur2 preconditioner with sliced layouts that way, and its
+    apply equals this process's bit for bit."""
+    import os
+    import subprocess
+    import sys
+    api = gpu_modules()
+    monkeypatch.setenv("MGD_SELL_MIN_ROWS", "256")
+    inp = si.generate(3, 2, 24, 41)
+    co, gsys = gpu_system(ctx, inp)
+    M = api.BlockPreconditioner(ctx, gsys, "schur2", amg_seed=5, batched=1, use_graph=0,
+                                amg_precision=1)
+    r = to_dev(ctx, np.random.default_rng(4).standard_normal(gsys.n))
+    z = to_host(M.apply(r))
+    M.close()
+    out = tmp_path / "child.npy"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, MGD_DEBUG_UNION="1")
+    p = subprocess.run([sys.executable, "-c", _DEBUG_UNION_CHILD, root, str(out)],
+                       capture_output=True, text=True, timeout=240, env=env)
+    assert p.returncode == 0, p.stderr[-2000:]
+    assert np.array_equal(np.load(out), z)
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_autotune_layouts_and_cache(ctx, monkeypatch, tmp_path, precision):
     """autotune = 1 times every level matrix's layouts (SELL, CSR with 1-32
