@@ -11,12 +11,17 @@ the GPU path; both consume the arrays drawn by ``synth_inputs``.
 
 Modules
   assemble  block system of eq. 2.2 from per-cell coefficients
-  amg       classical AMG: strength, PMIS, modified classical interpolation,
-            Galerkin coarse operators, CF-l1-Jacobi V(1,1) cycle
+  amg       classical AMG: strength, PMIS and HMIS, modified classical
+            interpolation, aggressive coarsening with multipass
+            interpolation, Galerkin coarse operators, CF-l1-Jacobi and
+            multicolour Gauss-Seidel V(1,1) cycles
   interp.c  the modified classical interpolation as a plain loop over rows
             (built by ``cext`` with gcc, loaded with ctypes)
+  cext      builds and loads interp.c
   precond   monolithic AMG, block-diagonal, PCTL (Sec. 3.2), Schur1/Schur2
-            (Sec. 3.3) with the diagonal approximations of Sec. 3.4
+            (Sec. 3.3) with the diagonal approximations of Sec. 3.4, inner
+            solves to a tolerance and option #4 (Sec. 3.4)
+  adaptive  Definitions 1 and 2 and the preconditioners they select (Sec. 3.5)
   krylov    restarted right-preconditioned (flexible) GMRES(m)
   adjoint   transposed-system solve and coefficient gradients
 
