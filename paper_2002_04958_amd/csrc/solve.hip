@@ -1103,7 +1103,8 @@ __global__ void __launch_bounds__(256) k_dense(const DenseDev* __restrict__ tab,
                                                const T* __restrict__ b, T* __restrict__ X) {
   __shared__ double part[4][64];
   const DenseDev d = tab[blockIdx.y];
-  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // the wave: a scalar
   const int i = blockIdx.x * 64 + lane;
   const int quarter = (d.n + 3) / 4;
   const int j0 = min(d.n, q * quarter), j1 = min(d.n, j0 + quarter);
@@ -1111,18 +1112,20 @@ __global__ void __launch_bounds__(256) k_dense(const DenseDev* __restrict__ tab,
   if (i < d.n) {
     const double* __restrict__ col = d.inv + i;
     const T* __restrict__ bb = b + d.off;
-    int j = j0;
-    for (; j + 8 <= j1; j += 8) {
+    // eight columns at a time, the last batch cut at j1 (a scalar, like j0:
+    // the branches are uniform); the sum in column order
+    for (int j = j0; j < j1; j += 8) {
       double a[8], x[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        a[k] = col[(size_t)(j + k) * d.n];
-        x[k] = (double)bb[j + k];
-      }
+      for (int k = 0; k < 8; ++k)
+        if (j + k < j1) {
+          a[k] = col[(size_t)(j + k) * d.n];
+          x[k] = (double)bb[j + k];
+        }
 #pragma unroll
-      for (int k = 0; k < 8; ++k) s += a[k] * x[k];
+      for (int k = 0; k < 8; ++k)
+        if (j + k < j1) s += a[k] * x[k];
     }
-    for (; j < j1; ++j) s += col[(size_t)j * d.n] * (double)bb[j];
   }
   part[q][lane] = s;
   __syncthreads();
