@@ -44,7 +44,7 @@ from oracle import precond as opc  # noqa: E402
 
 # workload -> preconditioner kinds (FP64 throughout; the AMG seed is the workload seed)
 CASES = {
-    "g20_3d64": ["schur2"],
+    "g20_3d64": ["schur2", "schur1", "pctl"],
     "g20_2d256": ["bdiag"],
     "g1_2d1024": ["amg", "pctl", "schur2_lower", "schur1", "schur2"],
     "g20_2d512": ["schur2", "adjoint_schur2"],

@@ -205,6 +205,15 @@ def test_g20_3d64_schur2_fp64_batched_graph_against_oracle(ctx):
     fp64_solve_checks(ctx, "g20_3d64", "schur2", 4, batched=True, graph=True)
 
 
+@pytest.mark.parametrize("kind", ["schur1", "pctl"])
+def test_g20_3d64_other_kinds_against_oracle(ctx, kind):
+    """Schur1 (eq. 3.2, with C^_E, C^_g) and PCTL (Section 3.2, eq. 3.1) at the
+    headline size: hierarchies as the oracle's (PCTL's A_c in structure, with
+    equal p-vector cycle counts), the FGMRES iteration count +-1 of the
+    oracle's, the same-iteration solution to 1e-10."""
+    fp64_solve_checks(ctx, "g20_3d64", kind, 4, batched=True, graph=True)
+
+
 @pytest.mark.parametrize("autotune", [0, 1])
 def test_g20_3d64_schur2_fp32_batched_against_oracle(ctx, autotune):
     """The benchmark's form (FP32 hierarchies, batched, graph-replayed, FP64
