@@ -237,6 +237,26 @@ def test_g20_3d64_schur2_fp32_batched_against_oracle(ctx, autotune):
                             "FP32 batched solution against the oracle")
 
 
+@pytest.mark.parametrize("kind", ["schur1", "pctl"])
+def test_g20_3d64_fp32_batched_other_kinds_against_oracle(ctx, kind):
+    """Schur1 and PCTL in the benchmark's form (FP32 hierarchies, batched,
+    graph-replayed, FP64 FGMRES): the iteration count within +-2 of the
+    oracle's, the true FP64 residual meets 1e-8, the solution agrees with
+    the oracle's to 1e-6 of each block segment's largest entry."""
+    api = gpu_modules()
+    inp, osys, co, gsys = workload(ctx, "g20_3d64")
+    meta, arrays = golden("g20_3d64")
+    case = meta["cases"][kind]
+    M = api.BlockPreconditioner(ctx, gsys, kind, amg_seed=4, amg_precision=1, batched=1,
+                                use_graph=1)
+    x, r = api.gmres(ctx, gsys, M, to_dev(ctx, inp.b), rtol=1e-8, flexible=1)
+    assert r.converged and abs(r.iters - case["gmres"]["iters"]) <= 2, (kind, r.iters)
+    xh = to_host(x)
+    assert true_relres(osys, xh, inp.b) <= 1e-8 * (1 + 1e-6)
+    assert_solution_matches(xh, case, arrays, f"{kind}/x", inp.G, inp.N, FP32_SOLUTION_TOL, 1.0,
+                            f"FP32 batched {kind} solution against the oracle")
+
+
 @pytest.mark.parametrize("aggressive", [0, 1])
 def test_g20_3d64_E_block_hierarchy_and_vcycle(ctx, aggressive):
     """The whole AMG hierarchy of A_E (262,144 rows) equals the oracle's bit for
