@@ -168,7 +168,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the adaptive, option #4, aggressive and inner-tolerance variants")
+                    help="skip Schur1, PCTL and lower Schur2 in the benchmark's form, and the "
+                         "adaptive, option #4, aggressive and inner-tolerance variants of Schur2")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the 2D 1024^2, 2D 256^2 and 2D 512^2 workloads")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
@@ -275,14 +276,20 @@ def main():
         forms["ratios_vs_fp64_plain"] = {k: p / v["ms"] for k, v in forms.items()
                                          if isinstance(v, dict) and "ms" in v}
 
-    # the adaptive, option #4, aggressive and inner-tolerance variants (Sections 3.4, 3.5)
+    # the other block preconditioners of Sections 3.2-3.3 in the same form, and
+    # the adaptive, option #4, aggressive and inner-tolerance variants of Schur2
+    # (Sections 3.4, 3.5)
     variants = {}
     if not a.no_variants:
-        for key, kw, graph in (("alpha_schur2", dict(adaptive=1), True),
-                               ("option4_2steps", dict(option4_steps=2), True),
-                               ("aggressive_finest", dict(amg_aggressive_levels=1), True),
-                               ("inner_tol_1e-2", dict(inner_tol=1e-2), False)):
-            M, su = build(sysg, "schur2", w.seed, True, True, graph, **kw)
+        for key, kind, kw, graph in (("schur1", "schur1", {}, True),
+                                     ("pctl", "pctl", {}, True),
+                                     ("schur2_lower", "schur2_lower", {}, True),
+                                     ("alpha_schur2", "schur2", dict(adaptive=1), True),
+                                     ("option4_2steps", "schur2", dict(option4_steps=2), True),
+                                     ("aggressive_finest", "schur2", dict(amg_aggressive_levels=1),
+                                      True),
+                                     ("inner_tol_1e-2", "schur2", dict(inner_tol=1e-2), False)):
+            M, su = build(sysg, kind, w.seed, True, True, graph, **kw)
             steps = 1 if key.startswith("inner") else a.form_steps
             ms, it, xv, rv = timed(sysg, M, b, steps)
             rr = float(torch.linalg.vector_norm(b - sysg.matvec(xv))) / bnorm
