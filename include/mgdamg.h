@@ -128,14 +128,17 @@ typedef struct amg_params {
   int32_t n_pre, n_post;  /* 1, 1 */
   int32_t precision;      /* 0: FP64 solve phase; 1: FP32 matrices and vectors
                              (coarsest solve stays FP64) */
-  int32_t autotune;       /* 1: time the residual kernel of every level matrix in each
-                             candidate layout (sliced ELL; CSR with 1-32 lanes per row;
-                             64, 128 or 256 threads per workgroup), keep the fastest unless
-                             the default layout is within 3% of it, and cache the choice
-                             per (rows, nnz, longest row) in the process and, when the
-                             environment names one, in the file MGD_AUTOTUNE_CACHE.  The
-                             layout changes which lanes add a row's entries, so results
-                             may differ from the default layouts' in rounding. */
+  int32_t autotune;       /* 1: time the residual kernel of every level matrix, and the
+                             restriction kernel of every restriction, of at least 131072
+                             rows in each candidate layout (sliced ELL; CSR with 1-32
+                             lanes per row; 64, 128 or 256 threads per workgroup), keep
+                             the fastest unless the default layout is within 3% of it,
+                             and cache the choice per (role, rows, nnz, longest row) in
+                             the process and, when the environment names one, in the
+                             file MGD_AUTOTUNE_CACHE; smaller matrices keep the default
+                             layouts.  The layout changes which lanes add a row's
+                             entries, so results may differ from the default layouts'
+                             in rounding. */
   int32_t coarsening;     /* 0: PMIS; 1: HMIS (Ruge-Stueben first pass inside tiles of
                              hmis_tile consecutive rows, then PMIS for the rest) */
   int32_t hmis_tile;      /* 1024, in [1, 1024] */

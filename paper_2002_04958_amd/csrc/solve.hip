@@ -1988,9 +1988,10 @@ static std::mutex g_tune_mu;
 static std::map<std::string, int> g_tune;
 static bool g_tune_loaded = false;
 
-static std::string tune_key(long long rows, long long nnz, int maxrow, bool fp32) {
+static std::string tune_key(long long rows, long long nnz, int maxrow, bool fp32,
+                            const char* kind) {
   std::ostringstream o;
-  o << (fp32 ? "f32:" : "f64:") << rows << ":" << nnz << ":" << maxrow;
+  o << (fp32 ? "f32:" : "f64:") << kind << rows << ":" << nnz << ":" << maxrow;
   return o.str();
 }
 static void tune_load_locked() {
@@ -2025,16 +2026,17 @@ static void tune_save_locked() {
   }
   f << "\n}\n";
 }
-int autotune_lookup(long long rows, long long nnz, int maxrow, bool fp32) {
+int autotune_lookup(long long rows, long long nnz, int maxrow, bool fp32, const char* kind) {
   std::lock_guard<std::mutex> g(g_tune_mu);
   tune_load_locked();
-  auto it = g_tune.find(tune_key(rows, nnz, maxrow, fp32));
+  auto it = g_tune.find(tune_key(rows, nnz, maxrow, fp32, kind));
   return it == g_tune.end() ? 0 : it->second;
 }
-void autotune_store(long long rows, long long nnz, int maxrow, bool fp32, int tpr) {
+void autotune_store(long long rows, long long nnz, int maxrow, bool fp32, int tpr,
+                    const char* kind) {
   std::lock_guard<std::mutex> g(g_tune_mu);
   tune_load_locked();
-  g_tune[tune_key(rows, nnz, maxrow, fp32)] = tpr;
+  g_tune[tune_key(rows, nnz, maxrow, fp32, kind)] = tpr;
   tune_save_locked();
 }
 
@@ -2235,6 +2237,9 @@ static long long sell_stored(Ctx* c, const Csr<double>& M) {
 
 template <typename T>
 static void tune_layout(Ctx* c, ULevel<T>& lv, const Csr<double>& A, int autotune, bool fp32);
+template <typename T>
+static void tune_restrict(Ctx* c, const ULevel<T>& lv, int nS, int nC, int nCn,
+                          const Csr<double>& Wt, LMat<T>& out, int autotune, bool fp32);
 
 constexpr long long kFillLanes = 1 << 17;  // lanes that keep all compute units busy
 constexpr int kSellMinRows = 1 << 17;
@@ -2244,6 +2249,15 @@ constexpr int kSellMinRows = 1 << 17;
 static long long sell_min_rows() {
   const char* e = std::getenv("MGD_SELL_MIN_ROWS");
   return e && *e ? std::max(1LL, std::atoll(e)) : (long long)kSellMinRows;
+}
+// Matrices with fewer rows keep the default layout rule: their launches are
+// latency bound, and timing them back to back with their data in cache does
+// not rank the layouts as their launches inside a cycle do.  MGD_TUNE_MIN_ROWS
+// (tests) lowers the bound.
+constexpr int kTuneMinRows = 1 << 17;
+static long long tune_min_rows() {
+  const char* e = std::getenv("MGD_TUNE_MIN_ROWS");
+  return e && *e ? std::max(1LL, std::atoll(e)) : (long long)kTuneMinRows;
 }
 static bool sell16_enabled() {
   const char* e = std::getenv("MGD_SELL16");
@@ -2256,15 +2270,21 @@ static int small_level_tpr(long long rows, double avg) {
   return t;
 }
 // interpolation / restriction layout: SELL for large matrices with little
-// padding, otherwise CSR with enough lanes per row
+// padding (sell_entries: the SELL layout's stored entries), otherwise CSR with
+// enough lanes per row; the result is kTuneSell (1000) or the lanes per row
+static int transfer_default(const Csr<double>& M, long long sell_entries) {
+  const double avg = M.n_rows ? (double)M.nnz / M.n_rows : 1.0;
+  if (M.nnz > 0 && M.n_rows >= sell_min_rows() && sell_entries <= (long long)(1.5 * M.nnz))
+    return 1000;
+  return std::max(small_level_tpr(M.n_rows, avg), default_tpr(avg));
+}
 template <typename T>
 static void layout_transfer(Ctx* c, const Csr<double>& M, LMat<T>& out, int split16) {
-  const double avg = M.n_rows ? (double)M.nnz / M.n_rows : 1.0;
-  if (M.nnz > 0 && M.n_rows >= sell_min_rows() && sell_stored(c, M) <= (long long)(1.5 * M.nnz))
+  const int d = transfer_default(M, M.nnz > 0 && M.n_rows >= sell_min_rows() ? sell_stored(c, M) : 0);
+  if (d == 1000)
     to_layout<T>(c, M, kFmtSELL, 1, false, out, sell16_enabled() ? split16 : -1);
   else
-    to_layout<T>(c, M, kFmtCSR, std::max(small_level_tpr(M.n_rows, avg), default_tpr(avg)), false,
-                 out);
+    to_layout<T>(c, M, kFmtCSR, d, false, out);
 }
 
 template <typename T>
@@ -2396,7 +2416,7 @@ static void finalize_levels(Ctx* c, std::vector<BuildLevel<T>>& bl, Union<T>& U,
       // W gathers from three regions of the next level: 32-bit columns;
       // W^T's columns are F indices, one region
       layout_transfer<T>(c, b.W, lv.W, -1);
-      layout_transfer<T>(c, Wt2, lv.Wt, 0);
+      tune_restrict<T>(c, lv, b.nS, b.nC, nb.nC, Wt2, lv.Wt, autotune, sizeof(T) == 4);
     }
     c->check_device_errors("stored-order level");
     tune_layout<T>(c, lv, b.A, autotune, sizeof(T) == 4);
@@ -2427,22 +2447,85 @@ static void finalize_levels(Ctx* c, std::vector<BuildLevel<T>>& bl, Union<T>& U,
 // = threads / lanes per row; 64-row slices for SELL): the best of three runs
 // of back-to-back launches (enough launches for about 0.2 ms per run), and
 // keeps the fastest unless the default layout is within kTuneMargin of it, so
-// that timing noise does not pick the layout.
+// that timing noise does not pick the layout.  A restriction W^T is tuned the
+// same way with the restriction kernel (its own cache entries).  Only matrices
+// of at least tune_min_rows() rows are timed.
 constexpr int kTuneSell = 1000;
 constexpr int kTuneBsUnit = 100000;
 constexpr double kTuneMargin = 1.03;
+
+static int max_row_len(Ctx* c, int rows, const int* rp) {
+  DBuf<int> mr(c, 1);
+  fill<int>(c, mr.get(), 0, 1);
+  if (rows > 0) {
+    hipLaunchKernelGGL(k_max_row, dim3(cdiv(rows, 256)), dim3(256), 0, c->stream, rows, rp,
+                       mr.get());
+    MGD_CHECK_LAUNCH();
+  }
+  return read1(c, mr.get());
+}
+// candidate layouts: SELL while its padding stays within 2x, CSR with 1 lane
+// and with up to twice the mean row length in lanes, and the default
+static std::vector<int> tune_layouts(long long sell_entries, long long nnz, double avg, int dflt) {
+  std::vector<int> layouts;
+  if (sell_entries <= 2 * nnz) layouts.push_back(kTuneSell);
+  for (int t : {1, 2, 4, 8, 16, 32})
+    if (t == 1 || t <= 2 * std::max(avg, 1.0)) layouts.push_back(t);
+  if (std::find(layouts.begin(), layouts.end(), dflt) == layouts.end()) layouts.push_back(dflt);
+  return layouts;
+}
+// the timed choice among layouts x {64, 128, 256} threads: apply(value) sets a
+// layout up, run() launches the kernel once on it; reps launches per run
+template <typename Apply, typename Run>
+static int tune_pick(Ctx* c, const std::vector<int>& layouts, int dflt, int reps,
+                     const Apply& apply, const Run& run) {
+  hipEvent_t e0, e1;
+  MGD_HIP(hipEventCreate(&e0));
+  MGD_HIP(hipEventCreate(&e1));
+  const int dflt_value = dflt + 4 * kTuneBsUnit;  // the default layout, 256 threads
+  float best = 1e30f, t_dflt = 1e30f;
+  int bt = dflt_value;
+  const bool prof = c->profiling;
+  c->profiling = false;
+  for (int code : layouts)
+    for (int bs : {64, 128, 256}) {
+      const int cand = code + (bs / 64) * kTuneBsUnit;
+      apply(cand);
+      run();
+      float ms = 1e30f;
+      for (int trial = 0; trial < 3; ++trial) {
+        MGD_HIP(hipEventRecord(e0, c->stream));
+        for (int rep = 0; rep < reps; ++rep) run();
+        MGD_HIP(hipEventRecord(e1, c->stream));
+        MGD_HIP(hipEventSynchronize(e1));
+        float t = 0;
+        MGD_HIP(hipEventElapsedTime(&t, e0, e1));
+        ms = std::min(ms, t);
+      }
+      if (cand == dflt_value) t_dflt = ms;
+      if (ms < best) {
+        best = ms;
+        bt = cand;
+      }
+    }
+  if (t_dflt <= best * kTuneMargin) bt = dflt_value;
+  c->profiling = prof;
+  MGD_HIP(hipEventDestroy(e0));
+  MGD_HIP(hipEventDestroy(e1));
+  return bt;
+}
+// launches per timed run: about 0.2 ms of work at 5 TB/s, 4 to 64 launches
+static int tune_reps(double bytes) {
+  return (int)std::min(64.0, std::max(4.0, 1e9 / std::max(bytes, 1.0)));
+}
+
 template <typename T>
 static void tune_layout(Ctx* c, ULevel<T>& lv, const Csr<double>& A, int autotune, bool fp32) {
   if (lv.nS == 0) {
     to_layout<T>(c, A, kFmtCSR, 1, true, lv.A);
     return;
   }
-  DBuf<int> mr(c, 1);
-  fill<int>(c, mr.get(), 0, 1);
-  hipLaunchKernelGGL(k_max_row, dim3(cdiv(lv.nS, 256)), dim3(256), 0, c->stream, lv.nS,
-                     (const int*)A.rp.get(), mr.get());
-  MGD_CHECK_LAUNCH();
-  const int maxrow = read1(c, mr.get());
+  const int maxrow = max_row_len(c, lv.nS, A.rp.get());
   const double avg = (double)A.nnz / lv.nS;
   const long long st = sell_stored(c, A);
   auto apply = [&](int value) {
@@ -2463,58 +2546,70 @@ static void tune_layout(Ctx* c, ULevel<T>& lv, const Csr<double>& A, int autotun
   const int dflt = (lv.nS >= sell_min_rows() && st <= (long long)(1.3 * A.nnz))
                        ? kTuneSell
                        : std::max(small_level_tpr(lv.nS, avg), default_tpr(avg));
-  if (!autotune) {
+  if (!autotune || lv.nS < tune_min_rows()) {
     apply(dflt);
     return;
   }
-  std::vector<int> cands;
-  std::vector<int> layouts;
-  if (st <= 2 * A.nnz) layouts.push_back(kTuneSell);
-  for (int t : {1, 2, 4, 8, 16, 32})
-    if (t == 1 || t <= 2 * std::max(avg, 1.0)) layouts.push_back(t);
-  if (std::find(layouts.begin(), layouts.end(), dflt) == layouts.end()) layouts.push_back(dflt);
-  for (int code : layouts)
-    for (int bs : {64, 128, 256}) cands.push_back(code + (bs / 64) * kTuneBsUnit);
   DBuf<T> x(c, (size_t)std::max(lv.nX, 1)), bb(c, (size_t)lv.nS), r(c, (size_t)lv.nS);
   fill<T>(c, x.get(), (T)1, (size_t)std::max(lv.nX, 1));
   fill<T>(c, bb.get(), (T)1, (size_t)lv.nS);
-  hipEvent_t e0, e1;
-  MGD_HIP(hipEventCreate(&e0));
-  MGD_HIP(hipEventCreate(&e1));
-  float best = 1e30f, t_dflt = 1e30f;
-  int bt = dflt;
-  const bool prof = c->profiling;
-  c->profiling = false;
-  // launches per timed run: about 0.2 ms of work at 5 TB/s, 4 to 64 launches
-  const double level_bytes = (double)A.nnz * (sizeof(T) + 4) + 4.0 * sizeof(T) * lv.nS;
-  const int reps = (int)std::min(64.0, std::max(4.0, 1e9 / std::max(level_bytes, 1.0)));
-  for (int cand : cands) {
-    apply(cand);
-    const auto g = gather_cf<T>(x.get(), x.get(), lv.nC);
-    ResidL<T> run{c, lv.A, lv.nS, bb.get(), g, r.get()};
-    with_layout(lv.A.fmt, lv.A.tpr, run);
-    float ms = 1e30f;
-    for (int trial = 0; trial < 3; ++trial) {
-      MGD_HIP(hipEventRecord(e0, c->stream));
-      for (int rep = 0; rep < reps; ++rep) with_layout(lv.A.fmt, lv.A.tpr, run);
-      MGD_HIP(hipEventRecord(e1, c->stream));
-      MGD_HIP(hipEventSynchronize(e1));
-      float t = 0;
-      MGD_HIP(hipEventElapsedTime(&t, e0, e1));
-      ms = std::min(ms, t);
-    }
-    if (cand % kTuneBsUnit == dflt && cand / kTuneBsUnit == 4) t_dflt = ms;  // 256 threads
-    if (ms < best) {
-      best = ms;
-      bt = cand;
-    }
-  }
-  if (t_dflt <= best * kTuneMargin) bt = dflt + 4 * kTuneBsUnit;  // the default, 256 threads
-  c->profiling = prof;
-  MGD_HIP(hipEventDestroy(e0));
-  MGD_HIP(hipEventDestroy(e1));
+  const auto g = gather_cf<T>(x.get(), x.get(), lv.nC);
+  auto run = [&]() {
+    ResidL<T> launch{c, lv.A, lv.nS, bb.get(), g, r.get()};
+    with_layout(lv.A.fmt, lv.A.tpr, launch);
+  };
+  const int reps = tune_reps((double)A.nnz * (sizeof(T) + 4) + 4.0 * sizeof(T) * lv.nS);
+  const int bt = tune_pick(c, tune_layouts(st, A.nnz, avg, dflt), dflt, reps, apply, run);
   apply(bt);
   autotune_store(lv.nS, A.nnz, maxrow, fp32, bt);
+}
+
+// Layout of the restriction W^T of level l (rows: level l+1 in its extended
+// order, columns: level l's F-block), chosen like a level matrix's with the
+// restriction kernel timed into scratch vectors of the two levels' sizes
+// (cpos, the C-block position of each coarse row, is the level's own).
+template <typename T>
+static void tune_restrict(Ctx* c, const ULevel<T>& lv, int nS, int nC, int nCn,
+                          const Csr<double>& Wt, LMat<T>& out, int autotune, bool fp32) {
+  if (Wt.n_rows == 0 || Wt.nnz == 0) {
+    layout_transfer<T>(c, Wt, out, 0);
+    return;
+  }
+  const int maxrow = max_row_len(c, Wt.n_rows, Wt.rp.get());
+  auto apply = [&](int value) {
+    const int code = value % kTuneBsUnit, units = value / kTuneBsUnit;
+    if (code == kTuneSell)
+      to_layout<T>(c, Wt, kFmtSELL, 1, false, out, sell16_enabled() ? 0 : -1);
+    else
+      to_layout<T>(c, Wt, kFmtCSR, code, false, out);
+    out.bs = units ? 64 * units : 256;
+  };
+  const int cached = autotune_lookup(Wt.n_rows, Wt.nnz, maxrow, fp32, "wt:");
+  if (cached > 0) {
+    apply(cached);
+    return;
+  }
+  if (!autotune || Wt.n_rows < tune_min_rows()) {
+    layout_transfer<T>(c, Wt, out, 0);
+    return;
+  }
+  const double avg = (double)Wt.nnz / Wt.n_rows;
+  const long long st = sell_stored(c, Wt);
+  const int dflt = transfer_default(Wt, st);
+  const int nXn = Wt.n_rows;
+  DBuf<T> R(c, (size_t)std::max(nS, 1)), dn(c, (size_t)std::max(nCn, 1));
+  DBuf<T> Bn(c, (size_t)nXn), XCn(c, (size_t)std::max(nCn, 1));
+  fill<T>(c, R.get(), (T)1, (size_t)std::max(nS, 1));
+  fill<T>(c, dn.get(), (T)1, (size_t)std::max(nCn, 1));
+  auto run = [&]() {
+    RestrictL<T> launch{c, out, nXn, nC, nCn, lv.cpos.get(), R.get(), dn.get(), Bn.get(),
+                        XCn.get(), true};
+    with_layout(out.fmt, out.tpr, launch);
+  };
+  const int reps = tune_reps((double)Wt.nnz * (sizeof(T) + 4) + 3.0 * sizeof(T) * nXn);
+  const int bt = tune_pick(c, tune_layouts(st, Wt.nnz, avg, dflt), dflt, reps, apply, run);
+  apply(bt);
+  autotune_store(Wt.n_rows, Wt.nnz, maxrow, fp32, bt, "wt:");
 }
 
 template struct Union<double>;

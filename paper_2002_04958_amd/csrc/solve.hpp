@@ -159,12 +159,14 @@ template <typename T>
 std::unique_ptr<Union<T>> build_union(Ctx* c, const std::vector<const SetupHierarchy*>& members,
                                       int n_pre, int n_post, int autotune, int smoother);
 
-// Tuned row-group widths, keyed by (rows, nnz, max row length); persisted to
-// the JSON file named by MGD_AUTOTUNE_CACHE when set.
-int autotune_lookup(long long rows, long long nnz, int maxrow, bool fp32);
+// Tuned layouts, keyed by the matrix's role (kind: "" a level matrix, "wt:" a
+// restriction) and (rows, nnz, max row length); persisted to the JSON file
+// named by MGD_AUTOTUNE_CACHE when set.
+int autotune_lookup(long long rows, long long nnz, int maxrow, bool fp32, const char* kind = "");
 // Level kernels' row ranges per workgroup: contiguous shares per chiplet (1)
 // or in dispatch order (0) for every device kernel launched afterwards.
 void set_xcd_rows(int on);
-void autotune_store(long long rows, long long nnz, int maxrow, bool fp32, int tpr);
+void autotune_store(long long rows, long long nnz, int maxrow, bool fp32, int tpr,
+                    const char* kind = "");
 
 }  // namespace mgd
