@@ -104,6 +104,44 @@ __global__ void k_group_out(int N, int nm, const SegOut* __restrict__ tab, const
   if (SUM) sT[i] = (T)s;
 }
 
+// the same from a union's result left in stored order: member m's row i read
+// at its stored position (C, F or dense region), the arithmetic unchanged
+template <typename T, bool SUM>
+__global__ void k_group_out_st(int N, int nm, const SegOut* __restrict__ tab, StoredOut<T> so,
+                               double* __restrict__ z, T* __restrict__ sT) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double s = 0.0;
+  for (int m0 = 0; m0 < nm; m0 += 4) {
+    int k[4];
+    double x[4], cf[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (m0 + q < nm) {
+        const SegOut d = tab[m0 + q];
+        k[q] = so.iperm[(size_t)(m0 + q) * N + i];
+        cf[q] = (SUM && d.coef) ? d.coef[i] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (m0 + q < nm) {
+        const T* src = k[q] < so.nC ? so.xc : (k[q] < so.nS ? so.xf : so.xd);
+        x[q] = (double)src[k[q]];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (m0 + q < nm) {
+        const SegOut d = tab[m0 + q];
+        z[(size_t)d.seg * N + i] = x[q];
+        if (SUM && d.coef) s = s + cf[q] * x[q];
+      }
+    }
+  }
+  if (SUM) sT[i] = (T)s;
+}
+
 // out = (T)(a - coef o w)   (coef may be null)
 template <typename T, typename W>
 __global__ void k_single_in(int N, const double* __restrict__ a, const double* __restrict__ coef,
@@ -833,17 +871,38 @@ static void apply_impl(block_precond* bp, PcExec<T>& X, const double* r, double*
     MGD_CHECK_LAUNCH();
   };
   // group_in, then the group's inverses; a batched group of V-cycle members
-  // with one cycle each forms its inputs in the union's entry kernel instead
+  // with one cycle each forms its inputs in the union's entry kernel instead,
+  // and (CF-l1-Jacobi, MGD_STORED_OUT not 0) leaves its result in stored
+  // order for group_out to read
+  bool grp_stored = false;
   auto group_solve = [&](const T* w) {
+    grp_stored = false;
     if (!grp.tol && grp.cycles == 1 && grp.batched && grp.n_amg == nm) {
-      grp.batched->apply_seg(c, N, (const SegIn*)grp.in_tab.get(), r, w, grp.out.get());
+      const char* so = std::getenv("MGD_STORED_OUT");
+      grp_stored = !grp.batched->gs && grp.batched->tail_from != 0 && !(so && so[0] == '0');
+      grp.batched->apply_seg(c, N, (const SegIn*)grp.in_tab.get(), r, w,
+                             grp_stored ? nullptr : grp.out.get());
       return;
     }
     group_in(w);
     run_group(bp, grp);
   };
   auto group_out = [&](bool sum, T* sT) {
-    ProfScope ps(c, KC_VEC, (double)nm * N * (sizeof(T) + 8 + (sum ? 8 : 0)));
+    if (grp_stored) {
+      ProfScope ps(c, KC_VEC, (double)nm * N * (4 + sizeof(T) + 8 + (sum ? 8 : 0)),
+                   ksym(c, "k_group_out_st", {type_name<T>(), sum ? "true" : "false"}));
+      const StoredOut<T> so = grp.batched->stored_out();
+      if (sum)
+        hipLaunchKernelGGL((k_group_out_st<T, true>), g1, b1, 0, c->stream, N, nm,
+                           (const SegOut*)grp.out_tab.get(), so, z, sT);
+      else
+        hipLaunchKernelGGL((k_group_out_st<T, false>), g1, b1, 0, c->stream, N, nm,
+                           (const SegOut*)grp.out_tab.get(), so, z, sT);
+      MGD_CHECK_LAUNCH();
+      return;
+    }
+    ProfScope ps(c, KC_VEC, (double)nm * N * (sizeof(T) + 8 + (sum ? 8 : 0)),
+                 ksym(c, "k_group_out", {type_name<T>(), sum ? "true" : "false"}));
     if (sum)
       hipLaunchKernelGGL((k_group_out<T, true>), g1, b1, 0, c->stream, N, nm,
                          (const SegOut*)grp.out_tab.get(), (const T*)grp.out.get(), z, sT);

@@ -1622,7 +1622,7 @@ void Union<T>::vcycle(Ctx* c, T* z) {
                                Xb(l, 1 - cf[l])});
           cf[l] = 1 - cf[l];
         }
-        if (last_out && s == n_post - 1) {  // final C half writes the natural result
+        if (last_out && z && s == n_post - 1) {  // final C half writes the natural result
           ProfScope ps = prof_level(c, KC_SMOOTH_L0, lv.A, lv.nnz_C, lv.nC,
                                     (double)lv.nC * 3 * ts + lv.nS * ts + (double)lv.nX * (4 + ts),
                                     kname(c, "k_half_out", lv.A));
@@ -1640,6 +1640,11 @@ void Union<T>::vcycle(Ctx* c, T* z) {
                              Xb(l, 1 - cc[l])});
         cc[l] = 1 - cc[l];
       }
+    }
+    if (last_out && !z) {  // the result stays in stored order
+      out_cc = cc[0];
+      out_cf = cf[0];
+      return;
     }
     if (last_out) {  // no post-smoothing (or no stored rows): copy out
       hipLaunchKernelGGL(k_out<T>, dim3(cdiv(lv.nX, 256)), dim3(256), 0, c->stream, lv.nX,
@@ -1897,6 +1902,7 @@ template <typename T>
 void Union<T>::apply_seg(Ctx* c, int N, const SegIn* tab, const double* r, const T* w, T* z) {
   ULevel<T>& l0 = L[0];
   MGD_REQUIRE(N > 0 && (long long)N * members == l0.nX, "apply_seg: rows do not match the union");
+  MGD_REQUIRE(z || (!gs && tail_from != 0), "apply_seg: stored-order result needs level-0 launches");
   const bool pre = n_pre > 0 && !gs;
   {
     // iperm, r and the coefficients (FP64), w, d^-1 on C rows, B and X_C written
@@ -1919,6 +1925,13 @@ void Union<T>::apply_seg(Ctx* c, int N, const SegIn* tab, const double* r, const
   else
     vcycle(c, z);
   t_prof_level = -1;
+}
+
+template <typename T>
+StoredOut<T> Union<T>::stored_out() const {
+  const ULevel<T>& l0 = L[0];
+  return {l0.iperm.get(), (out_cc ? X1[0] : X0[0]).get(), (out_cf ? X1[0] : X0[0]).get(),
+          X0[0].get(), l0.nC, l0.nS};
 }
 
 template <typename T>

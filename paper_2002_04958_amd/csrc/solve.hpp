@@ -118,6 +118,16 @@ struct TailOp {
   int ndense, dchunks;
 };
 
+// A union's level-0 result left in stored order: member m's row i sits at
+// stored index k = iperm[m N + i] of the C region (k < nC), the F region
+// (k < nS) or the dense rows (each region in a buffer of its own, indexed by k)
+template <typename T>
+struct StoredOut {
+  const int* iperm;
+  const T *xc, *xf, *xd;
+  int nC, nS;
+};
+
 template <typename T>
 struct Union {
   std::vector<ULevel<T>> L;
@@ -144,12 +154,16 @@ struct Union {
   // One cycle with the members' right-hand sides formed in the entry kernel:
   // member m's is (T)(r[tab[m].seg] - tab[m].coef o w) over N rows, the same
   // arithmetic as forming them into a vector first and calling apply.
+  // With z null (CF-l1-Jacobi only) the result stays in stored order, the
+  // final C half-sweep in place, for stored_out() to read until the next cycle.
   void apply_seg(Ctx* c, int N, const SegIn* tab, const double* r, const T* w, T* z);
+  StoredOut<T> stored_out() const;
   double bytes_per_vcycle() const;
 
  private:
+  int out_cc = 0, out_cf = 0;  // level-0 buffers of the C and F regions after a cycle
   // one V-cycle on B[0] (already in stored order, C values of X0[0] set)
-  // ending with z (natural) = the result
+  // ending with z (natural) = the result, or with it left in stored order (z null)
   void vcycle(Ctx* c, T* z);
   void vcycle_gs(Ctx* c, T* z);
   void gs_sweep(Ctx* c, int l, bool descending);

@@ -1037,6 +1037,34 @@ def test_step_overlap_switch_leaves_solve_unchanged(ctx, monkeypatch, precision)
         assert v[1] == ref[1] and np.array_equal(v[0], ref[0]), k
 
 
+@pytest.mark.parametrize("kind", ["schur2", "schur1", "pctl", "bdiag"])
+def test_stored_order_group_output_leaves_solve_unchanged(ctx, monkeypatch, kind):
+    """A batched group of single V-cycles leaves its result in the union's
+    stored order (the last C half-sweep in place), and the kernel that spreads
+    the members over the block vector reads each row at its stored position:
+    with MGD_STORED_OUT=0 (the last half-sweep writes the natural order, the
+    spreading kernel reads it there) FGMRES gives the same solution bit for
+    bit, in FP64 and FP32, with graph replay and without."""
+    api = gpu_modules()
+    inp = si.generate(3, 2, 24, 67)
+    co, gsys = gpu_system(ctx, inp)
+    b = to_dev(ctx, inp.b)
+    for precision in (0, 1):
+        out = {}
+        for so in ("1", "0"):
+            monkeypatch.setenv("MGD_STORED_OUT", so)
+            for graph in (0, 1):
+                M = api.BlockPreconditioner(ctx, gsys, kind, amg_seed=6, batched=1,
+                                            use_graph=graph, amg_precision=precision)
+                x, r = api.gmres(ctx, gsys, M, b, rtol=1e-9, flexible=1)
+                assert r.converged
+                out[(so, graph)] = (to_host(x), r.iters)
+                M.close()
+        ref = out[("1", 1)]
+        for k, v in out.items():
+            assert v[1] == ref[1] and np.array_equal(v[0], ref[0]), (precision, k)
+
+
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("blocks", ["3", "256"])
 @pytest.mark.parametrize("precision", [0, 1])
