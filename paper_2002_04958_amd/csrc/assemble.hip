@@ -13,10 +13,18 @@
 
 #include "handles.hpp"
 #include "kernels.hpp"
+#include "spmv.hpp"
 
 using namespace mgd;
 
 namespace {
+
+// Half storage of symmetric blocks for the block matvec (BlockSysDev::sym_*).
+struct SymHalf {
+  DBuf<int> urp, src;
+  long long unnz = 0;
+  std::vector<DBuf<double>> uv;
+};
 
 struct OwnedSystem {
   std::vector<mgd_csr> desc;
@@ -24,6 +32,7 @@ struct OwnedSystem {
   DBuf<int> rp, ci;                  // shared pattern (assembly)
   std::vector<DBuf<double>> vals;    // per-block values (assembly)
   DBuf<double> d_gE, d_Eg, d_EI, d_IE;
+  std::unique_ptr<SymHalf> sym;      // set when every block is symmetric
 };
 
 std::mutex g_sys_mu;
@@ -147,7 +156,142 @@ __global__ void k_grad_coupling(int G, int N, const double* __restrict__ x,
   dc[(size_t)2 * G * N + c] = -lam[E + c] * (x[E + c] - x[I + c]) - lam[I + c] * (x[I + c] - x[E + c]);
 }
 
+// Per row of a sorted pattern: the diagonal's position and the number of
+// entries from it to the row's end; flags[0] = 1 when a row has no diagonal,
+// more than kSymMaxRow entries or more than kSymMaxUpper from the diagonal on
+// (no half storage then).
+__global__ void k_sym_rows(int N, const int* __restrict__ rp, const int* __restrict__ ci,
+                           int* __restrict__ dpos, int* __restrict__ ulen,
+                           int* __restrict__ flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int e0 = rp[i], e1 = rp[i + 1];
+  int k = e0;
+  while (k < e1 && ci[k] < i) ++k;
+  if (k == e1 || ci[k] != i || e1 - e0 > kSymMaxRow || e1 - k > kSymMaxUpper) {
+    atomicOr(flags, 1);
+    dpos[i] = e0;
+    ulen[i] = 0;
+    return;
+  }
+  dpos[i] = k;
+  ulen[i] = e1 - k;
+}
+
+// src[k] for every entry of row i: its own half-storage position on and
+// above the diagonal, below it the position of its mirror (j, i), found by
+// bisection among row j's entries right of j's diagonal.  flags[0] = 1 when a
+// mirror is missing or some block's value differs from its mirror's in any bit.
+__global__ void k_sym_src(int N, int nb, const int* __restrict__ rp, const int* __restrict__ ci,
+                          const int* __restrict__ dpos, const int* __restrict__ urp,
+                          const double* const* __restrict__ vals, int* __restrict__ src,
+                          int* __restrict__ flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int e1 = rp[i + 1];
+  for (int k = rp[i]; k < e1; ++k) {
+    const int j = ci[k];
+    if (j >= i) {
+      src[k] = urp[i] + (k - dpos[i]);
+      continue;
+    }
+    int lo = dpos[j] + 1, hi = rp[j + 1] - 1, kj = -1;
+    while (lo <= hi) {
+      const int mid = (lo + hi) >> 1;
+      const int cm = ci[mid];
+      if (cm == i) {
+        kj = mid;
+        break;
+      }
+      if (cm < i)
+        lo = mid + 1;
+      else
+        hi = mid - 1;
+    }
+    if (kj < 0) {
+      atomicOr(flags, 1);
+      src[k] = urp[i];  // a valid position; the half storage is not used
+      continue;
+    }
+    src[k] = urp[j] + (kj - dpos[j]);
+    for (int a = 0; a < nb; ++a)
+      if (__double_as_longlong(vals[a][k]) != __double_as_longlong(vals[a][kj])) {
+        atomicOr(flags, 1);
+        break;
+      }
+  }
+}
+
+// block blockIdx.y's values on and above the diagonal, row after row
+__global__ void k_sym_fill(int N, const int* __restrict__ rp, const int* __restrict__ dpos,
+                           const int* __restrict__ urp, const double* const* __restrict__ vals,
+                           double* const* __restrict__ uv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double* __restrict__ v = vals[blockIdx.y];
+  double* __restrict__ u = uv[blockIdx.y];
+  const int d = dpos[i], e1 = rp[i + 1], o = urp[i];
+  for (int k = d; k < e1; ++k) u[o + (k - d)] = v[k];
+}
+
+// The half storage of nb blocks sharing the pattern (rp, ci): null when a
+// block differs from its transpose in any bit or a row is longer than
+// kSymMaxRow.
+std::unique_ptr<SymHalf> build_sym(Ctx* c, int N, long long nnz, const int* rp, const int* ci,
+                                   const std::vector<const double*>& vals) {
+  const int nb = (int)vals.size();
+  if (N <= 0 || nnz <= 0 || nb <= 0) return nullptr;
+  DBuf<int> dpos(c, (size_t)N), ulen(c, (size_t)N), flags(c, 1);
+  fill<int>(c, flags.get(), 0, 1);
+  hipLaunchKernelGGL(k_sym_rows, dim3(cdiv(N, 256)), dim3(256), 0, c->stream, N, rp, ci, dpos.get(),
+                     ulen.get(), flags.get());
+  MGD_CHECK_LAUNCH();
+  if (read1(c, flags.get())) return nullptr;
+  auto h = std::make_unique<SymHalf>();
+  h->urp.alloc(c, (size_t)N + 1);
+  h->unnz = exclusive_scan_total(c, ulen.get(), h->urp.get(), N);
+  h->src.alloc(c, (size_t)nnz);
+  DBuf<const double*> vtab(c, (size_t)nb);
+  copy_h2d(c, vtab.get(), vals.data(), (size_t)nb);
+  hipLaunchKernelGGL(k_sym_src, dim3(cdiv(N, 256)), dim3(256), 0, c->stream, N, nb, rp, ci,
+                     (const int*)dpos.get(), (const int*)h->urp.get(),
+                     (const double* const*)vtab.get(), h->src.get(), flags.get());
+  MGD_CHECK_LAUNCH();
+  if (read1(c, flags.get())) return nullptr;
+  std::vector<double*> up(nb);
+  h->uv.resize(nb);
+  for (int a = 0; a < nb; ++a) {
+    h->uv[a].alloc(c, (size_t)std::max(h->unnz, 1LL));
+    up[a] = h->uv[a].get();
+  }
+  DBuf<double*> utab(c, (size_t)nb);
+  copy_h2d(c, utab.get(), up.data(), (size_t)nb);
+  hipLaunchKernelGGL(k_sym_fill, dim3(cdiv(N, 256), nb), dim3(256), 0, c->stream, N, rp,
+                     (const int*)dpos.get(), (const int*)h->urp.get(),
+                     (const double* const*)vtab.get(), (double* const*)utab.get());
+  MGD_CHECK_LAUNCH();
+  c->sync();
+  return h;
+}
+
 }  // namespace
+
+namespace mgd {
+void attach_half_storage(const mgd_block_system* A, BlockSysDev& S) {
+  const char* e = std::getenv("MGD_SYM_MATVEC");
+  if (e && e[0] == '0') return;
+  std::lock_guard<std::mutex> g(g_sys_mu);
+  auto it = g_systems.find(A->blocks);
+  if (it == g_systems.end() || !it->second->sym) return;
+  const SymHalf& h = *it->second->sym;
+  if ((int)h.uv.size() != A->G + 2) return;
+  S.sym = 1;
+  S.sym_urp = h.urp.get();
+  S.sym_src = h.src.get();
+  S.sym_nnz = h.unnz;
+  for (int a = 0; a < A->G + 2; ++a) S.sym_v[a] = h.uv[a].get();
+}
+}  // namespace mgd
 
 void check_coeffs(const mgd_coeffs* cf) {
   MGD_REQUIRE(cf, "coeffs is NULL");
@@ -207,6 +351,10 @@ void assemble_impl(Ctx* c, const mgd_coeffs* cf, mgd_block_system* out) {
   hipLaunchKernelGGL(k_negate, dim3(cdiv(N, 256)), dim3(256), 0, c->stream, (size_t)N, cf->c_EI, os->d_IE.get());
   MGD_CHECK_LAUNCH();
   c->sync();
+  {
+    std::vector<const double*> cv(vp.begin(), vp.end());
+    os->sym = build_sym(c, N, nnz, os->rp.get(), os->ci.get(), cv);
+  }
   os->desc.resize(G + 2);
   for (int a = 0; a < G + 2; ++a)
     os->desc[a] = {N, N, nnz, os->rp.get(), os->ci.get(), os->vals[a].get()};
@@ -255,6 +403,12 @@ void system_transpose_impl(Ctx* c, const mgd_block_system* A, mgd_block_system* 
     }
     const auto& P = shared ? os->blocks[0] : B;
     os->desc[a] = {B.n_rows, B.n_cols, B.nnz, P.rp.get(), P.ci.get(), B.v.get()};
+  }
+  if (shared) {
+    std::vector<const double*> cv(G + 2);
+    for (int a = 0; a < G + 2; ++a) cv[a] = os->blocks[a].v.get();
+    os->sym = build_sym(c, N, os->blocks[0].nnz, os->blocks[0].rp.get(), os->blocks[0].ci.get(),
+                        cv);
   }
   out->G = G;
   out->N = N;

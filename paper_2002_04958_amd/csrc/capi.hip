@@ -288,6 +288,7 @@ BlockSysDev make_block_sys_dev(const mgd_block_system* A) {
   S.d_Eg = A->d_Eg;
   S.d_EI = A->d_EI;
   S.d_IE = A->d_IE;
+  if (S.shared) attach_half_storage(A, S);
   return S;
 }
 

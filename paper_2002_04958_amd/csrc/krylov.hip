@@ -252,6 +252,12 @@ mgd_status gmres_impl(Ctx* c, const BlockSysDev& S, block_precond* M, const doub
       sys_key.push_back((uintptr_t)S.blk[a].ci);
       sys_key.push_back((uintptr_t)S.blk[a].v);
     }
+    sys_key.push_back((uintptr_t)S.sym);  // the half storage, when attached
+    if (S.sym) {
+      sys_key.push_back((uintptr_t)S.sym_urp);
+      sys_key.push_back((uintptr_t)S.sym_src);
+      for (int a = 0; a < S.G + 2; ++a) sys_key.push_back((uintptr_t)S.sym_v[a]);
+    }
   }
   // Enqueue graph-replayed step jj (z = M^{-1} v_jj, w = A z, the Gram-Schmidt
   // step) and the readback of its coefficients into pinned slot jj % 2.

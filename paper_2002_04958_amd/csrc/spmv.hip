@@ -101,16 +101,28 @@ struct BlockMatvecLaunch {
 // produces x_E: y_g = A_g x_g, y_I = A_I x_I and y_E = sum_g d_Eg[g] o x_g
 // (the E block's values are not read); k_block_matvec_finish adds the rest
 // in the order of the whole kernel, so that the result is the same.
-template <int R, bool RESID, bool SPLIT>
+//
+// SYM (S.sym: every block equal to its transpose, rows of at most kSymMaxRow
+// entries): a block's values are read from its half storage.  The segment of
+// the workgroup's rows (on and above the diagonal) is staged in LDS; an entry
+// below the diagonal takes its mirror's value, from LDS when the mirror row is
+// one of the workgroup's rows, else from the half storage in memory.  The
+// values are the same bits, summed in the same order, so the result is that
+// of the full storage; the values move about 4/7 of the bytes (3D stencil).
+template <int R, bool RESID, bool SPLIT, bool SYM>
 __global__ void __launch_bounds__(R) k_block_matvec_shared(BlockSysDev S,
                                                            const double* __restrict__ x,
                                                            const double* __restrict__ b,
                                                            double* __restrict__ y) {
   constexpr int CAP = 7 * R + 64;        // staged pattern entries per chunk
   constexpr int PT = (CAP + R - 1) / R;  // staging loads per thread and block
+  static_assert(!SYM || kSymMaxRow * R <= CAP, "a symmetric segment must fit one chunk");
+  // SYM: a half-storage segment holds at most kSymMaxUpper values per row
+  constexpr int VCAP = SYM ? kSymMaxUpper * R : CAP;
   __shared__ int s_rp[R + 1];
   __shared__ int s_ci[CAP];
-  __shared__ double s_v[CAP];
+  __shared__ double s_v[VCAP];
+  __shared__ int s_src[SYM ? kSymMaxRow * R : 1];
   const int G = S.G, N = S.N, nb = S.G + 2;
   const int t = threadIdx.x;
   const int i0 = blockIdx.x * R;
@@ -123,9 +135,14 @@ __global__ void __launch_bounds__(R) k_block_matvec_shared(BlockSysDev S,
   const bool active = t < nr;
   const int i = i0 + t;
   const int rb = active ? s_rp[t] : 0, re = active ? s_rp[t + 1] : 0;
-  const bool one_chunk = end - beg <= CAP;
+  const bool one_chunk = end - beg <= CAP;  // always with SYM (rows of <= kSymMaxRow)
   if (one_chunk)
-    for (int k = t; k < end - beg; k += R) s_ci[k] = ci[beg + k];
+    for (int k = t; k < end - beg; k += R) {
+      s_ci[k] = ci[beg + k];
+      if (SYM) s_src[k] = S.sym_src[beg + k];
+    }
+  // SYM: the half-storage segment [ub, ue) of the workgroup's rows
+  const int ub = SYM ? S.sym_urp[i0] : 0, ue = SYM ? S.sym_urp[i0 + nr] : 0;
   const double xE = (active && !SPLIT) ? x[(size_t)G * N + i] : 0.0;
   double sE = 0.0;
   for (int a = 0; a < nb; ++a) {
@@ -135,6 +152,43 @@ __global__ void __launch_bounds__(R) k_block_matvec_shared(BlockSysDev S,
       if (active) y[(size_t)G * N + i] = sE;
       continue;
     }
+    if (SYM) {
+      const int ul = ue - ub;  // in [nr, kSymMaxUpper nr]: every row holds its diagonal
+      const double* __restrict__ uv = S.sym_v[a];
+      double r[kSymMaxUpper];
+#pragma unroll
+      for (int j = 0; j < kSymMaxUpper; ++j) {
+        const int k = t + j * R;
+        if (k < ul) r[j] = uv[ub + k];
+      }
+      __syncthreads();  // every thread is done with the previous block
+#pragma unroll
+      for (int j = 0; j < kSymMaxUpper; ++j) {
+        const int k = t + j * R;
+        if (k < ul) s_v[k] = r[j];
+      }
+      __syncthreads();
+      // eight entries at a time, as below
+      for (int k0 = rb; k0 < re; k0 += 8) {
+        int jj[8];
+        double av[8], xv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int kq = min(k0 + q, re - 1) - beg;
+          jj[q] = s_ci[kq];
+          const int u = s_src[kq];
+          if (u >= ub && u < ue)
+            av[q] = s_v[u - ub];
+          else
+            av[q] = uv[u];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xv[q] = xa[jj[q]];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (k0 + q < re) s += av[q] * xv[q];
+      }
+    } else
     for (int cb = beg; cb < end; cb += CAP) {
       const int cl = min(CAP, end - cb);
       const double* __restrict__ v = S.blk[a].v + cb;
@@ -187,6 +241,7 @@ __global__ void __launch_bounds__(R) k_block_matvec_shared(BlockSysDev S,
 // the rest of a SPLIT block matvec, once x_E is known: the E row's stencil
 // sum, then + sum_g d_Eg[g] o x_g (held in y_E) + d_EI o x_I; y_g += d_gE o x_E;
 // y_I += d_IE o x_E
+template <bool SYM>
 __global__ void __launch_bounds__(256) k_block_matvec_finish(BlockSysDev S,
                                                              const double* __restrict__ x,
                                                              double* __restrict__ y) {
@@ -197,7 +252,7 @@ __global__ void __launch_bounds__(256) k_block_matvec_finish(BlockSysDev S,
   const double xE = xEv[i];
   const int* __restrict__ rp = S.blk[0].rp;
   const int* __restrict__ ci = S.blk[0].ci;
-  const double* __restrict__ v = S.blk[G].v;
+  const double* __restrict__ v = SYM ? S.sym_v[G] : S.blk[G].v;
   double s = 0.0;
   const int kb = rp[i], ke = rp[i + 1];
   for (int k0 = kb; k0 < ke; k0 += 8) {  // as in k_block_matvec_shared
@@ -207,7 +262,7 @@ __global__ void __launch_bounds__(256) k_block_matvec_finish(BlockSysDev S,
     for (int q = 0; q < 8; ++q) {
       const int kq = min(k0 + q, ke - 1);
       jj[q] = ci[kq];
-      av[q] = v[kq];
+      av[q] = v[SYM ? S.sym_src[kq] : kq];
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) xv[q] = xEv[jj[q]];
@@ -230,13 +285,18 @@ constexpr int kSharedRows = 512;
 
 // values, pattern (once when shared, or per block with csr = true: the plain
 // CSR pricing of every block), x, couplings, y (and b)
+// (with the half storage: its values per block, and the value positions and
+// its row starts once)
 double block_matvec_bytes(const BlockSysDev& S, bool resid, bool csr) {
   const double n = (double)(S.G + 2) * S.N;
   double nnz = 0;
   for (int a = 0; a < S.G + 2; ++a) nnz += S.nnz[a];
   const double pattern = (S.shared && !csr) ? 4.0 * S.nnz[0] + 4.0 * (S.N + 1)
                                             : 4.0 * nnz + 4.0 * n;
-  return 8.0 * nnz + pattern + 8.0 * (2.0 * S.G + 2.0) * S.N + 8.0 * n * (resid ? 3 : 2);
+  const double values = (S.sym && !csr)
+                            ? 8.0 * S.sym_nnz * (S.G + 2) + 4.0 * S.nnz[0] + 4.0 * (S.N + 1)
+                            : 8.0 * nnz;
+  return values + pattern + 8.0 * (2.0 * S.G + 2.0) * S.N + 8.0 * n * (resid ? 3 : 2);
 }
 
 void block_matvec(Ctx* c, const BlockSysDev& S, const double* x, const double* b, double* y) {
@@ -246,12 +306,20 @@ void block_matvec(Ctx* c, const BlockSysDev& S, const double* x, const double* b
                  ksym(c, "k_block_matvec_shared", {std::to_string(R), b ? "true" : "false"}),
                  block_matvec_bytes(S, b != nullptr, true));
     const dim3 grid(cdiv(S.N, R));
-    if (b)
-      hipLaunchKernelGGL((k_block_matvec_shared<R, true, false>), grid, dim3(R), 0, c->stream, S, x,
-                         b, y);
-    else
-      hipLaunchKernelGGL((k_block_matvec_shared<R, false, false>), grid, dim3(R), 0, c->stream, S,
-                         x, b, y);
+    if (S.sym) {
+      if (b)
+        hipLaunchKernelGGL((k_block_matvec_shared<R, true, false, true>), grid, dim3(R), 0,
+                           c->stream, S, x, b, y);
+      else
+        hipLaunchKernelGGL((k_block_matvec_shared<R, false, false, true>), grid, dim3(R), 0,
+                           c->stream, S, x, b, y);
+    } else if (b) {
+      hipLaunchKernelGGL((k_block_matvec_shared<R, true, false, false>), grid, dim3(R), 0,
+                         c->stream, S, x, b, y);
+    } else {
+      hipLaunchKernelGGL((k_block_matvec_shared<R, false, false, false>), grid, dim3(R), 0,
+                         c->stream, S, x, b, y);
+    }
     MGD_CHECK_LAUNCH();
     return;
   }
@@ -268,7 +336,9 @@ static void split_bytes(const BlockSysDev& S, double& stored, double& csr) {
   for (int a = 0; a < S.G + 2; ++a)
     if (a != S.G) nnz += S.nnz[a];
   const double vec = 8.0 * (G + 1) * N + 8.0 * G * N + 8.0 * (G + 2) * N;
-  stored = 8.0 * nnz + 4.0 * S.nnz[0] + 4.0 * (N + 1) + vec;
+  const double values =
+      S.sym ? 8.0 * S.sym_nnz * (G + 1) + 4.0 * S.nnz[0] + 4.0 * (N + 1) : 8.0 * nnz;
+  stored = values + 4.0 * S.nnz[0] + 4.0 * (N + 1) + vec;
   csr = 12.0 * nnz + 4.0 * (G + 1) * (N + 1) + vec;
 }
 
@@ -280,8 +350,12 @@ void block_matvec_split(Ctx* c, const BlockSysDev& S, const double* x, double* y
   if (c->profiling) split_bytes(S, bs, bc);
   ProfScope ps(c, KC_BLOCK_MATVEC, bs,
                ksym(c, "k_block_matvec_shared", {std::to_string(R), "false", "true"}), bc, stream);
-  hipLaunchKernelGGL((k_block_matvec_shared<R, false, true>), dim3(cdiv(S.N, R)), dim3(R), 0,
-                     stream, S, x, (const double*)nullptr, y);
+  if (S.sym)
+    hipLaunchKernelGGL((k_block_matvec_shared<R, false, true, true>), dim3(cdiv(S.N, R)), dim3(R),
+                       0, stream, S, x, (const double*)nullptr, y);
+  else
+    hipLaunchKernelGGL((k_block_matvec_shared<R, false, true, false>), dim3(cdiv(S.N, R)), dim3(R),
+                       0, stream, S, x, (const double*)nullptr, y);
   MGD_CHECK_LAUNCH();
 }
 
@@ -290,9 +364,15 @@ void block_matvec_finish(Ctx* c, const BlockSysDev& S, const double* x, double* 
   const double N = S.N, G = S.G;
   const double b = 12.0 * S.nnz[S.G] + 4.0 * (N + 1) + 8.0 * 4 * N + 8.0 * G * N +
                    16.0 * (G + 2) * N;
-  ProfScope ps(c, KC_BLOCK_MATVEC, b, ksym(c, "k_block_matvec_finish", {}));
-  hipLaunchKernelGGL(k_block_matvec_finish, dim3(cdiv(S.N, 256)), dim3(256), 0, c->stream, S, x,
-                     y);
+  // with the half storage: its values and the value positions instead of the values
+  const double bs = S.sym ? b - 8.0 * S.nnz[S.G] + 8.0 * S.sym_nnz + 4.0 * S.nnz[S.G] : b;
+  ProfScope ps(c, KC_BLOCK_MATVEC, bs, ksym(c, "k_block_matvec_finish", {}), b);
+  if (S.sym)
+    hipLaunchKernelGGL(k_block_matvec_finish<true>, dim3(cdiv(S.N, 256)), dim3(256), 0, c->stream,
+                       S, x, y);
+  else
+    hipLaunchKernelGGL(k_block_matvec_finish<false>, dim3(cdiv(S.N, 256)), dim3(256), 0,
+                       c->stream, S, x, y);
   MGD_CHECK_LAUNCH();
 }
 

@@ -1037,6 +1037,61 @@ def test_step_overlap_switch_leaves_solve_unchanged(ctx, monkeypatch, precision)
         assert v[1] == ref[1] and np.array_equal(v[0], ref[0]), k
 
 
+@pytest.mark.parametrize("dim,n,nonsym", [(3, 16, False), (2, 40, False), (3, 16, True)])
+def test_half_storage_block_matvec_is_bit_exact(ctx, monkeypatch, dim, n, nonsym):
+    """An assembled system whose blocks equal their transposes bit for bit gets
+    a half storage for the block matvec: each block's values on and above the
+    diagonal, an entry below it reading its mirror's (from LDS inside the
+    workgroup's rows, from memory across them: 16^3 and 40^2 meshes put the
+    -z and -y mirrors on both sides of a 512-row tile).  y = A x, FGMRES with
+    a graph-replayed batched Schur2 (the split matvec and its finishing pass)
+    and the adjoint solve on the transposed system equal those of the full
+    storage (MGD_SYM_MATVEC=0) bit for bit, and the profiled bytes of the
+    matvec show which storage ran.  The nonsymmetric variant keeps the full
+    storage."""
+    api = gpu_modules()
+    G = 3
+    inp = si.generate(G, dim, n, 71, nonsym=nonsym)
+    N = n ** dim
+    A0 = sp.csr_matrix(oracle_system(inp).blocks[0])
+    rows = np.repeat(np.arange(N), np.diff(A0.indptr))
+    nnz0, unnz = A0.nnz, int(np.count_nonzero(A0.indices >= rows))
+    rest = 4.0 * nnz0 + 4.0 * (N + 1) + 8.0 * (2 * G + 2) * N + 16.0 * (G + 2) * N
+    full = 8.0 * nnz0 * (G + 2) + rest
+    half = 8.0 * unnz * (G + 2) + 4.0 * nnz0 + 4.0 * (N + 1) + rest
+    rng = np.random.default_rng(8)
+    x = to_dev(ctx, rng.standard_normal((G + 2) * N))
+    b = to_dev(ctx, inp.b)
+    out = {}
+    for sym in ("1", "0"):
+        monkeypatch.setenv("MGD_SYM_MATVEC", sym)
+        co, gsys = gpu_system(ctx, inp)
+        ctx.reset_kernel_stats()
+        ctx.set_profiling(True)
+        y = to_host(gsys.matvec(x))
+        ctx.set_profiling(False)
+        st = ctx.kernel_symbol_stats()["k_block_matvec_shared<512, false>"]
+        M = api.BlockPreconditioner(ctx, gsys, "schur2", amg_seed=6, batched=1, use_graph=1,
+                                    amg_precision=1)
+        xs, r = api.gmres(ctx, gsys, M, b, rtol=1e-9, flexible=1)
+        assert r.converged
+        adj = (None,) * 4
+        if not nonsym:  # the gradients are those of the symmetric assembly
+            MT = api.BlockPreconditioner(ctx, gsys, "schur2", amg_seed=6, transpose=1)
+            lam, dk, dc, ra = api.adjoint(ctx, co, gsys, MT, xs, xs - b, rtol=1e-10)
+            adj = (to_host(lam), ra.iters, to_host(dk), to_host(dc))
+            MT.close()
+        out[sym] = (y, st["bytes"] / st["launches"], to_host(xs), r.iters) + adj
+        M.close()
+        gsys.close()
+    on, off = out["1"], out["0"]
+    assert off[1] == pytest.approx(full)
+    assert on[1] == pytest.approx(full if nonsym else half)
+    for k in (0, 2) if nonsym else (0, 2, 4, 6, 7):
+        assert np.array_equal(on[k], off[k]), k
+    assert on[3] == off[3] and on[5] == off[5]
+
+
 @pytest.mark.parametrize("kind", ["schur2", "schur1", "pctl", "bdiag"])
 def test_stored_order_group_output_leaves_solve_unchanged(ctx, monkeypatch, kind):
     """A batched group of single V-cycles leaves its result in the union's
