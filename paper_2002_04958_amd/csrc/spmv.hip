@@ -141,8 +141,22 @@ __global__ void __launch_bounds__(R) k_block_matvec_shared(BlockSysDev S,
       s_ci[k] = ci[beg + k];
       if (SYM) s_src[k] = S.sym_src[beg + k];
     }
-  // SYM: the half-storage segment [ub, ue) of the workgroup's rows
+  // SYM: the half-storage segment [ub, ue) of the workgroup's rows, and the
+  // thread's row (at most kSymMaxRow entries): columns and value positions,
+  // the same for every block, kept in registers
   const int ub = SYM ? S.sym_urp[i0] : 0, ue = SYM ? S.sym_urp[i0 + nr] : 0;
+  int sj[kSymMaxRow], su[kSymMaxRow];
+  const int ne = SYM ? re - rb : 0;
+  if (SYM) {
+    __syncthreads();  // s_ci and s_src staged
+#pragma unroll
+    for (int q = 0; q < kSymMaxRow; ++q) {
+      // rows of active threads are not empty; other threads read entry 0
+      const int kq = active ? (q < ne ? rb + q : rb) - beg : 0;
+      sj[q] = s_ci[kq];
+      su[q] = s_src[kq];
+    }
+  }
   const double xE = (active && !SPLIT) ? x[(size_t)G * N + i] : 0.0;
   double sE = 0.0;
   for (int a = 0; a < nb; ++a) {
@@ -155,11 +169,20 @@ __global__ void __launch_bounds__(R) k_block_matvec_shared(BlockSysDev S,
     if (SYM) {
       const int ul = ue - ub;  // in [nr, kSymMaxUpper nr]: every row holds its diagonal
       const double* __restrict__ uv = S.sym_v[a];
-      double r[kSymMaxUpper];
+      // every load of the block at once: the segment's staging loads, the
+      // row's gathers of x_a and its values outside the segment
+      double r[kSymMaxUpper], xv[kSymMaxRow], mv[kSymMaxRow];
 #pragma unroll
       for (int j = 0; j < kSymMaxUpper; ++j) {
         const int k = t + j * R;
         if (k < ul) r[j] = uv[ub + k];
+      }
+#pragma unroll
+      for (int q = 0; q < kSymMaxRow; ++q) {
+        if (q < ne) {
+          xv[q] = xa[sj[q]];
+          if (su[q] < ub || su[q] >= ue) mv[q] = uv[su[q]];
+        }
       }
       __syncthreads();  // every thread is done with the previous block
 #pragma unroll
@@ -168,25 +191,15 @@ __global__ void __launch_bounds__(R) k_block_matvec_shared(BlockSysDev S,
         if (k < ul) s_v[k] = r[j];
       }
       __syncthreads();
-      // eight entries at a time, as below
-      for (int k0 = rb; k0 < re; k0 += 8) {
-        int jj[8];
-        double av[8], xv[8];
+      // the row's sum in entry order, as below
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int kq = min(k0 + q, re - 1) - beg;
-          jj[q] = s_ci[kq];
-          const int u = s_src[kq];
-          if (u >= ub && u < ue)
-            av[q] = s_v[u - ub];
-          else
-            av[q] = uv[u];
+      for (int q = 0; q < kSymMaxRow; ++q) {
+        if (q < ne) {
+          const int lo = su[q] - ub;
+          const bool seg = (unsigned)lo < (unsigned)ul;
+          const double av = seg ? s_v[seg ? lo : 0] : mv[q];
+          s += av * xv[q];
         }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) xv[q] = xa[jj[q]];
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (k0 + q < re) s += av[q] * xv[q];
       }
     } else
     for (int cb = beg; cb < end; cb += CAP) {
