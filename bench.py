@@ -336,6 +336,36 @@ def main():
         for k, v in sorted(tagged.items(), key=lambda kv: -kv[1]["ms"])[:40]))
     log(f"[bench] dominant {dom}: {avg_us:.2f} us/launch, {achieved:.0f} GB/s (CSR model), "
         f"{achieved_stored:.0f} GB/s (stored layout); copy {copy_gbs:.0f} GB/s")
+    # The block matvec alone on the device: y = A x over all G+2 blocks, the
+    # kernel family and storage of the split launch (which shares the device
+    # with the E V-cycle in the solve), 20 launches back to back, event-timed.
+    xa_ = torch.rand(sysg.n, dtype=torch.float64, device=ctx.device)
+    ya_ = ctx.empty(sysg.n)
+    for _ in range(3):
+        sysg.matvec(xa_, ya_)
+    ctx.reset_kernel_stats()
+    ctx.set_profiling(True)
+    for _ in range(20):
+        sysg.matvec(xa_, ya_)
+    ctx.set_profiling(False)
+    al_stats = ctx.kernel_symbol_stats()
+    alone_k = next((k for k in al_stats if k.startswith("k_block_matvec_shared<512, false, false")),
+                   None)
+    al = al_stats.get(alone_k) if alone_k else None
+    standalone = None
+    if al and al["launches"]:
+        al_us = 1e3 * al["ms"] / al["launches"]
+        al_b, al_bc = al["bytes"] / al["launches"], al["bytes_csr"] / al["launches"]
+        al_csr, al_st = al_bc / (al_us * 1e-6) / 1e9, al_b / (al_us * 1e-6) / 1e9
+        standalone = {"kernel": alone_k, "what": "y = A x over all blocks, alone on the device",
+                      "launches": al["launches"], "avg_launch_us": al_us,
+                      "bytes_per_launch": al_bc, "bytes_per_launch_stored": al_b,
+                      "achieved": al_csr, "frac": al_csr / HBM_PEAK_GBS,
+                      "achieved_stored": al_st, "frac_stored": al_st / HBM_PEAK_GBS,
+                      "frac_of_copy": al_st / copy_gbs}
+        log(f"[bench] {alone_k} alone: {al_us:.2f} us/launch, {al_csr:.0f} GB/s (CSR model), "
+            f"{al_st:.0f} GB/s (stored)")
+    del xa_, ya_
     # the whole solve: every launch's algorithmic bytes (the same 38-step solve,
     # event-timed above) over the graph-replayed time of one solve
     # (the class totals include the few launches profiled without a symbol:
@@ -447,7 +477,8 @@ def main():
                      "copy_ceiling": copy_gbs,
                      # the bytes the launch moves as stored, against a device copy's rate
                      "frac_of_copy": achieved_stored / copy_gbs,
-                     "launches": s["launches"], "avg_launch_us": avg_us},
+                     "launches": s["launches"], "avg_launch_us": avg_us,
+                     "standalone": standalone},
         "solve_bandwidth": {"bytes_stored": solve_bytes, "bytes_csr": solve_bytes_csr,
                             "GB/s_stored": solve_gbs, "frac_of_peak": solve_gbs / HBM_PEAK_GBS,
                             "frac_of_copy": solve_gbs / copy_gbs,

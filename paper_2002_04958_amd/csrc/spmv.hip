@@ -110,7 +110,7 @@ struct BlockMatvecLaunch {
 // values are the same bits, summed in the same order, so the result is that
 // of the full storage; the values move about 4/7 of the bytes (3D stencil).
 template <int R, bool RESID, bool SPLIT, bool SYM>
-__global__ void __launch_bounds__(R) k_block_matvec_shared(BlockSysDev S,
+__global__ void __launch_bounds__(R, (SYM && !SPLIT) ? 4 : 1) k_block_matvec_shared(BlockSysDev S,
                                                            const double* __restrict__ x,
                                                            const double* __restrict__ b,
                                                            double* __restrict__ y) {
@@ -165,6 +165,23 @@ __global__ void __launch_bounds__(R) k_block_matvec_shared(BlockSysDev S,
     if (SPLIT && a == G) {  // uniform over the workgroup
       if (active) y[(size_t)G * N + i] = sE;
       continue;
+    }
+    // the row's coupling operands and b of this block, loaded ahead of the
+    // sum so that they are in flight with its other loads
+    const size_t ro = (size_t)a * N + i;
+    double c1 = 0.0, c2 = 0.0, xo = 0.0, bo = 0.0;
+    if (active) {
+      if (a < G) {
+        if (!SPLIT) c1 = S.d_gE[ro];
+        c2 = S.d_Eg[ro];
+        xo = xa[i];
+      } else if (a == G) {
+        c1 = S.d_EI[i];
+        xo = x[(size_t)(G + 1) * N + i];
+      } else if (!SPLIT) {
+        c1 = S.d_IE[i];
+      }
+      if (RESID) bo = b[ro];
     }
     if (SYM) {
       const int ul = ue - ub;  // in [nr, kSymMaxUpper nr]: every row holds its diagonal
@@ -238,16 +255,15 @@ __global__ void __launch_bounds__(R) k_block_matvec_shared(BlockSysDev S,
     }
     if (!active) continue;
     if (a < G) {
-      if (!SPLIT) s += S.d_gE[(size_t)a * N + i] * xE;
-      sE += S.d_Eg[(size_t)a * N + i] * xa[i];
+      if (!SPLIT) s += c1 * xE;
+      sE += c2 * xo;
     } else if (a == G) {
       s += sE;
-      s += S.d_EI[i] * x[(size_t)(G + 1) * N + i];
+      s += c1 * xo;
     } else if (!SPLIT) {
-      s += S.d_IE[i] * xE;
+      s += c1 * xE;
     }
-    const size_t ro = (size_t)a * N + i;
-    y[ro] = RESID ? b[ro] - s : s;
+    y[ro] = RESID ? bo - s : s;
   }
 }
 
@@ -316,7 +332,8 @@ void block_matvec(Ctx* c, const BlockSysDev& S, const double* x, const double* b
   if (S.shared) {
     constexpr int R = kSharedRows;
     ProfScope ps(c, KC_BLOCK_MATVEC, block_matvec_bytes(S, b != nullptr, false),
-                 ksym(c, "k_block_matvec_shared", {std::to_string(R), b ? "true" : "false"}),
+                 ksym(c, "k_block_matvec_shared",
+                      {std::to_string(R), b ? "true" : "false", "false", S.sym ? "true" : "false"}),
                  block_matvec_bytes(S, b != nullptr, true));
     const dim3 grid(cdiv(S.N, R));
     if (S.sym) {
@@ -362,7 +379,9 @@ void block_matvec_split(Ctx* c, const BlockSysDev& S, const double* x, double* y
   double bs = 0, bc = 0;
   if (c->profiling) split_bytes(S, bs, bc);
   ProfScope ps(c, KC_BLOCK_MATVEC, bs,
-               ksym(c, "k_block_matvec_shared", {std::to_string(R), "false", "true"}), bc, stream);
+               ksym(c, "k_block_matvec_shared",
+                    {std::to_string(R), "false", "true", S.sym ? "true" : "false"}),
+               bc, stream);
   if (S.sym)
     hipLaunchKernelGGL((k_block_matvec_shared<R, false, true, true>), dim3(cdiv(S.N, R)), dim3(R),
                        0, stream, S, x, (const double*)nullptr, y);
@@ -379,7 +398,8 @@ void block_matvec_finish(Ctx* c, const BlockSysDev& S, const double* x, double* 
                    16.0 * (G + 2) * N;
   // with the half storage: its values and the value positions instead of the values
   const double bs = S.sym ? b - 8.0 * S.nnz[S.G] + 8.0 * S.sym_nnz + 4.0 * S.nnz[S.G] : b;
-  ProfScope ps(c, KC_BLOCK_MATVEC, bs, ksym(c, "k_block_matvec_finish", {}), b);
+  ProfScope ps(c, KC_BLOCK_MATVEC, bs,
+               ksym(c, "k_block_matvec_finish", {S.sym ? "true" : "false"}), b);
   if (S.sym)
     hipLaunchKernelGGL(k_block_matvec_finish<true>, dim3(cdiv(S.N, 256)), dim3(256), 0, c->stream,
                        S, x, y);

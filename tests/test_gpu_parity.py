@@ -1070,7 +1070,9 @@ def test_half_storage_block_matvec_is_bit_exact(ctx, monkeypatch, dim, n, nonsym
         ctx.set_profiling(True)
         y = to_host(gsys.matvec(x))
         ctx.set_profiling(False)
-        st = ctx.kernel_symbol_stats()["k_block_matvec_shared<512, false>"]
+        name = "k_block_matvec_shared<512, false, false, %s>" % (
+            "true" if sym == "1" and not nonsym else "false")
+        st = ctx.kernel_symbol_stats()[name]
         M = api.BlockPreconditioner(ctx, gsys, "schur2", amg_seed=6, batched=1, use_graph=1,
                                     amg_precision=1)
         xs, r = api.gmres(ctx, gsys, M, b, rtol=1e-9, flexible=1)
