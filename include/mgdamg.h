@@ -219,10 +219,15 @@ typedef struct mgd_coeffs {
 } mgd_coeffs;
 
 /* Assemble eq. 2.2 on the device into library-owned arrays; release with
- * mgd_block_system_free. */
+ * mgd_block_system_free.  The arrays are read-only for the caller: when every
+ * block equals its transpose bit for bit (xi == NULL), the library also keeps
+ * each block's values on and above the diagonal for the block matvec (the
+ * entries below read their mirrors'; same results bit for bit), freed with the
+ * system. */
 mgd_status mgd_assemble(mgd_ctx* ctx, const mgd_coeffs* c, mgd_block_system* out);
 /* A^T as a block system (blocks transposed, D_gE and D_Eg swapped, D_EI and
- * D_IE swapped), library-owned. */
+ * D_IE swapped), library-owned and read-only like an assembled one (with the
+ * same half storage when its blocks share one pattern and are symmetric). */
 mgd_status mgd_block_system_transpose(mgd_ctx* ctx, const mgd_block_system* A,
                                       mgd_block_system* out);
 mgd_status mgd_block_system_free(mgd_ctx* ctx, mgd_block_system* s);
