@@ -240,6 +240,11 @@ def main():
         M32, _ = build(sysg, "schur2", w.seed, True, True, True)
         for _ in range(max(1, a.steps)):
             x, r = solve(sysg, M32, b)
+        # and the all-block matvec alone (roofline.standalone)
+        xa_ = torch.rand(sysg.n, dtype=torch.float64, device=ctx.device)
+        ya_ = ctx.empty(sysg.n)
+        for _ in range(5):
+            sysg.matvec(xa_, ya_)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "counters", "workload": w.name, "iters": r.iters,
                           "calibration_bytes": {"read": 1 << 30, "written": 1 << 30}}))
@@ -359,6 +364,7 @@ def main():
         al_csr, al_st = al_bc / (al_us * 1e-6) / 1e9, al_b / (al_us * 1e-6) / 1e9
         standalone = {"kernel": alone_k, "what": "y = A x over all blocks, alone on the device",
                       "launches": al["launches"], "avg_launch_us": al_us,
+                      "traffic": recorded_traffic(alone_k),
                       "bytes_per_launch": al_bc, "bytes_per_launch_stored": al_b,
                       "achieved": al_csr, "frac": al_csr / HBM_PEAK_GBS,
                       "achieved_stored": al_st, "frac_stored": al_st / HBM_PEAK_GBS,
